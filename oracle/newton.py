@@ -1,0 +1,92 @@
+"""Newton-Léja action of log on a block of vectors (oracle side, FP64).
+
+Sec. 4 scales the matrix: Q~ = Q/sigma when lambda_min(Q) < 1, else Q~ = Q
+(Eq. scaled_sigma_matrix), so that log det Q = n log(sigma) + tr log(Q~).
+Reading: sigma is taken from the *input* lower bound, sigma = lmin if
+lmin < 1 else 1, and the interval of Q~ is [lo, hi] = [lmin, lmax]/sigma.
+
+Alg. 2 applies the Newton form (Eq. Léja6) of the interpolant of log at the
+mapped Léja points z_j = c + gamma*xi_j to v, with w_0 = v, P = d_0 w_0 and
+w_{j+1} = (Q~ - z_j I) w_j, P += d_{j+1} w_{j+1}.  Reading: the recurrence is
+run in the mapped variable T = (Q~ - cI)/gamma, whose spectrum lies in
+[-2, 2], with the xi-variable divided differences d_j = gamma^j log[z_0..z_j]:
+
+    w_{j+1} = (T - xi_j I) w_j = alpha*Q w_j - beta_j w_j,
+    alpha = 1/(sigma*gamma),  beta_j = c/gamma + xi_j.
+
+This is the same polynomial P_m(Q~) (each factor carries 1/gamma and each
+d_j carries gamma^j), but keeps ||w_j|| bounded.  The degree m is fixed
+(the number of matrix products per column); the paper's adaptive stopping
+rule is not part of this path.
+
+Pinned by: polynomial exactness with the divided differences of xi^q,
+interpolation of log at the nodes for a diagonal matrix with the nodes as
+eigenvalues, and closed-form Dirichlet-Laplacian eigenvectors
+(tests/test_oracle_newton.py).
+"""
+from __future__ import annotations
+
+import math
+
+import numpy as np
+
+from .divdiff import exact_dd, interval_map
+from .leja import fast_leja_vectorised
+
+
+def scaling(lmin: float, lmax: float):
+    """sigma and the interval [lo, hi] of Q~ (Eq. scaled_sigma_matrix)."""
+    if not (0.0 < lmin < lmax):
+        raise ValueError("need 0 < lmin < lmax")
+    sigma = lmin if lmin < 1.0 else 1.0
+    return sigma, lmin / sigma, lmax / sigma
+
+
+class NewtonPlan:
+    """Everything the recurrence needs for an interval and a degree."""
+
+    def __init__(self, lmin: float, lmax: float, degree: int):
+        if degree < 1:
+            raise ValueError("degree >= 1")
+        self.sigma, self.lo, self.hi = scaling(lmin, lmax)
+        self.degree = degree
+        self.xi = fast_leja_vectorised(degree + 1)
+        self.d = exact_dd(self.lo, self.hi, self.xi)
+        self.c, self.gamma = interval_map(self.lo, self.hi)
+        self.alpha = 1.0 / (self.sigma * self.gamma)
+        self.beta = self.c / self.gamma + self.xi[:degree]
+
+    def apply_poly(self, Q, V):
+        """P_m(Q~) V by the forward Newton recurrence (Alg. 2, mapped form)."""
+        W = np.array(V, dtype=np.float64, copy=True)
+        P = self.d[0] * W
+        for j in range(self.degree):
+            W = self.alpha * (Q @ W) - self.beta[j] * W
+            P += self.d[j + 1] * W
+        return P
+
+    def dots(self, Q, X):
+        """s[j, col] = <X[:, col], w_j[:, col]> for j = 0..m, w_0 = X (DOT form)."""
+        W = np.array(X, dtype=np.float64, copy=True)
+        out = np.empty((self.degree + 1, X.shape[1]))
+        out[0] = np.einsum("ij,ij->j", X, W)
+        for j in range(self.degree):
+            W = self.alpha * (Q @ W) - self.beta[j] * W
+            out[j + 1] = np.einsum("ij,ij->j", X, W)
+        return out
+
+    def eval_scalar(self, lam):
+        """P_m(lam/sigma) for eigenvalues lam of Q (Newton form, Eq. Léja6)."""
+        t = (np.asarray(lam, dtype=np.float64) / self.sigma - self.c) / self.gamma
+        acc = np.full_like(t, self.d[0])
+        prod = np.ones_like(t)
+        for j in range(self.degree):
+            prod = prod * (t - self.xi[j])
+            acc = acc + self.d[j + 1] * prod
+        return acc
+
+
+def apply_log(Q, V, lmin: float, lmax: float, degree: int):
+    """log(Q) V ~= P_m(Q~) V + log(sigma) V."""
+    plan = NewtonPlan(lmin, lmax, degree)
+    return plan.apply_poly(Q, V) + math.log(plan.sigma) * np.asarray(V, dtype=np.float64)

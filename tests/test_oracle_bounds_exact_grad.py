@@ -1,0 +1,91 @@
+"""Pins for the spectral bounds, the exact references and the gradient oracle."""
+import math
+
+import numpy as np
+import pytest
+import scipy.sparse as sp
+
+import workloads as w
+from oracle import bounds, exact, grad, hutchpp
+
+
+def test_gershgorin_grids():
+    assert bounds.gershgorin(w.grid_laplacian_2d(32, 0.5)) == (0.5, 8.5)
+    lo, hi = bounds.gershgorin(w.grid_laplacian_3d(6, 0.05))
+    assert lo == pytest.approx(0.05, abs=1e-15) and hi == pytest.approx(12.05, abs=1e-14)
+    lo, hi = bounds.gershgorin(w.grid_laplacian_2d(16, 0.1, tau=1.5))
+    assert lo == pytest.approx(0.15) and hi == pytest.approx(12.15)
+
+
+def test_gershgorin_contains_spectrum():
+    A = w.chung_lu_laplacian(2000, seed=3)
+    lo, hi = bounds.gershgorin(A)
+    ev = np.linalg.eigvalsh(w.to_scipy(A).toarray())
+    assert lo <= ev[0] + 1e-12 and ev[-1] <= hi + 1e-9
+    assert lo == pytest.approx(1e-2, abs=1e-9)     # Laplacian rows sum to zero
+
+
+def test_lanczos_lmax():
+    A = w.chung_lu_laplacian(1500, seed=1)
+    Q = w.to_scipy(A)
+    ev = np.linalg.eigvalsh(Q.toarray())
+    est = bounds.lanczos_lmax(Q, 60)
+    assert est <= ev[-1] * (1 + 1e-12)
+    assert est == pytest.approx(ev[-1], rel=1e-6)
+
+
+def test_closed_form_logdets():
+    for N, k2 in ((5, 0.5), (9, 0.1)):
+        Q = w.to_scipy(w.grid_laplacian_2d(N, k2, tau=1.5)).toarray()
+        assert exact.grid_logdet_2d(N, k2, 1.5) == pytest.approx(exact.cholesky_logdet(Q), rel=1e-13)
+    Q3 = w.to_scipy(w.grid_laplacian_3d(6, 0.05)).toarray()
+    assert exact.grid_logdet_3d(6, 0.05) == pytest.approx(exact.cholesky_logdet(Q3), rel=1e-13)
+    # d/dkappa by central differences of the closed form
+    k = math.sqrt(0.1)
+    h = 1e-6
+    fd = (exact.grid_logdet_2d(9, (k + h) ** 2) - exact.grid_logdet_2d(9, (k - h) ** 2)) / (2 * h)
+    assert exact.grid_logdet_2d_dkappa(9, 0.1) == pytest.approx(fd, rel=1e-7)
+
+
+@pytest.mark.parametrize("seed", [0, 3])
+def test_gradient_against_finite_differences(seed):
+    A = w.grid_laplacian_2d(8, 0.5)
+    est, g = grad.logdet_grad(A, 0.5, 8.5, 20, 12, seed)
+    assert est == pytest.approx(hutchpp.logdet_estimate(w.to_scipy(A), 0.5, 8.5, 20, 12, seed), rel=1e-14)
+    rng = np.random.default_rng(seed + 10)
+    for _ in range(2):
+        E = rng.standard_normal(len(A[2]))
+        fd = grad.fd_directional(A, E, 0.5, 8.5, 20, 12, seed, 1e-5)
+        assert g @ E == pytest.approx(fd, rel=1e-7)
+    # a single entry (the sketch-basis term is what makes this match)
+    E = np.zeros(len(A[2]))
+    E[17] = 1.0
+    fd = grad.fd_directional(A, E, 0.5, 8.5, 20, 12, seed, 1e-5)
+    assert g[17] == pytest.approx(fd, rel=1e-6, abs=1e-9)
+
+
+def test_gradient_gmrf_hyperparameters_and_exact_limit():
+    # Q = tau (kappa^2 I + L): d/dtau = <g, val>/tau, d/dkappa = 2 kappa tau sum_diag g.
+    N, k2, tau = 10, 0.5, 1.5
+    A = w.grid_laplacian_2d(N, k2, tau)
+    lmin, lmax = tau * k2 * 0.999, tau * (k2 + 8)
+    est, g = grad.logdet_grad(A, lmin, lmax, 40, 60, 1)
+    row_ptr, col_idx, val, n = A
+    rows = np.repeat(np.arange(n), np.diff(row_ptr))
+    diag = rows == col_idx
+    d_tau = g @ val / tau
+    d_kappa = 2 * math.sqrt(k2) * tau * g[diag].sum()
+
+    def est_at(kk, tt):
+        B = w.grid_laplacian_2d(N, kk, tt)
+        return hutchpp.logdet_estimate(w.to_scipy(B), lmin, lmax, 40, 60, 1)
+
+    h = 1e-5
+    fd_tau = (est_at(k2, tau + h) - est_at(k2, tau - h)) / (2 * h)
+    k = math.sqrt(k2)
+    fd_kappa = (est_at((k + h) ** 2, tau) - est_at((k - h) ** 2, tau)) / (2 * h)
+    assert d_tau == pytest.approx(fd_tau, rel=1e-7)
+    assert d_kappa == pytest.approx(fd_kappa, rel=1e-7)
+    # estimator derivatives approximate the exact ones (n/tau and the closed form)
+    assert d_tau == pytest.approx(n / tau, rel=0.05)
+    assert d_kappa == pytest.approx(tau * 0 + exact.grid_logdet_2d_dkappa(N, k2), rel=0.1)
