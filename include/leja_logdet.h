@@ -1,0 +1,211 @@
+/*
+ * leja_logdet.h -- C ABI of the MI355X (gfx950) Léja + Hutch++ log-determinant
+ * library.
+ *
+ * The method is that of "Novel technique based on Léja Points Approximation for
+ * Log-determinant Estimation of Large matrices" (arXiv 2603.02207):
+ *   - log det Q = tr log Q (Sec. 2, Eqs. Léja1-Léja2);
+ *   - the spectral interval [lmin, lmax] is mapped from [-2, 2] (Sec. 3.1,
+ *     Eqs. z_mapping, eq_centre, eq_gamma) and log is interpolated at real fast
+ *     Léja points (Eq. Léja5) in Newton form (Eq. Léja6);
+ *   - the divided differences come from the scaled Taylor expansion of the
+ *     matrix logarithm of the Léja bidiagonal matrix (Alg. 1);
+ *   - log(Q~)v is applied by the Newton recurrence (Alg. 2);
+ *   - the trace is estimated by Hutch++ (Sec. 4.1, Alg. 3), after the scaling
+ *     Q~ = Q/sigma (Eq. scaled_sigma_matrix).
+ *
+ * Conventions for every entry point:
+ *   - Return value: LD_OK (0) on success, a negative LD_E* code on failure; no
+ *     exception crosses the ABI.  ld_error_string() names the code; the
+ *     thread-local ld_last_error_detail() gives a human-readable reason.
+ *   - Matrix and vector data are DEVICE pointers owned by the caller; the
+ *     library never frees them.  Dense blocks are row-major n x ncols
+ *     (row r holds its ncols entries contiguously), element type = the
+ *     matrix dtype.
+ *   - Work is ordered on the caller's HIP stream (`stream`, a hipStream_t
+ *     passed as void*; NULL = the default stream).  Calls that return host
+ *     scalars synchronise that stream before returning.
+ *   - Scratch memory comes from the caller's workspace (ld_workspace_size);
+ *     with workspace == NULL the library allocates and frees it itself.
+ *   - The matrix must be symmetric positive definite with sorted column
+ *     indices in each row (CSR, int32 indices).  Symmetry is assumed, not
+ *     checked; the CSR structure is checked unless opts->trusted_csr != 0.
+ *   - Results are deterministic for fixed inputs and options (no atomics in
+ *     any reduction).
+ */
+#ifndef LEJA_LOGDET_H
+#define LEJA_LOGDET_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- error codes ---------------------------------------------------------- */
+#define LD_OK 0
+#define LD_EINVAL (-1)      /* bad scalar argument or null pointer            */
+#define LD_ECSR (-2)        /* row_ptr / col_idx not a valid CSR structure     */
+#define LD_EBREAKDOWN (-3)  /* CholQR Gram matrix not positive definite        */
+#define LD_EWORKSPACE (-4)  /* caller's workspace too small                    */
+#define LD_EHIP (-5)        /* a HIP runtime call failed                       */
+#define LD_EINDEF (-6)      /* Gershgorin lower bound <= 0                      */
+#define LD_ENOMEM (-7)      /* internal allocation failed                      */
+
+/* ---- element types -------------------------------------------------------- */
+#define LD_F32 0            /* float values; bulk recurrence in FP32            */
+#define LD_F64 1            /* double values; bulk recurrence in FP64           */
+
+/* ---- scaling value of Alg. 1 (Sec. 3.1) ----------------------------------- */
+#define LD_SVAL_CENTER 0    /* s = (lo+hi)/2, optimal by the Lemma of Sec. 3.1 */
+#define LD_SVAL_HALF_LMAX 1 /* s = hi/2, the paper's other variant             */
+
+/* ---- how the quadratic forms x^T P_m(Q~) x are accumulated ---------------- */
+#define LD_DOT_AUTO 0       /* SQUARED unless its coefficients are ill-conditioned */
+#define LD_DOT_FORWARD 1    /* Alg. 2 forward: m steps, <x, w_j> every step    */
+#define LD_DOT_SQUARED 2    /* ceil(m/2) steps: <w_a,w_a>, <w_a,w_a+1>          */
+
+typedef struct {
+    int64_t n;               /* rows = columns                                 */
+    int64_t nnz;             /* stored entries, < 2^31                         */
+    const int32_t* row_ptr;  /* device, n+1 entries, row_ptr[0] = 0            */
+    const int32_t* col_idx;  /* device, nnz entries in [0, n), sorted per row   */
+    const void* val;         /* device, nnz entries of float or double         */
+    int32_t dtype;           /* LD_F32 or LD_F64                               */
+} ld_csr;
+
+typedef struct {
+    int32_t s_val_mode;      /* LD_SVAL_CENTER (default) or LD_SVAL_HALF_LMAX  */
+    int32_t block_cols;      /* columns per kernel launch; 0 = all at once      */
+    int64_t taylor_cap;      /* max Taylor order of Alg. 1; 0 = 100000000      */
+    int32_t ckpt_stride;     /* gradient checkpoint stride; 0 = ceil(sqrt(m))  */
+    int32_t dot_mode;        /* LD_DOT_AUTO / LD_DOT_FORWARD / LD_DOT_SQUARED  */
+    int32_t trusted_csr;     /* nonzero: skip the device CSR structure check    */
+    int32_t reserved[3];
+} ld_options;
+
+typedef struct {
+    double ms_total;         /* wall time of the call (host clock)             */
+    double ms_phase1;        /* sketch Y = P_m(Q~) S                           */
+    double ms_qr;            /* CholQR2 + deflation                            */
+    double ms_phase23;       /* quadratic forms on [Q_b | U]                   */
+    double ms_adjoint;       /* reverse sweep (gradient only)                  */
+    double bytes_alg;        /* algorithmic HBM bytes of the recurrence kernels */
+    int64_t taylor_terms;    /* Taylor order used by Alg. 1                    */
+    double sigma, lo, hi;    /* scaling and interval of Q~                     */
+    int32_t k, k_G;          /* sketch width and residual probe count          */
+    int32_t dot_mode_used;   /* LD_DOT_FORWARD or LD_DOT_SQUARED                */
+    int32_t spmm_launches;   /* recurrence kernel launches                     */
+    double t_low, t_res;     /* the two traces of Alg. 3 steps 5 and 6         */
+    /* Recurrence kernels only, timed with HIP events on `stream` around the
+     * back-to-back step launches of each phase: */
+    double ms_steps1;        /* phase-1 step launches (sketch)                 */
+    double ms_steps23;       /* phase-2+3 step launches (quadratic forms)      */
+    int32_t launches1, launches23;
+    double bytes1, bytes23;  /* algorithmic bytes of those launches            */
+} ld_stats;
+
+/* Defaults for ld_options (all zero except as documented). */
+void ld_default_options(ld_options* opts);
+
+/* Library version string. */
+const char* ld_version(void);
+
+/* Name of an error code. */
+const char* ld_error_string(int code);
+
+/* Detail of the last error raised on the calling thread ("" if none). */
+const char* ld_last_error_detail(void);
+
+/* ---- host-side pieces of the method (no GPU needed) ----------------------- */
+
+/* First `count` real fast Léja points on [-2, 2] (Sec. 3, Eq. Léja5, computed by
+ * the fast Léja algorithm the paper cites: maximise prod |x - xi_k| over the
+ * midpoints of adjacent points; xi_0 = +2, xi_1 = -2; products equal within a
+ * relative 1e-12 are tied and the larger x wins).  xi_host: host, count doubles.
+ * Errors: LD_EINVAL if count < 0 or xi_host is NULL with count > 0. */
+int ld_leja_points(int32_t count, double* xi_host);
+
+/* Divided differences d_0..d_degree of g(xi) = log(c + gamma*xi) at the Léja
+ * points, c = (lo+hi)/2, gamma = (hi-lo)/4 (Sec. 3.1), by the paper's Alg. 1:
+ * the first column of log(Q_m) for the Léja bidiagonal matrix Q_m = cI +
+ * gamma*Q^_m (Eq. eq_leja_matrix), via log(s) + Taylor series of log(I + W),
+ * W = (Q_m - sI)/s, summed until the largest term falls below 2^-60 of the
+ * largest entry (at most taylor_cap terms, 0 = 1e8).
+ * d_host: host, degree+1 doubles.  terms: host, may be NULL.
+ * Errors: LD_EINVAL unless 0 < lo < hi, degree >= 0, valid s_val_mode. */
+int ld_divided_differences(double lo, double hi, int32_t degree, int32_t s_val_mode,
+                           int64_t taylor_cap, double* d_host, int64_t* terms);
+
+/* Probe entries of the counter-based SplitMix64 generator (Sec. 4.1, Alg. 3
+ * step 2 draws +-1 entries with probability 1/2; the generator is a reading):
+ * entry (row, col) of stream `stream` = sign of output (col*n + row + 1) of
+ * SplitMix64 seeded with key = output (stream+1) of SplitMix64(seed).
+ * Writes rows [row0, row0+nrows) x cols [col0, col0+ncols) as int8 +-1,
+ * row-major, into out_host.  Errors: LD_EINVAL on negative sizes / NULL. */
+int ld_rademacher_host(uint64_t seed, int32_t stream, int64_t n, int64_t row0, int64_t nrows,
+                       int64_t col0, int64_t ncols, int8_t* out_host);
+
+/* Coefficients c_0..c_m of the same polynomial in the basis of products
+ * q_2a = pi_a^2, q_2a+1 = pi_a pi_a+1 (pi_j = Newton basis at the Léja points),
+ * used by LD_DOT_SQUARED so that x^T P(T) x = sum_i c_i nu_i with
+ * nu_2a = <w_a, w_a>, nu_2a+1 = <w_a, w_a+1>, w_a = pi_a(T) x.  Computed by
+ * repeated change of Newton centres in double-double arithmetic.
+ * d_host: in, degree+1; c_host: out, degree+1.  Errors: LD_EINVAL. */
+int ld_squared_basis_coefficients(int32_t degree, const double* d_host, double* c_host);
+
+/* ---- device entry points -------------------------------------------------- */
+
+/* Bytes of workspace needed by ld_logdet_estimate (want_grad = 0) or
+ * ld_logdet_grad (want_grad = 1) for this matrix, degree and query count, or by
+ * ld_apply_log when n_matvec is negative (then -n_matvec = number of columns).
+ * opts may be NULL.  Errors: LD_EINVAL. */
+int ld_workspace_size(const ld_csr* A, int32_t degree, int32_t n_matvec, int32_t want_grad,
+                      const ld_options* opts, size_t* bytes);
+
+/* PV = P_m(Q~) V + log(sigma) V ~= log(Q) V for a block of ncols vectors
+ * (Alg. 2, run in the mapped variable T = (Q~ - cI)/gamma, Horner order;
+ * sigma = lmin if lmin < 1 else 1, Eq. scaled_sigma_matrix).
+ * V, PV: device, n x ncols row-major, dtype of A, must not overlap.
+ * Errors: LD_EINVAL (0 < lmin < lmax, degree >= 1, ncols >= 0), LD_ECSR,
+ * LD_EWORKSPACE, LD_EHIP. */
+int ld_apply_log(const ld_csr* A, double lmin, double lmax, int32_t degree, const void* V,
+                 void* PV, int64_t ncols, const ld_options* opts, void* workspace,
+                 size_t ws_bytes, void* stream);
+
+/* Léja + Hutch++ estimate of log det A (Alg. 3) with n_matvec queries:
+ * k = floor(n_matvec/3) sketch columns (probe stream 0), k_G = n_matvec - 2k
+ * residual probes (stream 1), degree = number of recurrence steps m.
+ * out_logdet: host double.  stats: host, may be NULL.
+ * Errors: LD_EINVAL (0 < lmin < lmax, degree >= 1, n_matvec >= 3, k <= n),
+ * LD_ECSR, LD_EBREAKDOWN, LD_EWORKSPACE, LD_EHIP. */
+int ld_logdet_estimate(const ld_csr* A, double lmin, double lmax, int32_t degree,
+                       int32_t n_matvec, uint64_t seed, const ld_options* opts,
+                       void* workspace, size_t ws_bytes, void* stream, double* out_logdet,
+                       ld_stats* stats);
+
+/* As ld_logdet_estimate, and the exact derivative of the returned estimate
+ * with respect to each stored value of A (same probes, interval and sigma
+ * held fixed; includes the dependence of the sketch basis on A), by a reverse
+ * sweep of the Newton recurrence with checkpoints every opts->ckpt_stride
+ * steps.  grad_val: device, nnz entries of A's dtype, overwritten.
+ * Errors: as ld_logdet_estimate. */
+int ld_logdet_grad(const ld_csr* A, double lmin, double lmax, int32_t degree, int32_t n_matvec,
+                   uint64_t seed, const ld_options* opts, void* workspace, size_t ws_bytes,
+                   void* stream, double* out_logdet, void* grad_val, ld_stats* stats);
+
+/* Gershgorin interval [min_i a_ii - r_i, max_i a_ii + r_i], r_i = sum_{j!=i}
+ * |a_ij| (Sec. 3; Alg. 1/2 step 1), reduced in FP64 on the device; with
+ * lanczos_steps > 0 the upper end is refined by that many Lanczos steps
+ * (App. A) plus the last residual norm, and never raised above Gershgorin's.
+ * lmin, lmax: host doubles.  Returns LD_EINDEF (with both bounds written) when
+ * the lower bound is <= 0.  Errors: LD_EINVAL, LD_ECSR, LD_EHIP. */
+int ld_spectral_bounds(const ld_csr* A, int32_t lanczos_steps, void* stream, double* lmin,
+                       double* lmax);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* LEJA_LOGDET_H */

@@ -1,0 +1,640 @@
+// C-ABI entry points: argument checks, workspace layout and the host-side
+// orchestration of the Léja + Hutch++ estimator (Alg. 3) on one GPU.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "kernels.h"
+#include "ld_internal.h"
+
+namespace ld {
+namespace {
+
+#define LD_CHECK_HIP(expr)                                                               \
+    do {                                                                                 \
+        hipError_t e_ = (expr);                                                          \
+        if (e_ != hipSuccess)                                                            \
+            return fail(LD_EHIP, std::string(#expr) + ": " + hipGetErrorString(e_));     \
+    } while (0)
+
+#define LD_CHECK(expr)            \
+    do {                          \
+        int rc_ = (expr);         \
+        if (rc_ != LD_OK) return rc_; \
+    } while (0)
+
+constexpr size_t kAlign = 256;
+inline size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
+
+// leading dimension of an internal block: a multiple of the 16-byte vector
+inline int padded_ld(int cols, int elem) {
+    const int v = 16 / elem;
+    return (cols + v - 1) / v * v;
+}
+
+ld_options resolve(const ld_options* o) {
+    ld_options r;
+    ld_default_options(&r);
+    if (o) r = *o;
+    return r;
+}
+
+int check_csr_args(const ld_csr* A) {
+    if (!A) return fail(LD_EINVAL, "A is null");
+    if (A->n <= 0) return fail(LD_EINVAL, "n must be positive");
+    if (A->n >= (1ll << 31) || A->nnz < 0 || A->nnz >= (1ll << 31))
+        return fail(LD_EINVAL, "n and nnz must fit int32");
+    if (A->dtype != LD_F32 && A->dtype != LD_F64) return fail(LD_EINVAL, "dtype must be LD_F32 or LD_F64");
+    if (!A->row_ptr || (A->nnz > 0 && (!A->col_idx || !A->val)))
+        return fail(LD_EINVAL, "null CSR array");
+    return LD_OK;
+}
+
+CsrDev dev_of(const ld_csr* A) {
+    return CsrDev{(int)A->n, (int)A->nnz, A->row_ptr, A->col_idx, A->val};
+}
+
+// Bump allocator over the caller's (or our own) workspace.
+struct Arena {
+    char* base = nullptr;
+    size_t size = 0, used = 0;
+    void* take(size_t bytes) {
+        void* p = base ? base + used : nullptr;
+        used += align_up(bytes);
+        return p;
+    }
+};
+
+// Owns an internally allocated workspace when the caller passed none.
+struct OwnedWs {
+    void* p = nullptr;
+    ~OwnedWs() {
+        if (p) (void)hipFree(p);
+    }
+};
+
+int get_workspace(void* ws, size_t ws_bytes, size_t need, OwnedWs& own, Arena& ar) {
+    if (ws) {
+        if (ws_bytes < need)
+            return fail(LD_EWORKSPACE, "workspace has " + std::to_string(ws_bytes) + " bytes, needs " +
+                                           std::to_string(need));
+        ar.base = (char*)ws;
+        ar.size = ws_bytes;
+        return LD_OK;
+    }
+    if (hipMalloc(&own.p, need) != hipSuccess) return fail(LD_ENOMEM, "hipMalloc of workspace failed");
+    ar.base = (char*)own.p;
+    ar.size = need;
+    return LD_OK;
+}
+
+int validate_csr(const ld_csr* A, int* dflag, hipStream_t st) {
+    LD_CHECK_HIP(hipMemsetAsync(dflag, 0, sizeof(int), st));
+    LD_CHECK_HIP(launch_validate_csr(dev_of(A), dflag, st));
+    int h = 0;
+    LD_CHECK_HIP(hipMemcpyAsync(&h, dflag, sizeof(int), hipMemcpyDeviceToHost, st));
+    LD_CHECK_HIP(hipStreamSynchronize(st));
+    if (h) return fail(LD_ECSR, "row_ptr/col_idx is not a CSR structure with sorted in-range columns");
+    return LD_OK;
+}
+
+// ---------------------------------------------------------------------------
+// sizes and layout of the estimator workspace
+// ---------------------------------------------------------------------------
+struct EstLayout {
+    int k, kg, nc, ldk, ldx, nslots, nwg_dot, col_block;
+    size_t elem;
+    size_t mask, Y, X, W0, W1, part, small, nu, flag;
+    // gradient extras
+    size_t L, ckpt, seg, FA, lam0, lam1;
+    int nckpt, stride;
+};
+
+int dot_slots(int degree, int mode) {
+    return mode == LD_DOT_SQUARED ? 2 * ((degree + 1) / 2) + 1 : degree + 1;
+}
+
+EstLayout layout_estimate(const ld_csr* A, int degree, int n_matvec, bool grad,
+                          const ld_options& o) {
+    EstLayout L{};
+    const int n = (int)A->n;
+    L.elem = A->dtype == LD_F64 ? 8 : 4;
+    L.k = n_matvec / 3;
+    L.kg = n_matvec - 2 * L.k;
+    L.nc = L.k + L.kg;
+    L.ldk = padded_ld(L.k, (int)L.elem);
+    L.ldx = padded_ld(grad ? L.nc + L.k : L.nc, (int)L.elem);
+    const int vmax = 16 / (int)L.elem;
+    L.col_block = L.nc;
+    if (o.block_cols > 0 && o.block_cols < L.nc)
+        L.col_block = std::min(L.nc, (o.block_cols + vmax - 1) / vmax * vmax);
+    L.nslots = std::max(dot_slots(degree, LD_DOT_SQUARED), dot_slots(degree, LD_DOT_FORWARD));
+    L.nwg_dot = step_num_wg_bound(n, L.col_block, (int)L.elem);
+    const size_t blk = (size_t)n * L.ldx * L.elem;
+    L.mask = (size_t)n * 8;
+    L.Y = (size_t)n * L.ldx * L.elem;
+    L.X = blk;
+    L.W0 = blk;
+    L.W1 = blk;
+    const size_t cross = (size_t)cross_num_wg(n) * 64 * 64 * 8;
+    const size_t dotp = (size_t)L.nslots * L.nwg_dot * L.nc * 8;
+    L.part = std::max(cross, dotp);
+    L.small = (size_t)6 * 64 * 64 * 8;
+    L.nu = (size_t)L.nslots * L.nc * 8;
+    L.flag = 256;
+    if (grad) {
+        L.stride = o.ckpt_stride > 0 ? o.ckpt_stride : (int)std::ceil(std::sqrt((double)degree));
+        L.stride = std::max(1, std::min(L.stride, degree));
+        L.nckpt = (degree + L.stride - 1) / L.stride;   // w_0, w_s, w_2s, ...
+        const int gcols = L.nc + L.k;                   // [A, sqrt(c)U, S] / [A, sqrt(c)U, 2Z]
+        const size_t gblk = (size_t)n * padded_ld(gcols, (int)L.elem) * L.elem;
+        L.L = gblk;
+        L.ckpt = gblk * L.nckpt;
+        L.seg = gblk * L.stride;
+        L.FA = blk;
+        L.lam0 = gblk;
+        L.lam1 = gblk;
+    }
+    return L;
+}
+
+size_t layout_bytes(const EstLayout& L, bool grad) {
+    size_t b = 0;
+    for (size_t s : {L.mask, L.Y, L.X, L.W0, L.W1, L.part, L.small, L.nu, L.flag}) b += align_up(s);
+    if (grad)
+        for (size_t s : {L.L, L.ckpt, L.seg, L.FA, L.lam0, L.lam1}) b += align_up(s);
+    return b;
+}
+
+struct Timer {
+    hipEvent_t ev[8];
+    int count = 0;
+    hipStream_t st;
+    explicit Timer(hipStream_t s) : st(s) {
+        for (auto& e : ev) e = nullptr;
+    }
+    void mark() {
+        if (count < 8 && hipEventCreate(&ev[count]) == hipSuccess) {
+            (void)hipEventRecord(ev[count], st);
+            ++count;
+        }
+    }
+    double ms(int a, int b) const {
+        float t = 0.f;
+        if (a < count && b < count && hipEventElapsedTime(&t, ev[a], ev[b]) == hipSuccess) return t;
+        return 0.0;
+    }
+    ~Timer() {
+        for (int i = 0; i < count; ++i) (void)hipEventDestroy(ev[i]);
+    }
+};
+
+// bytes the recurrence kernels must move (FP values, int32 indices; the
+// matrix once per launch, blocks as listed per step kind)
+double alg_bytes_step(const ld_csr* A, int cols, int kind, size_t elem) {
+    const double a = (double)A->nnz * (elem + 4) + 4.0 * (A->n + 1);
+    double per = 0;
+    switch (kind) {
+        case STEP_HORNER_SIGNS: per = 2.0 * elem * cols; break;
+        case STEP_HORNER_VEC: per = 3.0 * elem * cols; break;
+        case STEP_DOT_FWD: per = 3.0 * elem * cols; break;
+        case STEP_DOT_SQ: per = 2.0 * elem * cols; break;
+        default: per = 2.0 * elem * cols; break;
+    }
+    double extra = kind == STEP_HORNER_SIGNS ? 8.0 * A->n : 0.0;   // sign mask word per row
+    return a + per * (double)A->n + extra;
+}
+
+// Launch one Newton step over all columns in blocks of col_block.
+int run_step(bool f64, const ld_csr* A, StepArgs s, int ncols, int col_block, hipStream_t st,
+             int* nwg_used) {
+    const CsrDev d = dev_of(A);
+    int nwg = 0;
+    for (int c0 = 0; c0 < ncols; c0 += col_block) {
+        s.c0 = c0;
+        s.bcols = std::min(col_block, ncols - c0);
+        nwg = std::max(nwg, step_num_wg(f64, (int)A->n, s));
+        if ((s.ps0 || s.ps1 || s.ps2) && nwg > step_num_wg_bound((int)A->n, col_block, f64 ? 8 : 4))
+            return fail(LD_EINVAL, "internal: misaligned block for the dot kernels");
+        LD_CHECK_HIP(launch_step(f64, d, s, st));
+    }
+    if (nwg_used) *nwg_used = nwg;
+    return LD_OK;
+}
+
+// Gram / cross product X^T Z reduced to a kx x kz FP64 matrix on the device.
+int cross_product(bool f64, int n, const void* X, int ldx, int kx, const void* Z, int ldz, int kz,
+                  bool zsigns, uint64_t key, double* part, double* out, hipStream_t st) {
+    LD_CHECK_HIP(launch_cross(f64, n, X, ldx, kx, Z, ldz, kz, zsigns, key, part, st));
+    LD_CHECK_HIP(launch_reduce(part, cross_num_wg(n), kx * kz, 1, 0, out, st));
+    return LD_OK;
+}
+
+// One CholQR pass: R from the Gram of Y, then Q = Y R^{-1}.
+int cholqr_pass(bool f64, int n, const void* Y, int ldy, int k, void* Q, int ldq, double* part,
+                double* dG, double* dRinv, double* Rh, hipStream_t st) {
+    LD_CHECK(cross_product(f64, n, Y, ldy, k, Y, ldy, k, false, 0, part, dG, st));
+    std::vector<double> G((size_t)k * k), R((size_t)k * k), Rinv((size_t)k * k);
+    LD_CHECK_HIP(hipMemcpyAsync(G.data(), dG, sizeof(double) * k * k, hipMemcpyDeviceToHost, st));
+    LD_CHECK_HIP(hipStreamSynchronize(st));
+    for (double g : G)
+        if (!std::isfinite(g)) return fail(LD_EBREAKDOWN, "non-finite Gram entry in CholQR");
+    if (!cholesky_upper(G.data(), k, R.data(), Rinv.data()))
+        return fail(LD_EBREAKDOWN, "CholQR Gram matrix is not positive definite (rank-deficient sketch)");
+    if (Rh) std::memcpy(Rh, R.data(), sizeof(double) * k * k);
+    LD_CHECK_HIP(hipMemcpyAsync(dRinv, Rinv.data(), sizeof(double) * k * k, hipMemcpyHostToDevice, st));
+    LD_CHECK_HIP(launch_rowmat(f64, n, Y, ldy, k, dRinv, k, 1.0, false, 0, Q, ldq, st));
+    // the host vectors die at return; make sure the copy has consumed them
+    LD_CHECK_HIP(hipStreamSynchronize(st));
+    return LD_OK;
+}
+
+struct EstimateState {
+    Plan plan;
+    EstLayout L;
+    int mode;                       // LD_DOT_FORWARD / LD_DOT_SQUARED
+    std::vector<double> coef;       // d (forward) or c (squared)
+    void *mask, *Y, *X, *W0, *W1;
+    double *part, *small, *nu;
+    int* flag;
+    double R1[64 * 64], R2[64 * 64];   // CholQR factors (host), Y = Q_b * R2 * R1
+    int spmm_launches = 0;
+    double bytes_alg = 0;
+    int launches1 = 0, launches23 = 0;
+    double bytes1 = 0, bytes23 = 0;
+    hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};   // step-phase brackets
+    ~EstimateState() {
+        for (hipEvent_t e : ev)
+            if (e) (void)hipEventDestroy(e);
+    }
+};
+
+int record(EstimateState& S, int i, hipStream_t st) {
+    if (!S.ev[i]) LD_CHECK_HIP(hipEventCreate(&S.ev[i]));
+    LD_CHECK_HIP(hipEventRecord(S.ev[i], st));
+    return LD_OK;
+}
+
+double elapsed(const EstimateState& S, int a, int b) {
+    float t = 0.f;
+    if (S.ev[a] && S.ev[b] && hipEventElapsedTime(&t, S.ev[a], S.ev[b]) == hipSuccess) return t;
+    return 0.0;
+}
+
+int choose_dot_mode(const Plan& p, int requested, std::vector<double>& coef) {
+    if (requested == LD_DOT_FORWARD) {
+        coef = p.d;
+        return LD_DOT_FORWARD;
+    }
+    std::vector<double> c;
+    squared_basis(p.xi, p.d, c);
+    if (requested == LD_DOT_AUTO) {
+        double sd = 0, sc = 0;
+        for (double x : p.d) sd += std::fabs(x);
+        for (double x : c) sc += std::fabs(x);
+        if (!(sc <= 4.0 * sd)) {
+            coef = p.d;
+            return LD_DOT_FORWARD;
+        }
+    }
+    coef = c;
+    return LD_DOT_SQUARED;
+}
+
+// Phases 1 (sketch), CholQR2 and deflation; leaves X = [Q_b | U].
+int estimate_front(const ld_csr* A, uint64_t seed, const ld_options& o, EstimateState& S,
+                   hipStream_t st, Timer& tm) {
+    const bool f64 = A->dtype == LD_F64;
+    const int n = (int)A->n;
+    const Plan& p = S.plan;
+    const EstLayout& L = S.L;
+    const int m = p.degree;
+    const uint64_t key0 = probe_stream_key(seed, 0), key1 = probe_stream_key(seed, 1);
+
+    // ---- phase 1: Y = P_m(Q~) S in Horner order, S from the sign mask
+    LD_CHECK_HIP(launch_sign_mask(n, L.k, key0, (uint64_t*)S.mask, st));
+    // step j (= m-1 .. 0) writes buffer (j even ? Y : W0); r_m sits in the other one
+    void* bufs[2] = {S.Y, S.W0};
+    LD_CHECK_HIP(launch_fill_signs(f64, n, L.k, L.ldk, (const uint64_t*)S.mask, p.d[m],
+                                   bufs[(m - 1) % 2 == 0 ? 1 : 0], st));
+    const int kblock = std::min(L.col_block, L.k);
+    LD_CHECK(record(S, 0, st));
+    for (int j = m - 1; j >= 0; --j) {
+        StepArgs s{};
+        s.kind = STEP_HORNER_SIGNS;
+        s.win = bufs[j % 2 == 0 ? 1 : 0];
+        s.wout = bufs[j % 2 == 0 ? 0 : 1];
+        s.ld = L.ldk;
+        s.alpha = p.alpha;
+        s.beta = p.beta[j];
+        s.dj = p.d[j];
+        s.mask = (const uint64_t*)S.mask;
+        LD_CHECK(run_step(f64, A, s, L.k, kblock, st, nullptr));
+        S.launches1 += (L.k + kblock - 1) / kblock;
+        S.bytes1 += alg_bytes_step(A, L.k, STEP_HORNER_SIGNS, L.elem);
+    }
+    LD_CHECK(record(S, 1, st));
+    S.spmm_launches += S.launches1;
+    S.bytes_alg += S.bytes1;
+    tm.mark();
+
+    // ---- CholQR2: Q1 = Y R1^{-1} (into W0), Q_b = Q1 R2^{-1} (into X[:, :k])
+    double* dG = S.small;
+    double* dRinv = S.small + 64 * 64;
+    double* dC = S.small + 2 * 64 * 64;
+    LD_CHECK(cholqr_pass(f64, n, S.Y, L.ldk, L.k, S.W0, L.ldk, S.part, dG, dRinv, S.R1, st));
+    LD_CHECK(cholqr_pass(f64, n, S.W0, L.ldk, L.k, S.X, L.ldx, S.part, dG, dRinv, S.R2, st));
+    // ---- deflation: C = Q_b^T G, U = G - Q_b C (G = probe stream 1) into X[:, k:]
+    LD_CHECK(cross_product(f64, n, S.X, L.ldx, L.k, nullptr, 0, L.kg, true, key1, S.part, dC, st));
+    LD_CHECK_HIP(launch_rowmat(f64, n, S.X, L.ldx, L.k, dC, L.kg, -1.0, true, key1,
+                               (char*)S.X + (size_t)L.k * L.elem, L.ldx, st));
+    tm.mark();
+    return LD_OK;
+}
+
+// Quadratic forms x^T P_m(Q~) x for every column of X; nu_host[slot][col].
+int estimate_dots(const ld_csr* A, EstimateState& S, hipStream_t st, std::vector<double>& nu_host) {
+    const bool f64 = A->dtype == LD_F64;
+    const int n = (int)A->n;
+    const Plan& p = S.plan;
+    const EstLayout& L = S.L;
+    const int m = p.degree;
+    const size_t slot_stride = (size_t)L.nwg_dot * L.nc;
+    int nwg = 0, nslots = 0;
+    if (L.col_block < L.nc)   // blocks of different widths leave some partial rows unwritten
+        LD_CHECK_HIP(hipMemsetAsync(S.part, 0, sizeof(double) * L.nslots * slot_stride, st));
+    LD_CHECK(record(S, 2, st));
+    if (S.mode == LD_DOT_SQUARED) {
+        const int h = (m + 1) / 2;
+        nslots = 2 * h + 1;
+        void* cur = S.X;
+        void* nxt = S.W0;
+        for (int a = 0; a < h; ++a) {
+            StepArgs s{};
+            s.kind = STEP_DOT_SQ;
+            s.first = a == 0;
+            s.win = cur;
+            s.wout = nxt;
+            s.ld = L.ldx;
+            s.alpha = p.alpha;
+            s.beta = p.beta[a];
+            s.ps0 = S.part;
+            s.ps1 = S.part + (size_t)(2 * a + 1) * slot_stride;
+            s.ps2 = S.part + (size_t)(2 * a + 2) * slot_stride;
+            s.part_ld = L.nc;
+            LD_CHECK(run_step(f64, A, s, L.nc, L.col_block, st, &nwg));
+            S.launches23 += (L.nc + L.col_block - 1) / L.col_block;
+            S.bytes23 += alg_bytes_step(A, L.nc, STEP_DOT_SQ, L.elem);
+            std::swap(cur, nxt);
+        }
+    } else {
+        nslots = m + 1;
+        const void* cur = S.X;
+        void* pp[2] = {S.W0, S.W1};
+        for (int j = 0; j < m; ++j) {
+            StepArgs s{};
+            s.kind = STEP_DOT_FWD;
+            s.first = j == 0;
+            s.win = cur;
+            s.wout = pp[j % 2];
+            s.ld = L.ldx;
+            s.alpha = p.alpha;
+            s.beta = p.beta[j];
+            s.vsrc = S.X;
+            s.ldv = L.ldx;
+            s.ps0 = S.part;
+            s.ps1 = S.part + (size_t)(j + 1) * slot_stride;
+            s.part_ld = L.nc;
+            LD_CHECK(run_step(f64, A, s, L.nc, L.col_block, st, &nwg));
+            S.launches23 += (L.nc + L.col_block - 1) / L.col_block;
+            S.bytes23 += alg_bytes_step(A, L.nc, STEP_DOT_FWD, L.elem);
+            cur = pp[j % 2];
+        }
+    }
+    LD_CHECK(record(S, 3, st));
+    S.spmm_launches += S.launches23;
+    S.bytes_alg += S.bytes23;
+    (void)n;
+    LD_CHECK_HIP(launch_reduce(S.part, nwg, L.nc, nslots, (long long)slot_stride, S.nu, st));
+    nu_host.assign((size_t)nslots * L.nc, 0.0);
+    LD_CHECK_HIP(hipMemcpyAsync(nu_host.data(), S.nu, sizeof(double) * nu_host.size(),
+                                hipMemcpyDeviceToHost, st));
+    LD_CHECK_HIP(hipStreamSynchronize(st));
+    return LD_OK;
+}
+
+int carve(Arena& ar, const EstLayout& L, EstimateState& S) {
+    S.mask = ar.take(L.mask);
+    S.Y = ar.take(L.Y);
+    S.X = ar.take(L.X);
+    S.W0 = ar.take(L.W0);
+    S.W1 = ar.take(L.W1);
+    S.part = (double*)ar.take(L.part);
+    S.small = (double*)ar.take(L.small);
+    S.nu = (double*)ar.take(L.nu);
+    S.flag = (int*)ar.take(L.flag);
+    return LD_OK;
+}
+
+int check_estimate_args(const ld_csr* A, double lmin, double lmax, int degree, int n_matvec) {
+    LD_CHECK(check_csr_args(A));
+    if (!(lmin > 0.0) || !(lmax > lmin) || !std::isfinite(lmax))
+        return fail(LD_EINVAL, "need 0 < lmin < lmax");
+    if (degree < 1) return fail(LD_EINVAL, "degree must be >= 1");
+    if (n_matvec < 3) return fail(LD_EINVAL, "n_matvec must be >= 3");
+    const int k = n_matvec / 3, kg = n_matvec - 2 * k;
+    if (k > 64 || kg > 64) return fail(LD_EINVAL, "n_matvec must be <= 192 (k, k_G <= 64)");
+    if (k > A->n) return fail(LD_EINVAL, "sketch width k = n_matvec/3 exceeds n");
+    return LD_OK;
+}
+
+}  // namespace
+}  // namespace ld
+
+using namespace ld;
+
+extern "C" {
+
+int ld_workspace_size(const ld_csr* A, int32_t degree, int32_t n_matvec, int32_t want_grad,
+                      const ld_options* opts, size_t* bytes) {
+    clear_error();
+    if (!bytes) return fail(LD_EINVAL, "bytes is null");
+    LD_CHECK(check_csr_args(A));
+    if (degree < 1) return fail(LD_EINVAL, "degree must be >= 1");
+    const ld_options o = resolve(opts);
+    if (n_matvec < 0) {
+        const size_t elem = A->dtype == LD_F64 ? 8 : 4;
+        *bytes = 2 * align_up((size_t)A->n * (size_t)(-(int64_t)n_matvec) * elem) + align_up(256);
+        return LD_OK;
+    }
+    if (n_matvec < 3) return fail(LD_EINVAL, "n_matvec must be >= 3");
+    const EstLayout L = layout_estimate(A, degree, n_matvec, want_grad != 0, o);
+    *bytes = layout_bytes(L, want_grad != 0);
+    return LD_OK;
+}
+
+int ld_apply_log(const ld_csr* A, double lmin, double lmax, int32_t degree, const void* V, void* PV,
+                 int64_t ncols, const ld_options* opts, void* workspace, size_t ws_bytes,
+                 void* stream) {
+    clear_error();
+    LD_CHECK(check_csr_args(A));
+    if (ncols < 0 || ncols > (1 << 20)) return fail(LD_EINVAL, "bad ncols");
+    if (ncols > 0 && (!V || !PV)) return fail(LD_EINVAL, "V or PV is null");
+    const ld_options o = resolve(opts);
+    Plan p;
+    LD_CHECK(make_plan(lmin, lmax, degree, o, p));
+    if (ncols == 0) return LD_OK;
+    hipStream_t st = (hipStream_t)stream;
+    const bool f64 = A->dtype == LD_F64;
+    const size_t elem = f64 ? 8 : 4;
+    const int n = (int)A->n, nc = (int)ncols;
+    const size_t blk = (size_t)n * nc * elem;
+    const uint8_t* v8 = (const uint8_t*)V;
+    const uint8_t* p8 = (const uint8_t*)PV;
+    if (v8 < p8 + blk && p8 < v8 + blk) return fail(LD_EINVAL, "V and PV overlap");
+    const size_t need = 2 * align_up(blk) + align_up(256);
+    OwnedWs own;
+    Arena ar;
+    LD_CHECK(get_workspace(workspace, ws_bytes, need, own, ar));
+    void* B0 = ar.take(blk);
+    void* B1 = ar.take(blk);
+    int* flag = (int*)ar.take(256);
+    if (!o.trusted_csr) LD_CHECK(validate_csr(A, flag, st));
+    const int m = p.degree;
+    const int cb = (o.block_cols > 0 && o.block_cols < std::min(nc, 64)) ? o.block_cols : std::min(nc, 64);
+    // Horner: r_m = d_m V; r_j = (T - xi_j) r_{j+1} + d_j V, with d_0 carrying
+    // log(sigma); r_m starts in B0, the steps ping-pong B0/B1, step 0 writes PV.
+    LD_CHECK_HIP(launch_scale_copy(f64, n, nc, V, nc, p.d[m], B0, nc, st));
+    const void* cur = B0;
+    for (int j = m - 1; j >= 0; --j) {
+        void* out = j == 0 ? PV : (cur == B0 ? B1 : B0);
+        StepArgs s{};
+        s.kind = STEP_HORNER_VEC;
+        s.win = cur;
+        s.wout = out;
+        s.ld = nc;
+        s.alpha = p.alpha;
+        s.beta = p.beta[j];
+        s.dj = j == 0 ? p.d[0] + std::log(p.sigma) : p.d[j];
+        s.vsrc = V;
+        s.ldv = nc;
+        LD_CHECK(run_step(f64, A, s, nc, cb, st, nullptr));
+        cur = out;
+    }
+    if (!workspace) LD_CHECK_HIP(hipStreamSynchronize(st));
+    return LD_OK;
+}
+
+int ld_logdet_estimate(const ld_csr* A, double lmin, double lmax, int32_t degree,
+                       int32_t n_matvec, uint64_t seed, const ld_options* opts, void* workspace,
+                       size_t ws_bytes, void* stream, double* out_logdet, ld_stats* stats) {
+    clear_error();
+    const auto t0 = std::chrono::steady_clock::now();
+    if (!out_logdet) return fail(LD_EINVAL, "out_logdet is null");
+    LD_CHECK(check_estimate_args(A, lmin, lmax, degree, n_matvec));
+    const ld_options o = resolve(opts);
+    hipStream_t st = (hipStream_t)stream;
+    EstimateState S;
+    LD_CHECK(make_plan(lmin, lmax, degree, o, S.plan));
+    S.L = layout_estimate(A, degree, n_matvec, false, o);
+    S.mode = choose_dot_mode(S.plan, o.dot_mode, S.coef);
+    OwnedWs own;
+    Arena ar;
+    LD_CHECK(get_workspace(workspace, ws_bytes, layout_bytes(S.L, false), own, ar));
+    carve(ar, S.L, S);
+    if (!o.trusted_csr) LD_CHECK(validate_csr(A, S.flag, st));
+    Timer tm(st);
+    tm.mark();
+    LD_CHECK(estimate_front(A, seed, o, S, st, tm));
+    std::vector<double> nu;
+    LD_CHECK(estimate_dots(A, S, st, nu));
+    tm.mark();
+    // ---- combine (Alg. 3 step 7): n log(sigma) + t_low + t_res
+    const EstLayout& L = S.L;
+    const int ncoef = S.plan.degree + 1;
+    KahanSum tl, tr;
+    for (int col = 0; col < L.nc; ++col)
+        for (int i = 0; i < ncoef; ++i) {
+            const double v = S.coef[i] * nu[(size_t)i * L.nc + col];
+            if (col < L.k)
+                tl.add(v);
+            else
+                tr.add(v);
+        }
+    const double t_low = tl.value(), t_res = tr.value() / L.kg;
+    KahanSum tot;
+    tot.add((double)A->n * std::log(S.plan.sigma));
+    tot.add(t_low);
+    tot.add(t_res);
+    *out_logdet = tot.value();
+    if (stats) {
+        std::memset(stats, 0, sizeof(*stats));
+        stats->ms_phase1 = tm.ms(0, 1);
+        stats->ms_qr = tm.ms(1, 2);
+        stats->ms_phase23 = tm.ms(2, 3);
+        stats->bytes_alg = S.bytes_alg;
+        stats->taylor_terms = S.plan.taylor_terms;
+        stats->sigma = S.plan.sigma;
+        stats->lo = S.plan.lo;
+        stats->hi = S.plan.hi;
+        stats->k = L.k;
+        stats->k_G = L.kg;
+        stats->dot_mode_used = S.mode;
+        stats->spmm_launches = S.spmm_launches;
+        stats->t_low = t_low;
+        stats->t_res = t_res;
+        stats->ms_steps1 = elapsed(S, 0, 1);
+        stats->ms_steps23 = elapsed(S, 2, 3);
+        stats->launches1 = S.launches1;
+        stats->launches23 = S.launches23;
+        stats->bytes1 = S.bytes1;
+        stats->bytes23 = S.bytes23;
+        stats->ms_total =
+            std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+    }
+    return LD_OK;
+}
+
+int ld_spectral_bounds(const ld_csr* A, int32_t lanczos_steps, void* stream, double* lmin,
+                       double* lmax) {
+    clear_error();
+    LD_CHECK(check_csr_args(A));
+    if (!lmin || !lmax || lanczos_steps < 0) return fail(LD_EINVAL, "bad arguments");
+    if (lanczos_steps > 0) return fail(LD_EINVAL, "Lanczos refinement is not available");
+    hipStream_t st = (hipStream_t)stream;
+    const int nwg = gersh_num_wg((int)A->n);
+    OwnedWs own;
+    if (hipMalloc(&own.p, (size_t)2 * nwg * sizeof(double) + 256) != hipSuccess)
+        return fail(LD_ENOMEM, "hipMalloc failed");
+    int* flag = (int*)((char*)own.p + (size_t)2 * nwg * sizeof(double));
+    LD_CHECK(validate_csr(A, flag, st));
+    LD_CHECK_HIP(launch_gershgorin(A->dtype == LD_F64, dev_of(A), (double*)own.p, st));
+    std::vector<double> h((size_t)2 * nwg);
+    LD_CHECK_HIP(hipMemcpyAsync(h.data(), own.p, sizeof(double) * h.size(), hipMemcpyDeviceToHost, st));
+    LD_CHECK_HIP(hipStreamSynchronize(st));
+    double lo = INFINITY, hi = -INFINITY;
+    for (int i = 0; i < nwg; ++i) {
+        lo = std::fmin(lo, h[2 * i]);
+        hi = std::fmax(hi, h[2 * i + 1]);
+    }
+    *lmin = lo;
+    *lmax = hi;
+    if (!(lo > 0.0)) return fail(LD_EINDEF, "Gershgorin lower bound is not positive");
+    return LD_OK;
+}
+
+int ld_logdet_grad(const ld_csr* A, double lmin, double lmax, int32_t degree, int32_t n_matvec,
+                   uint64_t seed, const ld_options* opts, void* workspace, size_t ws_bytes,
+                   void* stream, double* out_logdet, void* grad_val, ld_stats* stats) {
+    clear_error();
+    (void)A; (void)lmin; (void)lmax; (void)degree; (void)n_matvec; (void)seed; (void)opts;
+    (void)workspace; (void)ws_bytes; (void)stream; (void)out_logdet; (void)grad_val; (void)stats;
+    return fail(LD_EINVAL, "gradient entry point not built yet");
+}
+
+}  // extern "C"

@@ -1,0 +1,108 @@
+// Launchers of the gfx950 kernels (kernels.hip).  All launches are
+// asynchronous on `stream`; shapes are checked by the caller (api.hip).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+namespace ld {
+
+// Kinds of Newton step (one SpMM pass over a block of columns).
+enum StepKind : int {
+    STEP_HORNER_SIGNS = 0,  // out = alpha*A*in - beta*in + dj*S   (S from the sign mask)
+    STEP_HORNER_VEC = 1,    // out = alpha*A*in - beta*in + dj*V   (V in memory)
+    STEP_DOT_FWD = 2,       // out = alpha*A*in - beta*in; <X,out> (and <X,in> if first)
+    STEP_DOT_SQ = 3,        // out = alpha*A*in - beta*in; <in,out>, <out,out> (and <in,in>)
+    STEP_PLAIN = 4,         // out = alpha*A*in - beta*in
+};
+
+struct CsrDev {
+    int n;
+    int nnz;
+    const int* row_ptr;
+    const int* col_idx;
+    const void* val;
+};
+
+// Geometry of a Newton step launch over columns [c0, c0+bcols) of row-major
+// blocks with leading dimension ld (elements).
+struct StepArgs {
+    int kind;
+    bool first;
+    const void* win;
+    void* wout;
+    int ld, c0, bcols;
+    double alpha, beta, dj;
+    const void* vsrc;          // HORNER_VEC: V;  DOT_FWD: X
+    int ldv;
+    const uint64_t* mask;      // HORNER_SIGNS: one word of sign bits per row
+    double* ps0;               // partial sums [nwg][part_ld], may be null
+    double* ps1;
+    double* ps2;
+    int part_ld;
+};
+
+// Workgroups of a step launch (the dot kinds write one partial row per
+// workgroup); the bound holds for 16-byte aligned blocks of at most bcols.
+int step_num_wg(bool f64, int n, const StepArgs& s);
+int step_num_wg_bound(int n, int bcols, int elem_bytes);
+
+hipError_t launch_step(bool f64, const CsrDev& A, const StepArgs& s, hipStream_t st);
+
+// Sign mask of stream `key`: bit c of word r = (probe(r, c) == -1), c < k <= 64.
+hipError_t launch_sign_mask(int n, int k, uint64_t key, uint64_t* mask, hipStream_t st);
+
+// out[r, c] = scale * S[r, c] for c < k, 0 for k <= c < ld.
+hipError_t launch_fill_signs(bool f64, int n, int k, int ld, const uint64_t* mask, double scale,
+                             void* out, hipStream_t st);
+
+// out[r, c] = scale * V[r, c] (row-major, V with ldv, out with ldo), c < ncols.
+hipError_t launch_scale_copy(bool f64, int n, int ncols, const void* V, int ldv, double scale,
+                             void* out, int ldo, hipStream_t st);
+
+// Partial cross products X^T Z per workgroup on FP64 MFMA: part[wg][i*kz+j].
+// Z is either a second block (zsigns_key ignored) or, with zsigns, the probe
+// signs of stream key for columns [0, kz).
+int cross_num_wg(int n);
+hipError_t launch_cross(bool f64, int n, const void* X, int ldx, int kx, const void* Z, int ldz,
+                        int kz, bool zsigns, uint64_t key, double* part, hipStream_t st);
+
+// out[outer][j] = sum_wg part[outer*outer_stride + wg*len + j] (Neumaier, fixed order).
+hipError_t launch_reduce(const double* part, int nwg, int len, int outer, long long outer_stride,
+                         double* out, hipStream_t st);
+
+// out[r, j] = (signs ? S_key[r, j] : 0) + sign_m * sum_i Y[r, i] M[i, j],
+// M k_y x k_out FP64 (device), j < k_out.
+hipError_t launch_rowmat(bool f64, int n, const void* Y, int ldy, int ky, const double* M, int kout,
+                         double sign_m, bool signs, uint64_t key, void* out, int ldo,
+                         hipStream_t st);
+
+// CSR structure check: *flag (device int) set to 1 on any violation.
+hipError_t launch_validate_csr(const CsrDev& A, int* flag, hipStream_t st);
+
+// Gershgorin: per-workgroup (min(a_ii - r_i), max(a_ii + r_i)) into part[2*wg].
+int gersh_num_wg(int n);
+hipError_t launch_gershgorin(bool f64, const CsrDev& A, double* part, hipStream_t st);
+
+// Adjoint step of the reverse sweep:
+//   lam_out = alpha*A*lam_in - beta*lam_in + dj*L
+//   grad[nz(r,c)] += alpha * sum_cols lam_in[r,:] * w[c,:]
+struct AdjArgs {
+    const void* lam_in;
+    void* lam_out;
+    const void* w;
+    const void* L;
+    void* grad;
+    int ld, ncols;
+    double alpha, beta, dj;
+    bool first;      // grad is overwritten instead of accumulated
+    bool last;       // no lam_out needed (only the SDDMM)
+};
+hipError_t launch_adjoint(bool f64, const CsrDev& A, const AdjArgs& a, hipStream_t st);
+
+// y = a*x + b*y elementwise on contiguous arrays of length len.
+hipError_t launch_axpby(bool f64, long long len, double a, const void* x, double b, void* y,
+                        hipStream_t st);
+
+}  // namespace ld

@@ -1,0 +1,743 @@
+// gfx950 kernels of the Léja + Hutch++ hot path.
+//
+// Data layout: dense blocks are row-major n x ld (a row's columns are
+// contiguous), so one sparse row's gather W[col_idx[k], c0:c0+b] is a single
+// contiguous run of b elements.  A wave64 is split into row groups of
+// lpr = ceil(b/VEC) lanes; each lane owns VEC adjacent columns (16-byte
+// vectors), so a row group reads a gathered row with one coalesced access.
+//
+// Work distribution is XCD-aware: workgroups are issued round-robin over the
+// 8 XCDs, so the logical row tile of a workgroup is remapped such that each
+// XCD walks one contiguous band of rows.  Stencil neighbours (rows r +- N)
+// are then mostly found in that XCD's own L2.
+//
+// Reductions never use atomics: each workgroup writes FP64 partial sums and a
+// separate kernel adds them in a fixed order (Neumaier), so every result is
+// deterministic.
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "kernels.h"
+
+namespace ld {
+
+namespace {
+
+constexpr int kThreads = 256;
+constexpr int kWaves = kThreads / 64;
+constexpr int kXcds = 8;
+
+template <typename T, int V>
+struct alignas(sizeof(T) * V) Pack {
+    T v[V];
+};
+
+template <typename T, int V>
+__device__ __forceinline__ Pack<T, V> load_pack(const T* p) {
+    return *reinterpret_cast<const Pack<T, V>*>(p);
+}
+template <typename T, int V>
+__device__ __forceinline__ void store_pack(T* p, const Pack<T, V>& x) {
+    *reinterpret_cast<Pack<T, V>*>(p) = x;
+}
+
+// Logical tile of this workgroup: XCD x (= blockIdx % 8) gets the contiguous
+// tile range [x*(nwg/8) + min(x, nwg%8), ...).
+__device__ __forceinline__ int xcd_tile(int bid, int nwg) {
+    const int x = bid % kXcds;
+    const int i = bid / kXcds;
+    const int base = nwg / kXcds, rem = nwg % kXcds;
+    return x * base + (x < rem ? x : rem) + i;
+}
+
+// SplitMix64 output number i of the generator seeded with key.
+__device__ __forceinline__ uint64_t probe_bits(uint64_t key, uint64_t i) {
+    uint64_t z = key + i * 0x9E3779B97F4A7C15ull;
+    z ^= z >> 30;
+    z *= 0xBF58476D1CE4E5B9ull;
+    z ^= z >> 27;
+    z *= 0x94D049BB133111EBull;
+    z ^= z >> 31;
+    return z;
+}
+
+int div_up(long long a, long long b) { return (int)((a + b - 1) / b); }
+
+// rows of one row group iteration
+inline int lanes_per_row(int bcols, int vec) { return (bcols + vec - 1) / vec; }
+
+inline int step_iters(int kind) { return (kind == STEP_DOT_FWD || kind == STEP_DOT_SQ) ? 4 : 1; }
+
+// ---------------------------------------------------------------------------
+// Newton step: out = alpha*A*in - beta*in (+ dj*source), optional dot partials.
+// ---------------------------------------------------------------------------
+template <typename T, int VEC, int KIND, bool FIRST>
+__global__ __launch_bounds__(kThreads) void step_kernel(
+    int n, const int* __restrict__ row_ptr, const int* __restrict__ col_idx,
+    const T* __restrict__ val, const T* __restrict__ win, T* __restrict__ wout, int ld, int c0,
+    int bcols, T alpha, T beta, T dj, const T* __restrict__ vsrc, int ldv,
+    const uint64_t* __restrict__ mask, double* __restrict__ ps0, double* __restrict__ ps1,
+    double* __restrict__ ps2, int part_ld, int lpr, int rpw, int iters) {
+    constexpr bool kDot = (KIND == STEP_DOT_FWD || KIND == STEP_DOT_SQ);
+    const int lane = threadIdx.x & 63;
+    const int wave = threadIdx.x >> 6;
+    const int g = lane / lpr;
+    const int li = lane - g * lpr;
+    const bool lane_ok = g < rpw;
+    const int col = c0 + li * VEC;
+    const int tile = xcd_tile(blockIdx.x, gridDim.x);
+    const int rows_per_wg = kWaves * rpw * iters;
+
+    double s0[VEC], s1[VEC], s2[VEC];
+#pragma unroll
+    for (int e = 0; e < VEC; ++e) s0[e] = s1[e] = s2[e] = 0.0;
+    bool valid[VEC];
+#pragma unroll
+    for (int e = 0; e < VEC; ++e) valid[e] = lane_ok && (col + e < c0 + bcols);
+
+    for (int it = 0; it < iters; ++it) {
+        const int row = tile * rows_per_wg + (it * kWaves + wave) * rpw + g;
+        if (!lane_ok || row >= n) continue;
+        const int beg = row_ptr[row], end = row_ptr[row + 1];
+        T acc[VEC];
+#pragma unroll
+        for (int e = 0; e < VEC; ++e) acc[e] = T(0);
+        for (int base = beg; base < end; base += 8) {
+            int cidx[8];
+            T a[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+                const int k = base + u;
+                cidx[u] = row;
+                a[u] = T(0);
+                if (k < end) {
+                    cidx[u] = col_idx[k];
+                    a[u] = val[k];
+                }
+            }
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+                if (base + u < end) {
+                    const Pack<T, VEC> x = load_pack<T, VEC>(win + (size_t)cidx[u] * ld + col);
+#pragma unroll
+                    for (int e = 0; e < VEC; ++e) acc[e] = fma(a[u], x.v[e], acc[e]);
+                }
+            }
+        }
+        const Pack<T, VEC> w = load_pack<T, VEC>(win + (size_t)row * ld + col);
+        Pack<T, VEC> o;
+#pragma unroll
+        for (int e = 0; e < VEC; ++e) o.v[e] = alpha * acc[e] - beta * w.v[e];
+        if constexpr (KIND == STEP_HORNER_SIGNS) {
+            const uint64_t bits = mask[row];
+#pragma unroll
+            for (int e = 0; e < VEC; ++e) {
+                const T sgn = ((bits >> ((col + e) & 63)) & 1ull) ? T(-1) : T(1);
+                o.v[e] = fma(dj, sgn, o.v[e]);
+            }
+        } else if constexpr (KIND == STEP_HORNER_VEC) {
+            const Pack<T, VEC> v = load_pack<T, VEC>(vsrc + (size_t)row * ldv + col);
+#pragma unroll
+            for (int e = 0; e < VEC; ++e) o.v[e] = fma(dj, v.v[e], o.v[e]);
+        } else if constexpr (KIND == STEP_DOT_FWD) {
+            const Pack<T, VEC> x = load_pack<T, VEC>(vsrc + (size_t)row * ldv + col);
+#pragma unroll
+            for (int e = 0; e < VEC; ++e) {
+                if (FIRST) s0[e] += (double)x.v[e] * (double)w.v[e];
+                s1[e] += (double)x.v[e] * (double)o.v[e];
+            }
+        } else if constexpr (KIND == STEP_DOT_SQ) {
+#pragma unroll
+            for (int e = 0; e < VEC; ++e) {
+                if (FIRST) s0[e] += (double)w.v[e] * (double)w.v[e];
+                s1[e] += (double)w.v[e] * (double)o.v[e];
+                s2[e] += (double)o.v[e] * (double)o.v[e];
+            }
+        }
+        {
+            // columns outside [c0, c0+bcols) are left untouched
+            bool all = true;
+#pragma unroll
+            for (int e = 0; e < VEC; ++e) all = all && valid[e];
+            if (all) {
+                store_pack<T, VEC>(wout + (size_t)row * ld + col, o);
+            } else {
+#pragma unroll
+                for (int e = 0; e < VEC; ++e)
+                    if (valid[e]) wout[(size_t)row * ld + col + e] = o.v[e];
+            }
+        }
+    }
+
+    if constexpr (kDot) {
+        __shared__ double red[kThreads * VEC];
+        double* const outs[3] = {ps0, ps1, ps2};
+        const double* const sums[3] = {s0, s1, s2};
+#pragma unroll
+        for (int q = 0; q < 3; ++q) {
+            if (q == 0 && !FIRST) continue;
+            if (q == 2 && KIND != STEP_DOT_SQ) continue;
+#pragma unroll
+            for (int e = 0; e < VEC; ++e) red[threadIdx.x * VEC + e] = sums[q][e];
+            __syncthreads();
+            for (int t = threadIdx.x; t < bcols; t += kThreads) {
+                const int tl = t / VEC, te = t - tl * VEC;
+                double acc = 0.0;
+                for (int wv = 0; wv < kWaves; ++wv)
+                    for (int gg = 0; gg < rpw; ++gg)
+                        acc += red[(wv * 64 + gg * lpr + tl) * VEC + te];
+                outs[q][(size_t)blockIdx.x * part_ld + c0 + t] = acc;
+            }
+            __syncthreads();
+        }
+    }
+}
+
+template <typename T, int VEC, int KIND, bool FIRST>
+hipError_t launch_step_t(const CsrDev& A, const StepArgs& s, hipStream_t st) {
+    const int lpr = lanes_per_row(s.bcols, VEC);
+    const int rpw = 64 / lpr;
+    const int iters = step_iters(KIND);
+    const int rows_per_wg = kWaves * rpw * iters;
+    const int nwg = div_up(A.n, rows_per_wg);
+    if (nwg == 0) return hipSuccess;
+    hipLaunchKernelGGL((step_kernel<T, VEC, KIND, FIRST>), dim3(nwg), dim3(kThreads), 0, st, A.n,
+                       A.row_ptr, A.col_idx, (const T*)A.val, (const T*)s.win, (T*)s.wout, s.ld,
+                       s.c0, s.bcols, (T)s.alpha, (T)s.beta, (T)s.dj, (const T*)s.vsrc, s.ldv,
+                       s.mask, s.ps0, s.ps1, s.ps2, s.part_ld, lpr, rpw, iters);
+    return hipGetLastError();
+}
+
+template <typename T, int VEC>
+hipError_t launch_step_v(const CsrDev& A, const StepArgs& s, hipStream_t st) {
+    switch (s.kind) {
+        case STEP_HORNER_SIGNS: return launch_step_t<T, VEC, STEP_HORNER_SIGNS, false>(A, s, st);
+        case STEP_HORNER_VEC: return launch_step_t<T, VEC, STEP_HORNER_VEC, false>(A, s, st);
+        case STEP_PLAIN: return launch_step_t<T, VEC, STEP_PLAIN, false>(A, s, st);
+        case STEP_DOT_FWD:
+            return s.first ? launch_step_t<T, VEC, STEP_DOT_FWD, true>(A, s, st)
+                           : launch_step_t<T, VEC, STEP_DOT_FWD, false>(A, s, st);
+        case STEP_DOT_SQ:
+            return s.first ? launch_step_t<T, VEC, STEP_DOT_SQ, true>(A, s, st)
+                           : launch_step_t<T, VEC, STEP_DOT_SQ, false>(A, s, st);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+// widest vector (16 bytes max) compatible with the leading dimensions,
+// column offset and pointer alignment
+inline int pick_vec(const StepArgs& s, int elem_bytes) {
+    int vec = 16 / elem_bytes;
+    auto ok = [&](int v) {
+        const uintptr_t align = (uintptr_t)v * elem_bytes;
+        if (s.ld % v || s.c0 % v) return false;
+        if ((uintptr_t)s.win % align || (uintptr_t)s.wout % align) return false;
+        if (s.vsrc && (s.ldv % v || (uintptr_t)s.vsrc % align)) return false;
+        return true;
+    };
+    while (vec > 1 && !ok(vec)) vec /= 2;
+    return vec;
+}
+
+}  // namespace
+
+int step_num_wg_bound(int n, int bcols, int elem_bytes) {
+    // blocks aligned to the 16-byte vector (the estimator's internal layout)
+    const int rows = kWaves * (64 / lanes_per_row(bcols, 16 / elem_bytes)) * 4;
+    return div_up(n, rows);
+}
+
+int step_num_wg(bool f64, int n, const StepArgs& s) {
+    const int vec = pick_vec(s, f64 ? 8 : 4);
+    const int rows = kWaves * (64 / lanes_per_row(s.bcols, vec)) * step_iters(s.kind);
+    return div_up(n, rows);
+}
+
+hipError_t launch_step(bool f64, const CsrDev& A, const StepArgs& s, hipStream_t st) {
+    if (f64) {
+        const int vec = pick_vec(s, 8);
+        return vec == 2 ? launch_step_v<double, 2>(A, s, st) : launch_step_v<double, 1>(A, s, st);
+    }
+    const int vec = pick_vec(s, 4);
+    if (vec == 4) return launch_step_v<float, 4>(A, s, st);
+    if (vec == 2) return launch_step_v<float, 2>(A, s, st);
+    return launch_step_v<float, 1>(A, s, st);
+}
+
+// ---------------------------------------------------------------------------
+// probe signs
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(kThreads) void sign_mask_kernel(int n, int k, uint64_t key,
+                                                             uint64_t* __restrict__ mask) {
+    const int r = blockIdx.x * kThreads + threadIdx.x;
+    if (r >= n) return;
+    uint64_t bits = 0;
+    for (int c = 0; c < k; ++c) {
+        const uint64_t x = probe_bits(key, (uint64_t)c * (uint64_t)n + (uint64_t)r + 1ull);
+        bits |= (x >> 63) << c;
+    }
+    mask[r] = bits;
+}
+
+hipError_t launch_sign_mask(int n, int k, uint64_t key, uint64_t* mask, hipStream_t st) {
+    if (n == 0) return hipSuccess;
+    hipLaunchKernelGGL(sign_mask_kernel, dim3(div_up(n, kThreads)), dim3(kThreads), 0, st, n, k,
+                       key, mask);
+    return hipGetLastError();
+}
+
+template <typename T>
+__global__ __launch_bounds__(kThreads) void fill_signs_kernel(int n, int k, int ld,
+                                                              const uint64_t* __restrict__ mask,
+                                                              T scale, T* __restrict__ out) {
+    const long long i = (long long)blockIdx.x * kThreads + threadIdx.x;
+    if (i >= (long long)n * ld) return;
+    const int r = (int)(i / ld), c = (int)(i - (long long)r * ld);
+    T v = T(0);
+    if (c < k) v = ((mask[r] >> c) & 1ull) ? -scale : scale;
+    out[i] = v;
+}
+
+hipError_t launch_fill_signs(bool f64, int n, int k, int ld, const uint64_t* mask, double scale,
+                             void* out, hipStream_t st) {
+    const long long tot = (long long)n * ld;
+    if (tot == 0) return hipSuccess;
+    const int nb = div_up(tot, kThreads);
+    if (f64)
+        hipLaunchKernelGGL(fill_signs_kernel<double>, dim3(nb), dim3(kThreads), 0, st, n, k, ld,
+                           mask, scale, (double*)out);
+    else
+        hipLaunchKernelGGL(fill_signs_kernel<float>, dim3(nb), dim3(kThreads), 0, st, n, k, ld,
+                           mask, (float)scale, (float*)out);
+    return hipGetLastError();
+}
+
+template <typename T>
+__global__ __launch_bounds__(kThreads) void scale_copy_kernel(int n, int ncols,
+                                                              const T* __restrict__ V, int ldv,
+                                                              T scale, T* __restrict__ out,
+                                                              int ldo) {
+    const long long i = (long long)blockIdx.x * kThreads + threadIdx.x;
+    if (i >= (long long)n * ncols) return;
+    const int r = (int)(i / ncols), c = (int)(i - (long long)r * ncols);
+    out[(size_t)r * ldo + c] = scale * V[(size_t)r * ldv + c];
+}
+
+hipError_t launch_scale_copy(bool f64, int n, int ncols, const void* V, int ldv, double scale,
+                             void* out, int ldo, hipStream_t st) {
+    const long long tot = (long long)n * ncols;
+    if (tot == 0) return hipSuccess;
+    const int nb = div_up(tot, kThreads);
+    if (f64)
+        hipLaunchKernelGGL(scale_copy_kernel<double>, dim3(nb), dim3(kThreads), 0, st, n, ncols,
+                           (const double*)V, ldv, scale, (double*)out, ldo);
+    else
+        hipLaunchKernelGGL(scale_copy_kernel<float>, dim3(nb), dim3(kThreads), 0, st, n, ncols,
+                           (const float*)V, ldv, (float)scale, (float*)out, ldo);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// X^T Z on FP64 MFMA (v_mfma_f64_16x16x4_f64).  Operand layout of the 16x16x4
+// instruction: lane l holds A[l%16][l/16] and B[l/16][l%16]; the 16x16 result
+// has D[l/16 + 4v][l%16] in accumulator element v (checked on gfx950).  With
+// A = X^T and B = Z over a chunk of 4 rows, lane l simply loads
+// X[r0 + l/16][16*t + l%16].
+// ---------------------------------------------------------------------------
+constexpr int kCrossRows = 1024;   // rows per workgroup
+
+typedef double double4_t __attribute__((ext_vector_type(4)));
+
+template <typename T, int TX, int TZ, bool ZSIGNS>
+__global__ __launch_bounds__(kThreads) void cross_kernel(int n, const T* __restrict__ X, int ldx,
+                                                         int kx, const T* __restrict__ Z, int ldz,
+                                                         int kz, uint64_t key,
+                                                         double* __restrict__ part) {
+    const int lane = threadIdx.x & 63;
+    const int wave = threadIdx.x >> 6;
+    const int sub = lane >> 4;       // row within a chunk of 4
+    const int cit = lane & 15;       // column within a 16-wide tile
+    const int tile = xcd_tile(blockIdx.x, gridDim.x);
+    const int row0 = tile * kCrossRows;
+    double4_t acc[TX][TZ];
+#pragma unroll
+    for (int a = 0; a < TX; ++a)
+#pragma unroll
+        for (int b = 0; b < TZ; ++b) acc[a][b] = double4_t{0.0, 0.0, 0.0, 0.0};
+
+    for (int r0 = row0 + wave * 4; r0 < row0 + kCrossRows && r0 < n; r0 += kWaves * 4) {
+        const int r = r0 + sub;
+        const bool rok = r < n;
+        double xa[TX], zb[TZ];
+#pragma unroll
+        for (int a = 0; a < TX; ++a) {
+            const int c = a * 16 + cit;
+            xa[a] = (rok && c < kx) ? (double)X[(size_t)r * ldx + c] : 0.0;
+        }
+#pragma unroll
+        for (int b = 0; b < TZ; ++b) {
+            const int c = b * 16 + cit;
+            double z = 0.0;
+            if (rok && c < kz) {
+                if constexpr (ZSIGNS) {
+                    const uint64_t x = probe_bits(key, (uint64_t)c * (uint64_t)n + (uint64_t)r + 1ull);
+                    z = (x >> 63) ? -1.0 : 1.0;
+                } else {
+                    z = (double)Z[(size_t)r * ldz + c];
+                }
+            }
+            zb[b] = z;
+        }
+#pragma unroll
+        for (int a = 0; a < TX; ++a)
+#pragma unroll
+            for (int b = 0; b < TZ; ++b)
+                acc[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(xa[a], zb[b], acc[a][b], 0, 0, 0);
+    }
+
+    // sum the four waves in a fixed order through LDS
+    __shared__ double sh[TX * TZ * 256];
+    for (int wv = 0; wv < kWaves; ++wv) {
+        if (wave == wv) {
+#pragma unroll
+            for (int a = 0; a < TX; ++a)
+#pragma unroll
+                for (int b = 0; b < TZ; ++b)
+#pragma unroll
+                    for (int v = 0; v < 4; ++v) {
+                        const int idx = ((a * TZ + b) * 4 + v) * 64 + lane;
+                        sh[idx] = (wv == 0) ? acc[a][b][v] : sh[idx] + acc[a][b][v];
+                    }
+        }
+        __syncthreads();
+    }
+    // scatter to part[tile][i*kz + j]
+    for (int e = threadIdx.x; e < TX * TZ * 256; e += kThreads) {
+        const int l = e & 63;
+        const int v = (e >> 6) & 3;
+        const int ab = e >> 8;
+        const int a = ab / TZ, b = ab - a * TZ;
+        const int i = a * 16 + (l >> 4) + 4 * v;
+        const int j = b * 16 + (l & 15);
+        if (i < kx && j < kz) part[(size_t)blockIdx.x * kx * kz + i * kz + j] = sh[e];
+    }
+}
+
+template <typename T, int TX, int TZ>
+hipError_t launch_cross_t(int n, const void* X, int ldx, int kx, const void* Z, int ldz, int kz,
+                          bool zsigns, uint64_t key, double* part, hipStream_t st) {
+    const int nwg = div_up(n, kCrossRows);
+    if (nwg == 0) return hipSuccess;
+    if (zsigns)
+        hipLaunchKernelGGL((cross_kernel<T, TX, TZ, true>), dim3(nwg), dim3(kThreads), 0, st, n,
+                           (const T*)X, ldx, kx, (const T*)Z, ldz, kz, key, part);
+    else
+        hipLaunchKernelGGL((cross_kernel<T, TX, TZ, false>), dim3(nwg), dim3(kThreads), 0, st, n,
+                           (const T*)X, ldx, kx, (const T*)Z, ldz, kz, key, part);
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_cross_tx(int n, const void* X, int ldx, int kx, const void* Z, int ldz, int kz,
+                           bool zsigns, uint64_t key, double* part, hipStream_t st) {
+    const int tx = (kx + 15) / 16, tz = (kz + 15) / 16;
+#define LD_CROSS_CASE(A, B) \
+    if (tx == A && tz == B) return launch_cross_t<T, A, B>(n, X, ldx, kx, Z, ldz, kz, zsigns, key, part, st);
+    LD_CROSS_CASE(1, 1) LD_CROSS_CASE(1, 2) LD_CROSS_CASE(1, 3) LD_CROSS_CASE(1, 4)
+    LD_CROSS_CASE(2, 1) LD_CROSS_CASE(2, 2) LD_CROSS_CASE(2, 3) LD_CROSS_CASE(2, 4)
+    LD_CROSS_CASE(3, 1) LD_CROSS_CASE(3, 2) LD_CROSS_CASE(3, 3) LD_CROSS_CASE(3, 4)
+    LD_CROSS_CASE(4, 1) LD_CROSS_CASE(4, 2) LD_CROSS_CASE(4, 3) LD_CROSS_CASE(4, 4)
+#undef LD_CROSS_CASE
+    return hipErrorInvalidValue;
+}
+
+int cross_num_wg(int n) { return div_up(n, kCrossRows); }
+
+hipError_t launch_cross(bool f64, int n, const void* X, int ldx, int kx, const void* Z, int ldz,
+                        int kz, bool zsigns, uint64_t key, double* part, hipStream_t st) {
+    if (kx < 1 || kz < 1 || kx > 64 || kz > 64) return hipErrorInvalidValue;
+    return f64 ? launch_cross_tx<double>(n, X, ldx, kx, Z, ldz, kz, zsigns, key, part, st)
+               : launch_cross_tx<float>(n, X, ldx, kx, Z, ldz, kz, zsigns, key, part, st);
+}
+
+// ---------------------------------------------------------------------------
+// fixed-order compensated reduction over workgroup partials
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(kThreads) void reduce_kernel(const double* __restrict__ part, int nwg,
+                                                          int len, int outer,
+                                                          long long outer_stride,
+                                                          double* __restrict__ out) {
+    const long long i = (long long)blockIdx.x * kThreads + threadIdx.x;
+    if (i >= (long long)outer * len) return;
+    const int o = (int)(i / len), j = (int)(i - (long long)o * len);
+    const double* p = part + (size_t)o * outer_stride + j;
+    double s = 0.0, c = 0.0;
+    for (int w = 0; w < nwg; ++w) {
+        const double x = p[(size_t)w * len];
+        const double t = s + x;
+        c += (fabs(s) >= fabs(x)) ? (s - t) + x : (x - t) + s;
+        s = t;
+    }
+    out[i] = s + c;
+}
+
+hipError_t launch_reduce(const double* part, int nwg, int len, int outer, long long outer_stride,
+                         double* out, hipStream_t st) {
+    const long long tot = (long long)outer * len;
+    if (tot == 0) return hipSuccess;
+    hipLaunchKernelGGL(reduce_kernel, dim3(div_up(tot, kThreads)), dim3(kThreads), 0, st, part,
+                       nwg, len, outer, outer_stride, out);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// row block times a small FP64 matrix (TRSM with R^{-1}; deflation G - Q C)
+// ---------------------------------------------------------------------------
+constexpr int kRowmatRows = 64;
+
+template <typename T, bool SIGNS>
+__global__ __launch_bounds__(kThreads) void rowmat_kernel(int n, const T* __restrict__ Y, int ldy,
+                                                          int ky, const double* __restrict__ M,
+                                                          int kout, double sign_m, uint64_t key,
+                                                          T* __restrict__ out, int ldo) {
+    __shared__ double ms[64 * 64];
+    __shared__ double ys[kRowmatRows * 64];
+    const int row0 = xcd_tile(blockIdx.x, gridDim.x) * kRowmatRows;
+    for (int e = threadIdx.x; e < ky * kout; e += kThreads) ms[e] = M[e];
+    for (int e = threadIdx.x; e < kRowmatRows * ky; e += kThreads) {
+        const int r = e / ky, i = e - r * ky;
+        ys[e] = (row0 + r < n) ? (double)Y[(size_t)(row0 + r) * ldy + i] : 0.0;
+    }
+    __syncthreads();
+    for (int e = threadIdx.x; e < kRowmatRows * kout; e += kThreads) {
+        const int r = e / kout, j = e - r * kout;
+        const int row = row0 + r;
+        if (row >= n) continue;
+        double acc = 0.0;
+        for (int i = 0; i < ky; ++i) acc = fma(ys[r * ky + i], ms[i * kout + j], acc);
+        double v = sign_m * acc;
+        if constexpr (SIGNS) {
+            const uint64_t x = probe_bits(key, (uint64_t)j * (uint64_t)n + (uint64_t)row + 1ull);
+            v += (x >> 63) ? -1.0 : 1.0;
+        }
+        out[(size_t)row * ldo + j] = (T)v;
+    }
+}
+
+hipError_t launch_rowmat(bool f64, int n, const void* Y, int ldy, int ky, const double* M, int kout,
+                         double sign_m, bool signs, uint64_t key, void* out, int ldo,
+                         hipStream_t st) {
+    if (ky > 64 || kout > 64) return hipErrorInvalidValue;
+    const int nwg = div_up(n, kRowmatRows);
+    if (nwg == 0) return hipSuccess;
+#define LD_ROWMAT(T, S)                                                                         \
+    hipLaunchKernelGGL((rowmat_kernel<T, S>), dim3(nwg), dim3(kThreads), 0, st, n, (const T*)Y, \
+                       ldy, ky, M, kout, sign_m, key, (T*)out, ldo)
+    if (f64) {
+        if (signs) LD_ROWMAT(double, true); else LD_ROWMAT(double, false);
+    } else {
+        if (signs) LD_ROWMAT(float, true); else LD_ROWMAT(float, false);
+    }
+#undef LD_ROWMAT
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// CSR structure check (reads col_idx only inside [0, nnz))
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(kThreads) void validate_kernel(int n, int nnz,
+                                                            const int* __restrict__ row_ptr,
+                                                            const int* __restrict__ col_idx,
+                                                            int* __restrict__ flag) {
+    const int r = blockIdx.x * kThreads + threadIdx.x;
+    if (r >= n) return;
+    const int b = row_ptr[r], e = row_ptr[r + 1];
+    bool bad = (b < 0) || (e < b) || (e > nnz) || (r == 0 && b != 0) || (r == n - 1 && e != nnz);
+    if (!bad) {
+        int prev = -1;
+        for (int k = b; k < e; ++k) {
+            const int c = col_idx[k];
+            if (c < 0 || c >= n || c <= prev) {
+                bad = true;
+                break;
+            }
+            prev = c;
+        }
+    }
+    if (bad) *flag = 1;
+}
+
+hipError_t launch_validate_csr(const CsrDev& A, int* flag, hipStream_t st) {
+    if (A.n == 0) return hipSuccess;
+    hipLaunchKernelGGL(validate_kernel, dim3(div_up(A.n, kThreads)), dim3(kThreads), 0, st, A.n,
+                       A.nnz, A.row_ptr, A.col_idx, flag);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Gershgorin discs
+// ---------------------------------------------------------------------------
+template <typename T>
+__global__ __launch_bounds__(kThreads) void gersh_kernel(int n, const int* __restrict__ row_ptr,
+                                                         const int* __restrict__ col_idx,
+                                                         const T* __restrict__ val,
+                                                         double* __restrict__ part) {
+    const int r = blockIdx.x * kThreads + threadIdx.x;
+    double lo = __builtin_inf(), hi = -__builtin_inf();
+    if (r < n) {
+        double diag = 0.0, rad = 0.0;
+        for (int k = row_ptr[r]; k < row_ptr[r + 1]; ++k) {
+            const double v = (double)val[k];
+            if (col_idx[k] == r)
+                diag += v;
+            else
+                rad += fabs(v);
+        }
+        lo = diag - rad;
+        hi = diag + rad;
+    }
+    __shared__ double slo[kThreads], shi[kThreads];
+    slo[threadIdx.x] = lo;
+    shi[threadIdx.x] = hi;
+    __syncthreads();
+    for (int s = kThreads / 2; s > 0; s >>= 1) {
+        if (threadIdx.x < s) {
+            slo[threadIdx.x] = fmin(slo[threadIdx.x], slo[threadIdx.x + s]);
+            shi[threadIdx.x] = fmax(shi[threadIdx.x], shi[threadIdx.x + s]);
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        part[2 * blockIdx.x] = slo[0];
+        part[2 * blockIdx.x + 1] = shi[0];
+    }
+}
+
+int gersh_num_wg(int n) { return div_up(n, kThreads); }
+
+hipError_t launch_gershgorin(bool f64, const CsrDev& A, double* part, hipStream_t st) {
+    const int nwg = gersh_num_wg(A.n);
+    if (nwg == 0) return hipSuccess;
+    if (f64)
+        hipLaunchKernelGGL(gersh_kernel<double>, dim3(nwg), dim3(kThreads), 0, st, A.n, A.row_ptr,
+                           A.col_idx, (const double*)A.val, part);
+    else
+        hipLaunchKernelGGL(gersh_kernel<float>, dim3(nwg), dim3(kThreads), 0, st, A.n, A.row_ptr,
+                           A.col_idx, (const float*)A.val, part);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// elementwise y = a x + b y
+// ---------------------------------------------------------------------------
+template <typename T>
+__global__ __launch_bounds__(kThreads) void axpby_kernel(long long len, T a, const T* __restrict__ x,
+                                                         T b, T* __restrict__ y) {
+    const long long i = (long long)blockIdx.x * kThreads + threadIdx.x;
+    if (i < len) y[i] = a * x[i] + b * y[i];
+}
+
+hipError_t launch_axpby(bool f64, long long len, double a, const void* x, double b, void* y,
+                        hipStream_t st) {
+    if (len == 0) return hipSuccess;
+    const int nb = div_up(len, kThreads);
+    if (f64)
+        hipLaunchKernelGGL(axpby_kernel<double>, dim3(nb), dim3(kThreads), 0, st, len, a,
+                           (const double*)x, b, (double*)y);
+    else
+        hipLaunchKernelGGL(axpby_kernel<float>, dim3(nb), dim3(kThreads), 0, st, len, (float)a,
+                           (const float*)x, (float)b, (float*)y);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// adjoint step (reverse sweep of the gradient), one row per row group:
+//   lam_out[r] = alpha * sum_k a_rk lam_in[c_k] - beta lam_in[r] + dj L[r]
+//   grad[k]   (+)= alpha * <lam_in[r, :], w[c_k, :]>
+// A is symmetric, so A^T lam = A lam uses the same CSR rows.
+// ---------------------------------------------------------------------------
+template <typename T, int VEC>
+__global__ __launch_bounds__(kThreads) void adjoint_kernel(
+    int n, const int* __restrict__ row_ptr, const int* __restrict__ col_idx,
+    const T* __restrict__ val, const T* __restrict__ lam_in, T* __restrict__ lam_out,
+    const T* __restrict__ w, const T* __restrict__ L, T* __restrict__ grad, int ld, int ncols,
+    T alpha, T beta, T dj, int first, int last, int lpr, int rpw) {
+    const int lane = threadIdx.x & 63;
+    const int wave = threadIdx.x >> 6;
+    const int g = lane / lpr;
+    const int li = lane - g * lpr;
+    if (g >= rpw) return;   // whole row groups only; no barriers below
+    const int col = li * VEC;
+    const int row = xcd_tile(blockIdx.x, gridDim.x) * (kWaves * rpw) + wave * rpw + g;
+    if (row >= n) return;
+    bool valid[VEC];
+#pragma unroll
+    for (int e = 0; e < VEC; ++e) valid[e] = col + e < ncols;
+    const Pack<T, VEC> lr = load_pack<T, VEC>(lam_in + (size_t)row * ld + col);
+    T acc[VEC];
+#pragma unroll
+    for (int e = 0; e < VEC; ++e) acc[e] = T(0);
+    const int beg = row_ptr[row], end = row_ptr[row + 1];
+    for (int k = beg; k < end; ++k) {
+        const int c = col_idx[k];
+        const T a = val[k];
+        // SDDMM term: <lam_in[row], w[c]> over all columns (row-group reduction)
+        const Pack<T, VEC> wc = load_pack<T, VEC>(w + (size_t)c * ld + col);
+        T part = T(0);
+#pragma unroll
+        for (int e = 0; e < VEC; ++e) part = valid[e] ? fma(lr.v[e], wc.v[e], part) : part;
+        // reduce over the lpr lanes of this row group with shuffles
+        for (int off = 1; off < lpr; off <<= 1) {
+            const T other = __shfl_xor(part, off, 64);
+            // lanes whose partner lies outside the row group keep their value
+            const int partner = li ^ off;
+            part = (partner < lpr) ? part + other : part;
+        }
+        if (!last) {
+            const Pack<T, VEC> lc = load_pack<T, VEC>(lam_in + (size_t)c * ld + col);
+#pragma unroll
+            for (int e = 0; e < VEC; ++e) acc[e] = fma(a, lc.v[e], acc[e]);
+        }
+        if (li == 0) {
+            const T gv = alpha * part;
+            grad[k] = first ? gv : grad[k] + gv;
+        }
+    }
+    if (!last) {
+        const Pack<T, VEC> Lr = load_pack<T, VEC>(L + (size_t)row * ld + col);
+        Pack<T, VEC> o;
+#pragma unroll
+        for (int e = 0; e < VEC; ++e)
+            o.v[e] = valid[e] ? fma(dj, Lr.v[e], alpha * acc[e] - beta * lr.v[e]) : T(0);
+        store_pack<T, VEC>(lam_out + (size_t)row * ld + col, o);
+    }
+}
+
+hipError_t launch_adjoint(bool f64, const CsrDev& A, const AdjArgs& a, hipStream_t st) {
+    const int elem = f64 ? 8 : 4;
+    int vec = 16 / elem;
+    while (vec > 1 && (a.ld % vec)) vec /= 2;
+    const int lpr = lanes_per_row(a.ncols, vec);
+    if (lpr > 64) return hipErrorInvalidValue;
+    // the shuffle reduction needs the row group to be a power of two wide
+    int lp2 = 1;
+    while (lp2 < lpr) lp2 <<= 1;
+    const int rpw = 64 / lp2;
+    const int nwg = div_up(A.n, kWaves * rpw);
+    if (nwg == 0) return hipSuccess;
+#define LD_ADJ(T, V)                                                                              \
+    hipLaunchKernelGGL((adjoint_kernel<T, V>), dim3(nwg), dim3(kThreads), 0, st, A.n, A.row_ptr, \
+                       A.col_idx, (const T*)A.val, (const T*)a.lam_in, (T*)a.lam_out,            \
+                       (const T*)a.w, (const T*)a.L, (T*)a.grad, a.ld, a.ncols, (T)a.alpha,      \
+                       (T)a.beta, (T)a.dj, (int)a.first, (int)a.last, lp2, rpw)
+    if (f64) {
+        if (vec == 2) LD_ADJ(double, 2); else LD_ADJ(double, 1);
+    } else {
+        if (vec == 4) LD_ADJ(float, 4); else if (vec == 2) LD_ADJ(float, 2); else LD_ADJ(float, 1);
+    }
+#undef LD_ADJ
+    return hipGetLastError();
+}
+
+}  // namespace ld

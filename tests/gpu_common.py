@@ -1,0 +1,39 @@
+"""Helpers shared by the GPU tests (inputs only; no arithmetic of the method)."""
+import json
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+
+
+def golden(name):
+    path = os.path.join(HERE, "golden", f"{name}.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        return json.load(f)
+
+
+def random_spd_csr(n, seed, density=0.02, long_rows=0, shift=0.5):
+    """Seeded sparse SPD matrix (symmetric, diagonally dominant) with ragged rows.
+
+    ``long_rows`` rows are made dense-ish to exercise long-row handling.
+    """
+    import scipy.sparse as sp
+
+    rng = np.random.default_rng(seed)
+    B = sp.random(n, n, density=density, random_state=rng, data_rvs=lambda k: rng.uniform(-1, 1, k))
+    B = sp.triu(B, 1)
+    if long_rows:
+        rows = rng.choice(n, size=long_rows, replace=False)
+        extra = sp.coo_matrix((rng.uniform(-0.2, 0.2, long_rows * (n // 2)),
+                               (np.repeat(rows, n // 2), rng.integers(0, n, long_rows * (n // 2)))),
+                              shape=(n, n))
+        B = B + sp.triu(extra, 1)
+    S = (B + B.T).tocsr()
+    S.sum_duplicates()
+    radius = np.asarray(abs(S).sum(axis=1)).ravel()
+    Q = (S + sp.diags(radius + shift + rng.uniform(0, 1, n))).tocsr()
+    Q.sort_indices()
+    return (Q.indptr.astype(np.int32), Q.indices.astype(np.int32), Q.data.astype(np.float64), n)

@@ -1,0 +1,232 @@
+"""GPU parity: the HIP path (through the C ABI) against the FP64 CPU oracle.
+
+Tolerances: FP64 bulk 1e-10 relative; FP32 bulk 1e-4 relative on the
+estimate (the target), with tighter checks where the arithmetic allows.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import workloads as w
+from oracle import bounds, exact, hutchpp, newton
+from tests.gpu_common import golden, random_spd_csr
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():  # pragma: no cover
+    pytest.skip("no GPU", allow_module_level=True)
+
+import paper_2603_02207_amd as ld  # noqa: E402
+
+DEV = "cuda:0"
+
+
+def to_gpu(csr, dtype):
+    row_ptr, col_idx, val, n = csr
+    vals = np.asarray(val, dtype=np.float32 if dtype == torch.float32 else np.float64)
+    return ld.CSR.from_arrays(row_ptr, col_idx, vals, n, device=DEV, dtype=dtype), vals.astype(np.float64)
+
+
+def rel(a, b):
+    return abs(a - b) / abs(b)
+
+
+# ---------------------------------------------------------------- apply_log
+
+@pytest.mark.parametrize("dtype,tol", [(torch.float64, 1e-12), (torch.float32, 2e-5)])
+@pytest.mark.parametrize("ncols", [1, 3, 8, 20, 33])
+def test_apply_log_random_block(dtype, tol, ncols):
+    csr = w.grid_laplacian_2d(37, 0.5)          # n = 1369: several tiles plus a ragged tail
+    A, vals = to_gpu(csr, dtype)
+    rng = np.random.default_rng(ncols)
+    V = rng.standard_normal((csr[3], ncols))
+    Vd = torch.tensor(V, dtype=dtype, device=DEV)
+    Vin = Vd.double().cpu().numpy()
+    out = ld.apply_log(A, 0.5, 8.5, 40, Vd).double().cpu().numpy()
+    Q = w.to_scipy((csr[0], csr[1], vals, csr[3]))
+    ref = newton.apply_log(Q, Vin, 0.5, 8.5, 40)
+    err = np.linalg.norm(out - ref, axis=0) / np.linalg.norm(ref, axis=0)
+    assert err.max() < tol
+
+
+def test_apply_log_block_width_invariance_bitwise():
+    csr = w.grid_laplacian_2d(30, 0.5)
+    A, _ = to_gpu(csr, torch.float32)
+    V = torch.tensor(np.random.default_rng(0).standard_normal((900, 24)), dtype=torch.float32, device=DEV)
+    full = ld.apply_log(A, 0.5, 8.5, 30, V)
+    for b in (4, 8, 12):
+        part = ld.apply_log(A, 0.5, 8.5, 30, V, options=ld.Options(block_cols=b))
+        assert torch.equal(full, part)
+    # each column alone gives the same bits as inside the block
+    one = ld.apply_log(A, 0.5, 8.5, 30, V[:, 5:6].contiguous())
+    assert torch.equal(one[:, 0], full[:, 5])
+
+
+@pytest.mark.parametrize("dtype,tol", [(torch.float64, 1e-12), (torch.float32, 1e-5)])
+def test_apply_log_dirichlet_eigenvectors_full_size(dtype, tol):
+    # 1024 x 1024 grid, degree 80: P_m(Q~)v = P_m(lambda/sigma) v for the sine eigenvectors.
+    N, k2, m = 1024, 0.1, 80
+    csr = w.grid_laplacian_2d(N, k2)
+    A, _ = to_gpu(csr, dtype)
+    plan = newton.NewtonPlan(k2, k2 + 8.0, m)
+    modes = [(1, 1), (3, 700), (512, 513), (1024, 1024)]
+    V = np.stack([w.dirichlet_sine_vector_2d(N, a, b) for a, b in modes], axis=1)
+    Vd = torch.tensor(V, dtype=dtype, device=DEV)
+    out = ld.apply_log(A, k2, k2 + 8.0, m, Vd).double().cpu().numpy()
+    Vin = Vd.double().cpu().numpy()
+    for i, (a, b) in enumerate(modes):
+        lam = exact.grid_eigenvalue_2d(N, k2, a, b)
+        scal = float(plan.eval_scalar(lam)) + math.log(plan.sigma)
+        ref = scal * Vin[:, i]
+        err = np.linalg.norm(out[:, i] - ref) / np.linalg.norm(ref)
+        assert err < tol, (a, b, err)
+
+
+def test_apply_log_empty_block_and_degree_one():
+    csr = w.grid_laplacian_2d(8, 0.5)
+    A, vals = to_gpu(csr, torch.float64)
+    V = torch.zeros((64, 0), dtype=torch.float64, device=DEV)
+    assert ld.apply_log(A, 0.5, 8.5, 10, V).shape == (64, 0)
+    V = torch.tensor(np.random.default_rng(1).standard_normal((64, 2)), device=DEV)
+    out = ld.apply_log(A, 0.5, 8.5, 1, V).cpu().numpy()
+    ref = newton.apply_log(w.to_scipy((csr[0], csr[1], vals, 64)), V.cpu().numpy(), 0.5, 8.5, 1)
+    np.testing.assert_allclose(out, ref, rtol=1e-13, atol=1e-13)
+
+
+# ---------------------------------------------------------------- estimator
+
+@pytest.mark.parametrize("seed", range(5))
+def test_estimate_grid32_against_oracle(seed):
+    g = golden("grid32_k0.5")
+    csr = w.grid_laplacian_2d(32, 0.5)
+    A64, _ = to_gpu(csr, torch.float64)
+    A32, vals32 = to_gpu(csr, torch.float32)
+    ref = g["results"][str(seed)]["logdet"]
+    e64 = ld.logdet(A64, 0.5, 8.5, 40, 30, seed)
+    assert rel(e64, ref) < 1e-10
+    e32 = ld.logdet(A32, 0.5, 8.5, 40, 30, seed)
+    assert rel(e32, ref) < 1e-4
+    # against the oracle run on the FP32-rounded values: FP32 arithmetic error only
+    ref32 = hutchpp.logdet_estimate(w.to_scipy((csr[0], csr[1], vals32, csr[3])), 0.5, 8.5, 40, 30, seed)
+    assert rel(e32, ref32) < 1e-5
+
+
+@pytest.mark.parametrize("mode", [ld.LD_DOT_FORWARD, ld.LD_DOT_SQUARED])
+@pytest.mark.parametrize("dtype,tol", [(torch.float64, 1e-10), (torch.float32, 1e-5)])
+def test_estimate_dot_modes(mode, dtype, tol):
+    csr = w.grid_laplacian_2d(45, 0.3)        # n = 2025, ragged against every tile size
+    A, vals = to_gpu(csr, dtype)
+    lmin, lmax = bounds.gershgorin(csr)
+    for deg, mv in ((33, 21), (40, 30)):       # odd and even degree
+        est, st = ld.logdet(A, lmin, lmax, deg, mv, 3, options=ld.Options(dot_mode=mode), return_stats=True)
+        assert st["dot_mode_used"] == mode
+        ref = hutchpp.logdet_estimate(w.to_scipy((csr[0], csr[1], vals, csr[3])), lmin, lmax, deg, mv, 3)
+        assert rel(est, ref) < tol
+
+
+def test_estimate_block_cols_invariance():
+    csr = w.grid_laplacian_2d(40, 0.5)
+    A, _ = to_gpu(csr, torch.float32)
+    base = ld.logdet(A, 0.5, 8.5, 30, 48, 1)
+    for b in (4, 16, 20):
+        e = ld.logdet(A, 0.5, 8.5, 30, 48, 1, options=ld.Options(block_cols=b))
+        assert rel(e, base) < 1e-12
+    # deterministic repeat
+    assert ld.logdet(A, 0.5, 8.5, 30, 48, 1) == base
+
+
+@pytest.mark.parametrize("n,long_rows,seed", [(700, 0, 0), (1500, 3, 1), (333, 1, 2)])
+@pytest.mark.parametrize("dtype,tol", [(torch.float64, 1e-10), (torch.float32, 1e-4)])
+def test_estimate_irregular_sparsity(n, long_rows, seed, dtype, tol):
+    csr = random_spd_csr(n, seed, long_rows=long_rows)
+    A, vals = to_gpu(csr, dtype)
+    csr_v = (csr[0], csr[1], vals, n)
+    lmin, lmax = bounds.gershgorin(csr_v)
+    est = ld.logdet(A, lmin, lmax, 50, 24, seed)
+    ref = hutchpp.logdet_estimate(w.to_scipy(csr_v), lmin, lmax, 50, 24, seed)
+    assert rel(est, ref) < tol
+
+
+def test_estimate_small_and_sigma_one():
+    # lmin >= 1 (sigma = 1), tiny n with k close to n
+    csr = w.grid_laplacian_2d(4, 3.0)
+    A, vals = to_gpu(csr, torch.float64)
+    est = ld.logdet(A, 3.0, 11.0, 25, 30, 0)
+    ref = hutchpp.logdet_estimate(w.to_scipy((csr[0], csr[1], vals, 16)), 3.0, 11.0, 25, 30, 0)
+    assert rel(est, ref) < 1e-10
+
+
+def test_estimate_grid1024_full_size():
+    g = golden("grid1024_k0.1")
+    if g is None:
+        pytest.skip("oracle value for the 1024 x 1024 grid not generated")
+    csr = w.grid_laplacian_2d(1024, 0.1)
+    ref = g["results"]["0"]["logdet"]
+    A32, _ = to_gpu(csr, torch.float32)
+    e32 = ld.logdet(A32, g["lmin"], g["lmax"], g["degree"], g["m_vec"], 0)
+    assert rel(e32, ref) < 1e-4
+    A64, _ = to_gpu(csr, torch.float64)
+    e64 = ld.logdet(A64, g["lmin"], g["lmax"], g["degree"], g["m_vec"], 0)
+    assert rel(e64, ref) < 1e-10
+
+
+# ---------------------------------------------------------------- bounds and errors
+
+def test_spectral_bounds_match_oracle():
+    for csr in (w.grid_laplacian_2d(50, 0.1), w.grid_laplacian_3d(9, 0.05), random_spd_csr(500, 4, long_rows=2)):
+        for dtype in (torch.float64, torch.float32):
+            A, vals = to_gpu(csr, dtype)
+            lo, hi = ld.spectral_bounds(A)
+            rlo, rhi = bounds.gershgorin((csr[0], csr[1], vals, csr[3]))
+            assert lo == pytest.approx(rlo, rel=1e-12, abs=1e-12)
+            assert hi == pytest.approx(rhi, rel=1e-12)
+
+
+def test_invalid_csr_is_rejected():
+    csr = w.grid_laplacian_2d(6, 0.5)
+    bad_cols = csr[1].copy()
+    bad_cols[10] = 999                        # out of range
+    A = ld.CSR.from_arrays(csr[0], bad_cols, csr[2], 36, device=DEV)
+    with pytest.raises(ld.NativeError) as e:
+        ld.logdet(A, 0.5, 8.5, 10, 9, 0)
+    assert e.value.code == -2
+    unsorted = csr[1].copy()
+    unsorted[[0, 1]] = unsorted[[1, 0]]
+    A = ld.CSR.from_arrays(csr[0], unsorted, csr[2], 36, device=DEV)
+    with pytest.raises(ld.NativeError):
+        ld.apply_log(A, 0.5, 8.5, 10, torch.ones((36, 2), device=DEV))
+    bad_ptr = csr[0].copy()
+    bad_ptr[5] = 10**6
+    A = ld.CSR.from_arrays(bad_ptr, csr[1], csr[2], 36, device=DEV)
+    with pytest.raises(ld.NativeError):
+        ld.spectral_bounds(A)
+
+
+def test_cholqr_breakdown_is_reported():
+    # n = 3 and k = 3: pick a seed whose 3 x 3 sketch is singular (two equal or
+    # opposite columns), so Y = F S is rank deficient.
+    from oracle import rng
+
+    seed = next(s for s in range(200) if abs(np.linalg.det(rng.rademacher(s, 0, 3, 3))) < 0.5)
+    row_ptr = np.array([0, 1, 2, 3], dtype=np.int32)
+    col_idx = np.array([0, 1, 2], dtype=np.int32)
+    A = ld.CSR.from_arrays(row_ptr, col_idx, np.array([2.0, 3.0, 5.0]), 3, device=DEV, dtype=torch.float64)
+    with pytest.raises(ld.NativeError) as e:
+        ld.logdet(A, 1.5, 6.0, 10, 9, seed)
+    assert e.value.code == -3
+
+
+def test_workspace_too_small():
+    csr = w.grid_laplacian_2d(8, 0.5)
+    A, _ = to_gpu(csr, torch.float32)
+    ws = torch.empty(16, dtype=torch.uint8, device=DEV)
+    import ctypes
+    from paper_2603_02207_amd import _native as nat
+
+    c = A.c_struct()
+    out = ctypes.c_double()
+    rc = nat.load().ld_logdet_estimate(ctypes.byref(c), 0.5, 8.5, 10, 9, 0, None, ctypes.c_void_p(ws.data_ptr()),
+                                       16, None, ctypes.byref(out), None)
+    assert rc == nat.LD_EWORKSPACE
