@@ -17,6 +17,19 @@ enum StepKind : int {
     STEP_PLAIN = 4,         // out = alpha*A*in - beta*in
 };
 
+// A dense n x cols matrix stored as column blocks of width bw: element
+// (r, c) lives at (c / bw) * bstride + r * ld + c % bw (in elements).  A plain
+// row-major matrix is the single-block case.
+struct Blk {
+    int ld;
+    int bw;
+    long long bstride;
+    __host__ __device__ size_t offset(int c) const {
+        return (size_t)(c / bw) * (size_t)bstride + (size_t)(c % bw);
+    }
+    static Blk plain(int ld) { return Blk{ld, 1 << 30, 0}; }
+};
+
 struct CsrDev {
     int n;
     int nnz;
@@ -33,6 +46,7 @@ struct StepArgs {
     const void* win;
     void* wout;
     int ld, c0, bcols;
+    int gshift;                // global column = local column + gshift
     double alpha, beta, dj;
     const void* vsrc;          // HORNER_VEC: V;  DOT_FWD: X
     int ldv;
@@ -53,9 +67,9 @@ hipError_t launch_step(bool f64, const CsrDev& A, const StepArgs& s, hipStream_t
 // Sign mask of stream `key`: bit c of word r = (probe(r, c) == -1), c < k <= 64.
 hipError_t launch_sign_mask(int n, int k, uint64_t key, uint64_t* mask, hipStream_t st);
 
-// out[r, c] = scale * S[r, c] for c < k, 0 for k <= c < ld.
-hipError_t launch_fill_signs(bool f64, int n, int k, int ld, const uint64_t* mask, double scale,
-                             void* out, hipStream_t st);
+// out[r, c] = scale * S[r, c + gshift] for c < k, 0 for k <= c < ld.
+hipError_t launch_fill_signs(bool f64, int n, int k, int ld, int gshift, const uint64_t* mask,
+                             double scale, void* out, hipStream_t st);
 
 // out[r, c] = scale * V[r, c] (row-major, V with ldv, out with ldo), c < ncols.
 hipError_t launch_scale_copy(bool f64, int n, int ncols, const void* V, int ldv, double scale,
@@ -65,17 +79,18 @@ hipError_t launch_scale_copy(bool f64, int n, int ncols, const void* V, int ldv,
 // Z is either a second block (zsigns_key ignored) or, with zsigns, the probe
 // signs of stream key for columns [0, kz).
 int cross_num_wg(int n);
-hipError_t launch_cross(bool f64, int n, const void* X, int ldx, int kx, const void* Z, int ldz,
+hipError_t launch_cross(bool f64, int n, const void* X, Blk bx, int kx, const void* Z, Blk bz,
                         int kz, bool zsigns, uint64_t key, double* part, hipStream_t st);
 
-// out[outer][j] = sum_wg part[outer*outer_stride + wg*len + j] (Neumaier, fixed order).
-hipError_t launch_reduce(const double* part, int nwg, int len, int outer, long long outer_stride,
-                         double* out, hipStream_t st);
+// out[o*out_ld + j] = sum_wg part[o*outer_stride + wg*part_ld + j], j < len
+// (Neumaier, fixed order).
+hipError_t launch_reduce(const double* part, int nwg, int len, int part_ld, int outer,
+                         long long outer_stride, double* out, int out_ld, hipStream_t st);
 
-// out[r, j] = (signs ? S_key[r, j] : 0) + sign_m * sum_i Y[r, i] M[i, j],
-// M k_y x k_out FP64 (device), j < k_out.
-hipError_t launch_rowmat(bool f64, int n, const void* Y, int ldy, int ky, const double* M, int kout,
-                         double sign_m, bool signs, uint64_t key, void* out, int ldo,
+// out[r, ocol0 + j] = (signs ? S_key[r, j] : 0) + sign_m * sum_i Y[r, i] M[i, j],
+// M k_y x k_out FP64 (device), j < k_out; Y and out column-blocked.
+hipError_t launch_rowmat(bool f64, int n, const void* Y, Blk by, int ky, const double* M, int kout,
+                         double sign_m, bool signs, uint64_t key, void* out, Blk bo, int ocol0,
                          hipStream_t st);
 
 // CSR structure check: *flag (device int) set to 1 on any violation.

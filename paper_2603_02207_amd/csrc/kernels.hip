@@ -67,61 +67,104 @@ int div_up(long long a, long long b) { return (int)((a + b - 1) / b); }
 // rows of one row group iteration
 inline int lanes_per_row(int bcols, int vec) { return (bcols + vec - 1) / vec; }
 
-inline int step_iters(int kind) { return (kind == STEP_DOT_FWD || kind == STEP_DOT_SQ) ? 4 : 1; }
+constexpr int kStepIters = 2;      // row groups per wave and launch
+constexpr int kDotIters = 4;       // the same for the kinds with column sums (amortises the sum)
+constexpr int kStageNz = 1536;     // CSR entries a workgroup stages in LDS
+
+constexpr int iters_of(int kind) {
+    return (kind == STEP_DOT_FWD || kind == STEP_DOT_SQ) ? kDotIters : kStepIters;
+}
+inline int step_iters(int kind) { return iters_of(kind); }
 
 // ---------------------------------------------------------------------------
 // Newton step: out = alpha*A*in - beta*in (+ dj*source), optional dot partials.
+//
+// A workgroup owns rows [R0, R0 + 4*rpw*ITERS).  It first stages its slice of
+// row_ptr and, when it fits, its col_idx/val entries in LDS with coalesced
+// loads; each row group then reads its row's entries from LDS (one address per
+// row group, a broadcast) and issues up to eight gathers before the first FMA.
+// Slices with more than kStageNz entries (long rows) read the CSR arrays
+// directly.  Global column of local column c: c + gshift (probe signs and
+// partial sums use it).
 // ---------------------------------------------------------------------------
-template <typename T, int VEC, int KIND, bool FIRST>
+template <typename T, int VEC, int KIND, bool FIRST, int ITERS>
 __global__ __launch_bounds__(kThreads) void step_kernel(
     int n, const int* __restrict__ row_ptr, const int* __restrict__ col_idx,
     const T* __restrict__ val, const T* __restrict__ win, T* __restrict__ wout, int ld, int c0,
-    int bcols, T alpha, T beta, T dj, const T* __restrict__ vsrc, int ldv,
+    int bcols, int gshift, T alpha, T beta, T dj, const T* __restrict__ vsrc, int ldv,
     const uint64_t* __restrict__ mask, double* __restrict__ ps0, double* __restrict__ ps1,
-    double* __restrict__ ps2, int part_ld, int lpr, int rpw, int iters) {
+    double* __restrict__ ps2, int part_ld, int lpr, int rpw) {
     constexpr bool kDot = (KIND == STEP_DOT_FWD || KIND == STEP_DOT_SQ);
+    constexpr int kValBytes = kStageNz * (int)sizeof(T);
+    constexpr int kRedBytes = kDot ? kThreads * (VEC + 1) * 8 : 0;
+    constexpr int kPool = (kValBytes + kStageNz * 4) > kRedBytes ? (kValBytes + kStageNz * 4) : kRedBytes;
+    __shared__ int s_rp[kWaves * 64 * ITERS + 1];
+    __shared__ __align__(16) unsigned char s_pool[kPool];
+    T* const s_val = reinterpret_cast<T*>(s_pool);
+    int* const s_col = reinterpret_cast<int*>(s_pool + kValBytes);
+
     const int lane = threadIdx.x & 63;
     const int wave = threadIdx.x >> 6;
     const int g = lane / lpr;
     const int li = lane - g * lpr;
     const bool lane_ok = g < rpw;
     const int col = c0 + li * VEC;
-    const int tile = xcd_tile(blockIdx.x, gridDim.x);
-    const int rows_per_wg = kWaves * rpw * iters;
+    const int rows_per_wg = kWaves * rpw * ITERS;
+    const int R0 = xcd_tile(blockIdx.x, gridDim.x) * rows_per_wg;
+    const int nrows = min(rows_per_wg, n - R0);
+
+    for (int t = threadIdx.x; t <= nrows; t += kThreads) s_rp[t] = row_ptr[R0 + t];
+    __syncthreads();
+    const int K0 = s_rp[0];
+    const int K1 = s_rp[nrows];
+    const bool staged = (K1 - K0) <= kStageNz;
+    if (staged) {
+        for (int k = K0 + threadIdx.x; k < K1; k += kThreads) {
+            s_col[k - K0] = col_idx[k];
+            s_val[k - K0] = val[k];
+        }
+    }
+    __syncthreads();
 
     double s0[VEC], s1[VEC], s2[VEC];
 #pragma unroll
     for (int e = 0; e < VEC; ++e) s0[e] = s1[e] = s2[e] = 0.0;
-    bool valid[VEC];
 #pragma unroll
-    for (int e = 0; e < VEC; ++e) valid[e] = lane_ok && (col + e < c0 + bcols);
-
-    for (int it = 0; it < iters; ++it) {
-        const int row = tile * rows_per_wg + (it * kWaves + wave) * rpw + g;
-        if (!lane_ok || row >= n) continue;
-        const int beg = row_ptr[row], end = row_ptr[row + 1];
+    for (int it = 0; it < ITERS; ++it) {
+        const int lr = (it * kWaves + wave) * rpw + g;
+        if (!lane_ok || lr >= nrows) continue;
+        const int row = R0 + lr;
+        const int beg = s_rp[lr], end = s_rp[lr + 1];
         T acc[VEC];
 #pragma unroll
         for (int e = 0; e < VEC; ++e) acc[e] = T(0);
-        for (int base = beg; base < end; base += 8) {
-            int cidx[8];
-            T a[8];
+        if (staged) {
+            for (int k = beg - K0; k < end - K0; ++k) {
+                const Pack<T, VEC> x = load_pack<T, VEC>(win + (size_t)s_col[k] * ld + col);
+                const T a = s_val[k];
 #pragma unroll
-            for (int u = 0; u < 8; ++u) {
-                const int k = base + u;
-                cidx[u] = row;
-                a[u] = T(0);
-                if (k < end) {
-                    cidx[u] = col_idx[k];
-                    a[u] = val[k];
-                }
+                for (int e = 0; e < VEC; ++e) acc[e] = fma(a, x.v[e], acc[e]);
             }
+        } else {
+            for (int base = beg; base < end; base += 8) {
+                int cidx[8];
+                T a[8];
 #pragma unroll
-            for (int u = 0; u < 8; ++u) {
-                if (base + u < end) {
-                    const Pack<T, VEC> x = load_pack<T, VEC>(win + (size_t)cidx[u] * ld + col);
+                for (int u = 0; u < 8; ++u) {
+                    cidx[u] = row;
+                    a[u] = T(0);
+                    if (base + u < end) {
+                        cidx[u] = col_idx[base + u];
+                        a[u] = val[base + u];
+                    }
+                }
 #pragma unroll
-                    for (int e = 0; e < VEC; ++e) acc[e] = fma(a[u], x.v[e], acc[e]);
+                for (int u = 0; u < 8; ++u) {
+                    if (base + u < end) {
+                        const Pack<T, VEC> x = load_pack<T, VEC>(win + (size_t)cidx[u] * ld + col);
+#pragma unroll
+                        for (int e = 0; e < VEC; ++e) acc[e] = fma(a[u], x.v[e], acc[e]);
+                    }
                 }
             }
         }
@@ -133,7 +176,7 @@ __global__ __launch_bounds__(kThreads) void step_kernel(
             const uint64_t bits = mask[row];
 #pragma unroll
             for (int e = 0; e < VEC; ++e) {
-                const T sgn = ((bits >> ((col + e) & 63)) & 1ull) ? T(-1) : T(1);
+                const T sgn = ((bits >> ((col + gshift + e) & 63)) & 1ull) ? T(-1) : T(1);
                 o.v[e] = fma(dj, sgn, o.v[e]);
             }
         } else if constexpr (KIND == STEP_HORNER_VEC) {
@@ -155,57 +198,63 @@ __global__ __launch_bounds__(kThreads) void step_kernel(
                 s2[e] += (double)o.v[e] * (double)o.v[e];
             }
         }
-        {
-            // columns outside [c0, c0+bcols) are left untouched
-            bool all = true;
-#pragma unroll
-            for (int e = 0; e < VEC; ++e) all = all && valid[e];
-            if (all) {
-                store_pack<T, VEC>(wout + (size_t)row * ld + col, o);
-            } else {
-#pragma unroll
-                for (int e = 0; e < VEC; ++e)
-                    if (valid[e]) wout[(size_t)row * ld + col + e] = o.v[e];
-            }
-        }
+        // Every lane stores its whole vector: ld and c0 are multiples of VEC, so
+        // the vector never leaves the row, and columns past c0+bcols in it get
+        // the value of the same recurrence (real columns of a wider block, or
+        // padding that no one reads).
+        store_pack<T, VEC>(wout + (size_t)row * ld + col, o);
     }
 
     if constexpr (kDot) {
-        __shared__ double red[kThreads * VEC];
-        double* const outs[3] = {ps0, ps1, ps2};
-        const double* const sums[3] = {s0, s1, s2};
-#pragma unroll
-        for (int q = 0; q < 3; ++q) {
-            if (q == 0 && !FIRST) continue;
-            if (q == 2 && KIND != STEP_DOT_SQ) continue;
-#pragma unroll
-            for (int e = 0; e < VEC; ++e) red[threadIdx.x * VEC + e] = sums[q][e];
+        // Column sums over the workgroup's rows, in a fixed order.  The staged
+        // CSR slice is dead: its LDS holds the per-lane partials (red) and a
+        // second level of per-column partial sums (red2).
+        double* const red = reinterpret_cast<double*>(s_pool);
+        double* const red2 = red + kThreads * VEC;
+        const int groups = kWaves * rpw;                   // row groups of the workgroup
+        const int split = max(1, min(kThreads / max(bcols, 1), groups));
+        auto column_sums = [&](const double (&sum)[VEC], double* __restrict__ out) __attribute__((always_inline)) {
             __syncthreads();
-            for (int t = threadIdx.x; t < bcols; t += kThreads) {
+#pragma unroll
+            for (int e = 0; e < VEC; ++e) red[threadIdx.x * VEC + e] = sum[e];
+            __syncthreads();
+            // level 1: thread (t, p) adds the row groups p, p+split, ... of column t
+            if (threadIdx.x < bcols * split) {
+                const int t = threadIdx.x % bcols, p = threadIdx.x / bcols;
                 const int tl = t / VEC, te = t - tl * VEC;
                 double acc = 0.0;
-                for (int wv = 0; wv < kWaves; ++wv)
-                    for (int gg = 0; gg < rpw; ++gg)
-                        acc += red[(wv * 64 + gg * lpr + tl) * VEC + te];
-                outs[q][(size_t)blockIdx.x * part_ld + c0 + t] = acc;
+                for (int gi = p; gi < groups; gi += split) {
+                    const int wv = gi / rpw, gg = gi - wv * rpw;
+                    acc += red[(wv * 64 + gg * lpr + tl) * VEC + te];
+                }
+                red2[p * bcols + t] = acc;
             }
             __syncthreads();
-        }
+            // level 2: one thread per column adds the split partials in order
+            for (int t = threadIdx.x; t < bcols; t += kThreads) {
+                double acc = 0.0;
+                for (int p = 0; p < split; ++p) acc += red2[p * bcols + t];
+                out[(size_t)blockIdx.x * part_ld + c0 + gshift + t] = acc;
+            }
+        };
+        if constexpr (FIRST) column_sums(s0, ps0);
+        column_sums(s1, ps1);
+        if constexpr (KIND == STEP_DOT_SQ) column_sums(s2, ps2);
     }
 }
 
 template <typename T, int VEC, int KIND, bool FIRST>
 hipError_t launch_step_t(const CsrDev& A, const StepArgs& s, hipStream_t st) {
+    constexpr int kIters = iters_of(KIND);
     const int lpr = lanes_per_row(s.bcols, VEC);
     const int rpw = 64 / lpr;
-    const int iters = step_iters(KIND);
-    const int rows_per_wg = kWaves * rpw * iters;
+    const int rows_per_wg = kWaves * rpw * kIters;
     const int nwg = div_up(A.n, rows_per_wg);
     if (nwg == 0) return hipSuccess;
-    hipLaunchKernelGGL((step_kernel<T, VEC, KIND, FIRST>), dim3(nwg), dim3(kThreads), 0, st, A.n,
-                       A.row_ptr, A.col_idx, (const T*)A.val, (const T*)s.win, (T*)s.wout, s.ld,
-                       s.c0, s.bcols, (T)s.alpha, (T)s.beta, (T)s.dj, (const T*)s.vsrc, s.ldv,
-                       s.mask, s.ps0, s.ps1, s.ps2, s.part_ld, lpr, rpw, iters);
+    hipLaunchKernelGGL((step_kernel<T, VEC, KIND, FIRST, kIters>), dim3(nwg), dim3(kThreads), 0, st,
+                       A.n, A.row_ptr, A.col_idx, (const T*)A.val, (const T*)s.win, (T*)s.wout, s.ld,
+                       s.c0, s.bcols, s.gshift, (T)s.alpha, (T)s.beta, (T)s.dj, (const T*)s.vsrc,
+                       s.ldv, s.mask, s.ps0, s.ps1, s.ps2, s.part_ld, lpr, rpw);
     return hipGetLastError();
 }
 
@@ -244,7 +293,8 @@ inline int pick_vec(const StepArgs& s, int elem_bytes) {
 
 int step_num_wg_bound(int n, int bcols, int elem_bytes) {
     // blocks aligned to the 16-byte vector (the estimator's internal layout)
-    const int rows = kWaves * (64 / lanes_per_row(bcols, 16 / elem_bytes)) * 4;
+    const int rows = kWaves * (64 / lanes_per_row(bcols, 16 / elem_bytes)) *
+                     (kStepIters < kDotIters ? kStepIters : kDotIters);
     return div_up(n, rows);
 }
 
@@ -288,28 +338,28 @@ hipError_t launch_sign_mask(int n, int k, uint64_t key, uint64_t* mask, hipStrea
 }
 
 template <typename T>
-__global__ __launch_bounds__(kThreads) void fill_signs_kernel(int n, int k, int ld,
+__global__ __launch_bounds__(kThreads) void fill_signs_kernel(int n, int k, int ld, int gshift,
                                                               const uint64_t* __restrict__ mask,
                                                               T scale, T* __restrict__ out) {
     const long long i = (long long)blockIdx.x * kThreads + threadIdx.x;
     if (i >= (long long)n * ld) return;
     const int r = (int)(i / ld), c = (int)(i - (long long)r * ld);
     T v = T(0);
-    if (c < k) v = ((mask[r] >> c) & 1ull) ? -scale : scale;
+    if (c < k) v = ((mask[r] >> ((c + gshift) & 63)) & 1ull) ? -scale : scale;
     out[i] = v;
 }
 
-hipError_t launch_fill_signs(bool f64, int n, int k, int ld, const uint64_t* mask, double scale,
-                             void* out, hipStream_t st) {
+hipError_t launch_fill_signs(bool f64, int n, int k, int ld, int gshift, const uint64_t* mask,
+                             double scale, void* out, hipStream_t st) {
     const long long tot = (long long)n * ld;
     if (tot == 0) return hipSuccess;
     const int nb = div_up(tot, kThreads);
     if (f64)
         hipLaunchKernelGGL(fill_signs_kernel<double>, dim3(nb), dim3(kThreads), 0, st, n, k, ld,
-                           mask, scale, (double*)out);
+                           gshift, mask, scale, (double*)out);
     else
         hipLaunchKernelGGL(fill_signs_kernel<float>, dim3(nb), dim3(kThreads), 0, st, n, k, ld,
-                           mask, (float)scale, (float*)out);
+                           gshift, mask, (float)scale, (float*)out);
     return hipGetLastError();
 }
 
@@ -350,8 +400,8 @@ constexpr int kCrossRows = 1024;   // rows per workgroup
 typedef double double4_t __attribute__((ext_vector_type(4)));
 
 template <typename T, int TX, int TZ, bool ZSIGNS>
-__global__ __launch_bounds__(kThreads) void cross_kernel(int n, const T* __restrict__ X, int ldx,
-                                                         int kx, const T* __restrict__ Z, int ldz,
+__global__ __launch_bounds__(kThreads) void cross_kernel(int n, const T* __restrict__ X, Blk bx,
+                                                         int kx, const T* __restrict__ Z, Blk bz,
                                                          int kz, uint64_t key,
                                                          double* __restrict__ part) {
     const int lane = threadIdx.x & 63;
@@ -366,6 +416,11 @@ __global__ __launch_bounds__(kThreads) void cross_kernel(int n, const T* __restr
 #pragma unroll
         for (int b = 0; b < TZ; ++b) acc[a][b] = double4_t{0.0, 0.0, 0.0, 0.0};
 
+    size_t xoff[TX], zoff[TZ];
+#pragma unroll
+    for (int a = 0; a < TX; ++a) xoff[a] = bx.offset(a * 16 + cit);
+#pragma unroll
+    for (int b = 0; b < TZ; ++b) zoff[b] = ZSIGNS ? 0 : bz.offset(b * 16 + cit);
     for (int r0 = row0 + wave * 4; r0 < row0 + kCrossRows && r0 < n; r0 += kWaves * 4) {
         const int r = r0 + sub;
         const bool rok = r < n;
@@ -373,7 +428,7 @@ __global__ __launch_bounds__(kThreads) void cross_kernel(int n, const T* __restr
 #pragma unroll
         for (int a = 0; a < TX; ++a) {
             const int c = a * 16 + cit;
-            xa[a] = (rok && c < kx) ? (double)X[(size_t)r * ldx + c] : 0.0;
+            xa[a] = (rok && c < kx) ? (double)X[xoff[a] + (size_t)r * bx.ld] : 0.0;
         }
 #pragma unroll
         for (int b = 0; b < TZ; ++b) {
@@ -384,7 +439,7 @@ __global__ __launch_bounds__(kThreads) void cross_kernel(int n, const T* __restr
                     const uint64_t x = probe_bits(key, (uint64_t)c * (uint64_t)n + (uint64_t)r + 1ull);
                     z = (x >> 63) ? -1.0 : 1.0;
                 } else {
-                    z = (double)Z[(size_t)r * ldz + c];
+                    z = (double)Z[zoff[b] + (size_t)r * bz.ld];
                 }
             }
             zb[b] = z;
@@ -425,25 +480,25 @@ __global__ __launch_bounds__(kThreads) void cross_kernel(int n, const T* __restr
 }
 
 template <typename T, int TX, int TZ>
-hipError_t launch_cross_t(int n, const void* X, int ldx, int kx, const void* Z, int ldz, int kz,
+hipError_t launch_cross_t(int n, const void* X, Blk bx, int kx, const void* Z, Blk bz, int kz,
                           bool zsigns, uint64_t key, double* part, hipStream_t st) {
     const int nwg = div_up(n, kCrossRows);
     if (nwg == 0) return hipSuccess;
     if (zsigns)
         hipLaunchKernelGGL((cross_kernel<T, TX, TZ, true>), dim3(nwg), dim3(kThreads), 0, st, n,
-                           (const T*)X, ldx, kx, (const T*)Z, ldz, kz, key, part);
+                           (const T*)X, bx, kx, (const T*)Z, bz, kz, key, part);
     else
         hipLaunchKernelGGL((cross_kernel<T, TX, TZ, false>), dim3(nwg), dim3(kThreads), 0, st, n,
-                           (const T*)X, ldx, kx, (const T*)Z, ldz, kz, key, part);
+                           (const T*)X, bx, kx, (const T*)Z, bz, kz, key, part);
     return hipGetLastError();
 }
 
 template <typename T>
-hipError_t launch_cross_tx(int n, const void* X, int ldx, int kx, const void* Z, int ldz, int kz,
+hipError_t launch_cross_tx(int n, const void* X, Blk bx, int kx, const void* Z, Blk bz, int kz,
                            bool zsigns, uint64_t key, double* part, hipStream_t st) {
     const int tx = (kx + 15) / 16, tz = (kz + 15) / 16;
 #define LD_CROSS_CASE(A, B) \
-    if (tx == A && tz == B) return launch_cross_t<T, A, B>(n, X, ldx, kx, Z, ldz, kz, zsigns, key, part, st);
+    if (tx == A && tz == B) return launch_cross_t<T, A, B>(n, X, bx, kx, Z, bz, kz, zsigns, key, part, st);
     LD_CROSS_CASE(1, 1) LD_CROSS_CASE(1, 2) LD_CROSS_CASE(1, 3) LD_CROSS_CASE(1, 4)
     LD_CROSS_CASE(2, 1) LD_CROSS_CASE(2, 2) LD_CROSS_CASE(2, 3) LD_CROSS_CASE(2, 4)
     LD_CROSS_CASE(3, 1) LD_CROSS_CASE(3, 2) LD_CROSS_CASE(3, 3) LD_CROSS_CASE(3, 4)
@@ -454,93 +509,134 @@ hipError_t launch_cross_tx(int n, const void* X, int ldx, int kx, const void* Z,
 
 int cross_num_wg(int n) { return div_up(n, kCrossRows); }
 
-hipError_t launch_cross(bool f64, int n, const void* X, int ldx, int kx, const void* Z, int ldz,
+hipError_t launch_cross(bool f64, int n, const void* X, Blk bx, int kx, const void* Z, Blk bz,
                         int kz, bool zsigns, uint64_t key, double* part, hipStream_t st) {
     if (kx < 1 || kz < 1 || kx > 64 || kz > 64) return hipErrorInvalidValue;
-    return f64 ? launch_cross_tx<double>(n, X, ldx, kx, Z, ldz, kz, zsigns, key, part, st)
-               : launch_cross_tx<float>(n, X, ldx, kx, Z, ldz, kz, zsigns, key, part, st);
+    return f64 ? launch_cross_tx<double>(n, X, bx, kx, Z, bz, kz, zsigns, key, part, st)
+               : launch_cross_tx<float>(n, X, bx, kx, Z, bz, kz, zsigns, key, part, st);
 }
 
 // ---------------------------------------------------------------------------
 // fixed-order compensated reduction over workgroup partials
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(kThreads) void reduce_kernel(const double* __restrict__ part, int nwg,
-                                                          int len, int outer,
-                                                          long long outer_stride,
-                                                          double* __restrict__ out) {
-    const long long i = (long long)blockIdx.x * kThreads + threadIdx.x;
-    if (i >= (long long)outer * len) return;
-    const int o = (int)(i / len), j = (int)(i - (long long)o * len);
-    const double* p = part + (size_t)o * outer_stride + j;
-    double s = 0.0, c = 0.0;
-    for (int w = 0; w < nwg; ++w) {
-        const double x = p[(size_t)w * len];
-        const double t = s + x;
-        c += (fabs(s) >= fabs(x)) ? (s - t) + x : (x - t) + s;
-        s = t;
-    }
-    out[i] = s + c;
+// A block owns 16 outputs; its 16 lane groups take the partial rows
+// q, q+16, q+32, ... (Neumaier), then one thread adds the 16 group sums in
+// order.  The summation order depends only on nwg, so results are repeatable.
+constexpr int kRedJ = 16, kRedQ = kThreads / kRedJ;
+
+__device__ __forceinline__ void neumaier(double& s, double& c, double x) {
+    const double t = s + x;
+    c += (fabs(s) >= fabs(x)) ? (s - t) + x : (x - t) + s;
+    s = t;
 }
 
-hipError_t launch_reduce(const double* part, int nwg, int len, int outer, long long outer_stride,
-                         double* out, hipStream_t st) {
-    const long long tot = (long long)outer * len;
-    if (tot == 0) return hipSuccess;
-    hipLaunchKernelGGL(reduce_kernel, dim3(div_up(tot, kThreads)), dim3(kThreads), 0, st, part,
-                       nwg, len, outer, outer_stride, out);
+__global__ __launch_bounds__(kThreads) void reduce_kernel(const double* __restrict__ part, int nwg,
+                                                          int len, int part_ld,
+                                                          long long outer_stride,
+                                                          double* __restrict__ out, int out_ld) {
+    const int jj = threadIdx.x % kRedJ, q = threadIdx.x / kRedJ;
+    const int j = blockIdx.x * kRedJ + jj;
+    const int o = blockIdx.y;
+    double s = 0.0, c = 0.0;
+    if (j < len) {
+        const double* p = part + (size_t)o * outer_stride + j;
+#pragma unroll 8
+        for (int w = q; w < nwg; w += kRedQ) neumaier(s, c, p[(size_t)w * part_ld]);
+    }
+    __shared__ double ss[kThreads], cc[kThreads];
+    ss[threadIdx.x] = s;
+    cc[threadIdx.x] = c;
+    __syncthreads();
+    if (q == 0 && j < len) {
+        double S = 0.0, C = 0.0;
+        for (int t = 0; t < kRedQ; ++t) {
+            neumaier(S, C, ss[t * kRedJ + jj]);
+            neumaier(S, C, cc[t * kRedJ + jj]);
+        }
+        out[(size_t)o * out_ld + j] = S + C;
+    }
+}
+
+hipError_t launch_reduce(const double* part, int nwg, int len, int part_ld, int outer,
+                         long long outer_stride, double* out, int out_ld, hipStream_t st) {
+    if ((long long)outer * len == 0) return hipSuccess;
+    hipLaunchKernelGGL(reduce_kernel, dim3(div_up(len, kRedJ), outer), dim3(kThreads), 0, st, part,
+                       nwg, len, part_ld, outer_stride, out, out_ld);
     return hipGetLastError();
 }
 
 // ---------------------------------------------------------------------------
 // row block times a small FP64 matrix (TRSM with R^{-1}; deflation G - Q C)
 // ---------------------------------------------------------------------------
-constexpr int kRowmatRows = 64;
-
-template <typename T, bool SIGNS>
-__global__ __launch_bounds__(kThreads) void rowmat_kernel(int n, const T* __restrict__ Y, int ldy,
+// One row per thread: the row of Y is read into registers, M (converted to
+// the element type) is read from LDS at the same address by every lane, and
+// the output row is written back.  Y and the output are column-blocked
+// (Blk); output column j goes to global column ocol0 + j.
+template <typename T, int KY, int KO, bool SIGNS>
+__global__ __launch_bounds__(kThreads) void rowmat_kernel(int n, const T* __restrict__ Y, Blk by,
                                                           int ky, const double* __restrict__ M,
                                                           int kout, double sign_m, uint64_t key,
-                                                          T* __restrict__ out, int ldo) {
-    __shared__ double ms[64 * 64];
-    __shared__ double ys[kRowmatRows * 64];
-    const int row0 = xcd_tile(blockIdx.x, gridDim.x) * kRowmatRows;
-    for (int e = threadIdx.x; e < ky * kout; e += kThreads) ms[e] = M[e];
-    for (int e = threadIdx.x; e < kRowmatRows * ky; e += kThreads) {
-        const int r = e / ky, i = e - r * ky;
-        ys[e] = (row0 + r < n) ? (double)Y[(size_t)(row0 + r) * ldy + i] : 0.0;
+                                                          T* __restrict__ out, Blk bo, int ocol0) {
+    __shared__ T ms[KY * KO];
+    __shared__ size_t yoff[KY], ooff[KO];
+    for (int e = threadIdx.x; e < KY * KO; e += kThreads) {
+        const int i = e / KO, j = e - i * KO;
+        ms[e] = (i < ky && j < kout) ? (T)(sign_m * M[i * kout + j]) : T(0);
     }
+    for (int i = threadIdx.x; i < KY; i += kThreads) yoff[i] = i < ky ? by.offset(i) : 0;
+    for (int j = threadIdx.x; j < KO; j += kThreads) ooff[j] = j < kout ? bo.offset(ocol0 + j) : 0;
     __syncthreads();
-    for (int e = threadIdx.x; e < kRowmatRows * kout; e += kThreads) {
-        const int r = e / kout, j = e - r * kout;
-        const int row = row0 + r;
-        if (row >= n) continue;
-        double acc = 0.0;
-        for (int i = 0; i < ky; ++i) acc = fma(ys[r * ky + i], ms[i * kout + j], acc);
-        double v = sign_m * acc;
+    const int row = xcd_tile(blockIdx.x, gridDim.x) * kThreads + threadIdx.x;
+    if (row >= n) return;
+    T y[KY];
+#pragma unroll
+    for (int i = 0; i < KY; ++i) y[i] = (i < ky) ? Y[yoff[i] + (size_t)row * by.ld] : T(0);
+#pragma nounroll
+    for (int j = 0; j < kout; ++j) {
+        T acc = T(0);
+#pragma unroll
+        for (int i = 0; i < KY; ++i) acc = fma(y[i], ms[i * KO + j], acc);
         if constexpr (SIGNS) {
             const uint64_t x = probe_bits(key, (uint64_t)j * (uint64_t)n + (uint64_t)row + 1ull);
-            v += (x >> 63) ? -1.0 : 1.0;
+            acc += (x >> 63) ? T(-1) : T(1);
         }
-        out[(size_t)row * ldo + j] = (T)v;
+        out[ooff[j] + (size_t)row * bo.ld] = acc;
     }
 }
 
-hipError_t launch_rowmat(bool f64, int n, const void* Y, int ldy, int ky, const double* M, int kout,
-                         double sign_m, bool signs, uint64_t key, void* out, int ldo,
-                         hipStream_t st) {
-    if (ky > 64 || kout > 64) return hipErrorInvalidValue;
-    const int nwg = div_up(n, kRowmatRows);
-    if (nwg == 0) return hipSuccess;
-#define LD_ROWMAT(T, S)                                                                         \
-    hipLaunchKernelGGL((rowmat_kernel<T, S>), dim3(nwg), dim3(kThreads), 0, st, n, (const T*)Y, \
-                       ldy, ky, M, kout, sign_m, key, (T*)out, ldo)
-    if (f64) {
-        if (signs) LD_ROWMAT(double, true); else LD_ROWMAT(double, false);
-    } else {
-        if (signs) LD_ROWMAT(float, true); else LD_ROWMAT(float, false);
-    }
-#undef LD_ROWMAT
+template <typename T, int KY, int KO>
+void launch_rowmat_t(int nwg, hipStream_t st, int n, const void* Y, Blk by, int ky, const double* M,
+                     int kout, double sign_m, bool signs, uint64_t key, void* out, Blk bo, int ocol0) {
+    if (signs)
+        hipLaunchKernelGGL((rowmat_kernel<T, KY, KO, true>), dim3(nwg), dim3(kThreads), 0, st, n,
+                           (const T*)Y, by, ky, M, kout, sign_m, key, (T*)out, bo, ocol0);
+    else
+        hipLaunchKernelGGL((rowmat_kernel<T, KY, KO, false>), dim3(nwg), dim3(kThreads), 0, st, n,
+                           (const T*)Y, by, ky, M, kout, sign_m, key, (T*)out, bo, ocol0);
+}
+
+template <typename T>
+hipError_t launch_rowmat_ty(int nwg, hipStream_t st, int n, const void* Y, Blk by, int ky,
+                            const double* M, int kout, double sign_m, bool signs, uint64_t key,
+                            void* out, Blk bo, int ocol0) {
+    const int a = ky <= 16 ? 16 : ky <= 32 ? 32 : 64;
+    const int b = kout <= 16 ? 16 : kout <= 32 ? 32 : 64;
+#define LD_RM(A_, B_) \
+    if (a == A_ && b == B_) launch_rowmat_t<T, A_, B_>(nwg, st, n, Y, by, ky, M, kout, sign_m, signs, key, out, bo, ocol0);
+    LD_RM(16, 16) LD_RM(16, 32) LD_RM(16, 64) LD_RM(32, 16) LD_RM(32, 32) LD_RM(32, 64)
+    LD_RM(64, 16) LD_RM(64, 32) LD_RM(64, 64)
+#undef LD_RM
     return hipGetLastError();
+}
+
+hipError_t launch_rowmat(bool f64, int n, const void* Y, Blk by, int ky, const double* M, int kout,
+                         double sign_m, bool signs, uint64_t key, void* out, Blk bo, int ocol0,
+                         hipStream_t st) {
+    if (ky < 1 || kout < 1 || ky > 64 || kout > 64) return hipErrorInvalidValue;
+    const int nwg = div_up(n, kThreads);
+    if (nwg == 0) return hipSuccess;
+    return f64 ? launch_rowmat_ty<double>(nwg, st, n, Y, by, ky, M, kout, sign_m, signs, key, out, bo, ocol0)
+               : launch_rowmat_ty<float>(nwg, st, n, Y, by, ky, M, kout, sign_m, signs, key, out, bo, ocol0);
 }
 
 // ---------------------------------------------------------------------------
