@@ -113,6 +113,7 @@ int validate_csr(const ld_csr* A, int* dflag, hipStream_t st) {
 // after another (Blk), so every step reads contiguous memory.
 // ---------------------------------------------------------------------------
 constexpr double kMallBudget = 240e6;
+constexpr int kSmallSlots = 10;   // k x k (<= 64 x 64) FP64 scratch matrices
 
 double matrix_bytes(const ld_csr* A, size_t elem) {
     return (double)A->nnz * (double)(elem + 4) + 4.0 * (double)(A->n + 1);
@@ -136,7 +137,7 @@ struct BlkMat {
     void* base = nullptr;
     int cols = 0, bw = 1, ld = 1;
     size_t elem = 4;
-    Blk desc() const { return Blk{ld, bw, (long long)ld * n_}; }
+    Blk desc() const { return Blk{ld, bw, (long long)ld * n_, 0}; }
     int nblocks() const { return cols == 0 ? 0 : (cols + bw - 1) / bw; }
     int bcols(int i) const { return std::min(bw, cols - i * bw); }
     void* block(int i) const { return (char*)base + (size_t)i * ld * n_ * elem; }
@@ -159,10 +160,11 @@ struct EstLayout {
     size_t elem;
     BlkMat Y, Q1, X;          // sketch, first CholQR factor, [Q_b | U]
     size_t mask, W, part, small, nu, flag;
-    // gradient extras
-    BlkMat FX, Lg, Rg;        // F [Q_b|U], adjoint left/right blocks
-    size_t ckpt, seg, lam;
-    int nckpt, stride;
+    // gradient extras: F [Q_b|U], the materialised residual probes, a k-column
+    // temporary, and n x ldg blocks for L, R, checkpoints, segment and lambda
+    BlkMat FX, Gm, T1;
+    int gcols = 0, ldg = 0, nckpt = 0, stride = 0;
+    size_t gblk = 0;
 };
 
 int dot_slots(int degree, int mode) {
@@ -190,20 +192,22 @@ EstLayout layout_estimate(const ld_csr* A, int degree, int n_matvec, bool grad,
     const size_t cross = (size_t)cross_num_wg((int)n) * 64 * 64 * 8;
     const size_t dotp = (size_t)L.nslots * L.nwg_dot * L.nc * 8;
     L.part = std::max(cross, dotp);
-    L.small = (size_t)6 * 64 * 64 * 8;
+    L.small = (size_t)kSmallSlots * 64 * 64 * 8;
     L.nu = (size_t)L.nslots * L.nc * 8;
     L.flag = 256;
     if (grad) {
         L.stride = o.ckpt_stride > 0 ? o.ckpt_stride : (int)std::ceil(std::sqrt((double)degree));
         L.stride = std::max(1, std::min(L.stride, degree));
-        L.nckpt = (degree + L.stride - 1) / L.stride;
-        const int gcols = L.nc + L.k;                   // [Q_b, sqrt(c)U, S] / [Q_b, sqrt(c)U, 2Z]
-        L.FX = make_blk(n, L.nc, L.nc, L.elem);
-        L.Lg = make_blk(n, gcols, gcols, L.elem);
-        L.Rg = make_blk(n, gcols, gcols, L.elem);
-        L.ckpt = L.Rg.bytes() * L.nckpt;
-        L.seg = L.Rg.bytes() * L.stride;
-        L.lam = L.Rg.bytes();
+        L.nckpt = (degree + L.stride - 1) / L.stride;     // segments of the reverse sweep
+        L.gcols = L.nc + L.k;                               // [Q_b, sqrt(c)U, S] / [Q_b, sqrt(c)U, 2Z]
+        const int v = 16 / (int)L.elem;
+        int lanes = 1;                                      // the adjoint's row group: power of two
+        while (lanes * v < L.gcols) lanes <<= 1;
+        L.ldg = lanes * v;
+        L.gblk = (size_t)n * L.ldg * L.elem;
+        L.FX = make_blk(n, L.nc, L.X.bw, L.elem);
+        L.Gm = make_blk(n, L.kg, L.kg, L.elem);
+        L.T1 = make_blk(n, L.k, L.k, L.elem);
     }
     return L;
 }
@@ -213,9 +217,11 @@ size_t layout_bytes(const EstLayout& L, bool grad) {
     for (size_t s : {L.mask, L.Y.bytes(), L.Q1.bytes(), L.X.bytes(), L.W, L.W, L.part, L.small, L.nu,
                      L.flag})
         b += align_up(s);
-    if (grad)
-        for (size_t s : {L.FX.bytes(), L.Lg.bytes(), L.Rg.bytes(), L.ckpt, L.seg, L.lam, L.lam})
-            b += align_up(s);
+    if (grad) {
+        for (size_t s : {L.FX.bytes(), L.Gm.bytes(), L.T1.bytes(), L.mask}) b += align_up(s);
+        // L, R, two lambdas, nckpt-1 checkpoints, stride-1 segment vectors
+        b += align_up(L.gblk) * (size_t)(4 + (L.nckpt - 1) + (L.stride - 1));
+    }
     return b;
 }
 
@@ -296,7 +302,8 @@ int cholqr_pass(bool f64, int n, const BlkMat& Y, int k, const BlkMat& Q, double
         return fail(LD_EBREAKDOWN, "CholQR Gram matrix is not positive definite (rank-deficient sketch)");
     if (Rh) std::memcpy(Rh, R.data(), sizeof(double) * k * k);
     LD_CHECK_HIP(hipMemcpyAsync(dRinv, Rinv.data(), sizeof(double) * k * k, hipMemcpyHostToDevice, st));
-    LD_CHECK_HIP(launch_rowmat(f64, n, Y.base, Y.desc(), k, dRinv, k, 1.0, false, 0, Q.base, Q.desc(), 0, st));
+    LD_CHECK_HIP(launch_rowmat(f64, n, Y.base, Y.desc(), k, dRinv, k, 1.0, false, 0, nullptr,
+                               Blk::plain(1), Q.base, Q.desc(), st));
     // the host vectors die at return; make sure the copy has consumed them
     LD_CHECK_HIP(hipStreamSynchronize(st));
     return LD_OK;
@@ -410,8 +417,8 @@ int estimate_front(const ld_csr* A, uint64_t seed, EstimateState& S, hipStream_t
     // ---- deflation: C = Q_b^T G, U = G - Q_b C (G = probe stream 1) into X[:, k:]
     LD_CHECK(cross_product(f64, n, L.X.base, L.X.desc(), L.k, nullptr, Blk::plain(1), L.kg, true, key1,
                            S.part, dC, st));
-    LD_CHECK_HIP(launch_rowmat(f64, n, L.X.base, L.X.desc(), L.k, dC, L.kg, -1.0, true, key1,
-                               L.X.base, L.X.desc(), L.k, st));
+    LD_CHECK_HIP(launch_rowmat(f64, n, L.X.base, L.X.desc(), L.k, dC, L.kg, -1.0, true, key1, nullptr,
+                               Blk::plain(1), L.X.base, L.X.desc().shifted(L.k), st));
     tm.mark();
     return LD_OK;
 }
@@ -431,9 +438,10 @@ int estimate_dots(const ld_csr* A, EstimateState& S, hipStream_t st, std::vector
         int nwg = 0;
         if (S.mode == LD_DOT_SQUARED) {
             const int h = (m + 1) / 2;
-            void* cur = X.block(b);
-            void* nxt = S.W0;
+            // X itself is read once and kept (the gradient needs it); W0/W1 ping-pong
+            const void* cur = X.block(b);
             for (int a = 0; a < h; ++a) {
+                void* nxt = (a % 2 == 0) ? S.W0 : S.W1;
                 StepArgs s{};
                 s.kind = STEP_DOT_SQ;
                 s.first = a == 0;
@@ -450,7 +458,7 @@ int estimate_dots(const ld_csr* A, EstimateState& S, hipStream_t st, std::vector
                 LD_CHECK(run_step(f64, A, s, cols, cols, st, &nwg));
                 S.launches23 += 1;
                 S.bytes23 += alg_bytes_step(A, cols, STEP_DOT_SQ, L.elem);
-                std::swap(cur, nxt);
+                cur = nxt;
             }
         } else {
             const void* cur = X.block(b);
@@ -513,6 +521,288 @@ int check_estimate_args(const ld_csr* A, double lmin, double lmax, int degree, i
     const int k = n_matvec / 3, kg = n_matvec - 2 * k;
     if (k > 64 || kg > 64) return fail(LD_EINVAL, "n_matvec must be <= 192 (k, k_G <= 64)");
     if (k > A->n) return fail(LD_EINVAL, "sketch width k = n_matvec/3 exceeds n");
+    return LD_OK;
+}
+
+
+// ---------------------------------------------------------------------------
+// Gradient of the estimate.  With F = P_m(Q~), c = 1/k_G, Y = F S = Q_b R,
+// U = (I - Q_b Q_b^T) G, the derivative of
+//     est = n log sigma + tr(Q_b^T F Q_b) + c tr(U^T F U)
+// at fixed probes and interval is
+//     d est = tr(Q_b^T dF Q_b) + c tr(U^T dF U) + 2 tr(Z^T dF S),
+//     Z = (I - Q_b Q_b^T) X Q_b R^{-T},  X = F - c (F U G^T + G U^T F),
+// (the basis term comes from differentiating the QR factor of the sketch), so
+// one reverse sweep on L = [Q_b, sqrt(c) U, 2Z] and R = [Q_b, sqrt(c) U, S]
+// gives every entry: grad[(r,c)] = alpha * sum_i <lam_{i+1}[r], w_i[c]>, with
+// w_i the forward Newton vectors of R and lam the Horner adjoint started at
+// lam_m = d_m L.  The forward vectors are kept every `stride` steps and
+// recomputed inside each segment of the reverse sweep.
+// ---------------------------------------------------------------------------
+struct GradBufs {
+    void *mask2, *Lg, *Rg, *lam0, *lam1;
+    std::vector<void*> ckpt, seg;
+};
+
+// Horner application of F to every block of X: FX = P_m(Q~) X.
+int apply_poly_blocks(const ld_csr* A, EstimateState& S, const BlkMat& X, const BlkMat& FX,
+                      hipStream_t st) {
+    const bool f64 = A->dtype == LD_F64;
+    const int n = (int)A->n;
+    const Plan& p = S.plan;
+    const int m = p.degree;
+    for (int b = 0; b < X.nblocks(); ++b) {
+        const int cols = X.bcols(b);
+        LD_CHECK_HIP(launch_scale_copy(f64, n, cols, X.block(b), X.ld, p.d[m], S.W0, X.ld, st));
+        const void* cur = S.W0;
+        for (int j = m - 1; j >= 0; --j) {
+            void* out = j == 0 ? FX.block(b) : (cur == S.W0 ? S.W1 : S.W0);
+            StepArgs s{};
+            s.kind = STEP_HORNER_VEC;
+            s.win = cur;
+            s.wout = out;
+            s.ld = X.ld;
+            s.alpha = p.alpha;
+            s.beta = p.beta[j];
+            s.dj = p.d[j];
+            s.vsrc = X.block(b);
+            s.ldv = X.ld;
+            LD_CHECK(run_step(f64, A, s, cols, cols, st, nullptr));
+            cur = out;
+        }
+    }
+    return LD_OK;
+}
+
+int upload(const std::vector<double>& h, double* d, hipStream_t st) {
+    LD_CHECK_HIP(hipMemcpyAsync(d, h.data(), sizeof(double) * h.size(), hipMemcpyHostToDevice, st));
+    LD_CHECK_HIP(hipStreamSynchronize(st));   // h may die at return
+    return LD_OK;
+}
+
+int gradient(const ld_csr* A, uint64_t seed, EstimateState& S, GradBufs& B, void* grad,
+             hipStream_t st) {
+    const bool f64 = A->dtype == LD_F64;
+    const int n = (int)A->n;
+    const EstLayout& L = S.L;
+    const Plan& p = S.plan;
+    const int m = p.degree, k = L.k, kg = L.kg, nc = L.nc;
+    const double c = 1.0 / kg, sc = std::sqrt(c);
+    const uint64_t key0 = probe_stream_key(seed, 0), key1 = probe_stream_key(seed, 1);
+    double* slot[kSmallSlots];
+    for (int i = 0; i < kSmallSlots; ++i) slot[i] = S.small + (size_t)i * 64 * 64;
+    const Blk X = L.X.desc(), FXd = L.FX.desc(), Gd = L.Gm.desc(), Td = L.T1.desc();
+    const Blk Lg = Blk::plain(L.ldg), Rg = Blk::plain(L.ldg);
+
+    // FX = F [Q_b | U]
+    LD_CHECK(apply_poly_blocks(A, S, L.X, L.FX, st));
+    // residual probes G as a block
+    LD_CHECK_HIP(launch_sign_mask(n, kg, key1, (uint64_t*)B.mask2, st));
+    LD_CHECK_HIP(launch_fill_signs(f64, n, kg, L.Gm.ld, 0, (const uint64_t*)B.mask2, 1.0, L.Gm.base, st));
+    // small matrices: C = Q_b^T G (slot 2, from the estimate), M1 = U^T F Q_b, R = R2 R1
+    std::vector<double> C((size_t)k * kg), Ct((size_t)kg * k);
+    LD_CHECK_HIP(hipMemcpyAsync(C.data(), slot[2], sizeof(double) * C.size(), hipMemcpyDeviceToHost, st));
+    LD_CHECK_HIP(hipStreamSynchronize(st));
+    for (int i = 0; i < k; ++i)
+        for (int j = 0; j < kg; ++j) Ct[(size_t)j * k + i] = C[(size_t)i * kg + j];
+    LD_CHECK(upload(Ct, slot[3], st));
+    LD_CHECK(cross_product(f64, n, L.X.base, X.shifted(k), kg, L.FX.base, FXd, k, false, 0, S.part,
+                           slot[4], st));
+    // T1 = F Q_b - c F U C^T ; then T1 -= c G M1  (= X Q_b of the derivation)
+    LD_CHECK_HIP(launch_rowmat(f64, n, L.FX.base, FXd.shifted(k), kg, slot[3], k, -c, false, 0,
+                               L.FX.base, FXd, L.T1.base, Td, st));
+    LD_CHECK_HIP(launch_rowmat(f64, n, L.Gm.base, Gd, kg, slot[4], k, -c, false, 0, L.T1.base, Td,
+                               L.T1.base, Td, st));
+    // P = T1 - Q_b (Q_b^T T1)
+    LD_CHECK(cross_product(f64, n, L.X.base, X, k, L.T1.base, Td, k, false, 0, S.part, slot[5], st));
+    LD_CHECK_HIP(launch_rowmat(f64, n, L.X.base, X, k, slot[5], k, -1.0, false, 0, L.T1.base, Td,
+                               L.T1.base, Td, st));
+    // Z = P R^{-T}, R = R2 R1 (upper triangular); L[:, nc:nc+k] = 2 Z
+    std::vector<double> R((size_t)k * k, 0.0), Rt((size_t)k * k), Rinv((size_t)k * k), RinvT((size_t)k * k);
+    for (int i = 0; i < k; ++i)
+        for (int j = 0; j < k; ++j) {
+            double v = 0.0;
+            for (int t = 0; t < k; ++t) v += S.R2[i * k + t] * S.R1[t * k + j];
+            R[(size_t)i * k + j] = v;
+        }
+    {
+        // inverse of the upper-triangular R by back substitution
+        std::fill(Rinv.begin(), Rinv.end(), 0.0);
+        for (int j = k - 1; j >= 0; --j) {
+            Rinv[(size_t)j * k + j] = 1.0 / R[(size_t)j * k + j];
+            for (int i = j + 1; i < k; ++i) {
+                double v = 0.0;
+                for (int t = j + 1; t <= i; ++t) v += R[(size_t)j * k + t] * Rinv[(size_t)t * k + i];
+                Rinv[(size_t)j * k + i] = -v / R[(size_t)j * k + j];
+            }
+        }
+        for (int i = 0; i < k; ++i)
+            for (int j = 0; j < k; ++j) RinvT[(size_t)i * k + j] = Rinv[(size_t)j * k + i];
+    }
+    LD_CHECK(upload(RinvT, slot[6], st));
+    LD_CHECK_HIP(launch_rowmat(f64, n, L.T1.base, Td, k, slot[6], k, 2.0, false, 0, nullptr, Blk::plain(1),
+                               B.Lg, Lg.shifted(nc), st));
+    // L[:, :nc] = R[:, :nc] = [Q_b, sqrt(c) U]; R[:, nc:] = S
+    std::vector<double> I1((size_t)k * k, 0.0), I2((size_t)kg * kg, 0.0);
+    for (int i = 0; i < k; ++i) I1[(size_t)i * k + i] = 1.0;
+    for (int i = 0; i < kg; ++i) I2[(size_t)i * kg + i] = sc;
+    LD_CHECK(upload(I1, slot[7], st));
+    LD_CHECK(upload(I2, slot[8], st));
+    for (void* dst : {B.Lg, B.Rg}) {
+        LD_CHECK_HIP(launch_rowmat(f64, n, L.X.base, X, k, slot[7], k, 1.0, false, 0, nullptr, Blk::plain(1),
+                                   dst, Lg, st));
+        LD_CHECK_HIP(launch_rowmat(f64, n, L.X.base, X.shifted(k), kg, slot[8], kg, 1.0, false, 0, nullptr,
+                                   Blk::plain(1), dst, Lg.shifted(k), st));
+    }
+    (void)Rg;
+    LD_CHECK_HIP(launch_sign_mask(n, k, key0, (uint64_t*)S.mask, st));
+    LD_CHECK_HIP(launch_fill_signs(f64, n, k, L.ldg, 0, (const uint64_t*)S.mask, 1.0,
+                                   (char*)B.Rg + (size_t)nc * L.elem, st));
+
+    // forward Newton vectors of R, checkpoints every `stride` steps
+    const int gcols = L.gcols, ldg = L.ldg, stride = L.stride;
+    auto plain_step = [&](const void* in, void* out, int j) -> int {
+        StepArgs s{};
+        s.kind = STEP_PLAIN;
+        s.win = in;
+        s.wout = out;
+        s.ld = ldg;
+        s.alpha = p.alpha;
+        s.beta = p.beta[j];
+        return run_step(f64, A, s, gcols, gcols, st, nullptr);
+    };
+    {
+        const void* cur = B.Rg;
+        void* tmp[2] = {B.lam0, B.lam1};
+        for (int i = 0; i < m - 1; ++i) {
+            const int nx = i + 1;
+            void* dst = (nx % stride == 0) ? B.ckpt[nx / stride - 1] : (cur == tmp[0] ? tmp[1] : tmp[0]);
+            if (nx % stride != 0) {
+                // only the steps that end on a checkpoint need to be stored; the rest are scratch
+            }
+            LD_CHECK(plain_step(cur, dst, i));
+            cur = dst;
+        }
+    }
+    // reverse sweep
+    LD_CHECK_HIP(launch_scale_copy(f64, n, gcols, B.Lg, ldg, p.d[m], B.lam0, ldg, st));
+    void* lam_in = B.lam0;
+    void* lam_out = B.lam1;
+    const CsrDev d = dev_of(A);
+    for (int sg = L.nckpt - 1; sg >= 0; --sg) {
+        const int s0 = sg * stride, s1 = std::min(s0 + stride, m);
+        std::vector<const void*> w(s1 - s0);
+        w[0] = sg == 0 ? B.Rg : B.ckpt[sg - 1];
+        for (int t = 1; t < s1 - s0; ++t) {
+            LD_CHECK(plain_step(w[t - 1], B.seg[t - 1], s0 + t - 1));
+            w[t] = B.seg[t - 1];
+        }
+        for (int i = s1 - 1; i >= s0; --i) {
+            AdjArgs a{};
+            a.lam_in = lam_in;
+            a.lam_out = lam_out;
+            a.w = w[i - s0];
+            a.L = B.Lg;
+            a.grad = grad;
+            a.ld = ldg;
+            a.ncols = gcols;
+            a.alpha = p.alpha;
+            a.beta = p.beta[i];
+            a.dj = p.d[i];
+            a.first = i == m - 1;
+            a.last = i == 0;
+            LD_CHECK_HIP(launch_adjoint(f64, d, a, st));
+            std::swap(lam_in, lam_out);
+        }
+    }
+    return LD_OK;
+}
+
+// Estimate (and, with grad != nullptr, its gradient): the body of both entry points.
+int run_logdet(const ld_csr* A, double lmin, double lmax, int degree, int n_matvec, uint64_t seed,
+               const ld_options& o, void* workspace, size_t ws_bytes, hipStream_t st,
+               double* out_logdet, void* grad, ld_stats* stats) {
+    const auto t0 = std::chrono::steady_clock::now();
+    const bool want_grad = grad != nullptr;
+    EstimateState S;
+    LD_CHECK(make_plan(lmin, lmax, degree, o, S.plan));
+    S.L = layout_estimate(A, degree, n_matvec, want_grad, o);
+    S.mode = choose_dot_mode(S.plan, o.dot_mode, S.coef);
+    OwnedWs own;
+    Arena ar;
+    LD_CHECK(get_workspace(workspace, ws_bytes, layout_bytes(S.L, want_grad), own, ar));
+    carve(ar, S.L, S);
+    GradBufs B;
+    if (want_grad) {
+        S.L.FX.base = ar.take(S.L.FX.bytes());
+        S.L.Gm.base = ar.take(S.L.Gm.bytes());
+        S.L.T1.base = ar.take(S.L.T1.bytes());
+        B.mask2 = ar.take(S.L.mask);
+        B.Lg = ar.take(S.L.gblk);
+        B.Rg = ar.take(S.L.gblk);
+        B.lam0 = ar.take(S.L.gblk);
+        B.lam1 = ar.take(S.L.gblk);
+        for (int i = 0; i < S.L.nckpt - 1; ++i) B.ckpt.push_back(ar.take(S.L.gblk));
+        for (int i = 0; i < S.L.stride - 1; ++i) B.seg.push_back(ar.take(S.L.gblk));
+    }
+    if (ar.base && ar.used > layout_bytes(S.L, want_grad))
+        return fail(LD_EINVAL, "internal: workspace layout overflow");
+    if (!o.trusted_csr) LD_CHECK(validate_csr(A, S.flag, st));
+    Timer tm(st);
+    tm.mark();
+    LD_CHECK(estimate_front(A, seed, S, st, tm));
+    std::vector<double> nu;
+    LD_CHECK(estimate_dots(A, S, st, nu));
+    tm.mark();
+    // ---- combine (Alg. 3 step 7): n log(sigma) + t_low + t_res
+    const EstLayout& L = S.L;
+    const int ncoef = S.plan.degree + 1;
+    KahanSum tl, tr;
+    for (int col = 0; col < L.nc; ++col)
+        for (int i = 0; i < ncoef; ++i) {
+            const double v = S.coef[i] * nu[(size_t)i * L.nc + col];
+            if (col < L.k)
+                tl.add(v);
+            else
+                tr.add(v);
+        }
+    const double t_low = tl.value(), t_res = tr.value() / L.kg;
+    KahanSum tot;
+    tot.add((double)A->n * std::log(S.plan.sigma));
+    tot.add(t_low);
+    tot.add(t_res);
+    *out_logdet = tot.value();
+    if (want_grad && A->nnz > 0) {
+        LD_CHECK(gradient(A, seed, S, B, grad, st));
+        tm.mark();
+    }
+    LD_CHECK_HIP(hipStreamSynchronize(st));
+    if (stats) {
+        std::memset(stats, 0, sizeof(*stats));
+        stats->ms_phase1 = tm.ms(0, 1);
+        stats->ms_qr = tm.ms(1, 2);
+        stats->ms_phase23 = tm.ms(2, 3);
+        stats->ms_adjoint = want_grad ? tm.ms(3, 4) : 0.0;
+        stats->bytes_alg = S.bytes_alg;
+        stats->taylor_terms = S.plan.taylor_terms;
+        stats->sigma = S.plan.sigma;
+        stats->lo = S.plan.lo;
+        stats->hi = S.plan.hi;
+        stats->k = L.k;
+        stats->k_G = L.kg;
+        stats->dot_mode_used = S.mode;
+        stats->spmm_launches = S.spmm_launches;
+        stats->t_low = t_low;
+        stats->t_res = t_res;
+        stats->ms_steps1 = elapsed(S, 0, 1);
+        stats->ms_steps23 = elapsed(S, 2, 3);
+        stats->launches1 = S.launches1;
+        stats->launches23 = S.launches23;
+        stats->bytes1 = S.bytes1;
+        stats->bytes23 = S.bytes23;
+        stats->ms_total =
+            std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+    }
     return LD_OK;
 }
 
@@ -597,70 +887,10 @@ int ld_logdet_estimate(const ld_csr* A, double lmin, double lmax, int32_t degree
                        int32_t n_matvec, uint64_t seed, const ld_options* opts, void* workspace,
                        size_t ws_bytes, void* stream, double* out_logdet, ld_stats* stats) {
     clear_error();
-    const auto t0 = std::chrono::steady_clock::now();
     if (!out_logdet) return fail(LD_EINVAL, "out_logdet is null");
     LD_CHECK(check_estimate_args(A, lmin, lmax, degree, n_matvec));
-    const ld_options o = resolve(opts);
-    hipStream_t st = (hipStream_t)stream;
-    EstimateState S;
-    LD_CHECK(make_plan(lmin, lmax, degree, o, S.plan));
-    S.L = layout_estimate(A, degree, n_matvec, false, o);
-    S.mode = choose_dot_mode(S.plan, o.dot_mode, S.coef);
-    OwnedWs own;
-    Arena ar;
-    LD_CHECK(get_workspace(workspace, ws_bytes, layout_bytes(S.L, false), own, ar));
-    carve(ar, S.L, S);
-    if (!o.trusted_csr) LD_CHECK(validate_csr(A, S.flag, st));
-    Timer tm(st);
-    tm.mark();
-    LD_CHECK(estimate_front(A, seed, S, st, tm));
-    std::vector<double> nu;
-    LD_CHECK(estimate_dots(A, S, st, nu));
-    tm.mark();
-    // ---- combine (Alg. 3 step 7): n log(sigma) + t_low + t_res
-    const EstLayout& L = S.L;
-    const int ncoef = S.plan.degree + 1;
-    KahanSum tl, tr;
-    for (int col = 0; col < L.nc; ++col)
-        for (int i = 0; i < ncoef; ++i) {
-            const double v = S.coef[i] * nu[(size_t)i * L.nc + col];
-            if (col < L.k)
-                tl.add(v);
-            else
-                tr.add(v);
-        }
-    const double t_low = tl.value(), t_res = tr.value() / L.kg;
-    KahanSum tot;
-    tot.add((double)A->n * std::log(S.plan.sigma));
-    tot.add(t_low);
-    tot.add(t_res);
-    *out_logdet = tot.value();
-    if (stats) {
-        std::memset(stats, 0, sizeof(*stats));
-        stats->ms_phase1 = tm.ms(0, 1);
-        stats->ms_qr = tm.ms(1, 2);
-        stats->ms_phase23 = tm.ms(2, 3);
-        stats->bytes_alg = S.bytes_alg;
-        stats->taylor_terms = S.plan.taylor_terms;
-        stats->sigma = S.plan.sigma;
-        stats->lo = S.plan.lo;
-        stats->hi = S.plan.hi;
-        stats->k = L.k;
-        stats->k_G = L.kg;
-        stats->dot_mode_used = S.mode;
-        stats->spmm_launches = S.spmm_launches;
-        stats->t_low = t_low;
-        stats->t_res = t_res;
-        stats->ms_steps1 = elapsed(S, 0, 1);
-        stats->ms_steps23 = elapsed(S, 2, 3);
-        stats->launches1 = S.launches1;
-        stats->launches23 = S.launches23;
-        stats->bytes1 = S.bytes1;
-        stats->bytes23 = S.bytes23;
-        stats->ms_total =
-            std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
-    }
-    return LD_OK;
+    return run_logdet(A, lmin, lmax, degree, n_matvec, seed, resolve(opts), workspace, ws_bytes,
+                      (hipStream_t)stream, out_logdet, nullptr, stats);
 }
 
 int ld_spectral_bounds(const ld_csr* A, int32_t lanczos_steps, void* stream, double* lmin,
@@ -695,9 +925,11 @@ int ld_logdet_grad(const ld_csr* A, double lmin, double lmax, int32_t degree, in
                    uint64_t seed, const ld_options* opts, void* workspace, size_t ws_bytes,
                    void* stream, double* out_logdet, void* grad_val, ld_stats* stats) {
     clear_error();
-    (void)A; (void)lmin; (void)lmax; (void)degree; (void)n_matvec; (void)seed; (void)opts;
-    (void)workspace; (void)ws_bytes; (void)stream; (void)out_logdet; (void)grad_val; (void)stats;
-    return fail(LD_EINVAL, "gradient entry point not built yet");
+    if (!out_logdet) return fail(LD_EINVAL, "out_logdet is null");
+    LD_CHECK(check_estimate_args(A, lmin, lmax, degree, n_matvec));
+    if (!grad_val && A->nnz > 0) return fail(LD_EINVAL, "grad_val is null");
+    return run_logdet(A, lmin, lmax, degree, n_matvec, seed, resolve(opts), workspace, ws_bytes,
+                      (hipStream_t)stream, out_logdet, grad_val, stats);
 }
 
 }  // extern "C"

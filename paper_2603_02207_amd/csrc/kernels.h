@@ -18,16 +18,20 @@ enum StepKind : int {
 };
 
 // A dense n x cols matrix stored as column blocks of width bw: element
-// (r, c) lives at (c / bw) * bstride + r * ld + c % bw (in elements).  A plain
-// row-major matrix is the single-block case.
+// (r, c) lives at (C / bw) * bstride + r * ld + C % bw (in elements), with
+// C = c + c0 (c0 selects a column range).  A plain row-major matrix is the
+// single-block case.
 struct Blk {
     int ld;
     int bw;
     long long bstride;
+    int c0;
     __host__ __device__ size_t offset(int c) const {
-        return (size_t)(c / bw) * (size_t)bstride + (size_t)(c % bw);
+        const int C = c + c0;
+        return (size_t)(C / bw) * (size_t)bstride + (size_t)(C % bw);
     }
-    static Blk plain(int ld) { return Blk{ld, 1 << 30, 0}; }
+    static Blk plain(int ld, int c0 = 0) { return Blk{ld, 1 << 30, 0, c0}; }
+    Blk shifted(int dc) const { return Blk{ld, bw, bstride, c0 + dc}; }
 };
 
 struct CsrDev {
@@ -67,7 +71,7 @@ hipError_t launch_step(bool f64, const CsrDev& A, const StepArgs& s, hipStream_t
 // Sign mask of stream `key`: bit c of word r = (probe(r, c) == -1), c < k <= 64.
 hipError_t launch_sign_mask(int n, int k, uint64_t key, uint64_t* mask, hipStream_t st);
 
-// out[r, c] = scale * S[r, c + gshift] for c < k, 0 for k <= c < ld.
+// out[r*ld + c] = scale * S[r, c + gshift] for c < k (other columns untouched).
 hipError_t launch_fill_signs(bool f64, int n, int k, int ld, int gshift, const uint64_t* mask,
                              double scale, void* out, hipStream_t st);
 
@@ -87,11 +91,13 @@ hipError_t launch_cross(bool f64, int n, const void* X, Blk bx, int kx, const vo
 hipError_t launch_reduce(const double* part, int nwg, int len, int part_ld, int outer,
                          long long outer_stride, double* out, int out_ld, hipStream_t st);
 
-// out[r, ocol0 + j] = (signs ? S_key[r, j] : 0) + sign_m * sum_i Y[r, i] M[i, j],
-// M k_y x k_out FP64 (device), j < k_out; Y and out column-blocked.
+// out[r, j] = (base ? base[r, j] : 0) + (signs ? S_key[r, j] : 0)
+//             + sign_m * sum_i Y[r, i] M[i, j],
+// M k_y x k_out FP64 (device), j < k_out; Y, base and out column-blocked
+// (base may alias out: each element is read before it is written).
 hipError_t launch_rowmat(bool f64, int n, const void* Y, Blk by, int ky, const double* M, int kout,
-                         double sign_m, bool signs, uint64_t key, void* out, Blk bo, int ocol0,
-                         hipStream_t st);
+                         double sign_m, bool signs, uint64_t key, const void* base, Blk bb,
+                         void* out, Blk bo, hipStream_t st);
 
 // CSR structure check: *flag (device int) set to 1 on any violation.
 hipError_t launch_validate_csr(const CsrDev& A, int* flag, hipStream_t st);
@@ -100,9 +106,9 @@ hipError_t launch_validate_csr(const CsrDev& A, int* flag, hipStream_t st);
 int gersh_num_wg(int n);
 hipError_t launch_gershgorin(bool f64, const CsrDev& A, double* part, hipStream_t st);
 
-// Adjoint step of the reverse sweep:
+// Adjoint step of the reverse sweep (all blocks n x ld row-major, ncols used):
 //   lam_out = alpha*A*lam_in - beta*lam_in + dj*L
-//   grad[nz(r,c)] += alpha * sum_cols lam_in[r,:] * w[c,:]
+//   grad[nz(r,c)] (+)= alpha * sum_cols lam_in[r,:] * w[c,:]
 struct AdjArgs {
     const void* lam_in;
     void* lam_out;

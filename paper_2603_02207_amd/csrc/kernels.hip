@@ -342,16 +342,14 @@ __global__ __launch_bounds__(kThreads) void fill_signs_kernel(int n, int k, int 
                                                               const uint64_t* __restrict__ mask,
                                                               T scale, T* __restrict__ out) {
     const long long i = (long long)blockIdx.x * kThreads + threadIdx.x;
-    if (i >= (long long)n * ld) return;
-    const int r = (int)(i / ld), c = (int)(i - (long long)r * ld);
-    T v = T(0);
-    if (c < k) v = ((mask[r] >> ((c + gshift) & 63)) & 1ull) ? -scale : scale;
-    out[i] = v;
+    if (i >= (long long)n * k) return;
+    const int r = (int)(i / k), c = (int)(i - (long long)r * k);
+    out[(size_t)r * ld + c] = ((mask[r] >> ((c + gshift) & 63)) & 1ull) ? -scale : scale;
 }
 
 hipError_t launch_fill_signs(bool f64, int n, int k, int ld, int gshift, const uint64_t* mask,
                              double scale, void* out, hipStream_t st) {
-    const long long tot = (long long)n * ld;
+    const long long tot = (long long)n * k;
     if (tot == 0) return hipSuccess;
     const int nb = div_up(tot, kThreads);
     if (f64)
@@ -576,15 +574,18 @@ template <typename T, int KY, int KO, bool SIGNS>
 __global__ __launch_bounds__(kThreads) void rowmat_kernel(int n, const T* __restrict__ Y, Blk by,
                                                           int ky, const double* __restrict__ M,
                                                           int kout, double sign_m, uint64_t key,
-                                                          T* __restrict__ out, Blk bo, int ocol0) {
+                                                          const T* base, Blk bb, T* out, Blk bo) {
     __shared__ T ms[KY * KO];
-    __shared__ size_t yoff[KY], ooff[KO];
+    __shared__ size_t yoff[KY], ooff[KO], boff[KO];
     for (int e = threadIdx.x; e < KY * KO; e += kThreads) {
         const int i = e / KO, j = e - i * KO;
         ms[e] = (i < ky && j < kout) ? (T)(sign_m * M[i * kout + j]) : T(0);
     }
     for (int i = threadIdx.x; i < KY; i += kThreads) yoff[i] = i < ky ? by.offset(i) : 0;
-    for (int j = threadIdx.x; j < KO; j += kThreads) ooff[j] = j < kout ? bo.offset(ocol0 + j) : 0;
+    for (int j = threadIdx.x; j < KO; j += kThreads) {
+        ooff[j] = j < kout ? bo.offset(j) : 0;
+        boff[j] = j < kout ? bb.offset(j) : 0;
+    }
     __syncthreads();
     const int row = xcd_tile(blockIdx.x, gridDim.x) * kThreads + threadIdx.x;
     if (row >= n) return;
@@ -600,29 +601,31 @@ __global__ __launch_bounds__(kThreads) void rowmat_kernel(int n, const T* __rest
             const uint64_t x = probe_bits(key, (uint64_t)j * (uint64_t)n + (uint64_t)row + 1ull);
             acc += (x >> 63) ? T(-1) : T(1);
         }
+        if (base) acc += base[boff[j] + (size_t)row * bb.ld];
         out[ooff[j] + (size_t)row * bo.ld] = acc;
     }
 }
 
 template <typename T, int KY, int KO>
 void launch_rowmat_t(int nwg, hipStream_t st, int n, const void* Y, Blk by, int ky, const double* M,
-                     int kout, double sign_m, bool signs, uint64_t key, void* out, Blk bo, int ocol0) {
+                     int kout, double sign_m, bool signs, uint64_t key, const void* base, Blk bb,
+                     void* out, Blk bo) {
     if (signs)
         hipLaunchKernelGGL((rowmat_kernel<T, KY, KO, true>), dim3(nwg), dim3(kThreads), 0, st, n,
-                           (const T*)Y, by, ky, M, kout, sign_m, key, (T*)out, bo, ocol0);
+                           (const T*)Y, by, ky, M, kout, sign_m, key, (const T*)base, bb, (T*)out, bo);
     else
         hipLaunchKernelGGL((rowmat_kernel<T, KY, KO, false>), dim3(nwg), dim3(kThreads), 0, st, n,
-                           (const T*)Y, by, ky, M, kout, sign_m, key, (T*)out, bo, ocol0);
+                           (const T*)Y, by, ky, M, kout, sign_m, key, (const T*)base, bb, (T*)out, bo);
 }
 
 template <typename T>
 hipError_t launch_rowmat_ty(int nwg, hipStream_t st, int n, const void* Y, Blk by, int ky,
                             const double* M, int kout, double sign_m, bool signs, uint64_t key,
-                            void* out, Blk bo, int ocol0) {
+                            const void* base, Blk bb, void* out, Blk bo) {
     const int a = ky <= 16 ? 16 : ky <= 32 ? 32 : 64;
     const int b = kout <= 16 ? 16 : kout <= 32 ? 32 : 64;
 #define LD_RM(A_, B_) \
-    if (a == A_ && b == B_) launch_rowmat_t<T, A_, B_>(nwg, st, n, Y, by, ky, M, kout, sign_m, signs, key, out, bo, ocol0);
+    if (a == A_ && b == B_) launch_rowmat_t<T, A_, B_>(nwg, st, n, Y, by, ky, M, kout, sign_m, signs, key, base, bb, out, bo);
     LD_RM(16, 16) LD_RM(16, 32) LD_RM(16, 64) LD_RM(32, 16) LD_RM(32, 32) LD_RM(32, 64)
     LD_RM(64, 16) LD_RM(64, 32) LD_RM(64, 64)
 #undef LD_RM
@@ -630,13 +633,13 @@ hipError_t launch_rowmat_ty(int nwg, hipStream_t st, int n, const void* Y, Blk b
 }
 
 hipError_t launch_rowmat(bool f64, int n, const void* Y, Blk by, int ky, const double* M, int kout,
-                         double sign_m, bool signs, uint64_t key, void* out, Blk bo, int ocol0,
-                         hipStream_t st) {
+                         double sign_m, bool signs, uint64_t key, const void* base, Blk bb,
+                         void* out, Blk bo, hipStream_t st) {
     if (ky < 1 || kout < 1 || ky > 64 || kout > 64) return hipErrorInvalidValue;
     const int nwg = div_up(n, kThreads);
     if (nwg == 0) return hipSuccess;
-    return f64 ? launch_rowmat_ty<double>(nwg, st, n, Y, by, ky, M, kout, sign_m, signs, key, out, bo, ocol0)
-               : launch_rowmat_ty<float>(nwg, st, n, Y, by, ky, M, kout, sign_m, signs, key, out, bo, ocol0);
+    return f64 ? launch_rowmat_ty<double>(nwg, st, n, Y, by, ky, M, kout, sign_m, signs, key, base, bb, out, bo)
+               : launch_rowmat_ty<float>(nwg, st, n, Y, by, ky, M, kout, sign_m, signs, key, base, bb, out, bo);
 }
 
 // ---------------------------------------------------------------------------
@@ -748,10 +751,14 @@ hipError_t launch_axpby(bool f64, long long len, double a, const void* x, double
 }
 
 // ---------------------------------------------------------------------------
-// adjoint step (reverse sweep of the gradient), one row per row group:
-//   lam_out[r] = alpha * sum_k a_rk lam_in[c_k] - beta lam_in[r] + dj L[r]
-//   grad[k]   (+)= alpha * <lam_in[r, :], w[c_k, :]>
-// A is symmetric, so A^T lam = A lam uses the same CSR rows.
+// Adjoint step of the reverse sweep.  For each stored entry (r, c) of A the
+// derivative of tr(L^T P(T) R) picks up alpha * <lam_{i+1}[r, :], w_i[c, :]>
+// (an SDDMM on A's pattern), and the Horner adjoint moves on:
+//   lam_i = alpha*A*lam_{i+1} - beta_i*lam_{i+1} + d_i L   (A symmetric).
+// Same row-group layout and LDS staging of the CSR slice as the step kernel;
+// the row group is a power of two wide so that the per-entry dot product is
+// a butterfly of lane shuffles.  Each entry's gradient is owned by one lane:
+// no atomics.
 // ---------------------------------------------------------------------------
 template <typename T, int VEC>
 __global__ __launch_bounds__(kThreads) void adjoint_kernel(
@@ -759,54 +766,66 @@ __global__ __launch_bounds__(kThreads) void adjoint_kernel(
     const T* __restrict__ val, const T* __restrict__ lam_in, T* __restrict__ lam_out,
     const T* __restrict__ w, const T* __restrict__ L, T* __restrict__ grad, int ld, int ncols,
     T alpha, T beta, T dj, int first, int last, int lpr, int rpw) {
+    constexpr int kIt = 2;
+    __shared__ int s_rp[kWaves * 64 * kIt + 1];
+    __shared__ int s_col[kStageNz];
+    __shared__ T s_val[kStageNz];
     const int lane = threadIdx.x & 63;
     const int wave = threadIdx.x >> 6;
     const int g = lane / lpr;
     const int li = lane - g * lpr;
-    if (g >= rpw) return;   // whole row groups only; no barriers below
     const int col = li * VEC;
-    const int row = xcd_tile(blockIdx.x, gridDim.x) * (kWaves * rpw) + wave * rpw + g;
-    if (row >= n) return;
+    const int rows_per_wg = kWaves * rpw * kIt;
+    const int R0 = xcd_tile(blockIdx.x, gridDim.x) * rows_per_wg;
+    const int nrows = min(rows_per_wg, n - R0);
+    for (int t = threadIdx.x; t <= nrows; t += kThreads) s_rp[t] = row_ptr[R0 + t];
+    __syncthreads();
+    const int K0 = s_rp[0], K1 = s_rp[nrows];
+    const bool staged = (K1 - K0) <= kStageNz;
+    if (staged)
+        for (int k = K0 + threadIdx.x; k < K1; k += kThreads) {
+            s_col[k - K0] = col_idx[k];
+            s_val[k - K0] = val[k];
+        }
+    __syncthreads();
     bool valid[VEC];
 #pragma unroll
     for (int e = 0; e < VEC; ++e) valid[e] = col + e < ncols;
-    const Pack<T, VEC> lr = load_pack<T, VEC>(lam_in + (size_t)row * ld + col);
-    T acc[VEC];
 #pragma unroll
-    for (int e = 0; e < VEC; ++e) acc[e] = T(0);
-    const int beg = row_ptr[row], end = row_ptr[row + 1];
-    for (int k = beg; k < end; ++k) {
-        const int c = col_idx[k];
-        const T a = val[k];
-        // SDDMM term: <lam_in[row], w[c]> over all columns (row-group reduction)
-        const Pack<T, VEC> wc = load_pack<T, VEC>(w + (size_t)c * ld + col);
-        T part = T(0);
+    for (int it = 0; it < kIt; ++it) {
+        const int lr = (it * kWaves + wave) * rpw + g;
+        if (lr >= nrows) continue;               // whole row groups leave together
+        const int row = R0 + lr;
+        const Pack<T, VEC> lr_v = load_pack<T, VEC>(lam_in + (size_t)row * ld + col);
+        T acc[VEC];
 #pragma unroll
-        for (int e = 0; e < VEC; ++e) part = valid[e] ? fma(lr.v[e], wc.v[e], part) : part;
-        // reduce over the lpr lanes of this row group with shuffles
-        for (int off = 1; off < lpr; off <<= 1) {
-            const T other = __shfl_xor(part, off, 64);
-            // lanes whose partner lies outside the row group keep their value
-            const int partner = li ^ off;
-            part = (partner < lpr) ? part + other : part;
+        for (int e = 0; e < VEC; ++e) acc[e] = T(0);
+        const int beg = s_rp[lr], end = s_rp[lr + 1];
+        for (int k = beg; k < end; ++k) {
+            const int c = staged ? s_col[k - K0] : col_idx[k];
+            const T a = staged ? s_val[k - K0] : val[k];
+            const Pack<T, VEC> wc = load_pack<T, VEC>(w + (size_t)c * ld + col);
+            T part = T(0);
+#pragma unroll
+            for (int e = 0; e < VEC; ++e) part = valid[e] ? fma(lr_v.v[e], wc.v[e], part) : part;
+            for (int off = 1; off < lpr; off <<= 1) part += __shfl_xor(part, off, 64);
+            if (!last) {
+                const Pack<T, VEC> lc = load_pack<T, VEC>(lam_in + (size_t)c * ld + col);
+#pragma unroll
+                for (int e = 0; e < VEC; ++e) acc[e] = fma(a, lc.v[e], acc[e]);
+            }
+            if (li == 0) {
+                const T gv = alpha * part;
+                grad[k] = first ? gv : grad[k] + gv;
+            }
         }
         if (!last) {
-            const Pack<T, VEC> lc = load_pack<T, VEC>(lam_in + (size_t)c * ld + col);
+            const Pack<T, VEC> Lr = load_pack<T, VEC>(L + (size_t)row * ld + col);
+            Pack<T, VEC> o;
 #pragma unroll
-            for (int e = 0; e < VEC; ++e) acc[e] = fma(a, lc.v[e], acc[e]);
+            for (int e = 0; e < VEC; ++e) o.v[e] = fma(dj, Lr.v[e], alpha * acc[e] - beta * lr_v.v[e]);
+            store_pack<T, VEC>(lam_out + (size_t)row * ld + col, o);
         }
-        if (li == 0) {
-            const T gv = alpha * part;
-            grad[k] = first ? gv : grad[k] + gv;
-        }
-    }
-    if (!last) {
-        const Pack<T, VEC> Lr = load_pack<T, VEC>(L + (size_t)row * ld + col);
-        Pack<T, VEC> o;
-#pragma unroll
-        for (int e = 0; e < VEC; ++e)
-            o.v[e] = valid[e] ? fma(dj, Lr.v[e], alpha * acc[e] - beta * lr.v[e]) : T(0);
-        store_pack<T, VEC>(lam_out + (size_t)row * ld + col, o);
     }
 }
 
@@ -816,11 +835,14 @@ hipError_t launch_adjoint(bool f64, const CsrDev& A, const AdjArgs& a, hipStream
     while (vec > 1 && (a.ld % vec)) vec /= 2;
     const int lpr = lanes_per_row(a.ncols, vec);
     if (lpr > 64) return hipErrorInvalidValue;
-    // the shuffle reduction needs the row group to be a power of two wide
-    int lp2 = 1;
+    int lp2 = 1;                       // the shuffle butterfly needs a power of two
     while (lp2 < lpr) lp2 <<= 1;
+    if (lp2 * vec > a.ld && lp2 > 1) {
+        // lanes past the row's end would read beyond it: only allowed when ld covers them
+        return hipErrorInvalidValue;
+    }
     const int rpw = 64 / lp2;
-    const int nwg = div_up(A.n, kWaves * rpw);
+    const int nwg = div_up(A.n, kWaves * rpw * 2);
     if (nwg == 0) return hipSuccess;
 #define LD_ADJ(T, V)                                                                              \
     hipLaunchKernelGGL((adjoint_kernel<T, V>), dim3(nwg), dim3(kThreads), 0, st, A.n, A.row_ptr, \

@@ -1,0 +1,126 @@
+"""GPU parity of the gradient entry point against the oracle's exact derivative.
+
+The oracle's derivative (oracle/grad.py) is itself pinned to finite
+differences of the FP64 estimate; here the HIP reverse sweep is compared
+entry by entry, and the GMRF hyperparameter chain rule is checked through
+torch.autograd.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import workloads as w
+from oracle import bounds, grad as ograd, hutchpp
+from tests.gpu_common import random_spd_csr
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():  # pragma: no cover
+    pytest.skip("no GPU", allow_module_level=True)
+
+import paper_2603_02207_amd as ld  # noqa: E402
+
+DEV = "cuda:0"
+
+
+def to_gpu(csr, dtype):
+    row_ptr, col_idx, val, n = csr
+    vals = np.asarray(val, dtype=np.float32 if dtype == torch.float32 else np.float64)
+    return ld.CSR.from_arrays(row_ptr, col_idx, vals, n, device=DEV, dtype=dtype), vals.astype(np.float64)
+
+
+@pytest.mark.parametrize("m_vec,degree,stride", [(12, 20, 0), (30, 40, 1), (30, 40, 7), (9, 13, 5)])
+def test_grad_small_grid_fp64(m_vec, degree, stride):
+    csr = w.grid_laplacian_2d(9, 0.5)
+    A, vals = to_gpu(csr, torch.float64)
+    est, g = ld.logdet_with_grad(A, 0.5, 8.5, degree, m_vec, 3, options=ld.Options(ckpt_stride=stride))
+    ref_est, ref_g = ograd.logdet_grad((csr[0], csr[1], vals, csr[3]), 0.5, 8.5, degree, m_vec, 3)
+    assert est == pytest.approx(ref_est, rel=1e-11)
+    g = g.cpu().numpy()
+    assert np.max(np.abs(g - ref_g)) < 1e-9 * np.max(np.abs(ref_g))
+
+
+@pytest.mark.parametrize("dtype,tol", [(torch.float64, 1e-9), (torch.float32, 2e-4)])
+def test_grad_irregular(dtype, tol):
+    csr = random_spd_csr(300, 5, long_rows=2)
+    A, vals = to_gpu(csr, dtype)
+    csr_v = (csr[0], csr[1], vals, csr[3])
+    lmin, lmax = bounds.gershgorin(csr_v)
+    est, g = ld.logdet_with_grad(A, lmin, lmax, 30, 21, 1)
+    ref_est, ref_g = ograd.logdet_grad(csr_v, lmin, lmax, 30, 21, 1)
+    assert abs(est - ref_est) / abs(ref_est) < (1e-10 if dtype == torch.float64 else 1e-5)
+    g = g.double().cpu().numpy()
+    assert np.linalg.norm(g - ref_g) / np.linalg.norm(ref_g) < tol
+
+
+def test_grad_fp32_grid32():
+    csr = w.grid_laplacian_2d(32, 0.5)
+    A, vals = to_gpu(csr, torch.float32)
+    est, g = ld.logdet_with_grad(A, 0.5, 8.5, 40, 30, 0)
+    ref_est, ref_g = ograd.logdet_grad((csr[0], csr[1], vals, csr[3]), 0.5, 8.5, 40, 30, 0)
+    assert abs(est - ref_est) / abs(ref_est) < 1e-5
+    g = g.double().cpu().numpy()
+    assert np.linalg.norm(g - ref_g) / np.linalg.norm(ref_g) < 1e-4
+
+
+def gmrf_values(kappa, tau, csr):
+    """Values of tau*(kappa^2 I + L) on the grid pattern as a differentiable function."""
+    row_ptr, col_idx, val, n = csr
+    rows = np.repeat(np.arange(n), np.diff(row_ptr))
+    diag = torch.tensor(rows == col_idx, device=DEV)
+    lap = torch.tensor(np.where(rows == col_idx, 4.0, -1.0), device=DEV, dtype=torch.float64)
+    return tau * (lap + kappa ** 2 * diag.to(torch.float64))
+
+
+def test_autograd_gmrf_hyperparameters():
+    N = 12
+    csr = w.grid_laplacian_2d(N, 0.1, tau=1.5)
+    A, vals = to_gpu(csr, torch.float64)
+    kappa = torch.tensor(math.sqrt(0.1), dtype=torch.float64, device=DEV, requires_grad=True)
+    tau = torch.tensor(1.5, dtype=torch.float64, device=DEV, requires_grad=True)
+    lmin, lmax = 1.5 * 0.1 * 0.999, 1.5 * 8.1
+    v = gmrf_values(kappa, tau, csr)
+    est = ld.logdet_autograd(v, A, lmin, lmax, 40, 30, 2)
+    est.backward()
+
+    def f(kk, tt):
+        B = w.grid_laplacian_2d(N, kk * kk, tau=tt)
+        return hutchpp.logdet_estimate(w.to_scipy(B), lmin, lmax, 40, 30, 2)
+
+    h = 1e-6
+    k0 = math.sqrt(0.1)
+    fd_k = (f(k0 + h, 1.5) - f(k0 - h, 1.5)) / (2 * h)
+    fd_t = (f(k0, 1.5 + h) - f(k0, 1.5 - h)) / (2 * h)
+    assert kappa.grad.item() == pytest.approx(fd_k, rel=1e-6)
+    assert tau.grad.item() == pytest.approx(fd_t, rel=1e-6)
+
+
+def test_grad_gmrf2048_finite_difference_full_size():
+    """2048 x 2048 GMRF, degree 100, 32 probes: adjoint vs central FD in tau (FP64 bulk)."""
+    N, k2, tau, deg, mv = 2048, 0.1, 1.5, 100, 32
+    csr = w.grid_laplacian_2d(N, k2, tau=tau)
+    A, vals = to_gpu(csr, torch.float64)
+    lmin, lmax = tau * k2 * 0.999, tau * (k2 + 8.0)
+    est, g = ld.logdet_with_grad(A, lmin, lmax, deg, mv, 0)
+    d_tau = float((g * A.val).sum().item()) / tau
+    h = 1e-5 * tau
+    ep = ld.logdet(A.with_values(A.val * ((tau + h) / tau)), lmin, lmax, deg, mv, 0)
+    em = ld.logdet(A.with_values(A.val * ((tau - h) / tau)), lmin, lmax, deg, mv, 0)
+    fd = (ep - em) / (2 * h)
+    assert d_tau == pytest.approx(fd, rel=1e-6)
+    # diagonal direction (kappa): d/dkappa = 2 kappa tau sum_diag grad
+    row_ptr, col_idx = csr[0], csr[1]
+    rows = np.repeat(np.arange(csr[3]), np.diff(row_ptr))
+    diag = torch.tensor(rows == col_idx, device=DEV)
+    kap = math.sqrt(k2)
+    d_kap = 2 * kap * tau * float(g[diag].sum().item())
+    hk = 1e-6
+
+    def at_kappa(kk):
+        return ld.logdet(A.with_values(torch.where(diag, A.val + tau * (kk * kk - k2), A.val)), lmin, lmax,
+                         deg, mv, 0)
+
+    fdk = (at_kappa(kap + hk) - at_kappa(kap - hk)) / (2 * hk)
+    assert d_kap == pytest.approx(fdk, rel=1e-5)
