@@ -40,7 +40,25 @@ def parse():
     p.add_argument("--dot-mode", choices=["auto", "forward", "squared"], default="auto")
     p.add_argument("--no-fp64", action="store_true")
     p.add_argument("--no-cpu-baseline", action="store_true")
+    p.add_argument("--calibrate-copy", action="store_true",
+                   help="only run a 1 GiB device-to-device copy (reference for the memory counters)")
     return p.parse_args()
+
+
+def calibrate_copy():
+    """A plain copy of known size: the yardstick for the FETCH_SIZE/WRITE_SIZE counters."""
+    import torch
+
+    src = torch.ones(1 << 28, dtype=torch.float32, device="cuda:0")   # 1 GiB
+    dst = torch.empty_like(src)
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    for _ in range(5):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t) / 5
+    print(json.dumps({"copy_bytes_read": src.numel() * 4, "copy_bytes_written": dst.numel() * 4,
+                      "GBps": 2 * src.numel() * 4 / dt / 1e9}), flush=True)
 
 
 def describe(name, cfg, n, nnz):
@@ -103,6 +121,9 @@ def cpu_baseline(csr, lmin, lmax, degree, m_vec, seed):
 
 def main():
     args = parse()
+    if args.calibrate_copy:
+        calibrate_copy()
+        return
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
         print("bench.py: this build runs on exactly one GPU; --gpus must be 1 "

@@ -114,6 +114,7 @@ int validate_csr(const ld_csr* A, int* dflag, hipStream_t st) {
 // ---------------------------------------------------------------------------
 constexpr double kMallBudget = 240e6;
 constexpr int kSmallSlots = 10;   // k x k (<= 64 x 64) FP64 scratch matrices
+constexpr int kMaxDotBlock = 64;  // widest column block of the quadratic-form launches
 
 double matrix_bytes(const ld_csr* A, size_t elem) {
     return (double)A->nnz * (double)(elem + 4) + 4.0 * (double)(A->n + 1);
@@ -180,7 +181,12 @@ EstLayout layout_estimate(const ld_csr* A, int degree, int n_matvec, bool grad,
     L.kg = n_matvec - 2 * L.k;
     L.nc = L.k + L.kg;
     const int bw1 = choose_block_width(A, L.elem, L.k, o.block_cols);
-    const int bw23 = choose_block_width(A, L.elem, L.nc, o.block_cols);
+    int bw23 = choose_block_width(A, L.elem, L.nc, o.block_cols);
+    if (bw23 > kMaxDotBlock) {   // the column-sum kernels take at most 64 columns per launch
+        const int v = 16 / (int)L.elem, nb = (bw23 + kMaxDotBlock - 1) / kMaxDotBlock;
+        bw23 = ((L.nc + nb - 1) / nb + v - 1) / v * v;
+        while (bw23 > kMaxDotBlock) bw23 -= v;
+    }
     L.Y = make_blk(n, L.k, bw1, L.elem);
     L.Q1 = make_blk(n, L.k, bw1, L.elem);
     L.X = make_blk(n, L.nc, bw23, L.elem);
@@ -189,8 +195,9 @@ EstLayout layout_estimate(const ld_csr* A, int degree, int n_matvec, bool grad,
     L.nwg_dot = step_num_wg_bound((int)n, L.X.bw, (int)L.elem);
     L.mask = (size_t)n * 8;
     L.W = (size_t)n * ldmax * L.elem;
-    const size_t cross = (size_t)cross_num_wg((int)n) * 64 * 64 * 8;
-    const size_t dotp = (size_t)L.nslots * L.nwg_dot * L.nc * 8;
+    const int kmax = std::max(L.k, L.kg);
+    const size_t cross = (size_t)cross_num_wg((int)n) * kmax * kmax * 8;
+    const size_t dotp = (size_t)L.X.nblocks() * L.nslots * L.nwg_dot * L.X.bw * 8;
     L.part = std::max(cross, dotp);
     L.small = (size_t)kSmallSlots * 64 * 64 * 8;
     L.nu = (size_t)L.nslots * L.nc * 8;
@@ -430,11 +437,13 @@ int estimate_dots(const ld_csr* A, EstimateState& S, hipStream_t st, std::vector
     const EstLayout& L = S.L;
     const BlkMat& X = L.X;
     const int m = p.degree;
-    const size_t slot_stride = (size_t)L.nwg_dot * L.nc;
     const int nslots = S.mode == LD_DOT_SQUARED ? 2 * ((m + 1) / 2) + 1 : m + 1;
+    // partial sums of block b: its own region [slot][workgroup][column of the block]
+    const size_t slot_stride = (size_t)L.nwg_dot * X.bw;
     LD_CHECK(record(S, 2, st));
     for (int b = 0; b < X.nblocks(); ++b) {
         const int cols = X.bcols(b), gcol = b * X.bw;
+        double* const part = S.part + (size_t)b * nslots * slot_stride;
         int nwg = 0;
         if (S.mode == LD_DOT_SQUARED) {
             const int h = (m + 1) / 2;
@@ -448,13 +457,12 @@ int estimate_dots(const ld_csr* A, EstimateState& S, hipStream_t st, std::vector
                 s.win = cur;
                 s.wout = nxt;
                 s.ld = X.ld;
-                s.gshift = gcol;
                 s.alpha = p.alpha;
                 s.beta = p.beta[a];
-                s.ps0 = S.part;
-                s.ps1 = S.part + (size_t)(2 * a + 1) * slot_stride;
-                s.ps2 = S.part + (size_t)(2 * a + 2) * slot_stride;
-                s.part_ld = L.nc;
+                s.ps0 = part;
+                s.ps1 = part + (size_t)(2 * a + 1) * slot_stride;
+                s.ps2 = part + (size_t)(2 * a + 2) * slot_stride;
+                s.part_ld = X.bw;
                 LD_CHECK(run_step(f64, A, s, cols, cols, st, &nwg));
                 S.launches23 += 1;
                 S.bytes23 += alg_bytes_step(A, cols, STEP_DOT_SQ, L.elem);
@@ -470,14 +478,13 @@ int estimate_dots(const ld_csr* A, EstimateState& S, hipStream_t st, std::vector
                 s.win = cur;
                 s.wout = pp[j % 2];
                 s.ld = X.ld;
-                s.gshift = gcol;
                 s.alpha = p.alpha;
                 s.beta = p.beta[j];
                 s.vsrc = X.block(b);
                 s.ldv = X.ld;
-                s.ps0 = S.part;
-                s.ps1 = S.part + (size_t)(j + 1) * slot_stride;
-                s.part_ld = L.nc;
+                s.ps0 = part;
+                s.ps1 = part + (size_t)(j + 1) * slot_stride;
+                s.part_ld = X.bw;
                 LD_CHECK(run_step(f64, A, s, cols, cols, st, &nwg));
                 S.launches23 += 1;
                 S.bytes23 += alg_bytes_step(A, cols, STEP_DOT_FWD, L.elem);
@@ -485,8 +492,8 @@ int estimate_dots(const ld_csr* A, EstimateState& S, hipStream_t st, std::vector
             }
         }
         if (nwg > L.nwg_dot) return fail(LD_EINVAL, "internal: dot partials overflow");
-        LD_CHECK_HIP(launch_reduce(S.part + gcol, nwg, cols, L.nc, nslots, (long long)slot_stride,
-                                   S.nu + gcol, L.nc, st));
+        LD_CHECK_HIP(launch_reduce(part, nwg, cols, X.bw, nslots, (long long)slot_stride, S.nu + gcol,
+                                   L.nc, st));
     }
     LD_CHECK(record(S, 3, st));
     S.spmm_launches += S.launches23;

@@ -68,40 +68,46 @@ int div_up(long long a, long long b) { return (int)((a + b - 1) / b); }
 inline int lanes_per_row(int bcols, int vec) { return (bcols + vec - 1) / vec; }
 
 constexpr int kStepIters = 2;      // row groups per wave and launch
-constexpr int kDotIters = 4;       // the same for the kinds with column sums (amortises the sum)
-constexpr int kStageNz = 1536;     // CSR entries a workgroup stages in LDS
+constexpr int kWaveNz = 384;       // CSR entries one wave stages in LDS
+constexpr int kStageNz = 1536;     // CSR entries one workgroup stages (adjoint kernel)
+constexpr int kMaxDotCols = 64;    // columns of one launch of the kinds with column sums
 
-constexpr int iters_of(int kind) {
-    return (kind == STEP_DOT_FWD || kind == STEP_DOT_SQ) ? kDotIters : kStepIters;
-}
-inline int step_iters(int kind) { return iters_of(kind); }
+constexpr bool is_dot(int kind) { return kind == STEP_DOT_FWD || kind == STEP_DOT_SQ; }
+constexpr int threads_of(int) { return 256; }
 
 // ---------------------------------------------------------------------------
 // Newton step: out = alpha*A*in - beta*in (+ dj*source), optional dot partials.
 //
-// A workgroup owns rows [R0, R0 + 4*rpw*ITERS).  It first stages its slice of
-// row_ptr and, when it fits, its col_idx/val entries in LDS with coalesced
-// loads; each row group then reads its row's entries from LDS (one address per
-// row group, a broadcast) and issues up to eight gathers before the first FMA.
-// Slices with more than kStageNz entries (long rows) read the CSR arrays
-// directly.  Global column of local column c: c + gshift (probe signs and
-// partial sums use it).
+// Wave w of a workgroup owns the contiguous rows R0 + w*rpw*ITERS + [0,
+// rpw*ITERS).  Each wave stages its own slice of row_ptr and, when it fits,
+// of col_idx/val in LDS (coalesced loads, no workgroup barrier); each row
+// group then reads its row's entries from LDS (one address per row group, a
+// broadcast) and issues the gathers.  Slices with more than kWaveNz entries
+// (long rows) read the CSR arrays directly.
+//
+// Column sums (dot kinds): each wave reduces its row groups through its own
+// LDS region, stores its column sums, and bumps an LDS counter; the last wave
+// to arrive adds the NW wave sums in wave order and writes the workgroup's
+// partial row.  No wave ever waits at a barrier, and the order of every
+// addition is fixed.  Global column of local column c: c + gshift.
 // ---------------------------------------------------------------------------
-template <typename T, int VEC, int KIND, bool FIRST, int ITERS>
-__global__ __launch_bounds__(kThreads) void step_kernel(
+template <typename T, int VEC, int KIND, bool FIRST, int ITERS, int NT>
+__global__ __launch_bounds__(NT) void step_kernel(
     int n, const int* __restrict__ row_ptr, const int* __restrict__ col_idx,
     const T* __restrict__ val, const T* __restrict__ win, T* __restrict__ wout, int ld, int c0,
     int bcols, int gshift, T alpha, T beta, T dj, const T* __restrict__ vsrc, int ldv,
     const uint64_t* __restrict__ mask, double* __restrict__ ps0, double* __restrict__ ps1,
     double* __restrict__ ps2, int part_ld, int lpr, int rpw) {
-    constexpr bool kDot = (KIND == STEP_DOT_FWD || KIND == STEP_DOT_SQ);
-    constexpr int kValBytes = kStageNz * (int)sizeof(T);
-    constexpr int kRedBytes = kDot ? kThreads * (VEC + 1) * 8 : 0;
-    constexpr int kPool = (kValBytes + kStageNz * 4) > kRedBytes ? (kValBytes + kStageNz * 4) : kRedBytes;
-    __shared__ int s_rp[kWaves * 64 * ITERS + 1];
-    __shared__ __align__(16) unsigned char s_pool[kPool];
-    T* const s_val = reinterpret_cast<T*>(s_pool);
-    int* const s_col = reinterpret_cast<int*>(s_pool + kValBytes);
+    constexpr bool kDot = is_dot(KIND);
+    constexpr int NW = NT / 64;
+    constexpr int kSums = kDot ? ((FIRST ? 1 : 0) + 1 + (KIND == STEP_DOT_SQ ? 1 : 0)) : 0;
+    constexpr int kStageBytes = kWaveNz * (int)(sizeof(T) + 4);
+    constexpr int kLaneBytes = 64 * VEC * 8;                  // per-lane sums of one wave
+    constexpr int kWaveBytes = kStageBytes > kLaneBytes ? kStageBytes : kLaneBytes;
+    __shared__ int s_rp[NW][64 * ITERS + 1];
+    __shared__ __align__(16) unsigned char s_wave[NW][kWaveBytes];
+    __shared__ double s_cols[kDot ? NW * kSums * kMaxDotCols : 1];
+    __shared__ unsigned s_count;
 
     const int lane = threadIdx.x & 63;
     const int wave = threadIdx.x >> 6;
@@ -109,32 +115,44 @@ __global__ __launch_bounds__(kThreads) void step_kernel(
     const int li = lane - g * lpr;
     const bool lane_ok = g < rpw;
     const int col = c0 + li * VEC;
-    const int rows_per_wg = kWaves * rpw * ITERS;
-    const int R0 = xcd_tile(blockIdx.x, gridDim.x) * rows_per_wg;
-    const int nrows = min(rows_per_wg, n - R0);
+    const int rows_per_wave = rpw * ITERS;
+    const int R0 = xcd_tile(blockIdx.x, gridDim.x) * (NW * rows_per_wave);
+    const int W0 = R0 + wave * rows_per_wave;             // first row of this wave
+    const int nrows = max(0, min(rows_per_wave, n - W0));
+    if constexpr (kDot) {
+        if (threadIdx.x == 0) s_count = 0;
+        __syncthreads();   // the only workgroup barrier: the counter is set before any wave can finish
+    }
 
-    for (int t = threadIdx.x; t <= nrows; t += kThreads) s_rp[t] = row_ptr[R0 + t];
-    __syncthreads();
-    const int K0 = s_rp[0];
-    const int K1 = s_rp[nrows];
-    const bool staged = (K1 - K0) <= kStageNz;
+    T* const s_val = reinterpret_cast<T*>(s_wave[wave]);
+    int* const s_col = reinterpret_cast<int*>(s_wave[wave] + kWaveNz * sizeof(T));
+    int* const rp = s_rp[wave];
+    if (nrows > 0)   // waves past the last row read nothing
+        for (int t = lane; t <= nrows; t += 64) rp[t] = row_ptr[W0 + t];
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    const int K0 = nrows > 0 ? rp[0] : 0;
+    const int K1 = nrows > 0 ? rp[nrows] : 0;
+    const bool staged = (K1 - K0) <= kWaveNz;
     if (staged) {
-        for (int k = K0 + threadIdx.x; k < K1; k += kThreads) {
+        for (int k = K0 + lane; k < K1; k += 64) {
             s_col[k - K0] = col_idx[k];
             s_val[k - K0] = val[k];
         }
     }
-    __syncthreads();
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
 
     double s0[VEC], s1[VEC], s2[VEC];
 #pragma unroll
     for (int e = 0; e < VEC; ++e) s0[e] = s1[e] = s2[e] = 0.0;
+
 #pragma unroll
     for (int it = 0; it < ITERS; ++it) {
-        const int lr = (it * kWaves + wave) * rpw + g;
+        const int lr = it * rpw + g;
         if (!lane_ok || lr >= nrows) continue;
-        const int row = R0 + lr;
-        const int beg = s_rp[lr], end = s_rp[lr + 1];
+        const int row = W0 + lr;
+        const int beg = rp[lr], end = rp[lr + 1];
         T acc[VEC];
 #pragma unroll
         for (int e = 0; e < VEC; ++e) acc[e] = T(0);
@@ -206,52 +224,59 @@ __global__ __launch_bounds__(kThreads) void step_kernel(
     }
 
     if constexpr (kDot) {
-        // Column sums over the workgroup's rows, in a fixed order.  The staged
-        // CSR slice is dead: its LDS holds the per-lane partials (red) and a
-        // second level of per-column partial sums (red2).
-        double* const red = reinterpret_cast<double*>(s_pool);
-        double* const red2 = red + kThreads * VEC;
-        const int groups = kWaves * rpw;                   // row groups of the workgroup
-        const int split = max(1, min(kThreads / max(bcols, 1), groups));
-        auto column_sums = [&](const double (&sum)[VEC], double* __restrict__ out) __attribute__((always_inline)) {
-            __syncthreads();
+        // 1) per wave: the row groups' sums of each column, in group order
+        double* const lanes = reinterpret_cast<double*>(s_wave[wave]);   // staging is dead
+        int q = 0;
+        auto wave_sum = [&](const double (&v)[VEC]) __attribute__((always_inline)) {
 #pragma unroll
-            for (int e = 0; e < VEC; ++e) red[threadIdx.x * VEC + e] = sum[e];
-            __syncthreads();
-            // level 1: thread (t, p) adds the row groups p, p+split, ... of column t
-            if (threadIdx.x < bcols * split) {
-                const int t = threadIdx.x % bcols, p = threadIdx.x / bcols;
+            for (int e = 0; e < VEC; ++e) lanes[lane * VEC + e] = v[e];
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            for (int t = lane; t < bcols; t += 64) {
                 const int tl = t / VEC, te = t - tl * VEC;
                 double acc = 0.0;
-                for (int gi = p; gi < groups; gi += split) {
-                    const int wv = gi / rpw, gg = gi - wv * rpw;
-                    acc += red[(wv * 64 + gg * lpr + tl) * VEC + te];
-                }
-                red2[p * bcols + t] = acc;
+                for (int gg = 0; gg < rpw; ++gg) acc += lanes[(gg * lpr + tl) * VEC + te];
+                s_cols[(wave * kSums + q) * kMaxDotCols + t] = acc;
             }
-            __syncthreads();
-            // level 2: one thread per column adds the split partials in order
-            for (int t = threadIdx.x; t < bcols; t += kThreads) {
-                double acc = 0.0;
-                for (int p = 0; p < split; ++p) acc += red2[p * bcols + t];
-                out[(size_t)blockIdx.x * part_ld + c0 + gshift + t] = acc;
-            }
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            ++q;
         };
-        if constexpr (FIRST) column_sums(s0, ps0);
-        column_sums(s1, ps1);
-        if constexpr (KIND == STEP_DOT_SQ) column_sums(s2, ps2);
+        if constexpr (FIRST) wave_sum(s0);
+        wave_sum(s1);
+        if constexpr (KIND == STEP_DOT_SQ) wave_sum(s2);
+        // 2) the last wave of the workgroup to get here adds the wave sums in
+        //    wave order and writes the workgroup's partial row
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+        unsigned ticket = 0;
+        if (lane == 0) ticket = atomicAdd(&s_count, 1u);
+        ticket = __shfl(ticket, 0, 64);
+        if (ticket == NW - 1) {
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+            double* const outs[3] = {FIRST ? ps0 : ps1, FIRST ? ps1 : ps2, ps2};
+            for (int t = lane; t < kSums * bcols; t += 64) {
+                const int qq = t / bcols, cc = t - qq * bcols;
+                double acc = 0.0;
+#pragma unroll
+                for (int wv = 0; wv < NW; ++wv) acc += s_cols[(wv * kSums + qq) * kMaxDotCols + cc];
+                double* const dst = qq == 0 ? outs[0] : (qq == 1 ? outs[1] : outs[2]);
+                dst[(size_t)blockIdx.x * part_ld + c0 + gshift + cc] = acc;
+            }
+        }
     }
 }
 
 template <typename T, int VEC, int KIND, bool FIRST>
 hipError_t launch_step_t(const CsrDev& A, const StepArgs& s, hipStream_t st) {
-    constexpr int kIters = iters_of(KIND);
+    constexpr int kIters = kStepIters;
+    constexpr int NT = threads_of(KIND);
+    if (is_dot(KIND) && s.bcols > kMaxDotCols) return hipErrorInvalidValue;
     const int lpr = lanes_per_row(s.bcols, VEC);
     const int rpw = 64 / lpr;
-    const int rows_per_wg = kWaves * rpw * kIters;
+    const int rows_per_wg = (NT / 64) * rpw * kIters;
     const int nwg = div_up(A.n, rows_per_wg);
     if (nwg == 0) return hipSuccess;
-    hipLaunchKernelGGL((step_kernel<T, VEC, KIND, FIRST, kIters>), dim3(nwg), dim3(kThreads), 0, st,
+    hipLaunchKernelGGL((step_kernel<T, VEC, KIND, FIRST, kIters, NT>), dim3(nwg), dim3(NT), 0, st,
                        A.n, A.row_ptr, A.col_idx, (const T*)A.val, (const T*)s.win, (T*)s.wout, s.ld,
                        s.c0, s.bcols, s.gshift, (T)s.alpha, (T)s.beta, (T)s.dj, (const T*)s.vsrc,
                        s.ldv, s.mask, s.ps0, s.ps1, s.ps2, s.part_ld, lpr, rpw);
@@ -293,14 +318,13 @@ inline int pick_vec(const StepArgs& s, int elem_bytes) {
 
 int step_num_wg_bound(int n, int bcols, int elem_bytes) {
     // blocks aligned to the 16-byte vector (the estimator's internal layout)
-    const int rows = kWaves * (64 / lanes_per_row(bcols, 16 / elem_bytes)) *
-                     (kStepIters < kDotIters ? kStepIters : kDotIters);
+    const int rows = (threads_of(STEP_PLAIN) / 64) * (64 / lanes_per_row(bcols, 16 / elem_bytes)) * kStepIters;
     return div_up(n, rows);
 }
 
 int step_num_wg(bool f64, int n, const StepArgs& s) {
     const int vec = pick_vec(s, f64 ? 8 : 4);
-    const int rows = kWaves * (64 / lanes_per_row(s.bcols, vec)) * step_iters(s.kind);
+    const int rows = (threads_of(s.kind) / 64) * (64 / lanes_per_row(s.bcols, vec)) * kStepIters;
     return div_up(n, rows);
 }
 
@@ -393,7 +417,7 @@ hipError_t launch_scale_copy(bool f64, int n, int ncols, const void* V, int ldv,
 // A = X^T and B = Z over a chunk of 4 rows, lane l simply loads
 // X[r0 + l/16][16*t + l%16].
 // ---------------------------------------------------------------------------
-constexpr int kCrossRows = 1024;   // rows per workgroup
+constexpr int kCrossRows = 256;    // rows per workgroup
 
 typedef double double4_t __attribute__((ext_vector_type(4)));
 
@@ -419,34 +443,40 @@ __global__ __launch_bounds__(kThreads) void cross_kernel(int n, const T* __restr
     for (int a = 0; a < TX; ++a) xoff[a] = bx.offset(a * 16 + cit);
 #pragma unroll
     for (int b = 0; b < TZ; ++b) zoff[b] = ZSIGNS ? 0 : bz.offset(b * 16 + cit);
-    for (int r0 = row0 + wave * 4; r0 < row0 + kCrossRows && r0 < n; r0 += kWaves * 4) {
-        const int r = r0 + sub;
-        const bool rok = r < n;
-        double xa[TX], zb[TZ];
+    // each wave takes chunks of 4 rows; two chunks are loaded before their MFMAs
+    for (int r0 = row0 + wave * 8; r0 < row0 + kCrossRows && r0 < n; r0 += kWaves * 8) {
+        double xa[2][TX], zb[2][TZ];
 #pragma unroll
-        for (int a = 0; a < TX; ++a) {
-            const int c = a * 16 + cit;
-            xa[a] = (rok && c < kx) ? (double)X[xoff[a] + (size_t)r * bx.ld] : 0.0;
-        }
+        for (int h = 0; h < 2; ++h) {
+            const int r = r0 + 4 * h + sub;
+            const bool rok = r < n;
 #pragma unroll
-        for (int b = 0; b < TZ; ++b) {
-            const int c = b * 16 + cit;
-            double z = 0.0;
-            if (rok && c < kz) {
-                if constexpr (ZSIGNS) {
-                    const uint64_t x = probe_bits(key, (uint64_t)c * (uint64_t)n + (uint64_t)r + 1ull);
-                    z = (x >> 63) ? -1.0 : 1.0;
-                } else {
-                    z = (double)Z[zoff[b] + (size_t)r * bz.ld];
-                }
+            for (int a = 0; a < TX; ++a) {
+                const int c = a * 16 + cit;
+                xa[h][a] = (rok && c < kx) ? (double)X[xoff[a] + (size_t)r * bx.ld] : 0.0;
             }
-            zb[b] = z;
+#pragma unroll
+            for (int b = 0; b < TZ; ++b) {
+                const int c = b * 16 + cit;
+                double z = 0.0;
+                if (rok && c < kz) {
+                    if constexpr (ZSIGNS) {
+                        const uint64_t x = probe_bits(key, (uint64_t)c * (uint64_t)n + (uint64_t)r + 1ull);
+                        z = (x >> 63) ? -1.0 : 1.0;
+                    } else {
+                        z = (double)Z[zoff[b] + (size_t)r * bz.ld];
+                    }
+                }
+                zb[h][b] = z;
+            }
         }
 #pragma unroll
-        for (int a = 0; a < TX; ++a)
+        for (int h = 0; h < 2; ++h)
 #pragma unroll
-            for (int b = 0; b < TZ; ++b)
-                acc[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(xa[a], zb[b], acc[a][b], 0, 0, 0);
+            for (int a = 0; a < TX; ++a)
+#pragma unroll
+                for (int b = 0; b < TZ; ++b)
+                    acc[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(xa[h][a], zb[h][b], acc[a][b], 0, 0, 0);
     }
 
     // sum the four waves in a fixed order through LDS
@@ -566,66 +596,86 @@ hipError_t launch_reduce(const double* part, int nwg, int len, int part_ld, int 
 // ---------------------------------------------------------------------------
 // row block times a small FP64 matrix (TRSM with R^{-1}; deflation G - Q C)
 // ---------------------------------------------------------------------------
-// One row per thread: the row of Y is read into registers, M (converted to
-// the element type) is read from LDS at the same address by every lane, and
-// the output row is written back.  Y and the output are column-blocked
-// (Blk); output column j goes to global column ocol0 + j.
-template <typename T, int KY, int KO, bool SIGNS>
-__global__ __launch_bounds__(kThreads) void rowmat_kernel(int n, const T* __restrict__ Y, Blk by,
-                                                          int ky, const double* __restrict__ M,
-                                                          int kout, double sign_m, uint64_t key,
-                                                          const T* base, Blk bb, T* out, Blk bo) {
+// A tile of RT rows per workgroup (one row per thread).  The tile of Y is
+// loaded into LDS with coalesced accesses (consecutive threads read
+// consecutive columns), each thread multiplies its row by M (read from LDS at
+// the same address by every lane), the results go back into the tile, and
+// the tile is written out coalesced, adding the optional base matrix and
+// probe signs.  Y, base and out are column-blocked (Blk).
+template <typename T, int KY, int KO, bool SIGNS, int RT>
+__global__ __launch_bounds__(RT) void rowmat_kernel(int n, const T* __restrict__ Y, Blk by,
+                                                    int ky, const double* __restrict__ M,
+                                                    int kout, double sign_m, uint64_t key,
+                                                    const T* base, Blk bb, T* out, Blk bo) {
+    constexpr int KS = (KY > KO ? KY : KO) + 1;      // padded row stride of the tile
     __shared__ T ms[KY * KO];
+    __shared__ T tile[RT * KS];
     __shared__ size_t yoff[KY], ooff[KO], boff[KO];
-    for (int e = threadIdx.x; e < KY * KO; e += kThreads) {
+    for (int e = threadIdx.x; e < KY * KO; e += RT) {
         const int i = e / KO, j = e - i * KO;
         ms[e] = (i < ky && j < kout) ? (T)(sign_m * M[i * kout + j]) : T(0);
     }
-    for (int i = threadIdx.x; i < KY; i += kThreads) yoff[i] = i < ky ? by.offset(i) : 0;
-    for (int j = threadIdx.x; j < KO; j += kThreads) {
+    for (int i = threadIdx.x; i < KY; i += RT) yoff[i] = i < ky ? by.offset(i) : 0;
+    for (int j = threadIdx.x; j < KO; j += RT) {
         ooff[j] = j < kout ? bo.offset(j) : 0;
         boff[j] = j < kout ? bb.offset(j) : 0;
     }
     __syncthreads();
-    const int row = xcd_tile(blockIdx.x, gridDim.x) * kThreads + threadIdx.x;
-    if (row >= n) return;
-    T y[KY];
+    const int row0 = xcd_tile(blockIdx.x, gridDim.x) * RT;
+    const int nr = min(RT, n - row0);
+    for (int e = threadIdx.x; e < nr * ky; e += RT) {
+        const int r = e / ky, i = e - r * ky;
+        tile[r * KS + i] = Y[yoff[i] + (size_t)(row0 + r) * by.ld];
+    }
+    __syncthreads();
+    if (threadIdx.x < nr) {
+        T y[KY];
 #pragma unroll
-    for (int i = 0; i < KY; ++i) y[i] = (i < ky) ? Y[yoff[i] + (size_t)row * by.ld] : T(0);
+        for (int i = 0; i < KY; ++i) y[i] = i < ky ? tile[threadIdx.x * KS + i] : T(0);
 #pragma nounroll
-    for (int j = 0; j < kout; ++j) {
-        T acc = T(0);
+        for (int j = 0; j < kout; ++j) {
+            T acc = T(0);
 #pragma unroll
-        for (int i = 0; i < KY; ++i) acc = fma(y[i], ms[i * KO + j], acc);
+            for (int i = 0; i < KY; ++i) acc = fma(y[i], ms[i * KO + j], acc);
+            tile[threadIdx.x * KS + j] = acc;
+        }
+    }
+    __syncthreads();
+    for (int e = threadIdx.x; e < nr * kout; e += RT) {
+        const int r = e / kout, j = e - r * kout;
+        const int row = row0 + r;
+        T v = tile[r * KS + j];
         if constexpr (SIGNS) {
             const uint64_t x = probe_bits(key, (uint64_t)j * (uint64_t)n + (uint64_t)row + 1ull);
-            acc += (x >> 63) ? T(-1) : T(1);
+            v += (x >> 63) ? T(-1) : T(1);
         }
-        if (base) acc += base[boff[j] + (size_t)row * bb.ld];
-        out[ooff[j] + (size_t)row * bo.ld] = acc;
+        if (base) v += base[boff[j] + (size_t)row * bb.ld];
+        out[ooff[j] + (size_t)row * bo.ld] = v;
     }
 }
 
 template <typename T, int KY, int KO>
-void launch_rowmat_t(int nwg, hipStream_t st, int n, const void* Y, Blk by, int ky, const double* M,
+void launch_rowmat_t(int n, hipStream_t st, const void* Y, Blk by, int ky, const double* M,
                      int kout, double sign_m, bool signs, uint64_t key, const void* base, Blk bb,
                      void* out, Blk bo) {
+    constexpr int RT = (sizeof(T) == 8 && KY == 64 && KO == 64) ? 128 : 256;
+    const int nwg = div_up(n, RT);
     if (signs)
-        hipLaunchKernelGGL((rowmat_kernel<T, KY, KO, true>), dim3(nwg), dim3(kThreads), 0, st, n,
+        hipLaunchKernelGGL((rowmat_kernel<T, KY, KO, true, RT>), dim3(nwg), dim3(RT), 0, st, n,
                            (const T*)Y, by, ky, M, kout, sign_m, key, (const T*)base, bb, (T*)out, bo);
     else
-        hipLaunchKernelGGL((rowmat_kernel<T, KY, KO, false>), dim3(nwg), dim3(kThreads), 0, st, n,
+        hipLaunchKernelGGL((rowmat_kernel<T, KY, KO, false, RT>), dim3(nwg), dim3(RT), 0, st, n,
                            (const T*)Y, by, ky, M, kout, sign_m, key, (const T*)base, bb, (T*)out, bo);
 }
 
 template <typename T>
-hipError_t launch_rowmat_ty(int nwg, hipStream_t st, int n, const void* Y, Blk by, int ky,
+hipError_t launch_rowmat_ty(hipStream_t st, int n, const void* Y, Blk by, int ky,
                             const double* M, int kout, double sign_m, bool signs, uint64_t key,
                             const void* base, Blk bb, void* out, Blk bo) {
     const int a = ky <= 16 ? 16 : ky <= 32 ? 32 : 64;
     const int b = kout <= 16 ? 16 : kout <= 32 ? 32 : 64;
 #define LD_RM(A_, B_) \
-    if (a == A_ && b == B_) launch_rowmat_t<T, A_, B_>(nwg, st, n, Y, by, ky, M, kout, sign_m, signs, key, base, bb, out, bo);
+    if (a == A_ && b == B_) launch_rowmat_t<T, A_, B_>(n, st, Y, by, ky, M, kout, sign_m, signs, key, base, bb, out, bo);
     LD_RM(16, 16) LD_RM(16, 32) LD_RM(16, 64) LD_RM(32, 16) LD_RM(32, 32) LD_RM(32, 64)
     LD_RM(64, 16) LD_RM(64, 32) LD_RM(64, 64)
 #undef LD_RM
@@ -636,10 +686,9 @@ hipError_t launch_rowmat(bool f64, int n, const void* Y, Blk by, int ky, const d
                          double sign_m, bool signs, uint64_t key, const void* base, Blk bb,
                          void* out, Blk bo, hipStream_t st) {
     if (ky < 1 || kout < 1 || ky > 64 || kout > 64) return hipErrorInvalidValue;
-    const int nwg = div_up(n, kThreads);
-    if (nwg == 0) return hipSuccess;
-    return f64 ? launch_rowmat_ty<double>(nwg, st, n, Y, by, ky, M, kout, sign_m, signs, key, base, bb, out, bo)
-               : launch_rowmat_ty<float>(nwg, st, n, Y, by, ky, M, kout, sign_m, signs, key, base, bb, out, bo);
+    if (n == 0) return hipSuccess;
+    return f64 ? launch_rowmat_ty<double>(st, n, Y, by, ky, M, kout, sign_m, signs, key, base, bb, out, bo)
+               : launch_rowmat_ty<float>(st, n, Y, by, ky, M, kout, sign_m, signs, key, base, bb, out, bo);
 }
 
 // ---------------------------------------------------------------------------
