@@ -40,6 +40,8 @@ def parse():
     p.add_argument("--dot-mode", choices=["auto", "forward", "squared"], default="auto")
     p.add_argument("--no-fp64", action="store_true")
     p.add_argument("--no-cpu-baseline", action="store_true")
+    p.add_argument("--grad", action="store_true",
+                   help="also time the gradient entry point against the estimate alone")
     p.add_argument("--calibrate-copy", action="store_true",
                    help="only run a 1 GiB device-to-device copy (reference for the memory counters)")
     return p.parse_args()
@@ -264,6 +266,21 @@ def main():
         if ref is not None:
             out["parity"]["rel_err_f64"] = abs(est64 - ref) / abs(ref)
         out["parity_f32_vs_f64"] = abs(est32 - est64) / abs(est64)
+
+    if args.grad:
+        k_g = max(2, args.steps // 4)
+        ld.logdet_with_grad(A32, lmin, lmax, degree, m_vec, args.seed, options=opts)
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        for _ in range(k_g):
+            _, _, stg = ld.logdet_with_grad(A32, lmin, lmax, degree, m_vec, args.seed, options=opts,
+                                            return_stats=True)
+        torch.cuda.synchronize()
+        dtg = (time.perf_counter() - t) / k_g
+        out["gradient"] = {"ms_estimate_and_gradient": dtg * 1e3, "ms_estimate": dt / args.steps * 1e3,
+                           "ms_reverse_sweep": stg["ms_adjoint"],
+                           "adjoint_over_forward": stg["ms_adjoint"] / (dt / args.steps * 1e3),
+                           "ckpt_stride": "ceil(sqrt(degree))"}
 
     if not args.no_cpu_baseline:
         vals32 = A32.val.double().cpu().numpy()

@@ -59,6 +59,11 @@ CsrDev dev_of(const ld_csr* A) {
     return CsrDev{(int)A->n, (int)A->nnz, A->row_ptr, A->col_idx, A->val};
 }
 
+// Workspace of the list of rows with more than kLongRow entries.
+size_t long_rows_bytes(const ld_csr* A) {
+    return align_up((size_t)A->n * 4) + align_up(((size_t)A->n / 256 + 4) * 4) + align_up(16);
+}
+
 // Bump allocator over the caller's (or our own) workspace.
 struct Arena {
     char* base = nullptr;
@@ -166,6 +171,7 @@ struct EstLayout {
     BlkMat FX, Gm, T1;
     int gcols = 0, ldg = 0, nckpt = 0, stride = 0;
     size_t gblk = 0;
+    size_t longb = 0;          // long-row list
 };
 
 int dot_slots(int degree, int mode) {
@@ -202,6 +208,7 @@ EstLayout layout_estimate(const ld_csr* A, int degree, int n_matvec, bool grad,
     L.small = (size_t)kSmallSlots * 64 * 64 * 8;
     L.nu = (size_t)L.nslots * L.nc * 8;
     L.flag = 256;
+    L.longb = long_rows_bytes(A);
     if (grad) {
         L.stride = o.ckpt_stride > 0 ? o.ckpt_stride : (int)std::ceil(std::sqrt((double)degree));
         L.stride = std::max(1, std::min(L.stride, degree));
@@ -224,6 +231,7 @@ size_t layout_bytes(const EstLayout& L, bool grad) {
     for (size_t s : {L.mask, L.Y.bytes(), L.Q1.bytes(), L.X.bytes(), L.W, L.W, L.part, L.small, L.nu,
                      L.flag})
         b += align_up(s);
+    b += L.longb;
     if (grad) {
         for (size_t s : {L.FX.bytes(), L.Gm.bytes(), L.T1.bytes(), L.mask}) b += align_up(s);
         // L, R, two lambdas, nckpt-1 checkpoints, stride-1 segment vectors
@@ -271,9 +279,16 @@ double alg_bytes_step(const ld_csr* A, int cols, int kind, size_t elem) {
 
 // Launch one Newton step over all columns of a row-major block, in column
 // chunks of col_block (user option of ld_apply_log).
+struct LongRows {
+    const int* list = nullptr;    // null: the matrix has no row above kLongRow entries
+    const int* count = nullptr;
+};
+
 int run_step(bool f64, const ld_csr* A, StepArgs s, int ncols, int col_block, hipStream_t st,
-             int* nwg_used) {
+             int* nwg_used, const LongRows& lr) {
     const CsrDev d = dev_of(A);
+    s.long_rows = lr.list;
+    s.long_count = lr.count;
     int nwg = 0;
     const int gshift = s.gshift;
     for (int c0 = 0; c0 < ncols; c0 += col_block) {
@@ -284,6 +299,24 @@ int run_step(bool f64, const ld_csr* A, StepArgs s, int ncols, int col_block, hi
         LD_CHECK_HIP(launch_step(f64, d, s, st));
     }
     if (nwg_used) *nwg_used = nwg;
+    return LD_OK;
+}
+
+
+// Lists the rows with more than kLongRow entries (one host sync for the count).
+int build_long_rows(const ld_csr* A, Arena& ar, hipStream_t st, LongRows& lr) {
+    int* list = (int*)ar.take((size_t)A->n * 4);
+    int* tmp = (int*)ar.take(((size_t)A->n / 256 + 4) * 4);
+    int* count = (int*)ar.take(16);
+    LD_CHECK_HIP(launch_long_rows(dev_of(A), tmp, list, count, st));
+    int h = 0;
+    LD_CHECK_HIP(hipMemcpyAsync(&h, count, sizeof(int), hipMemcpyDeviceToHost, st));
+    LD_CHECK_HIP(hipStreamSynchronize(st));
+    lr = LongRows{};
+    if (h > 0) {
+        lr.list = list;
+        lr.count = count;
+    }
     return LD_OK;
 }
 
@@ -330,6 +363,7 @@ struct EstimateState {
     int launches1 = 0, launches23 = 0;
     double bytes1 = 0, bytes23 = 0;
     hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};   // step-phase brackets
+    LongRows longrows;
     ~EstimateState() {
         for (hipEvent_t e : ev)
             if (e) (void)hipEventDestroy(e);
@@ -392,7 +426,7 @@ int sketch_phase(const ld_csr* A, EstimateState& S, hipStream_t st) {
             s.beta = p.beta[j];
             s.dj = p.d[j];
             s.mask = (const uint64_t*)S.mask;
-            LD_CHECK(run_step(f64, A, s, cols, cols, st, nullptr));
+            LD_CHECK(run_step(f64, A, s, cols, cols, st, nullptr, S.longrows));
             S.launches1 += 1;
             S.bytes1 += alg_bytes_step(A, cols, STEP_HORNER_SIGNS, S.L.elem);
         }
@@ -463,7 +497,7 @@ int estimate_dots(const ld_csr* A, EstimateState& S, hipStream_t st, std::vector
                 s.ps1 = part + (size_t)(2 * a + 1) * slot_stride;
                 s.ps2 = part + (size_t)(2 * a + 2) * slot_stride;
                 s.part_ld = X.bw;
-                LD_CHECK(run_step(f64, A, s, cols, cols, st, &nwg));
+                LD_CHECK(run_step(f64, A, s, cols, cols, st, &nwg, S.longrows));
                 S.launches23 += 1;
                 S.bytes23 += alg_bytes_step(A, cols, STEP_DOT_SQ, L.elem);
                 cur = nxt;
@@ -485,7 +519,7 @@ int estimate_dots(const ld_csr* A, EstimateState& S, hipStream_t st, std::vector
                 s.ps0 = part;
                 s.ps1 = part + (size_t)(j + 1) * slot_stride;
                 s.part_ld = X.bw;
-                LD_CHECK(run_step(f64, A, s, cols, cols, st, &nwg));
+                LD_CHECK(run_step(f64, A, s, cols, cols, st, &nwg, S.longrows));
                 S.launches23 += 1;
                 S.bytes23 += alg_bytes_step(A, cols, STEP_DOT_FWD, L.elem);
                 cur = pp[j % 2];
@@ -574,7 +608,7 @@ int apply_poly_blocks(const ld_csr* A, EstimateState& S, const BlkMat& X, const 
             s.dj = p.d[j];
             s.vsrc = X.block(b);
             s.ldv = X.ld;
-            LD_CHECK(run_step(f64, A, s, cols, cols, st, nullptr));
+            LD_CHECK(run_step(f64, A, s, cols, cols, st, nullptr, S.longrows));
             cur = out;
         }
     }
@@ -676,7 +710,7 @@ int gradient(const ld_csr* A, uint64_t seed, EstimateState& S, GradBufs& B, void
         s.ld = ldg;
         s.alpha = p.alpha;
         s.beta = p.beta[j];
-        return run_step(f64, A, s, gcols, gcols, st, nullptr);
+        return run_step(f64, A, s, gcols, gcols, st, nullptr, S.longrows);
     };
     {
         const void* cur = B.Rg;
@@ -755,6 +789,7 @@ int run_logdet(const ld_csr* A, double lmin, double lmax, int degree, int n_matv
     if (ar.base && ar.used > layout_bytes(S.L, want_grad))
         return fail(LD_EINVAL, "internal: workspace layout overflow");
     if (!o.trusted_csr) LD_CHECK(validate_csr(A, S.flag, st));
+    LD_CHECK(build_long_rows(A, ar, st, S.longrows));
     Timer tm(st);
     tm.mark();
     LD_CHECK(estimate_front(A, seed, S, st, tm));
@@ -829,7 +864,8 @@ int ld_workspace_size(const ld_csr* A, int32_t degree, int32_t n_matvec, int32_t
     const ld_options o = resolve(opts);
     if (n_matvec < 0) {
         const size_t elem = A->dtype == LD_F64 ? 8 : 4;
-        *bytes = 2 * align_up((size_t)A->n * (size_t)(-(int64_t)n_matvec) * elem) + align_up(256);
+        *bytes = 2 * align_up((size_t)A->n * (size_t)(-(int64_t)n_matvec) * elem) + align_up(256) +
+                 long_rows_bytes(A);
         return LD_OK;
     }
     if (n_matvec < 3) return fail(LD_EINVAL, "n_matvec must be >= 3");
@@ -857,7 +893,7 @@ int ld_apply_log(const ld_csr* A, double lmin, double lmax, int32_t degree, cons
     const uint8_t* v8 = (const uint8_t*)V;
     const uint8_t* p8 = (const uint8_t*)PV;
     if (v8 < p8 + blk && p8 < v8 + blk) return fail(LD_EINVAL, "V and PV overlap");
-    const size_t need = 2 * align_up(blk) + align_up(256);
+    const size_t need = 2 * align_up(blk) + align_up(256) + long_rows_bytes(A);
     OwnedWs own;
     Arena ar;
     LD_CHECK(get_workspace(workspace, ws_bytes, need, own, ar));
@@ -865,6 +901,8 @@ int ld_apply_log(const ld_csr* A, double lmin, double lmax, int32_t degree, cons
     void* B1 = ar.take(blk);
     int* flag = (int*)ar.take(256);
     if (!o.trusted_csr) LD_CHECK(validate_csr(A, flag, st));
+    LongRows lr;
+    LD_CHECK(build_long_rows(A, ar, st, lr));
     const int m = p.degree;
     const int cb = (o.block_cols > 0 && o.block_cols < std::min(nc, 64)) ? o.block_cols : std::min(nc, 64);
     // Horner: r_m = d_m V; r_j = (T - xi_j) r_{j+1} + d_j V, with d_0 carrying
@@ -883,7 +921,7 @@ int ld_apply_log(const ld_csr* A, double lmin, double lmax, int32_t degree, cons
         s.dj = j == 0 ? p.d[0] + std::log(p.sigma) : p.d[j];
         s.vsrc = V;
         s.ldv = nc;
-        LD_CHECK(run_step(f64, A, s, nc, cb, st, nullptr));
+        LD_CHECK(run_step(f64, A, s, nc, cb, st, nullptr, lr));
         cur = out;
     }
     if (!workspace) LD_CHECK_HIP(hipStreamSynchronize(st));

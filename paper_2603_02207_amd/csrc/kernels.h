@@ -59,7 +59,19 @@ struct StepArgs {
     double* ps1;
     double* ps2;
     int part_ld;
+    // Rows with more than kLongRow entries, when listed here, are skipped by the
+    // row-group kernel and done by a workgroup each (partial rows after the
+    // regular ones: kLongWgs of them).
+    const int* long_rows;      // device list of long rows (ascending), or null
+    const int* long_count;     // device count of the list
 };
+
+constexpr int kLongRow = 64;     // entries above which a row is "long"
+constexpr int kLongWgs = 1024;   // workgroups of the long-row launch
+
+// Deterministic list of the rows with more than kLongRow entries:
+// list[0..count) ascending, *count on the device.  tmp: >= n/256 + 2 ints.
+hipError_t launch_long_rows(const CsrDev& A, int* tmp, int* list, int* count, hipStream_t st);
 
 // Workgroups of a step launch (the dot kinds write one partial row per
 // workgroup); the bound holds for 16-byte aligned blocks of at most bcols.

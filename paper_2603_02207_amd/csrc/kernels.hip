@@ -97,7 +97,7 @@ __global__ __launch_bounds__(NT) void step_kernel(
     const T* __restrict__ val, const T* __restrict__ win, T* __restrict__ wout, int ld, int c0,
     int bcols, int gshift, T alpha, T beta, T dj, const T* __restrict__ vsrc, int ldv,
     const uint64_t* __restrict__ mask, double* __restrict__ ps0, double* __restrict__ ps1,
-    double* __restrict__ ps2, int part_ld, int lpr, int rpw) {
+    double* __restrict__ ps2, int part_ld, int lpr, int rpw, int skip_long) {
     constexpr bool kDot = is_dot(KIND);
     constexpr int NW = NT / 64;
     constexpr int kSums = kDot ? ((FIRST ? 1 : 0) + 1 + (KIND == STEP_DOT_SQ ? 1 : 0)) : 0;
@@ -153,6 +153,7 @@ __global__ __launch_bounds__(NT) void step_kernel(
         if (!lane_ok || lr >= nrows) continue;
         const int row = W0 + lr;
         const int beg = rp[lr], end = rp[lr + 1];
+        if (skip_long && end - beg > kLongRow) continue;   // done by long_row_kernel
         T acc[VEC];
 #pragma unroll
         for (int e = 0; e < VEC; ++e) acc[e] = T(0);
@@ -266,6 +267,128 @@ __global__ __launch_bounds__(NT) void step_kernel(
     }
 }
 
+// ---------------------------------------------------------------------------
+// Long rows: one workgroup per row (grid-stride over the list).  The row's
+// entries are dealt round-robin to the workgroup's row groups, each group
+// gathers and accumulates its share, and the group sums are added in group
+// order through LDS.  Column sums accumulate over the workgroup's rows and go
+// to partial row part_row0 + blockIdx.x.
+// ---------------------------------------------------------------------------
+template <typename T, int VEC, int KIND, bool FIRST>
+__global__ __launch_bounds__(256) void long_row_kernel(
+    int n, const int* __restrict__ row_ptr, const int* __restrict__ col_idx,
+    const T* __restrict__ val, const T* __restrict__ win, T* __restrict__ wout, int ld, int c0,
+    int bcols, int gshift, T alpha, T beta, T dj, const T* __restrict__ vsrc, int ldv,
+    const uint64_t* __restrict__ mask, double* __restrict__ ps0, double* __restrict__ ps1,
+    double* __restrict__ ps2, int part_ld, int lpr, int rpw, const int* __restrict__ list,
+    const int* __restrict__ count, int part_row0) {
+    constexpr int NW = 4;
+    __shared__ T s_acc[NW * 64 * VEC];
+    const int lane = threadIdx.x & 63;
+    const int wave = threadIdx.x >> 6;
+    const int g = lane / lpr;
+    const int li = lane - g * lpr;
+    const bool lane_ok = g < rpw;
+    const int col = c0 + li * VEC;
+    const int groups = NW * rpw;
+    const int gid = wave * rpw + g;
+    const int nlong = *count;
+    double s0[VEC], s1[VEC], s2[VEC];
+#pragma unroll
+    for (int e = 0; e < VEC; ++e) s0[e] = s1[e] = s2[e] = 0.0;
+    for (int i = blockIdx.x; i < nlong; i += gridDim.x) {
+        const int row = list[i];
+        const int beg = row_ptr[row], end = row_ptr[row + 1];
+        T acc[VEC];
+#pragma unroll
+        for (int e = 0; e < VEC; ++e) acc[e] = T(0);
+        if (lane_ok) {
+            int k = beg + gid;
+            for (; k + 3 * groups < end; k += 4 * groups) {
+                int cc[4];
+                T aa[4];
+#pragma unroll
+                for (int u = 0; u < 4; ++u) {
+                    cc[u] = col_idx[k + u * groups];
+                    aa[u] = val[k + u * groups];
+                }
+#pragma unroll
+                for (int u = 0; u < 4; ++u) {
+                    const Pack<T, VEC> x = load_pack<T, VEC>(win + (size_t)cc[u] * ld + col);
+#pragma unroll
+                    for (int e = 0; e < VEC; ++e) acc[e] = fma(aa[u], x.v[e], acc[e]);
+                }
+            }
+            for (; k < end; k += groups) {
+                const Pack<T, VEC> x = load_pack<T, VEC>(win + (size_t)col_idx[k] * ld + col);
+                const T a = val[k];
+#pragma unroll
+                for (int e = 0; e < VEC; ++e) acc[e] = fma(a, x.v[e], acc[e]);
+            }
+        }
+#pragma unroll
+        for (int e = 0; e < VEC; ++e) s_acc[threadIdx.x * VEC + e] = acc[e];
+        __syncthreads();
+        if (wave == 0 && g == 0) {
+            // group sums in group order, then the Newton update of the row
+#pragma unroll
+            for (int e = 0; e < VEC; ++e) {
+                T t = T(0);
+                for (int q = 0; q < groups; ++q) {
+                    const int wv = q / rpw, gg = q - wv * rpw;
+                    t += s_acc[(wv * 64 + gg * lpr + li) * VEC + e];
+                }
+                acc[e] = t;
+            }
+            const Pack<T, VEC> w = load_pack<T, VEC>(win + (size_t)row * ld + col);
+            Pack<T, VEC> o;
+#pragma unroll
+            for (int e = 0; e < VEC; ++e) o.v[e] = alpha * acc[e] - beta * w.v[e];
+            if constexpr (KIND == STEP_HORNER_SIGNS) {
+                const uint64_t bits = mask[row];
+#pragma unroll
+                for (int e = 0; e < VEC; ++e) {
+                    const T sgn = ((bits >> ((col + gshift + e) & 63)) & 1ull) ? T(-1) : T(1);
+                    o.v[e] = fma(dj, sgn, o.v[e]);
+                }
+            } else if constexpr (KIND == STEP_HORNER_VEC) {
+                const Pack<T, VEC> v = load_pack<T, VEC>(vsrc + (size_t)row * ldv + col);
+#pragma unroll
+                for (int e = 0; e < VEC; ++e) o.v[e] = fma(dj, v.v[e], o.v[e]);
+            } else if constexpr (KIND == STEP_DOT_FWD) {
+                const Pack<T, VEC> x = load_pack<T, VEC>(vsrc + (size_t)row * ldv + col);
+#pragma unroll
+                for (int e = 0; e < VEC; ++e) {
+                    if (FIRST) s0[e] += (double)x.v[e] * (double)w.v[e];
+                    s1[e] += (double)x.v[e] * (double)o.v[e];
+                }
+            } else if constexpr (KIND == STEP_DOT_SQ) {
+#pragma unroll
+                for (int e = 0; e < VEC; ++e) {
+                    if (FIRST) s0[e] += (double)w.v[e] * (double)w.v[e];
+                    s1[e] += (double)w.v[e] * (double)o.v[e];
+                    s2[e] += (double)o.v[e] * (double)o.v[e];
+                }
+            }
+            store_pack<T, VEC>(wout + (size_t)row * ld + col, o);
+        }
+        __syncthreads();
+    }
+    if constexpr (is_dot(KIND)) {
+        if (wave == 0 && g == 0) {
+            const size_t prow = (size_t)(part_row0 + blockIdx.x) * part_ld + c0 + gshift;
+#pragma unroll
+            for (int e = 0; e < VEC; ++e) {
+                const int t = li * VEC + e;
+                if (t >= bcols) continue;
+                if (FIRST) ps0[prow + t] = s0[e];
+                ps1[prow + t] = s1[e];
+                if (KIND == STEP_DOT_SQ) ps2[prow + t] = s2[e];
+            }
+        }
+    }
+}
+
 template <typename T, int VEC, int KIND, bool FIRST>
 hipError_t launch_step_t(const CsrDev& A, const StepArgs& s, hipStream_t st) {
     constexpr int kIters = kStepIters;
@@ -276,10 +399,18 @@ hipError_t launch_step_t(const CsrDev& A, const StepArgs& s, hipStream_t st) {
     const int rows_per_wg = (NT / 64) * rpw * kIters;
     const int nwg = div_up(A.n, rows_per_wg);
     if (nwg == 0) return hipSuccess;
+    const int skip = s.long_rows != nullptr;
     hipLaunchKernelGGL((step_kernel<T, VEC, KIND, FIRST, kIters, NT>), dim3(nwg), dim3(NT), 0, st,
                        A.n, A.row_ptr, A.col_idx, (const T*)A.val, (const T*)s.win, (T*)s.wout, s.ld,
                        s.c0, s.bcols, s.gshift, (T)s.alpha, (T)s.beta, (T)s.dj, (const T*)s.vsrc,
-                       s.ldv, s.mask, s.ps0, s.ps1, s.ps2, s.part_ld, lpr, rpw);
+                       s.ldv, s.mask, s.ps0, s.ps1, s.ps2, s.part_ld, lpr, rpw, skip);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess || !skip) return e;
+    hipLaunchKernelGGL((long_row_kernel<T, VEC, KIND, FIRST>), dim3(kLongWgs), dim3(256), 0, st,
+                       A.n, A.row_ptr, A.col_idx, (const T*)A.val, (const T*)s.win, (T*)s.wout, s.ld,
+                       s.c0, s.bcols, s.gshift, (T)s.alpha, (T)s.beta, (T)s.dj, (const T*)s.vsrc,
+                       s.ldv, s.mask, s.ps0, s.ps1, s.ps2, s.part_ld, lpr, rpw, s.long_rows,
+                       s.long_count, nwg);
     return hipGetLastError();
 }
 
@@ -317,15 +448,16 @@ inline int pick_vec(const StepArgs& s, int elem_bytes) {
 }  // namespace
 
 int step_num_wg_bound(int n, int bcols, int elem_bytes) {
-    // blocks aligned to the 16-byte vector (the estimator's internal layout)
+    // blocks aligned to the 16-byte vector (the estimator's internal layout),
+    // plus the partial rows of the long-row launch
     const int rows = (threads_of(STEP_PLAIN) / 64) * (64 / lanes_per_row(bcols, 16 / elem_bytes)) * kStepIters;
-    return div_up(n, rows);
+    return div_up(n, rows) + kLongWgs;
 }
 
 int step_num_wg(bool f64, int n, const StepArgs& s) {
     const int vec = pick_vec(s, f64 ? 8 : 4);
     const int rows = (threads_of(s.kind) / 64) * (64 / lanes_per_row(s.bcols, vec)) * kStepIters;
-    return div_up(n, rows);
+    return div_up(n, rows) + (s.long_rows ? kLongWgs : 0);   // partial rows written
 }
 
 hipError_t launch_step(bool f64, const CsrDev& A, const StepArgs& s, hipStream_t st) {
@@ -337,6 +469,73 @@ hipError_t launch_step(bool f64, const CsrDev& A, const StepArgs& s, hipStream_t
     if (vec == 4) return launch_step_v<float, 4>(A, s, st);
     if (vec == 2) return launch_step_v<float, 2>(A, s, st);
     return launch_step_v<float, 1>(A, s, st);
+}
+
+// ---------------------------------------------------------------------------
+// deterministic list of long rows: per-block counts, one-block scan, scatter
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(kThreads) void long_count_kernel(int n, const int* __restrict__ row_ptr,
+                                                              int* __restrict__ cnt) {
+    const int r = blockIdx.x * kThreads + threadIdx.x;
+    const bool is_long = r < n && row_ptr[r + 1] - row_ptr[r] > kLongRow;
+    __shared__ int s[kThreads / 64];
+    const unsigned long long b = __ballot(is_long);
+    if ((threadIdx.x & 63) == 0) s[threadIdx.x >> 6] = __popcll(b);
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int t = 0;
+        for (int i = 0; i < kThreads / 64; ++i) t += s[i];
+        cnt[blockIdx.x] = t;
+    }
+}
+
+__global__ __launch_bounds__(1024) void long_scan_kernel(int nb, int* __restrict__ cnt,
+                                                         int* __restrict__ count) {
+    // exclusive scan of cnt[0..nb) in place, one block: contiguous chunks per thread
+    __shared__ int s[1024];
+    const int per = (nb + 1023) / 1024;
+    const int b0 = threadIdx.x * per, b1 = min(nb, b0 + per);
+    int local = 0;
+    for (int i = b0; i < b1; ++i) local += cnt[i];
+    s[threadIdx.x] = local;
+    __syncthreads();
+    for (int off = 1; off < 1024; off <<= 1) {
+        const int v = threadIdx.x >= off ? s[threadIdx.x - off] : 0;
+        __syncthreads();
+        s[threadIdx.x] += v;
+        __syncthreads();
+    }
+    int run = s[threadIdx.x] - local;   // exclusive prefix of this chunk
+    for (int i = b0; i < b1; ++i) {
+        const int c = cnt[i];
+        cnt[i] = run;
+        run += c;
+    }
+    if (threadIdx.x == 1023) *count = s[1023];
+}
+
+__global__ __launch_bounds__(kThreads) void long_scatter_kernel(int n, const int* __restrict__ row_ptr,
+                                                                const int* __restrict__ off,
+                                                                int* __restrict__ list) {
+    const int r = blockIdx.x * kThreads + threadIdx.x;
+    const bool is_long = r < n && row_ptr[r + 1] - row_ptr[r] > kLongRow;
+    __shared__ int s[kThreads / 64];
+    const unsigned long long b = __ballot(is_long);
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    if (lane == 0) s[wave] = __popcll(b);
+    __syncthreads();
+    int base = off[blockIdx.x];
+    for (int i = 0; i < wave; ++i) base += s[i];
+    if (is_long) list[base + __popcll(b & ((1ull << lane) - 1ull))] = r;
+}
+
+hipError_t launch_long_rows(const CsrDev& A, int* tmp, int* list, int* count, hipStream_t st) {
+    const int nb = div_up(A.n, kThreads);
+    if (nb == 0) return hipSuccess;
+    hipLaunchKernelGGL(long_count_kernel, dim3(nb), dim3(kThreads), 0, st, A.n, A.row_ptr, tmp);
+    hipLaunchKernelGGL(long_scan_kernel, dim3(1), dim3(1024), 0, st, nb, tmp, count);
+    hipLaunchKernelGGL(long_scatter_kernel, dim3(nb), dim3(kThreads), 0, st, A.n, A.row_ptr, tmp, list);
+    return hipGetLastError();
 }
 
 // ---------------------------------------------------------------------------

@@ -149,6 +149,26 @@ def test_estimate_irregular_sparsity(n, long_rows, seed, dtype, tol):
     assert rel(est, ref) < tol
 
 
+@pytest.mark.parametrize("dtype,tol", [(torch.float64, 1e-10), (torch.float32, 1e-4)])
+@pytest.mark.parametrize("permute", [False, True])
+def test_estimate_power_law_hub_rows(dtype, tol, permute):
+    # hub rows far above the long-row threshold, both row orders
+    csr = w.chung_lu_laplacian(30000, seed=2, permute=permute)
+    assert np.diff(csr[0]).max() > 200
+    A, vals = to_gpu(csr, dtype)
+    csr_v = (csr[0], csr[1], vals, csr[3])
+    lmin, lmax = bounds.gershgorin(csr_v)
+    Q = w.to_scipy(csr_v)
+    for mode in (ld.LD_DOT_FORWARD, ld.LD_DOT_SQUARED):
+        est = ld.logdet(A, lmin, lmax, 40, 24, 5, options=ld.Options(dot_mode=mode))
+        ref = hutchpp.logdet_estimate(Q, lmin, lmax, 40, 24, 5)
+        assert rel(est, ref) < tol, mode
+    V = np.random.default_rng(0).standard_normal((csr[3], 6))
+    out = ld.apply_log(A, lmin, lmax, 30, torch.tensor(V, dtype=dtype, device=DEV)).double().cpu().numpy()
+    refv = newton.apply_log(Q, torch.tensor(V, dtype=dtype).double().numpy(), lmin, lmax, 30)
+    assert np.linalg.norm(out - refv) / np.linalg.norm(refv) < (1e-10 if dtype == torch.float64 else 1e-5)
+
+
 def test_estimate_small_and_sigma_one():
     # lmin >= 1 (sigma = 1), tiny n with k close to n
     csr = w.grid_laplacian_2d(4, 3.0)
@@ -230,3 +250,22 @@ def test_workspace_too_small():
     rc = nat.load().ld_logdet_estimate(ctypes.byref(c), 0.5, 8.5, 10, 9, 0, None, ctypes.c_void_p(ws.data_ptr()),
                                        16, None, ctypes.byref(out), None)
     assert rc == nat.LD_EWORKSPACE
+
+
+# ---------------------------------------------------------------- the other workloads at full size
+
+@pytest.mark.parametrize("name,tol32", [("grid128c_k0.05", 1e-4), ("gmrf2048", 1e-4), ("chunglu_1M", 1e-4)])
+def test_estimate_full_size_workloads(name, tol32):
+    g = golden(name)
+    if g is None:
+        pytest.skip(f"oracle value for {name} not generated")
+    csr = w.build(g["workload"], **g["overrides"])
+    ref = g["results"]["0"]["logdet"]
+    A32, _ = to_gpu(csr, torch.float32)
+    A64, _ = to_gpu(csr, torch.float64)
+    lo, hi = ld.spectral_bounds(A64)
+    assert lo == pytest.approx(g["lmin"], rel=1e-12) and hi == pytest.approx(g["lmax"], rel=1e-12)
+    e32, st = ld.logdet(A32, g["lmin"], g["lmax"], g["degree"], g["m_vec"], 0, return_stats=True)
+    assert rel(e32, ref) < tol32, (e32, ref, st["dot_mode_used"])
+    e64 = ld.logdet(A64, g["lmin"], g["lmax"], g["degree"], g["m_vec"], 0)
+    assert rel(e64, ref) < 1e-10
