@@ -79,7 +79,10 @@ typedef struct {
     int32_t s_val_mode;      /* LD_SVAL_CENTER (default) or LD_SVAL_HALF_LMAX  */
     int32_t block_cols;      /* columns per kernel launch; 0 = all at once      */
     int64_t taylor_cap;      /* max Taylor order of Alg. 1; 0 = 100000000      */
-    int32_t ckpt_stride;     /* gradient checkpoint stride; 0 = ceil(sqrt(m))  */
+    int32_t ckpt_stride;     /* gradient checkpoint stride; 0 = auto: 1 (every
+                                forward vector kept, no recomputation) when the
+                                vectors fit 64 GiB, else the smallest stride that
+                                fits, at least ceil(sqrt(m))                    */
     int32_t dot_mode;        /* LD_DOT_AUTO / LD_DOT_FORWARD / LD_DOT_SQUARED  */
     int32_t trusted_csr;     /* nonzero: skip the device CSR structure check    */
     int32_t reserved[3];
@@ -89,8 +92,10 @@ typedef struct {
     double ms_total;         /* wall time of the call (host clock)             */
     double ms_phase1;        /* sketch Y = P_m(Q~) S                           */
     double ms_qr;            /* CholQR2 + deflation                            */
-    double ms_phase23;       /* quadratic forms on [Q_b | U]                   */
-    double ms_adjoint;       /* reverse sweep (gradient only)                  */
+    double ms_phase23;       /* quadratic forms on [Q_b | U] (estimate only)   */
+    double ms_adjoint;       /* gradient only: forward pass over [Q_b, U, S]
+                                with F [Q_b | U] accumulated, the k-column
+                                algebra and the reverse sweep                  */
     double bytes_alg;        /* algorithmic HBM bytes of the recurrence kernels */
     int64_t taylor_terms;    /* Taylor order used by Alg. 1                    */
     double sigma, lo, hi;    /* scaling and interval of Q~                     */
@@ -189,8 +194,11 @@ int ld_logdet_estimate(const ld_csr* A, double lmin, double lmax, int32_t degree
  * with respect to each stored value of A (same probes, interval and sigma
  * held fixed; includes the dependence of the sketch basis on A), by a reverse
  * sweep of the Newton recurrence with checkpoints every opts->ckpt_stride
- * steps.  grad_val: device, nnz entries of A's dtype, overwritten.
- * Errors: as ld_logdet_estimate. */
+ * steps.  The traces of the estimate come from F [Q_b | U] accumulated in the
+ * forward form of Alg. 2 (the same polynomial as ld_logdet_estimate's
+ * quadratic forms, summed in another order: the two estimates agree to
+ * rounding, not bitwise).  grad_val: device, nnz entries of A's dtype,
+ * overwritten.  Errors: as ld_logdet_estimate. */
 int ld_logdet_grad(const ld_csr* A, double lmin, double lmax, int32_t degree, int32_t n_matvec,
                    uint64_t seed, const ld_options* opts, void* workspace, size_t ws_bytes,
                    void* stream, double* out_logdet, void* grad_val, ld_stats* stats);

@@ -174,6 +174,21 @@ struct EstLayout {
     size_t longb = 0;          // long-row list
 };
 
+// Checkpoint stride of the reverse sweep: the smallest one whose stored
+// forward vectors (checkpoints + one segment) fit kCkptBudget, i.e. every
+// vector when memory allows (no recomputation); else the sqrt(m) stride that
+// minimises memory.
+constexpr double kCkptBudget = 64.0 * (1ull << 30);
+
+int auto_ckpt_stride(int degree, size_t gblk) {
+    for (int s = 1; s <= degree; ++s) {
+        const double vecs = (double)((degree + s - 1) / s - 1 + (s - 1));
+        if (vecs * (double)align_up(gblk) <= kCkptBudget) return s;
+        if (s * s >= degree) break;   // past sqrt(m) memory only grows again
+    }
+    return std::max(1, (int)std::ceil(std::sqrt((double)degree)));
+}
+
 int dot_slots(int degree, int mode) {
     return mode == LD_DOT_SQUARED ? 2 * ((degree + 1) / 2) + 1 : degree + 1;
 }
@@ -210,16 +225,15 @@ EstLayout layout_estimate(const ld_csr* A, int degree, int n_matvec, bool grad,
     L.flag = 256;
     L.longb = long_rows_bytes(A);
     if (grad) {
-        L.stride = o.ckpt_stride > 0 ? o.ckpt_stride : (int)std::ceil(std::sqrt((double)degree));
-        L.stride = std::max(1, std::min(L.stride, degree));
-        L.nckpt = (degree + L.stride - 1) / L.stride;     // segments of the reverse sweep
-        L.gcols = L.nc + L.k;                               // [Q_b, sqrt(c)U, S] / [Q_b, sqrt(c)U, 2Z]
+        L.gcols = L.nc + L.k;                               // R = [Q_b, U, S] / L = [Q_b, cU, 2Z]
         const int v = 16 / (int)L.elem;
         int lanes = 1;                                      // the adjoint's row group: power of two
         while (lanes * v < L.gcols) lanes <<= 1;
         L.ldg = lanes * v;
         L.gblk = (size_t)n * L.ldg * L.elem;
-        L.FX = make_blk(n, L.nc, L.X.bw, L.elem);
+        L.stride = o.ckpt_stride > 0 ? std::min(o.ckpt_stride, degree) : auto_ckpt_stride(degree, L.gblk);
+        L.nckpt = (degree + L.stride - 1) / L.stride;     // segments of the reverse sweep
+        L.FX = make_blk(n, L.nc, L.nc, L.elem);             // F [Q_b | U], one row-major block
         L.Gm = make_blk(n, L.kg, L.kg, L.elem);
         L.T1 = make_blk(n, L.k, L.k, L.elem);
     }
@@ -291,6 +305,9 @@ int run_step(bool f64, const ld_csr* A, StepArgs s, int ncols, int col_block, hi
     s.long_count = lr.count;
     int nwg = 0;
     const int gshift = s.gshift;
+    // one row group spans at most a wave: 64 lanes of the launch's vector width
+    s.c0 = 0;
+    col_block = std::min(col_block, step_max_cols(f64, s));
     for (int c0 = 0; c0 < ncols; c0 += col_block) {
         s.c0 = c0;
         s.bcols = std::min(col_block, ncols - c0);
@@ -567,53 +584,27 @@ int check_estimate_args(const ld_csr* A, double lmin, double lmax, int degree, i
 
 
 // ---------------------------------------------------------------------------
-// Gradient of the estimate.  With F = P_m(Q~), c = 1/k_G, Y = F S = Q_b R,
+// Estimate and gradient.  With F = P_m(Q~), c = 1/k_G, Y = F S = Q_b R,
 // U = (I - Q_b Q_b^T) G, the derivative of
 //     est = n log sigma + tr(Q_b^T F Q_b) + c tr(U^T F U)
 // at fixed probes and interval is
 //     d est = tr(Q_b^T dF Q_b) + c tr(U^T dF U) + 2 tr(Z^T dF S),
 //     Z = (I - Q_b Q_b^T) X Q_b R^{-T},  X = F - c (F U G^T + G U^T F),
 // (the basis term comes from differentiating the QR factor of the sketch), so
-// one reverse sweep on L = [Q_b, sqrt(c) U, 2Z] and R = [Q_b, sqrt(c) U, S]
-// gives every entry: grad[(r,c)] = alpha * sum_i <lam_{i+1}[r], w_i[c]>, with
-// w_i the forward Newton vectors of R and lam the Horner adjoint started at
-// lam_m = d_m L.  The forward vectors are kept every `stride` steps and
-// recomputed inside each segment of the reverse sweep.
+// one reverse sweep on L = [Q_b, c U, 2Z] and R = [Q_b, U, S] gives every
+// entry: grad[(r,c)] = alpha * sum_i <lam_{i+1}[r], w_i[c]>, with w_i the
+// forward Newton vectors of R and lam the Horner adjoint started at
+// lam_m = d_m L.
+//
+// One forward pass over R produces the w_i (stored every `stride` steps, all
+// of them when memory allows) and, accumulated on the way (Alg. 2's sum),
+// F [Q_b | U]: that gives both the two traces of the estimate and the
+// k-column algebra of Z, so no separate quadratic-form pass is needed.
 // ---------------------------------------------------------------------------
 struct GradBufs {
     void *mask2, *Lg, *Rg, *lam0, *lam1;
     std::vector<void*> ckpt, seg;
 };
-
-// Horner application of F to every block of X: FX = P_m(Q~) X.
-int apply_poly_blocks(const ld_csr* A, EstimateState& S, const BlkMat& X, const BlkMat& FX,
-                      hipStream_t st) {
-    const bool f64 = A->dtype == LD_F64;
-    const int n = (int)A->n;
-    const Plan& p = S.plan;
-    const int m = p.degree;
-    for (int b = 0; b < X.nblocks(); ++b) {
-        const int cols = X.bcols(b);
-        LD_CHECK_HIP(launch_scale_copy(f64, n, cols, X.block(b), X.ld, p.d[m], S.W0, X.ld, st));
-        const void* cur = S.W0;
-        for (int j = m - 1; j >= 0; --j) {
-            void* out = j == 0 ? FX.block(b) : (cur == S.W0 ? S.W1 : S.W0);
-            StepArgs s{};
-            s.kind = STEP_HORNER_VEC;
-            s.win = cur;
-            s.wout = out;
-            s.ld = X.ld;
-            s.alpha = p.alpha;
-            s.beta = p.beta[j];
-            s.dj = p.d[j];
-            s.vsrc = X.block(b);
-            s.ldv = X.ld;
-            LD_CHECK(run_step(f64, A, s, cols, cols, st, nullptr, S.longrows));
-            cur = out;
-        }
-    }
-    return LD_OK;
-}
 
 int upload(const std::vector<double>& h, double* d, hipStream_t st) {
     LD_CHECK_HIP(hipMemcpyAsync(d, h.data(), sizeof(double) * h.size(), hipMemcpyHostToDevice, st));
@@ -621,29 +612,94 @@ int upload(const std::vector<double>& h, double* d, hipStream_t st) {
     return LD_OK;
 }
 
-int gradient(const ld_csr* A, uint64_t seed, EstimateState& S, GradBufs& B, void* grad,
-             hipStream_t st) {
+int download(const double* d, std::vector<double>& h, hipStream_t st) {
+    LD_CHECK_HIP(hipMemcpyAsync(h.data(), d, sizeof(double) * h.size(), hipMemcpyDeviceToHost, st));
+    LD_CHECK_HIP(hipStreamSynchronize(st));
+    return LD_OK;
+}
+
+int estimate_and_gradient(const ld_csr* A, uint64_t seed, EstimateState& S, GradBufs& B, void* grad,
+                          hipStream_t st, double* t_low, double* t_res) {
     const bool f64 = A->dtype == LD_F64;
     const int n = (int)A->n;
     const EstLayout& L = S.L;
     const Plan& p = S.plan;
     const int m = p.degree, k = L.k, kg = L.kg, nc = L.nc;
-    const double c = 1.0 / kg, sc = std::sqrt(c);
+    const double c = 1.0 / kg;
     const uint64_t key0 = probe_stream_key(seed, 0), key1 = probe_stream_key(seed, 1);
     double* slot[kSmallSlots];
     for (int i = 0; i < kSmallSlots; ++i) slot[i] = S.small + (size_t)i * 64 * 64;
     const Blk X = L.X.desc(), FXd = L.FX.desc(), Gd = L.Gm.desc(), Td = L.T1.desc();
-    const Blk Lg = Blk::plain(L.ldg), Rg = Blk::plain(L.ldg);
+    const Blk Gb = Blk::plain(L.ldg);
+    const int gcols = L.gcols, ldg = L.ldg, stride = L.stride;
 
-    // FX = F [Q_b | U]
-    LD_CHECK(apply_poly_blocks(A, S, L.X, L.FX, st));
-    // residual probes G as a block
+    // ---- R = [Q_b, U, S]
+    auto diag = [](int q, double v) {
+        std::vector<double> M((size_t)q * q, 0.0);
+        for (int i = 0; i < q; ++i) M[(size_t)i * q + i] = v;
+        return M;
+    };
+    LD_CHECK(upload(diag(k, 1.0), slot[7], st));
+    LD_CHECK(upload(diag(kg, c), slot[8], st));
+    LD_CHECK(upload(diag(kg, 1.0), slot[9], st));
+    LD_CHECK_HIP(launch_rowmat(f64, n, L.X.base, X, k, slot[7], k, 1.0, false, 0, nullptr, Blk::plain(1),
+                               B.Rg, Gb, st));
+    LD_CHECK_HIP(launch_rowmat(f64, n, L.X.base, X.shifted(k), kg, slot[9], kg, 1.0, false, 0, nullptr,
+                               Blk::plain(1), B.Rg, Gb.shifted(k), st));
+    LD_CHECK_HIP(launch_sign_mask(n, k, key0, (uint64_t*)S.mask, st));
+    LD_CHECK_HIP(launch_fill_signs(f64, n, k, ldg, 0, (const uint64_t*)S.mask, 1.0,
+                                   (char*)B.Rg + (size_t)nc * L.elem, st));
+
+    // ---- forward Newton vectors of R; FX = sum_j d_j w_j[:, :nc] on the way
+    LD_CHECK_HIP(launch_scale_copy(f64, n, nc, B.Rg, ldg, p.d[0], L.FX.base, L.FX.ld, st));
+    auto step = [&](const void* in, void* out, int j, bool acc) -> int {
+        StepArgs s{};
+        s.kind = acc ? STEP_PLAIN_ACC : STEP_PLAIN;
+        s.win = in;
+        s.wout = out;
+        s.ld = ldg;
+        s.alpha = p.alpha;
+        s.beta = p.beta[j];
+        if (acc) {
+            s.dj = p.d[j + 1];
+            s.acc = L.FX.base;
+            s.ldacc = L.FX.ld;
+            s.acc_cols = nc;
+        }
+        return run_step(f64, A, s, gcols, gcols, st, nullptr, S.longrows);
+    };
+    {
+        const void* cur = B.Rg;
+        void* tmp[2] = {B.lam0, B.lam1};
+        for (int i = 0; i < m; ++i) {
+            const int nx = i + 1;   // w_nx is written; w_m only feeds the sum
+            const bool keep = nx < m && nx % stride == 0;
+            void* dst = keep ? B.ckpt[nx / stride - 1] : (cur == tmp[0] ? tmp[1] : tmp[0]);
+            LD_CHECK(step(cur, dst, i, true));
+            cur = dst;
+        }
+    }
+
+    // ---- the estimate's traces: diag(Q_b^T F Q_b), diag(U^T F U)
+    {
+        LD_CHECK(cross_product(f64, n, L.X.base, X, k, L.FX.base, FXd, k, false, 0, S.part, slot[0], st));
+        LD_CHECK(cross_product(f64, n, L.X.base, X.shifted(k), kg, L.FX.base, FXd.shifted(k), kg, false, 0,
+                               S.part, slot[1], st));
+        std::vector<double> ql((size_t)k * k), qr((size_t)kg * kg);
+        LD_CHECK(download(slot[0], ql, st));
+        LD_CHECK(download(slot[1], qr, st));
+        KahanSum tl, tr;
+        for (int i = 0; i < k; ++i) tl.add(ql[(size_t)i * k + i]);
+        for (int i = 0; i < kg; ++i) tr.add(qr[(size_t)i * kg + i]);
+        *t_low = tl.value();
+        *t_res = tr.value() * c;
+    }
+
+    // ---- Z: small matrices C = Q_b^T G (slot 2, from the deflation), M1 = U^T F Q_b
     LD_CHECK_HIP(launch_sign_mask(n, kg, key1, (uint64_t*)B.mask2, st));
     LD_CHECK_HIP(launch_fill_signs(f64, n, kg, L.Gm.ld, 0, (const uint64_t*)B.mask2, 1.0, L.Gm.base, st));
-    // small matrices: C = Q_b^T G (slot 2, from the estimate), M1 = U^T F Q_b, R = R2 R1
     std::vector<double> C((size_t)k * kg), Ct((size_t)kg * k);
-    LD_CHECK_HIP(hipMemcpyAsync(C.data(), slot[2], sizeof(double) * C.size(), hipMemcpyDeviceToHost, st));
-    LD_CHECK_HIP(hipStreamSynchronize(st));
+    LD_CHECK(download(slot[2], C, st));
     for (int i = 0; i < k; ++i)
         for (int j = 0; j < kg; ++j) Ct[(size_t)j * k + i] = C[(size_t)i * kg + j];
     LD_CHECK(upload(Ct, slot[3], st));
@@ -658,74 +714,35 @@ int gradient(const ld_csr* A, uint64_t seed, EstimateState& S, GradBufs& B, void
     LD_CHECK(cross_product(f64, n, L.X.base, X, k, L.T1.base, Td, k, false, 0, S.part, slot[5], st));
     LD_CHECK_HIP(launch_rowmat(f64, n, L.X.base, X, k, slot[5], k, -1.0, false, 0, L.T1.base, Td,
                                L.T1.base, Td, st));
-    // Z = P R^{-T}, R = R2 R1 (upper triangular); L[:, nc:nc+k] = 2 Z
-    std::vector<double> R((size_t)k * k, 0.0), Rt((size_t)k * k), Rinv((size_t)k * k), RinvT((size_t)k * k);
+    // Z = P R^{-T}, R = R2 R1 (upper triangular)
+    std::vector<double> R((size_t)k * k, 0.0), Rinv((size_t)k * k, 0.0), RinvT((size_t)k * k);
     for (int i = 0; i < k; ++i)
         for (int j = 0; j < k; ++j) {
             double v = 0.0;
             for (int t = 0; t < k; ++t) v += S.R2[i * k + t] * S.R1[t * k + j];
             R[(size_t)i * k + j] = v;
         }
-    {
-        // inverse of the upper-triangular R by back substitution
-        std::fill(Rinv.begin(), Rinv.end(), 0.0);
-        for (int j = k - 1; j >= 0; --j) {
-            Rinv[(size_t)j * k + j] = 1.0 / R[(size_t)j * k + j];
-            for (int i = j + 1; i < k; ++i) {
-                double v = 0.0;
-                for (int t = j + 1; t <= i; ++t) v += R[(size_t)j * k + t] * Rinv[(size_t)t * k + i];
-                Rinv[(size_t)j * k + i] = -v / R[(size_t)j * k + j];
-            }
+    for (int j = k - 1; j >= 0; --j) {   // inverse of the upper-triangular R by back substitution
+        Rinv[(size_t)j * k + j] = 1.0 / R[(size_t)j * k + j];
+        for (int i = j + 1; i < k; ++i) {
+            double v = 0.0;
+            for (int t = j + 1; t <= i; ++t) v += R[(size_t)j * k + t] * Rinv[(size_t)t * k + i];
+            Rinv[(size_t)j * k + i] = -v / R[(size_t)j * k + j];
         }
-        for (int i = 0; i < k; ++i)
-            for (int j = 0; j < k; ++j) RinvT[(size_t)i * k + j] = Rinv[(size_t)j * k + i];
     }
+    for (int i = 0; i < k; ++i)
+        for (int j = 0; j < k; ++j) RinvT[(size_t)i * k + j] = Rinv[(size_t)j * k + i];
     LD_CHECK(upload(RinvT, slot[6], st));
+    // L = [Q_b, c U, 2 Z]
     LD_CHECK_HIP(launch_rowmat(f64, n, L.T1.base, Td, k, slot[6], k, 2.0, false, 0, nullptr, Blk::plain(1),
-                               B.Lg, Lg.shifted(nc), st));
-    // L[:, :nc] = R[:, :nc] = [Q_b, sqrt(c) U]; R[:, nc:] = S
-    std::vector<double> I1((size_t)k * k, 0.0), I2((size_t)kg * kg, 0.0);
-    for (int i = 0; i < k; ++i) I1[(size_t)i * k + i] = 1.0;
-    for (int i = 0; i < kg; ++i) I2[(size_t)i * kg + i] = sc;
-    LD_CHECK(upload(I1, slot[7], st));
-    LD_CHECK(upload(I2, slot[8], st));
-    for (void* dst : {B.Lg, B.Rg}) {
-        LD_CHECK_HIP(launch_rowmat(f64, n, L.X.base, X, k, slot[7], k, 1.0, false, 0, nullptr, Blk::plain(1),
-                                   dst, Lg, st));
-        LD_CHECK_HIP(launch_rowmat(f64, n, L.X.base, X.shifted(k), kg, slot[8], kg, 1.0, false, 0, nullptr,
-                                   Blk::plain(1), dst, Lg.shifted(k), st));
-    }
-    (void)Rg;
-    LD_CHECK_HIP(launch_sign_mask(n, k, key0, (uint64_t*)S.mask, st));
-    LD_CHECK_HIP(launch_fill_signs(f64, n, k, L.ldg, 0, (const uint64_t*)S.mask, 1.0,
-                                   (char*)B.Rg + (size_t)nc * L.elem, st));
+                               B.Lg, Gb.shifted(nc), st));
+    LD_CHECK_HIP(launch_rowmat(f64, n, L.X.base, X, k, slot[7], k, 1.0, false, 0, nullptr, Blk::plain(1),
+                               B.Lg, Gb, st));
+    LD_CHECK_HIP(launch_rowmat(f64, n, L.X.base, X.shifted(k), kg, slot[8], kg, 1.0, false, 0, nullptr,
+                               Blk::plain(1), B.Lg, Gb.shifted(k), st));
 
-    // forward Newton vectors of R, checkpoints every `stride` steps
-    const int gcols = L.gcols, ldg = L.ldg, stride = L.stride;
-    auto plain_step = [&](const void* in, void* out, int j) -> int {
-        StepArgs s{};
-        s.kind = STEP_PLAIN;
-        s.win = in;
-        s.wout = out;
-        s.ld = ldg;
-        s.alpha = p.alpha;
-        s.beta = p.beta[j];
-        return run_step(f64, A, s, gcols, gcols, st, nullptr, S.longrows);
-    };
-    {
-        const void* cur = B.Rg;
-        void* tmp[2] = {B.lam0, B.lam1};
-        for (int i = 0; i < m - 1; ++i) {
-            const int nx = i + 1;
-            void* dst = (nx % stride == 0) ? B.ckpt[nx / stride - 1] : (cur == tmp[0] ? tmp[1] : tmp[0]);
-            if (nx % stride != 0) {
-                // only the steps that end on a checkpoint need to be stored; the rest are scratch
-            }
-            LD_CHECK(plain_step(cur, dst, i));
-            cur = dst;
-        }
-    }
-    // reverse sweep
+    // ---- reverse sweep, segment by segment (recomputing a segment's vectors
+    //      from its checkpoint when not all of them are stored)
     LD_CHECK_HIP(launch_scale_copy(f64, n, gcols, B.Lg, ldg, p.d[m], B.lam0, ldg, st));
     void* lam_in = B.lam0;
     void* lam_out = B.lam1;
@@ -735,7 +752,7 @@ int gradient(const ld_csr* A, uint64_t seed, EstimateState& S, GradBufs& B, void
         std::vector<const void*> w(s1 - s0);
         w[0] = sg == 0 ? B.Rg : B.ckpt[sg - 1];
         for (int t = 1; t < s1 - s0; ++t) {
-            LD_CHECK(plain_step(w[t - 1], B.seg[t - 1], s0 + t - 1));
+            LD_CHECK(step(w[t - 1], B.seg[t - 1], s0 + t - 1, false));
             w[t] = B.seg[t - 1];
         }
         for (int i = s1 - 1; i >= s0; --i) {
@@ -793,31 +810,35 @@ int run_logdet(const ld_csr* A, double lmin, double lmax, int degree, int n_matv
     Timer tm(st);
     tm.mark();
     LD_CHECK(estimate_front(A, seed, S, st, tm));
-    std::vector<double> nu;
-    LD_CHECK(estimate_dots(A, S, st, nu));
-    tm.mark();
-    // ---- combine (Alg. 3 step 7): n log(sigma) + t_low + t_res
     const EstLayout& L = S.L;
-    const int ncoef = S.plan.degree + 1;
-    KahanSum tl, tr;
-    for (int col = 0; col < L.nc; ++col)
-        for (int i = 0; i < ncoef; ++i) {
-            const double v = S.coef[i] * nu[(size_t)i * L.nc + col];
-            if (col < L.k)
-                tl.add(v);
-            else
-                tr.add(v);
-        }
-    const double t_low = tl.value(), t_res = tr.value() / L.kg;
+    double t_low = 0.0, t_res = 0.0;
+    if (!want_grad) {
+        std::vector<double> nu;
+        LD_CHECK(estimate_dots(A, S, st, nu));
+        tm.mark();
+        const int ncoef = S.plan.degree + 1;
+        KahanSum tl, tr;
+        for (int col = 0; col < L.nc; ++col)
+            for (int i = 0; i < ncoef; ++i) {
+                const double v = S.coef[i] * nu[(size_t)i * L.nc + col];
+                if (col < L.k)
+                    tl.add(v);
+                else
+                    tr.add(v);
+            }
+        t_low = tl.value();
+        t_res = tr.value() / L.kg;
+    } else {
+        tm.mark();   // no separate quadratic-form pass
+        LD_CHECK(estimate_and_gradient(A, seed, S, B, grad, st, &t_low, &t_res));
+        tm.mark();
+    }
+    // ---- combine (Alg. 3 step 7): n log(sigma) + t_low + t_res
     KahanSum tot;
     tot.add((double)A->n * std::log(S.plan.sigma));
     tot.add(t_low);
     tot.add(t_res);
     *out_logdet = tot.value();
-    if (want_grad && A->nnz > 0) {
-        LD_CHECK(gradient(A, seed, S, B, grad, st));
-        tm.mark();
-    }
     LD_CHECK_HIP(hipStreamSynchronize(st));
     if (stats) {
         std::memset(stats, 0, sizeof(*stats));
@@ -832,7 +853,7 @@ int run_logdet(const ld_csr* A, double lmin, double lmax, int degree, int n_matv
         stats->hi = S.plan.hi;
         stats->k = L.k;
         stats->k_G = L.kg;
-        stats->dot_mode_used = S.mode;
+        stats->dot_mode_used = want_grad ? LD_DOT_FORWARD : S.mode;
         stats->spmm_launches = S.spmm_launches;
         stats->t_low = t_low;
         stats->t_res = t_res;

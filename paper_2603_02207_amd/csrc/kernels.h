@@ -15,6 +15,7 @@ enum StepKind : int {
     STEP_DOT_FWD = 2,       // out = alpha*A*in - beta*in; <X,out> (and <X,in> if first)
     STEP_DOT_SQ = 3,        // out = alpha*A*in - beta*in; <in,out>, <out,out> (and <in,in>)
     STEP_PLAIN = 4,         // out = alpha*A*in - beta*in
+    STEP_PLAIN_ACC = 5,     // PLAIN, and acc[r, c] += dj*out[r, c] for columns c < acc_cols
 };
 
 // A dense n x cols matrix stored as column blocks of width bw: element
@@ -64,6 +65,8 @@ struct StepArgs {
     // regular ones: kLongWgs of them).
     const int* long_rows;      // device list of long rows (ascending), or null
     const int* long_count;     // device count of the list
+    void* acc;                 // PLAIN_ACC: row-major accumulator (column c of the step = column c)
+    int ldacc, acc_cols;
 };
 
 constexpr int kLongRow = 64;     // entries above which a row is "long"
@@ -76,6 +79,8 @@ hipError_t launch_long_rows(const CsrDev& A, int* tmp, int* list, int* count, hi
 // Workgroups of a step launch (the dot kinds write one partial row per
 // workgroup); the bound holds for 16-byte aligned blocks of at most bcols.
 int step_num_wg(bool f64, int n, const StepArgs& s);
+// Widest column range of one launch (a row group spans at most one wave).
+int step_max_cols(bool f64, const StepArgs& s);
 int step_num_wg_bound(int n, int bcols, int elem_bytes);
 
 hipError_t launch_step(bool f64, const CsrDev& A, const StepArgs& s, hipStream_t st);

@@ -69,14 +69,16 @@ inline int lanes_per_row(int bcols, int vec) { return (bcols + vec - 1) / vec; }
 
 constexpr int kStepIters = 2;      // row groups per wave and launch
 constexpr int kWaveNz = 384;       // CSR entries one wave stages in LDS
-constexpr int kStageNz = 1536;     // CSR entries one workgroup stages (adjoint kernel)
 constexpr int kMaxDotCols = 64;    // columns of one launch of the kinds with column sums
+constexpr int kAdjBatch = 4;       // CSR entries of a row whose gathers the adjoint issues together
+constexpr int kAdjStageNz = 1536;  // CSR entries one adjoint workgroup stages in LDS
 
 constexpr bool is_dot(int kind) { return kind == STEP_DOT_FWD || kind == STEP_DOT_SQ; }
 constexpr int threads_of(int) { return 256; }
 
 // ---------------------------------------------------------------------------
-// Newton step: out = alpha*A*in - beta*in (+ dj*source), optional dot partials.
+// Newton step: out = alpha*A*in - beta*in (+ dj*source), optional dot partials
+// or accumulation acc += dj*out.
 //
 // Wave w of a workgroup owns the contiguous rows R0 + w*rpw*ITERS + [0,
 // rpw*ITERS).  Each wave stages its own slice of row_ptr and, when it fits,
@@ -97,7 +99,8 @@ __global__ __launch_bounds__(NT) void step_kernel(
     const T* __restrict__ val, const T* __restrict__ win, T* __restrict__ wout, int ld, int c0,
     int bcols, int gshift, T alpha, T beta, T dj, const T* __restrict__ vsrc, int ldv,
     const uint64_t* __restrict__ mask, double* __restrict__ ps0, double* __restrict__ ps1,
-    double* __restrict__ ps2, int part_ld, int lpr, int rpw, int skip_long) {
+    double* __restrict__ ps2, int part_ld, int lpr, int rpw, int skip_long, T* __restrict__ accum,
+    int ldacc, int acc_cols) {
     constexpr bool kDot = is_dot(KIND);
     constexpr int NW = NT / 64;
     constexpr int kSums = kDot ? ((FIRST ? 1 : 0) + 1 + (KIND == STEP_DOT_SQ ? 1 : 0)) : 0;
@@ -221,6 +224,16 @@ __global__ __launch_bounds__(NT) void step_kernel(
         // the vector never leaves the row, and columns past c0+bcols in it get
         // the value of the same recurrence (real columns of a wider block, or
         // padding that no one reads).
+        if constexpr (KIND == STEP_PLAIN_ACC) {
+            if (col < acc_cols) {
+                T* const pa = accum + (size_t)row * ldacc + col;
+                const Pack<T, VEC> a0 = load_pack<T, VEC>(pa);
+                Pack<T, VEC> a1;
+#pragma unroll
+                for (int e = 0; e < VEC; ++e) a1.v[e] = fma(dj, o.v[e], a0.v[e]);
+                store_pack<T, VEC>(pa, a1);
+            }
+        }
         store_pack<T, VEC>(wout + (size_t)row * ld + col, o);
     }
 
@@ -281,7 +294,7 @@ __global__ __launch_bounds__(256) void long_row_kernel(
     int bcols, int gshift, T alpha, T beta, T dj, const T* __restrict__ vsrc, int ldv,
     const uint64_t* __restrict__ mask, double* __restrict__ ps0, double* __restrict__ ps1,
     double* __restrict__ ps2, int part_ld, int lpr, int rpw, const int* __restrict__ list,
-    const int* __restrict__ count, int part_row0) {
+    const int* __restrict__ count, int part_row0, T* __restrict__ accum, int ldacc, int acc_cols) {
     constexpr int NW = 4;
     __shared__ T s_acc[NW * 64 * VEC];
     const int lane = threadIdx.x & 63;
@@ -370,6 +383,16 @@ __global__ __launch_bounds__(256) void long_row_kernel(
                     s2[e] += (double)o.v[e] * (double)o.v[e];
                 }
             }
+            if constexpr (KIND == STEP_PLAIN_ACC) {
+                if (col < acc_cols) {
+                    T* const pa = accum + (size_t)row * ldacc + col;
+                    const Pack<T, VEC> a0 = load_pack<T, VEC>(pa);
+                    Pack<T, VEC> a1;
+#pragma unroll
+                    for (int e = 0; e < VEC; ++e) a1.v[e] = fma(dj, o.v[e], a0.v[e]);
+                    store_pack<T, VEC>(pa, a1);
+                }
+            }
             store_pack<T, VEC>(wout + (size_t)row * ld + col, o);
         }
         __syncthreads();
@@ -395,6 +418,7 @@ hipError_t launch_step_t(const CsrDev& A, const StepArgs& s, hipStream_t st) {
     constexpr int NT = threads_of(KIND);
     if (is_dot(KIND) && s.bcols > kMaxDotCols) return hipErrorInvalidValue;
     const int lpr = lanes_per_row(s.bcols, VEC);
+    if (lpr > 64) return hipErrorInvalidValue;
     const int rpw = 64 / lpr;
     const int rows_per_wg = (NT / 64) * rpw * kIters;
     const int nwg = div_up(A.n, rows_per_wg);
@@ -403,14 +427,15 @@ hipError_t launch_step_t(const CsrDev& A, const StepArgs& s, hipStream_t st) {
     hipLaunchKernelGGL((step_kernel<T, VEC, KIND, FIRST, kIters, NT>), dim3(nwg), dim3(NT), 0, st,
                        A.n, A.row_ptr, A.col_idx, (const T*)A.val, (const T*)s.win, (T*)s.wout, s.ld,
                        s.c0, s.bcols, s.gshift, (T)s.alpha, (T)s.beta, (T)s.dj, (const T*)s.vsrc,
-                       s.ldv, s.mask, s.ps0, s.ps1, s.ps2, s.part_ld, lpr, rpw, skip);
+                       s.ldv, s.mask, s.ps0, s.ps1, s.ps2, s.part_ld, lpr, rpw, skip, (T*)s.acc,
+                       s.ldacc, s.acc_cols);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess || !skip) return e;
     hipLaunchKernelGGL((long_row_kernel<T, VEC, KIND, FIRST>), dim3(kLongWgs), dim3(256), 0, st,
                        A.n, A.row_ptr, A.col_idx, (const T*)A.val, (const T*)s.win, (T*)s.wout, s.ld,
                        s.c0, s.bcols, s.gshift, (T)s.alpha, (T)s.beta, (T)s.dj, (const T*)s.vsrc,
                        s.ldv, s.mask, s.ps0, s.ps1, s.ps2, s.part_ld, lpr, rpw, s.long_rows,
-                       s.long_count, nwg);
+                       s.long_count, nwg, (T*)s.acc, s.ldacc, s.acc_cols);
     return hipGetLastError();
 }
 
@@ -420,6 +445,7 @@ hipError_t launch_step_v(const CsrDev& A, const StepArgs& s, hipStream_t st) {
         case STEP_HORNER_SIGNS: return launch_step_t<T, VEC, STEP_HORNER_SIGNS, false>(A, s, st);
         case STEP_HORNER_VEC: return launch_step_t<T, VEC, STEP_HORNER_VEC, false>(A, s, st);
         case STEP_PLAIN: return launch_step_t<T, VEC, STEP_PLAIN, false>(A, s, st);
+        case STEP_PLAIN_ACC: return launch_step_t<T, VEC, STEP_PLAIN_ACC, false>(A, s, st);
         case STEP_DOT_FWD:
             return s.first ? launch_step_t<T, VEC, STEP_DOT_FWD, true>(A, s, st)
                            : launch_step_t<T, VEC, STEP_DOT_FWD, false>(A, s, st);
@@ -439,6 +465,7 @@ inline int pick_vec(const StepArgs& s, int elem_bytes) {
         if (s.ld % v || s.c0 % v) return false;
         if ((uintptr_t)s.win % align || (uintptr_t)s.wout % align) return false;
         if (s.vsrc && (s.ldv % v || (uintptr_t)s.vsrc % align)) return false;
+        if (s.acc && (s.ldacc % v || (uintptr_t)s.acc % align)) return false;
         return true;
     };
     while (vec > 1 && !ok(vec)) vec /= 2;
@@ -453,6 +480,8 @@ int step_num_wg_bound(int n, int bcols, int elem_bytes) {
     const int rows = (threads_of(STEP_PLAIN) / 64) * (64 / lanes_per_row(bcols, 16 / elem_bytes)) * kStepIters;
     return div_up(n, rows) + kLongWgs;
 }
+
+int step_max_cols(bool f64, const StepArgs& s) { return 64 * pick_vec(s, f64 ? 8 : 4); }
 
 int step_num_wg(bool f64, int n, const StepArgs& s) {
     const int vec = pick_vec(s, f64 ? 8 : 4);
@@ -1003,107 +1032,168 @@ hipError_t launch_axpby(bool f64, long long len, double a, const void* x, double
 // derivative of tr(L^T P(T) R) picks up alpha * <lam_{i+1}[r, :], w_i[c, :]>
 // (an SDDMM on A's pattern), and the Horner adjoint moves on:
 //   lam_i = alpha*A*lam_{i+1} - beta_i*lam_{i+1} + d_i L   (A symmetric).
-// Same row-group layout and LDS staging of the CSR slice as the step kernel;
-// the row group is a power of two wide so that the per-entry dot product is
-// a butterfly of lane shuffles.  Each entry's gradient is owned by one lane:
-// no atomics.
+// Row groups of LPR lanes (a power of two) own one row; lane li holds the
+// columns (q*LPR + li)*VEC + [0, VEC) for q < CPL.  A row's entries go in
+// batches of NB = min(LPR, kAdjBatch): the batch's gathers of w and lam are
+// issued together, then the NB per-lane partial dot products are reduced
+// across the row group (butterfly over the lane bits >= NB, then a
+// reduce-scatter over the low bits, NB-1 shuffles) so that lane li ends with
+// entry li's sum and the batch's gradient entries are read (ahead of the
+// gathers) and written by NB adjacent lanes.  Each entry's gradient is owned
+// by one lane: no atomics.  The workgroup's CSR slice is staged in LDS when it
+// fits.
 // ---------------------------------------------------------------------------
-template <typename T, int VEC>
+template <typename T, int VEC, int LPR, int CPL>
 __global__ __launch_bounds__(kThreads) void adjoint_kernel(
     int n, const int* __restrict__ row_ptr, const int* __restrict__ col_idx,
     const T* __restrict__ val, const T* __restrict__ lam_in, T* __restrict__ lam_out,
     const T* __restrict__ w, const T* __restrict__ L, T* __restrict__ grad, int ld, int ncols,
-    T alpha, T beta, T dj, int first, int last, int lpr, int rpw) {
-    constexpr int kIt = 2;
-    __shared__ int s_rp[kWaves * 64 * kIt + 1];
-    __shared__ int s_col[kStageNz];
-    __shared__ T s_val[kStageNz];
+    T alpha, T beta, T dj, int first, int last) {
+    constexpr int RPW = 64 / LPR;
+    constexpr int NB = LPR < kAdjBatch ? LPR : kAdjBatch;
+    constexpr int rows_per_wg = kWaves * RPW;
+    __shared__ int s_rp[rows_per_wg + 1];
+    __shared__ int s_col[kAdjStageNz];
+    __shared__ T s_val[kAdjStageNz];
     const int lane = threadIdx.x & 63;
     const int wave = threadIdx.x >> 6;
-    const int g = lane / lpr;
-    const int li = lane - g * lpr;
-    const int col = li * VEC;
-    const int rows_per_wg = kWaves * rpw * kIt;
+    const int g = lane / LPR;
+    const int li = lane - g * LPR;
     const int R0 = xcd_tile(blockIdx.x, gridDim.x) * rows_per_wg;
     const int nrows = min(rows_per_wg, n - R0);
     for (int t = threadIdx.x; t <= nrows; t += kThreads) s_rp[t] = row_ptr[R0 + t];
     __syncthreads();
     const int K0 = s_rp[0], K1 = s_rp[nrows];
-    const bool staged = (K1 - K0) <= kStageNz;
+    const bool staged = (K1 - K0) <= kAdjStageNz;
     if (staged)
         for (int k = K0 + threadIdx.x; k < K1; k += kThreads) {
             s_col[k - K0] = col_idx[k];
             s_val[k - K0] = val[k];
         }
     __syncthreads();
-    bool valid[VEC];
+    const int lr = wave * RPW + g;
+    if (lr >= nrows) return;                     // whole row groups leave together
+    const int row = R0 + lr;
+    bool valid[CPL][VEC];
+    Pack<T, VEC> own[CPL], Lr[CPL];
+    T acc[CPL][VEC];
 #pragma unroll
-    for (int e = 0; e < VEC; ++e) valid[e] = col + e < ncols;
+    for (int q = 0; q < CPL; ++q) {
+        const size_t off = (size_t)row * ld + (q * LPR + li) * VEC;
+        own[q] = load_pack<T, VEC>(lam_in + off);
+        if (!last) Lr[q] = load_pack<T, VEC>(L + off);   // fetched early: used at the end
 #pragma unroll
-    for (int it = 0; it < kIt; ++it) {
-        const int lr = (it * kWaves + wave) * rpw + g;
-        if (lr >= nrows) continue;               // whole row groups leave together
-        const int row = R0 + lr;
-        const Pack<T, VEC> lr_v = load_pack<T, VEC>(lam_in + (size_t)row * ld + col);
-        T acc[VEC];
+        for (int e = 0; e < VEC; ++e) {
+            valid[q][e] = (q * LPR + li) * VEC + e < ncols;
+            acc[q][e] = T(0);
+        }
+    }
+    const int beg = s_rp[lr], end = s_rp[lr + 1];
+    for (int kb = beg; kb < end; kb += NB) {
+        // the gradient entry this lane updates, fetched ahead of the gathers
+        const int kg = kb + li;
+        const bool owner = li < NB && kg < end;
+        T gold = T(0);
+        if (owner && !first) gold = grad[kg];
+        int cidx[NB];
+        T a[NB];
 #pragma unroll
-        for (int e = 0; e < VEC; ++e) acc[e] = T(0);
-        const int beg = s_rp[lr], end = s_rp[lr + 1];
-        for (int k = beg; k < end; ++k) {
-            const int c = staged ? s_col[k - K0] : col_idx[k];
-            const T a = staged ? s_val[k - K0] : val[k];
-            const Pack<T, VEC> wc = load_pack<T, VEC>(w + (size_t)c * ld + col);
-            T part = T(0);
-#pragma unroll
-            for (int e = 0; e < VEC; ++e) part = valid[e] ? fma(lr_v.v[e], wc.v[e], part) : part;
-            for (int off = 1; off < lpr; off <<= 1) part += __shfl_xor(part, off, 64);
-            if (!last) {
-                const Pack<T, VEC> lc = load_pack<T, VEC>(lam_in + (size_t)c * ld + col);
-#pragma unroll
-                for (int e = 0; e < VEC; ++e) acc[e] = fma(a, lc.v[e], acc[e]);
-            }
-            if (li == 0) {
-                const T gv = alpha * part;
-                grad[k] = first ? gv : grad[k] + gv;
+        for (int u = 0; u < NB; ++u) {
+            const int k = kb + u;
+            cidx[u] = row;
+            a[u] = T(0);
+            if (k < end) {
+                cidx[u] = staged ? s_col[k - K0] : col_idx[k];
+                a[u] = staged ? s_val[k - K0] : val[k];
             }
         }
-        if (!last) {
-            const Pack<T, VEC> Lr = load_pack<T, VEC>(L + (size_t)row * ld + col);
+        T part[NB];
+#pragma unroll
+        for (int u = 0; u < NB; ++u) {
+            part[u] = T(0);
+            if (kb + u < end) {
+#pragma unroll
+                for (int q = 0; q < CPL; ++q) {
+                    const size_t off = (size_t)cidx[u] * ld + (q * LPR + li) * VEC;
+                    const Pack<T, VEC> wc = load_pack<T, VEC>(w + off);
+#pragma unroll
+                    for (int e = 0; e < VEC; ++e)
+                        part[u] = valid[q][e] ? fma(own[q].v[e], wc.v[e], part[u]) : part[u];
+                    if (!last) {
+                        const Pack<T, VEC> lc = load_pack<T, VEC>(lam_in + off);
+#pragma unroll
+                        for (int e = 0; e < VEC; ++e) acc[q][e] = fma(a[u], lc.v[e], acc[q][e]);
+                    }
+                }
+            }
+        }
+        // lane bits >= NB: plain butterfly on every entry of the batch
+#pragma unroll
+        for (int h = LPR / 2; h >= NB; h >>= 1)
+#pragma unroll
+            for (int u = 0; u < NB; ++u) part[u] += __shfl_xor(part[u], h, 64);
+        // low bits: reduce-scatter, after which part[0] of lane li is the sum of entry li % NB
+#pragma unroll
+        for (int h = NB / 2; h >= 1; h >>= 1) {
+            const bool hi = (li & h) != 0;
+#pragma unroll
+            for (int j = 0; j < h; ++j) {
+                const T send = hi ? part[j] : part[j + h];
+                const T keep = hi ? part[j + h] : part[j];
+                part[j] = keep + __shfl_xor(send, h, 64);
+            }
+        }
+        if (owner) grad[kg] = gold + alpha * part[0];
+    }
+    if (!last) {
+#pragma unroll
+        for (int q = 0; q < CPL; ++q) {
+            const size_t off = (size_t)row * ld + (q * LPR + li) * VEC;
             Pack<T, VEC> o;
 #pragma unroll
-            for (int e = 0; e < VEC; ++e) o.v[e] = fma(dj, Lr.v[e], alpha * acc[e] - beta * lr_v.v[e]);
-            store_pack<T, VEC>(lam_out + (size_t)row * ld + col, o);
+            for (int e = 0; e < VEC; ++e)
+                o.v[e] = fma(dj, Lr[q].v[e], alpha * acc[q][e] - beta * own[q].v[e]);
+            store_pack<T, VEC>(lam_out + off, o);
         }
     }
 }
 
-hipError_t launch_adjoint(bool f64, const CsrDev& A, const AdjArgs& a, hipStream_t st) {
-    const int elem = f64 ? 8 : 4;
-    int vec = 16 / elem;
-    while (vec > 1 && (a.ld % vec)) vec /= 2;
-    const int lpr = lanes_per_row(a.ncols, vec);
-    if (lpr > 64) return hipErrorInvalidValue;
-    int lp2 = 1;                       // the shuffle butterfly needs a power of two
-    while (lp2 < lpr) lp2 <<= 1;
-    if (lp2 * vec > a.ld && lp2 > 1) {
-        // lanes past the row's end would read beyond it: only allowed when ld covers them
-        return hipErrorInvalidValue;
-    }
-    const int rpw = 64 / lp2;
-    const int nwg = div_up(A.n, kWaves * rpw * 2);
+template <typename T, int VEC, int LPR, int CPL>
+hipError_t launch_adjoint_t(const CsrDev& A, const AdjArgs& a, hipStream_t st) {
+    constexpr int rows_per_wg = kWaves * (64 / LPR);
+    const int nwg = div_up(A.n, rows_per_wg);
     if (nwg == 0) return hipSuccess;
-#define LD_ADJ(T, V)                                                                              \
-    hipLaunchKernelGGL((adjoint_kernel<T, V>), dim3(nwg), dim3(kThreads), 0, st, A.n, A.row_ptr, \
-                       A.col_idx, (const T*)A.val, (const T*)a.lam_in, (T*)a.lam_out,            \
-                       (const T*)a.w, (const T*)a.L, (T*)a.grad, a.ld, a.ncols, (T)a.alpha,      \
-                       (T)a.beta, (T)a.dj, (int)a.first, (int)a.last, lp2, rpw)
-    if (f64) {
-        if (vec == 2) LD_ADJ(double, 2); else LD_ADJ(double, 1);
-    } else {
-        if (vec == 4) LD_ADJ(float, 4); else if (vec == 2) LD_ADJ(float, 2); else LD_ADJ(float, 1);
-    }
-#undef LD_ADJ
+    hipLaunchKernelGGL((adjoint_kernel<T, VEC, LPR, CPL>), dim3(nwg), dim3(kThreads), 0, st, A.n,
+                       A.row_ptr, A.col_idx, (const T*)A.val, (const T*)a.lam_in, (T*)a.lam_out,
+                       (const T*)a.w, (const T*)a.L, (T*)a.grad, a.ld, a.ncols, (T)a.alpha, (T)a.beta,
+                       (T)a.dj, (int)a.first, (int)a.last);
     return hipGetLastError();
+}
+
+template <typename T, int VEC>
+hipError_t launch_adjoint_v(const CsrDev& A, const AdjArgs& a, hipStream_t st) {
+    const int lanes = lanes_per_row(a.ncols, VEC);
+    int lp2 = 1;
+    while (lp2 < lanes) lp2 <<= 1;
+    const int cpl = lp2 > 64 ? lp2 / 64 : 1;
+    const int lpr = lp2 > 64 ? 64 : lp2;
+    // every lane's vectors must lie inside the row: ld covers the padded row group
+    if (cpl > 2 || lpr * cpl * VEC > a.ld || a.ld % VEC) return hipErrorInvalidValue;
+    if (cpl == 2) return launch_adjoint_t<T, VEC, 64, 2>(A, a, st);
+    switch (lpr) {
+        case 1: return launch_adjoint_t<T, VEC, 1, 1>(A, a, st);
+        case 2: return launch_adjoint_t<T, VEC, 2, 1>(A, a, st);
+        case 4: return launch_adjoint_t<T, VEC, 4, 1>(A, a, st);
+        case 8: return launch_adjoint_t<T, VEC, 8, 1>(A, a, st);
+        case 16: return launch_adjoint_t<T, VEC, 16, 1>(A, a, st);
+        case 32: return launch_adjoint_t<T, VEC, 32, 1>(A, a, st);
+        default: return launch_adjoint_t<T, VEC, 64, 1>(A, a, st);
+    }
+}
+
+hipError_t launch_adjoint(bool f64, const CsrDev& A, const AdjArgs& a, hipStream_t st) {
+    if (f64) return launch_adjoint_v<double, 2>(A, a, st);
+    return launch_adjoint_v<float, 4>(A, a, st);
 }
 
 }  // namespace ld
