@@ -204,11 +204,19 @@ int ld_logdet_grad(const ld_csr* A, double lmin, double lmax, int32_t degree, in
                    void* stream, double* out_logdet, void* grad_val, ld_stats* stats);
 
 /* Gershgorin interval [min_i a_ii - r_i, max_i a_ii + r_i], r_i = sum_{j!=i}
- * |a_ij| (Sec. 3; Alg. 1/2 step 1), reduced in FP64 on the device; with
- * lanczos_steps > 0 the upper end is refined by that many Lanczos steps
- * (App. A) plus the last residual norm, and never raised above Gershgorin's.
+ * |a_ij| (Sec. 3; Alg. 1/2 step 1), reduced in FP64 on the device.  With
+ * 0 < lanczos_steps <= 512 the upper end is refined as in App. A: that many
+ * Lanczos steps (A symmetric; in FP64, an FP32 matrix's values widened
+ * once; start vector the unit Rademacher vector of generator stream 2,
+ * seed 0; no reorthogonalisation), then the largest Ritz
+ * value plus its residual norm beta_k |s_k| plus a rounding margin, and never
+ * raised above Gershgorin's bound.  The residual term is the usual practical
+ * upper bound, not a guaranteed one.  The lower end is always Gershgorin's.
+ * The call allocates its Lanczos vectors (4n doubles, plus nnz doubles for
+ * an FP32 matrix).
  * lmin, lmax: host doubles.  Returns LD_EINDEF (with both bounds written) when
- * the lower bound is <= 0.  Errors: LD_EINVAL, LD_ECSR, LD_EHIP. */
+ * the lower bound is <= 0.  Errors: LD_EINVAL (null pointers, steps out of
+ * range, non-finite values), LD_ECSR, LD_ENOMEM, LD_EHIP. */
 int ld_spectral_bounds(const ld_csr* A, int32_t lanczos_steps, void* stream, double* lmin,
                        double* lmax);
 

@@ -9,9 +9,14 @@
   the caller must supply a positive lmin).
 * ``lanczos_lmax``: the alternative of Appendix A for lambda_max, a few
   Lanczos steps (largest Ritz value of the tridiagonal projection).
+* ``lanczos_upper``: the same projection from a given start vector, and the
+  largest Ritz value plus its residual norm beta_k |s_k| (s the Ritz vector
+  in the Krylov basis): the Ritz value alone is below lambda_max, the sum is
+  the usual practical upper bound.
 
-Pinned by: closed-form intervals of the Dirichlet grid Laplacians and dense
-eigenvalues of small random SPD matrices (tests/test_oracle_bounds.py).
+Pinned by: closed-form intervals of the Dirichlet grid Laplacians, dense
+eigenvalues of small SPD matrices, and the exact top eigenvalue when the
+Krylov space is the whole space (tests/test_oracle_bounds_exact_grad.py).
 """
 from __future__ import annotations
 
@@ -59,3 +64,37 @@ def lanczos_lmax(Q, steps: int, seed: int = 0):
     k = len(alphas)
     T = np.diag(alphas) + np.diag(betas[: k - 1], 1) + np.diag(betas[: k - 1], -1)
     return float(np.linalg.eigvalsh(T)[-1])
+
+
+def lanczos_upper(Q, steps: int, v0):
+    """(theta, theta + beta_k |s_k|) after ``steps`` Lanczos steps from v0.
+
+    Full reorthogonalisation; stops early on an invariant subspace (then the
+    residual term is zero).
+    """
+    n = Q.shape[0]
+    v = np.asarray(v0, dtype=np.float64)
+    v = v / np.linalg.norm(v)
+    V = [v]
+    alphas, betas = [], []
+    beta = 0.0
+    k_max = min(steps, n)
+    for j in range(k_max):
+        w = Q @ V[-1]
+        a = float(V[-1] @ w)
+        w = w - a * V[-1]
+        if j > 0:
+            w = w - betas[-1] * V[-2]
+        for u in V:                      # full reorthogonalisation
+            w = w - (u @ w) * u
+        alphas.append(a)
+        beta = float(np.linalg.norm(w))
+        if j + 1 == k_max or beta <= 1e-14 * max(abs(a), 1.0):
+            break
+        betas.append(beta)
+        V.append(w / beta)
+    k = len(alphas)
+    T = np.diag(alphas) + np.diag(betas[: k - 1], 1) + np.diag(betas[: k - 1], -1)
+    ev, S = np.linalg.eigh(T)
+    theta = float(ev[-1])
+    return theta, theta + beta * abs(float(S[-1, -1]))

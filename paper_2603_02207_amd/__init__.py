@@ -240,7 +240,8 @@ def apply_log(A: CSR, lmin: float, lmax: float, degree: int, V, options=None):
 
 
 def spectral_bounds(A: CSR, lanczos_steps: int = 0):
-    """Gershgorin interval (lmin, lmax) computed on the GPU in FP64."""
+    """Gershgorin interval (lmin, lmax) computed on the GPU in FP64; with
+    ``lanczos_steps`` > 0 the upper end is refined by Lanczos (App. A)."""
     lib = nat.load()
     c = A.c_struct()
     lo, hi = ctypes.c_double(0), ctypes.c_double(0)

@@ -874,6 +874,86 @@ int run_logdet(const ld_csr* A, double lmin, double lmax, int degree, int n_matv
 
 using namespace ld;
 
+// ---------------------------------------------------------------------------
+// Lanczos refinement of the upper end of the spectrum (App. A): `steps`
+// steps of the symmetric Lanczos recurrence in FP64 (an FP32 matrix's values
+// are widened once) from the unit Rademacher vector of generator stream 2
+// (seed 0), no reorthogonalisation; the largest Ritz
+// value theta of the tridiagonal projection plus its residual norm
+// beta_k |s_k| (s the Ritz vector in the Krylov basis) and a rounding margin.
+// The Ritz value alone underestimates lambda_max; the residual term is the
+// usual practical upper bound, not a guaranteed one, which is why the caller
+// caps it by Gershgorin's.  Allocates its own vectors.
+// ---------------------------------------------------------------------------
+constexpr int kMaxLanczos = 512;
+
+int lanczos_upper(const ld_csr* A_in, int steps, double abs_bound, hipStream_t st, double* out) {
+    const bool f64 = true;
+    const long long n = A_in->n;
+    const size_t elem = 8;
+    const size_t vb = align_up((size_t)n * elem);
+    const size_t pb = align_up((size_t)cross_num_wg((int)n) * sizeof(double));
+    const size_t wb = A_in->dtype == LD_F64 ? 0 : align_up((size_t)A_in->nnz * 8);
+    OwnedWs own;
+    if (hipMalloc(&own.p, 3 * vb + align_up((size_t)n * 8) + pb + 256 + wb) != hipSuccess)
+        return fail(LD_ENOMEM, "hipMalloc failed");
+    char* base = (char*)own.p;
+    ld_csr A64 = *A_in;
+    if (wb) {
+        double* v64 = (double*)(base + 3 * vb + align_up((size_t)n * 8) + pb + 256);
+        LD_CHECK_HIP(launch_widen(A_in->nnz, (const float*)A_in->val, v64, st));
+        A64.val = v64;
+        A64.dtype = LD_F64;
+    }
+    const ld_csr* A = &A64;
+    void* vec[3] = {base, base + vb, base + 2 * vb};     // v_{j-1}, v_j, w
+    uint64_t* mask = (uint64_t*)(base + 3 * vb);
+    double* part = (double*)(base + 3 * vb + align_up((size_t)n * 8));
+    double* scal = (double*)((char*)part + pb);
+    const Blk one = Blk::plain(1);
+    LD_CHECK_HIP(launch_sign_mask((int)n, 1, probe_stream_key(0, 2), mask, st));
+    LD_CHECK_HIP(launch_fill_signs(f64, (int)n, 1, 1, 0, mask, 1.0 / std::sqrt((double)n), vec[1], st));
+    const int k_max = (int)std::min<long long>(steps, n);
+    std::vector<double> a, b;   // diagonal, off-diagonal of the projection
+    double beta = 0.0;
+    auto dot = [&](const void* x, const void* y, double* r) -> int {
+        LD_CHECK(cross_product(f64, (int)n, x, one, 1, y, one, 1, false, 0, part, scal, st));
+        LD_CHECK_HIP(hipMemcpyAsync(r, scal, sizeof(double), hipMemcpyDeviceToHost, st));
+        LD_CHECK_HIP(hipStreamSynchronize(st));
+        return LD_OK;
+    };
+    for (int j = 0; j < k_max; ++j) {
+        StepArgs s{};
+        s.kind = STEP_PLAIN;
+        s.win = vec[1];
+        s.wout = vec[2];
+        s.ld = 1;
+        s.alpha = 1.0;
+        s.beta = 0.0;
+        LD_CHECK(run_step(f64, A, s, 1, 1, st, nullptr, LongRows{}));      // w = A v_j
+        double alpha = 0.0;
+        LD_CHECK(dot(vec[1], vec[2], &alpha));
+        LD_CHECK_HIP(launch_axpby(f64, n, -alpha, vec[1], 1.0, vec[2], st));
+        if (j > 0) LD_CHECK_HIP(launch_axpby(f64, n, -beta, vec[0], 1.0, vec[2], st));
+        a.push_back(alpha);
+        double bb = 0.0;
+        LD_CHECK(dot(vec[2], vec[2], &bb));
+        beta = std::sqrt(std::fmax(bb, 0.0));
+        if (!std::isfinite(alpha) || !std::isfinite(beta))
+            return fail(LD_EINVAL, "non-finite value in the Lanczos recurrence (non-finite entries of A?)");
+        if (j + 1 == k_max || beta <= 1e-14 * std::fmax(std::fabs(alpha), abs_bound)) break;   // done / invariant subspace
+        b.push_back(beta);
+        // v_{j+1} = w / beta into the buffer of v_{j-1}; then rotate
+        LD_CHECK_HIP(launch_scale_copy(f64, (int)n, 1, vec[2], 1, 1.0 / beta, vec[0], 1, st));
+        std::swap(vec[0], vec[1]);   // vec[1] = v_{j+1}, vec[0] = v_j
+    }
+    double theta = 0.0, last = 0.0;
+    tridiag_top_eigenpair(a, b, &theta, &last);
+    *out = theta + beta * std::fabs(last) + 8.0 * 0x1p-53 * abs_bound * std::sqrt((double)a.size());
+    LD_CHECK_HIP(hipStreamSynchronize(st));
+    return LD_OK;
+}
+
 extern "C" {
 
 int ld_workspace_size(const ld_csr* A, int32_t degree, int32_t n_matvec, int32_t want_grad,
@@ -963,8 +1043,9 @@ int ld_spectral_bounds(const ld_csr* A, int32_t lanczos_steps, void* stream, dou
                        double* lmax) {
     clear_error();
     LD_CHECK(check_csr_args(A));
-    if (!lmin || !lmax || lanczos_steps < 0) return fail(LD_EINVAL, "bad arguments");
-    if (lanczos_steps > 0) return fail(LD_EINVAL, "Lanczos refinement is not available");
+    if (!lmin || !lmax || lanczos_steps < 0 || lanczos_steps > kMaxLanczos)
+        return fail(LD_EINVAL, "need lmin, lmax non-null and 0 <= lanczos_steps <= " +
+                                   std::to_string(kMaxLanczos));
     hipStream_t st = (hipStream_t)stream;
     const int nwg = gersh_num_wg((int)A->n);
     OwnedWs own;
@@ -983,6 +1064,11 @@ int ld_spectral_bounds(const ld_csr* A, int32_t lanczos_steps, void* stream, dou
     }
     *lmin = lo;
     *lmax = hi;
+    if (lanczos_steps > 0 && A->n > 0) {
+        double top = hi;
+        LD_CHECK(lanczos_upper(A, lanczos_steps, std::fmax(std::fabs(lo), std::fabs(hi)), st, &top));
+        *lmax = std::fmin(hi, top);
+    }
     if (!(lo > 0.0)) return fail(LD_EINDEF, "Gershgorin lower bound is not positive");
     return LD_OK;
 }

@@ -268,6 +268,57 @@ bool cholesky_upper(const double* G, int k, double* R, double* Rinv) {
     return true;
 }
 
+void tridiag_top_eigenpair(const std::vector<double>& a, const std::vector<double>& b, double* theta,
+                           double* last) {
+    const int k = (int)a.size();
+    std::vector<double> M((size_t)k * k, 0.0), V((size_t)k * k, 0.0);
+    for (int i = 0; i < k; ++i) {
+        M[(size_t)i * k + i] = a[i];
+        V[(size_t)i * k + i] = 1.0;
+        if (i + 1 < k) M[(size_t)i * k + i + 1] = M[(size_t)(i + 1) * k + i] = b[i];
+    }
+    // cyclic Jacobi: rotate away each off-diagonal entry in turn until the
+    // off-diagonal mass is negligible against the diagonal
+    for (int sweep = 0; sweep < 100; ++sweep) {
+        double off = 0.0, dia = 0.0;
+        for (int i = 0; i < k; ++i)
+            for (int j = 0; j < k; ++j) {
+                const double x = M[(size_t)i * k + j];
+                (i == j ? dia : off) += x * x;
+            }
+        if (off <= 1e-32 * dia || off == 0.0) break;
+        for (int p = 0; p < k; ++p)
+            for (int q = p + 1; q < k; ++q) {
+                const double apq = M[(size_t)p * k + q];
+                if (apq == 0.0) continue;
+                const double app = M[(size_t)p * k + p], aqq = M[(size_t)q * k + q];
+                const double tau = (aqq - app) / (2.0 * apq);
+                const double t = (tau >= 0 ? 1.0 : -1.0) / (std::fabs(tau) + std::sqrt(1.0 + tau * tau));
+                const double c = 1.0 / std::sqrt(1.0 + t * t), s = t * c;
+                for (int r = 0; r < k; ++r) {   // M <- M J (columns p, q)
+                    const double mp = M[(size_t)r * k + p], mq = M[(size_t)r * k + q];
+                    M[(size_t)r * k + p] = c * mp - s * mq;
+                    M[(size_t)r * k + q] = s * mp + c * mq;
+                }
+                for (int r = 0; r < k; ++r) {   // M <- J^T M (rows p, q)
+                    const double mp = M[(size_t)p * k + r], mq = M[(size_t)q * k + r];
+                    M[(size_t)p * k + r] = c * mp - s * mq;
+                    M[(size_t)q * k + r] = s * mp + c * mq;
+                }
+                for (int r = 0; r < k; ++r) {   // V <- V J
+                    const double vp = V[(size_t)r * k + p], vq = V[(size_t)r * k + q];
+                    V[(size_t)r * k + p] = c * vp - s * vq;
+                    V[(size_t)r * k + q] = s * vp + c * vq;
+                }
+            }
+    }
+    int top = 0;
+    for (int i = 1; i < k; ++i)
+        if (M[(size_t)i * k + i] > M[(size_t)top * k + top]) top = i;
+    *theta = M[(size_t)top * k + top];
+    *last = V[(size_t)(k - 1) * k + top];   // column `top` of V is the eigenvector
+}
+
 void KahanSum::add(double x) {
     double t = s + x;
     if (std::fabs(s) >= std::fabs(x))

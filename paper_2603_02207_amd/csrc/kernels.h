@@ -139,6 +139,9 @@ struct AdjArgs {
 };
 hipError_t launch_adjoint(bool f64, const CsrDev& A, const AdjArgs& a, hipStream_t st);
 
+// y[i] = (double)x[i], i < len.
+hipError_t launch_widen(long long len, const float* x, double* y, hipStream_t st);
+
 // y = a*x + b*y elementwise on contiguous arrays of length len.
 hipError_t launch_axpby(bool f64, long long len, double a, const void* x, double b, void* y,
                         hipStream_t st);

@@ -1014,6 +1014,18 @@ __global__ __launch_bounds__(kThreads) void axpby_kernel(long long len, T a, con
     if (i < len) y[i] = a * x[i] + b * y[i];
 }
 
+__global__ __launch_bounds__(kThreads) void widen_kernel(long long len, const float* __restrict__ x,
+                                                         double* __restrict__ y) {
+    const long long i = (long long)blockIdx.x * kThreads + threadIdx.x;
+    if (i < len) y[i] = (double)x[i];
+}
+
+hipError_t launch_widen(long long len, const float* x, double* y, hipStream_t st) {
+    if (len == 0) return hipSuccess;
+    hipLaunchKernelGGL(widen_kernel, dim3(div_up(len, kThreads)), dim3(kThreads), 0, st, len, x, y);
+    return hipGetLastError();
+}
+
 hipError_t launch_axpby(bool f64, long long len, double a, const void* x, double b, void* y,
                         hipStream_t st) {
     if (len == 0) return hipSuccess;

@@ -36,6 +36,12 @@ uint64_t probe_stream_key(uint64_t seed, int stream);
 // numerically positive definite.
 bool cholesky_upper(const double* G, int k, double* R, double* Rinv);
 
+// Largest eigenvalue of the symmetric tridiagonal matrix with diagonal a[0..k)
+// and off-diagonal b[0..k-1) (cyclic Jacobi on the dense k x k matrix), and
+// the last component of its unit eigenvector.
+void tridiag_top_eigenpair(const std::vector<double>& a, const std::vector<double>& b, double* theta,
+                           double* last);
+
 // Neumaier-compensated FP64 sum.
 struct KahanSum {
     double s = 0.0, c = 0.0;

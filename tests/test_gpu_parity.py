@@ -204,6 +204,30 @@ def test_spectral_bounds_match_oracle():
             assert hi == pytest.approx(rhi, rel=1e-12)
 
 
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
+def test_lanczos_upper_bound(dtype):
+    # Appendix A's Lanczos refinement of lambda_max: the device result must lie
+    # between the true top eigenvalue and Gershgorin's bound, and agree with the
+    # oracle's Ritz value + residual from the same start vector.
+    from oracle import rng
+    cases = ((w.chung_lu_laplacian(1500, seed=1), 40), (w.grid_laplacian_2d(30, 0.5), 25),
+             (w.pentadiagonal(800, seed=3), 30), (random_spd_csr(600, 4, long_rows=2), 20))
+    for csr, steps in cases:
+        A, vals = to_gpu(csr, dtype)
+        csr_v = (csr[0], csr[1], vals, csr[3])
+        Q = w.to_scipy(csr_v)
+        top = np.linalg.eigvalsh(Q.toarray())[-1]
+        g_lo, g_hi = bounds.gershgorin(csr_v)
+        lo, hi = ld.spectral_bounds(A, lanczos_steps=steps)
+        assert lo == pytest.approx(g_lo, rel=1e-12, abs=1e-12)
+        assert top * (1 - 1e-9) <= hi <= g_hi * (1 + 1e-12)
+        theta, upper = bounds.lanczos_upper(Q, steps, rng.rademacher(0, 2, csr[3], 1)[:, 0])
+        # the refinement runs in FP64 on the (FP32-rounded) values in both cases
+        assert hi == pytest.approx(min(upper, g_hi), rel=1e-8)
+    with pytest.raises(ld.NativeError):
+        ld.spectral_bounds(A, lanczos_steps=10**6)
+
+
 def test_invalid_csr_is_rejected():
     csr = w.grid_laplacian_2d(6, 0.5)
     bad_cols = csr[1].copy()

@@ -34,6 +34,30 @@ def test_lanczos_lmax():
     assert est == pytest.approx(ev[-1], rel=1e-6)
 
 
+def test_lanczos_upper_brackets_top_eigenvalue():
+    from oracle import rng
+    for A, steps in ((w.chung_lu_laplacian(1500, seed=1), 40), (w.grid_laplacian_2d(30, 0.5), 25),
+                     (w.pentadiagonal(800, seed=3), 30)):
+        Q = w.to_scipy(A)
+        n = Q.shape[0]
+        ev = np.linalg.eigvalsh(Q.toarray())
+        v0 = rng.rademacher(0, 2, n, 1)[:, 0]
+        theta, upper = bounds.lanczos_upper(Q, steps, v0)
+        assert theta <= ev[-1] * (1 + 1e-12)         # a Ritz value never exceeds lambda_max
+        assert upper >= ev[-1] * (1 - 1e-12)         # the residual margin covers the gap
+        assert upper <= bounds.gershgorin(A)[1] * 1.5
+
+
+def test_lanczos_upper_whole_space_is_exact():
+    A = w.grid_laplacian_2d(6, 0.3)
+    Q = w.to_scipy(A)
+    ev = np.linalg.eigvalsh(Q.toarray())
+    from oracle import rng
+    theta, upper = bounds.lanczos_upper(Q, 36, rng.rademacher(0, 2, 36, 1)[:, 0])
+    assert theta == pytest.approx(ev[-1], rel=1e-12)
+    assert upper == pytest.approx(ev[-1], rel=1e-10)
+
+
 def test_closed_form_logdets():
     for N, k2 in ((5, 0.5), (9, 0.1)):
         Q = w.to_scipy(w.grid_laplacian_2d(N, k2, tau=1.5)).toarray()
