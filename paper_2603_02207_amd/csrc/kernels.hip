@@ -75,6 +75,11 @@ constexpr int kAdjStageNz = 1536;  // CSR entries one adjoint workgroup stages i
 
 constexpr bool is_dot(int kind) { return kind == STEP_DOT_FWD || kind == STEP_DOT_SQ; }
 constexpr int threads_of(int) { return 256; }
+// Kinds with column sums run a fixed grid of at most kDotWgs workgroups (all
+// resident on the 256 CUs), each looping over row tiles and reducing its
+// column sums once; the others launch one workgroup per tile.
+constexpr int kDotWgs = 2048;
+inline int grid_of(int kind, int ntiles) { return is_dot(kind) && ntiles > kDotWgs ? kDotWgs : ntiles; }
 
 // ---------------------------------------------------------------------------
 // Newton step: out = alpha*A*in - beta*in (+ dj*source), optional dot partials
@@ -100,7 +105,7 @@ __global__ __launch_bounds__(NT) void step_kernel(
     int bcols, int gshift, T alpha, T beta, T dj, const T* __restrict__ vsrc, int ldv,
     const uint64_t* __restrict__ mask, double* __restrict__ ps0, double* __restrict__ ps1,
     double* __restrict__ ps2, int part_ld, int lpr, int rpw, int skip_long, T* __restrict__ accum,
-    int ldacc, int acc_cols) {
+    int ldacc, int acc_cols, int ntiles) {
     constexpr bool kDot = is_dot(KIND);
     constexpr int NW = NT / 64;
     constexpr int kSums = kDot ? ((FIRST ? 1 : 0) + 1 + (KIND == STEP_DOT_SQ ? 1 : 0)) : 0;
@@ -119,9 +124,6 @@ __global__ __launch_bounds__(NT) void step_kernel(
     const bool lane_ok = g < rpw;
     const int col = c0 + li * VEC;
     const int rows_per_wave = rpw * ITERS;
-    const int R0 = xcd_tile(blockIdx.x, gridDim.x) * (NW * rows_per_wave);
-    const int W0 = R0 + wave * rows_per_wave;             // first row of this wave
-    const int nrows = max(0, min(rows_per_wave, n - W0));
     if constexpr (kDot) {
         if (threadIdx.x == 0) s_count = 0;
         __syncthreads();   // the only workgroup barrier: the counter is set before any wave can finish
@@ -130,8 +132,26 @@ __global__ __launch_bounds__(NT) void step_kernel(
     T* const s_val = reinterpret_cast<T*>(s_wave[wave]);
     int* const s_col = reinterpret_cast<int*>(s_wave[wave] + kWaveNz * sizeof(T));
     int* const rp = s_rp[wave];
+    double s0[VEC], s1[VEC], s2[VEC];
+#pragma unroll
+    for (int e = 0; e < VEC; ++e) s0[e] = s1[e] = s2[e] = 0.0;
+
+    // Tiles of NW*rows_per_wave rows.  XCD x (= blockIdx % 8) owns the
+    // contiguous band of tiles [x*base + min(x, rem), ...) and its workgroups
+    // take the band's tiles round-robin in order, so the XCD's active rows
+    // stay a narrow window; with one workgroup per tile each takes one.
+    const int xcd = blockIdx.x % kXcds;
+    const int base = ntiles / kXcds, rem = ntiles % kXcds;
+    const int band0 = xcd * base + (xcd < rem ? xcd : rem);
+    const int band_len = base + (xcd < rem ? 1 : 0);
+    const int wgs_here = gridDim.x / kXcds + (xcd < (int)(gridDim.x % kXcds) ? 1 : 0);
+    for (int t = blockIdx.x / kXcds; t < band_len; t += wgs_here) {
+    const int W0 = (band0 + t) * (NW * rows_per_wave) + wave * rows_per_wave;   // first row of this wave
+    const int nrows = max(0, min(rows_per_wave, n - W0));
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");   // the previous tile's LDS reads come first
+    __builtin_amdgcn_wave_barrier();
     if (nrows > 0)   // waves past the last row read nothing
-        for (int t = lane; t <= nrows; t += 64) rp[t] = row_ptr[W0 + t];
+        for (int t2 = lane; t2 <= nrows; t2 += 64) rp[t2] = row_ptr[W0 + t2];
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_wave_barrier();
     const int K0 = nrows > 0 ? rp[0] : 0;
@@ -145,10 +165,6 @@ __global__ __launch_bounds__(NT) void step_kernel(
     }
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_wave_barrier();
-
-    double s0[VEC], s1[VEC], s2[VEC];
-#pragma unroll
-    for (int e = 0; e < VEC; ++e) s0[e] = s1[e] = s2[e] = 0.0;
 
 #pragma unroll
     for (int it = 0; it < ITERS; ++it) {
@@ -236,6 +252,7 @@ __global__ __launch_bounds__(NT) void step_kernel(
         }
         store_pack<T, VEC>(wout + (size_t)row * ld + col, o);
     }
+    }   // tiles
 
     if constexpr (kDot) {
         // 1) per wave: the row groups' sums of each column, in group order
@@ -421,14 +438,15 @@ hipError_t launch_step_t(const CsrDev& A, const StepArgs& s, hipStream_t st) {
     if (lpr > 64) return hipErrorInvalidValue;
     const int rpw = 64 / lpr;
     const int rows_per_wg = (NT / 64) * rpw * kIters;
-    const int nwg = div_up(A.n, rows_per_wg);
+    const int ntiles = div_up(A.n, rows_per_wg);
+    const int nwg = grid_of(KIND, ntiles);
     if (nwg == 0) return hipSuccess;
     const int skip = s.long_rows != nullptr;
     hipLaunchKernelGGL((step_kernel<T, VEC, KIND, FIRST, kIters, NT>), dim3(nwg), dim3(NT), 0, st,
                        A.n, A.row_ptr, A.col_idx, (const T*)A.val, (const T*)s.win, (T*)s.wout, s.ld,
                        s.c0, s.bcols, s.gshift, (T)s.alpha, (T)s.beta, (T)s.dj, (const T*)s.vsrc,
                        s.ldv, s.mask, s.ps0, s.ps1, s.ps2, s.part_ld, lpr, rpw, skip, (T*)s.acc,
-                       s.ldacc, s.acc_cols);
+                       s.ldacc, s.acc_cols, ntiles);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess || !skip) return e;
     hipLaunchKernelGGL((long_row_kernel<T, VEC, KIND, FIRST>), dim3(kLongWgs), dim3(256), 0, st,
@@ -478,7 +496,7 @@ int step_num_wg_bound(int n, int bcols, int elem_bytes) {
     // blocks aligned to the 16-byte vector (the estimator's internal layout),
     // plus the partial rows of the long-row launch
     const int rows = (threads_of(STEP_PLAIN) / 64) * (64 / lanes_per_row(bcols, 16 / elem_bytes)) * kStepIters;
-    return div_up(n, rows) + kLongWgs;
+    return grid_of(STEP_DOT_SQ, div_up(n, rows)) + kLongWgs;
 }
 
 int step_max_cols(bool f64, const StepArgs& s) { return 64 * pick_vec(s, f64 ? 8 : 4); }
@@ -486,7 +504,7 @@ int step_max_cols(bool f64, const StepArgs& s) { return 64 * pick_vec(s, f64 ? 8
 int step_num_wg(bool f64, int n, const StepArgs& s) {
     const int vec = pick_vec(s, f64 ? 8 : 4);
     const int rows = (threads_of(s.kind) / 64) * (64 / lanes_per_row(s.bcols, vec)) * kStepIters;
-    return div_up(n, rows) + (s.long_rows ? kLongWgs : 0);   // partial rows written
+    return grid_of(s.kind, div_up(n, rows)) + (s.long_rows ? kLongWgs : 0);   // partial rows written
 }
 
 hipError_t launch_step(bool f64, const CsrDev& A, const StepArgs& s, hipStream_t st) {
