@@ -16,6 +16,7 @@
 // deterministic.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cstdint>
 
 #include "kernels.h"
@@ -63,6 +64,7 @@ __device__ __forceinline__ uint64_t probe_bits(uint64_t key, uint64_t i) {
 }
 
 int div_up(long long a, long long b) { return (int)((a + b - 1) / b); }
+__device__ __forceinline__ int div_up_dev(int a, int b) { return (int)(((long long)a + b - 1) / b); }
 
 // rows of one row group iteration
 inline int lanes_per_row(int bcols, int vec) { return (bcols + vec - 1) / vec; }
@@ -663,11 +665,14 @@ hipError_t launch_scale_copy(bool f64, int n, int ncols, const void* V, int ldv,
 // A = X^T and B = Z over a chunk of 4 rows, lane l simply loads
 // X[r0 + l/16][16*t + l%16].
 // ---------------------------------------------------------------------------
-constexpr int kCrossRows = 256;    // rows per workgroup
+constexpr int kCrossRows = 256;    // rows per tile
+constexpr int kCrossWgs = 2048;    // workgroups of a launch at most (each loops over tiles)
+constexpr int kCrossChunks = 4;    // 4-row chunks a wave loads before their MFMAs
 
 typedef double double4_t __attribute__((ext_vector_type(4)));
 
-template <typename T, int TX, int TZ, bool ZSIGNS>
+// SAME: Z is X (a Gram matrix): one load feeds both operands.
+template <typename T, int TX, int TZ, bool ZSIGNS, bool SAME>
 __global__ __launch_bounds__(kThreads) void cross_kernel(int n, const T* __restrict__ X, Blk bx,
                                                          int kx, const T* __restrict__ Z, Blk bz,
                                                          int kz, uint64_t key,
@@ -676,8 +681,6 @@ __global__ __launch_bounds__(kThreads) void cross_kernel(int n, const T* __restr
     const int wave = threadIdx.x >> 6;
     const int sub = lane >> 4;       // row within a chunk of 4
     const int cit = lane & 15;       // column within a 16-wide tile
-    const int tile = xcd_tile(blockIdx.x, gridDim.x);
-    const int row0 = tile * kCrossRows;
     double4_t acc[TX][TZ];
 #pragma unroll
     for (int a = 0; a < TX; ++a)
@@ -688,41 +691,50 @@ __global__ __launch_bounds__(kThreads) void cross_kernel(int n, const T* __restr
 #pragma unroll
     for (int a = 0; a < TX; ++a) xoff[a] = bx.offset(a * 16 + cit);
 #pragma unroll
-    for (int b = 0; b < TZ; ++b) zoff[b] = ZSIGNS ? 0 : bz.offset(b * 16 + cit);
-    // each wave takes chunks of 4 rows; two chunks are loaded before their MFMAs
-    for (int r0 = row0 + wave * 8; r0 < row0 + kCrossRows && r0 < n; r0 += kWaves * 8) {
-        double xa[2][TX], zb[2][TZ];
+    for (int b = 0; b < TZ; ++b) zoff[b] = (ZSIGNS || SAME) ? 0 : bz.offset(b * 16 + cit);
+    const int ntiles = div_up_dev(n, kCrossRows);
+    constexpr int kStep = kWaves * 4 * kCrossChunks;   // rows of one pass of the workgroup
+    for (int tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+        const int row0 = tile * kCrossRows;
+        const int row1 = min(row0 + kCrossRows, n);
+        for (int r0 = row0 + wave * 4 * kCrossChunks; r0 < row1; r0 += kStep) {
+            double xa[kCrossChunks][TX], zb[kCrossChunks][TZ];
 #pragma unroll
-        for (int h = 0; h < 2; ++h) {
-            const int r = r0 + 4 * h + sub;
-            const bool rok = r < n;
+            for (int h = 0; h < kCrossChunks; ++h) {
+                const int r = r0 + 4 * h + sub;
+                const bool rok = r < row1;
 #pragma unroll
-            for (int a = 0; a < TX; ++a) {
-                const int c = a * 16 + cit;
-                xa[h][a] = (rok && c < kx) ? (double)X[xoff[a] + (size_t)r * bx.ld] : 0.0;
-            }
+                for (int a = 0; a < TX; ++a) {
+                    const int c = a * 16 + cit;
+                    xa[h][a] = (rok && c < kx) ? (double)X[xoff[a] + (size_t)r * bx.ld] : 0.0;
+                }
+                if constexpr (!SAME) {
 #pragma unroll
-            for (int b = 0; b < TZ; ++b) {
-                const int c = b * 16 + cit;
-                double z = 0.0;
-                if (rok && c < kz) {
-                    if constexpr (ZSIGNS) {
-                        const uint64_t x = probe_bits(key, (uint64_t)c * (uint64_t)n + (uint64_t)r + 1ull);
-                        z = (x >> 63) ? -1.0 : 1.0;
-                    } else {
-                        z = (double)Z[zoff[b] + (size_t)r * bz.ld];
+                    for (int b = 0; b < TZ; ++b) {
+                        const int c = b * 16 + cit;
+                        double z = 0.0;
+                        if (rok && c < kz) {
+                            if constexpr (ZSIGNS) {
+                                const uint64_t x = probe_bits(key, (uint64_t)c * (uint64_t)n + (uint64_t)r + 1ull);
+                                z = (x >> 63) ? -1.0 : 1.0;
+                            } else {
+                                z = (double)Z[zoff[b] + (size_t)r * bz.ld];
+                            }
+                        }
+                        zb[h][b] = z;
                     }
                 }
-                zb[h][b] = z;
             }
+#pragma unroll
+            for (int h = 0; h < kCrossChunks; ++h)
+#pragma unroll
+                for (int a = 0; a < TX; ++a)
+#pragma unroll
+                    for (int b = 0; b < TZ; ++b)
+                        if (!SAME || a <= b)   // a Gram matrix: the tiles below the diagonal are mirrors
+                            acc[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(
+                                xa[h][a], SAME ? xa[h][b] : zb[h][b], acc[a][b], 0, 0, 0);
         }
-#pragma unroll
-        for (int h = 0; h < 2; ++h)
-#pragma unroll
-            for (int a = 0; a < TX; ++a)
-#pragma unroll
-                for (int b = 0; b < TZ; ++b)
-                    acc[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(xa[h][a], zb[h][b], acc[a][b], 0, 0, 0);
     }
 
     // sum the four waves in a fixed order through LDS
@@ -741,28 +753,41 @@ __global__ __launch_bounds__(kThreads) void cross_kernel(int n, const T* __restr
         }
         __syncthreads();
     }
-    // scatter to part[tile][i*kz + j]
+    // scatter to part[workgroup][i*kz + j]; element (il, jl) of tile (a, b) sits at
+    // lane 16*(il%4) + jl, accumulator element il/4
     for (int e = threadIdx.x; e < TX * TZ * 256; e += kThreads) {
         const int l = e & 63;
         const int v = (e >> 6) & 3;
         const int ab = e >> 8;
         const int a = ab / TZ, b = ab - a * TZ;
-        const int i = a * 16 + (l >> 4) + 4 * v;
-        const int j = b * 16 + (l & 15);
-        if (i < kx && j < kz) part[(size_t)blockIdx.x * kx * kz + i * kz + j] = sh[e];
+        const int il = (l >> 4) + 4 * v, jl = l & 15;
+        const int i = a * 16 + il;
+        const int j = b * 16 + jl;
+        if (i >= kx || j >= kz) continue;
+        double val;
+        if (SAME && a > b)   // mirror of element (jl, il) of tile (b, a)
+            val = sh[((b * TZ + a) * 4 + jl / 4) * 64 + 16 * (jl % 4) + il];
+        else
+            val = sh[e];
+        part[(size_t)blockIdx.x * kx * kz + i * kz + j] = val;
     }
 }
 
 template <typename T, int TX, int TZ>
 hipError_t launch_cross_t(int n, const void* X, Blk bx, int kx, const void* Z, Blk bz, int kz,
                           bool zsigns, uint64_t key, double* part, hipStream_t st) {
-    const int nwg = div_up(n, kCrossRows);
+    const int nwg = cross_num_wg(n);
     if (nwg == 0) return hipSuccess;
+    const bool same = !zsigns && X == Z && kx == kz && bx.ld == bz.ld && bx.bw == bz.bw &&
+                      bx.bstride == bz.bstride && bx.c0 == bz.c0;
     if (zsigns)
-        hipLaunchKernelGGL((cross_kernel<T, TX, TZ, true>), dim3(nwg), dim3(kThreads), 0, st, n,
+        hipLaunchKernelGGL((cross_kernel<T, TX, TZ, true, false>), dim3(nwg), dim3(kThreads), 0, st, n,
+                           (const T*)X, bx, kx, (const T*)Z, bz, kz, key, part);
+    else if (same && TX == TZ)
+        hipLaunchKernelGGL((cross_kernel<T, TX, TZ, false, TX == TZ>), dim3(nwg), dim3(kThreads), 0, st, n,
                            (const T*)X, bx, kx, (const T*)Z, bz, kz, key, part);
     else
-        hipLaunchKernelGGL((cross_kernel<T, TX, TZ, false>), dim3(nwg), dim3(kThreads), 0, st, n,
+        hipLaunchKernelGGL((cross_kernel<T, TX, TZ, false, false>), dim3(nwg), dim3(kThreads), 0, st, n,
                            (const T*)X, bx, kx, (const T*)Z, bz, kz, key, part);
     return hipGetLastError();
 }
@@ -781,7 +806,7 @@ hipError_t launch_cross_tx(int n, const void* X, Blk bx, int kx, const void* Z, 
     return hipErrorInvalidValue;
 }
 
-int cross_num_wg(int n) { return div_up(n, kCrossRows); }
+int cross_num_wg(int n) { return (int)std::min<long long>(div_up(n, kCrossRows), kCrossWgs); }
 
 hipError_t launch_cross(bool f64, int n, const void* X, Blk bx, int kx, const void* Z, Blk bz,
                         int kz, bool zsigns, uint64_t key, double* part, hipStream_t st) {
@@ -842,12 +867,15 @@ hipError_t launch_reduce(const double* part, int nwg, int len, int part_ld, int 
 // ---------------------------------------------------------------------------
 // row block times a small FP64 matrix (TRSM with R^{-1}; deflation G - Q C)
 // ---------------------------------------------------------------------------
-// A tile of RT rows per workgroup (one row per thread).  The tile of Y is
+// Tiles of RT rows (one row per thread); a grid of at most kRowmatWgs
+// workgroups loops over them, staging M once per workgroup.  The tile of Y is
 // loaded into LDS with coalesced accesses (consecutive threads read
 // consecutive columns), each thread multiplies its row by M (read from LDS at
 // the same address by every lane), the results go back into the tile, and
 // the tile is written out coalesced, adding the optional base matrix and
 // probe signs.  Y, base and out are column-blocked (Blk).
+constexpr int kRowmatWgs = 1024;
+
 template <typename T, int KY, int KO, bool SIGNS, int RT>
 __global__ __launch_bounds__(RT) void rowmat_kernel(int n, const T* __restrict__ Y, Blk by,
                                                     int ky, const double* __restrict__ M,
@@ -867,7 +895,9 @@ __global__ __launch_bounds__(RT) void rowmat_kernel(int n, const T* __restrict__
         boff[j] = j < kout ? bb.offset(j) : 0;
     }
     __syncthreads();
-    const int row0 = xcd_tile(blockIdx.x, gridDim.x) * RT;
+    const int ntiles = div_up_dev(n, RT);
+    for (int t = blockIdx.x; t < ntiles; t += gridDim.x) {
+    const int row0 = t * RT;
     const int nr = min(RT, n - row0);
     for (int e = threadIdx.x; e < nr * ky; e += RT) {
         const int r = e / ky, i = e - r * ky;
@@ -898,6 +928,8 @@ __global__ __launch_bounds__(RT) void rowmat_kernel(int n, const T* __restrict__
         if (base) v += base[boff[j] + (size_t)row * bb.ld];
         out[ooff[j] + (size_t)row * bo.ld] = v;
     }
+    __syncthreads();   // the tile is reused by the next iteration
+    }
 }
 
 template <typename T, int KY, int KO>
@@ -905,7 +937,7 @@ void launch_rowmat_t(int n, hipStream_t st, const void* Y, Blk by, int ky, const
                      int kout, double sign_m, bool signs, uint64_t key, const void* base, Blk bb,
                      void* out, Blk bo) {
     constexpr int RT = (sizeof(T) == 8 && KY == 64 && KO == 64) ? 128 : 256;
-    const int nwg = div_up(n, RT);
+    const int nwg = std::min(div_up(n, RT), kRowmatWgs);
     if (signs)
         hipLaunchKernelGGL((rowmat_kernel<T, KY, KO, true, RT>), dim3(nwg), dim3(RT), 0, st, n,
                            (const T*)Y, by, ky, M, kout, sign_m, key, (const T*)base, bb, (T*)out, bo);
