@@ -44,6 +44,9 @@ def parse():
                    help="also time the gradient entry point against the estimate alone")
     p.add_argument("--calibrate-copy", action="store_true",
                    help="only run a 1 GiB device-to-device copy (reference for the memory counters)")
+    p.add_argument("--all", action="store_true",
+                   help="one JSON line per workload (FP32 and FP64, no CPU baseline), about 2 s of "
+                        "timed work per precision each")
     return p.parse_args()
 
 
@@ -166,14 +169,31 @@ def main():
               "(multi-GPU sharding is described in DESIGN.md, not implemented)", file=sys.stderr)
         sys.exit(2)
 
+    import torch
+
+    import workloads
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    if not args.all:
+        print(json.dumps(run_workload(args, args.workload, args.steps)), flush=True)
+        return
+    for name in workloads.CONFIGS:
+        args.no_cpu_baseline = True
+        out = run_workload(args, name, None)
+        print(json.dumps(out), flush=True)
+        torch.cuda.empty_cache()
+
+
+def run_workload(args, workload, steps):
+    """One bench record for `workload`; steps=None: as many as fit about 2 s."""
     import numpy as np
     import torch
 
     import paper_2603_02207_amd as ld
     import workloads
 
-    assert torch.cuda.is_available(), "bench.py needs a GPU"
     dev = "cuda:0"
+    args.workload = workload
     cfg = dict(workloads.CONFIGS[args.workload])
     csr = workloads.build(args.workload)
     row_ptr, col_idx, val, n = csr
@@ -185,8 +205,12 @@ def main():
     lmin, lmax = ld.spectral_bounds(A32)           # Gershgorin on the device (also checks the CSR)
     A64 = ld.CSR.from_arrays(row_ptr, col_idx, val, n, device=dev, dtype=torch.float64)
     opts = ld.Options(block_cols=args.block_cols, dot_mode=mode, trusted_csr=1)
+    t = time.perf_counter()
     ld.logdet(A32, lmin, lmax, degree, m_vec, args.seed)   # validated call
     torch.cuda.synchronize()
+    if steps is None:
+        steps = int(min(20, max(3, 2.0 / max(time.perf_counter() - t, 1e-3))))
+    args.steps = steps
 
     est32, st, dt = time_estimates(ld, A32, lmin, lmax, degree, m_vec, args.seed, opts, args.steps,
                                    args.warmup)
@@ -285,11 +309,9 @@ def main():
                            "ckpt_stride": "auto (every forward vector kept when they fit 64 GiB)"}
 
     if not args.no_cpu_baseline:
-        vals32 = A32.val.double().cpu().numpy()
         out["cpu_baseline"] = cpu_baseline((row_ptr, col_idx, np.asarray(val), n), lmin, lmax, degree,
                                            m_vec, args.seed)
-        del vals32
-    print(json.dumps(out), flush=True)
+    return out
 
 
 if __name__ == "__main__":
