@@ -16,8 +16,11 @@ run in the mapped variable T = (Q~ - cI)/gamma, whose spectrum lies in
 
 This is the same polynomial P_m(Q~) (each factor carries 1/gamma and each
 d_j carries gamma^j), but keeps ||w_j|| bounded.  The degree m is fixed
-(the number of matrix products per column); the paper's adaptive stopping
-rule is not part of this path.
+(the number of matrix products per column) everywhere except in
+``apply_poly_adaptive``, which runs Alg. 2's loop: each column grows its own
+degree until the last Newton term is small, |d_m| ||w_m||_2 <= tol (reading:
+tol is absolute, as printed, with w_m the mapped-form vector; the loop never
+goes past the largest degree the Léja points allow).
 
 Pinned by: polynomial exactness with the divided differences of xi^q,
 interpolation of log at the nodes for a diagonal matrix with the nodes as
@@ -65,6 +68,28 @@ class NewtonPlan:
             P += self.d[j + 1] * W
         return P
 
+    def apply_poly_adaptive(self, Q, V, tol: float):
+        """Alg. 2 per column: (P, m) with m[c] the degree at which column c stopped.
+
+        Column c starts with w_0 = v, P = d_0 w_0, m = 0 and, while
+        |d_m| ||w_m||_2 > tol and m < degree, takes w_{m+1} = (T - xi_m) w_m,
+        m += 1, P += d_m w_m.
+        """
+        V = np.asarray(V, dtype=np.float64)
+        P = np.empty_like(V)
+        ms = np.zeros(V.shape[1], dtype=np.int64)
+        for c in range(V.shape[1]):
+            w = V[:, c].copy()
+            p = self.d[0] * w
+            m = 0
+            while abs(self.d[m]) * np.linalg.norm(w) > tol and m < self.degree:
+                w = self.alpha * (Q @ w) - self.beta[m] * w
+                m += 1
+                p = p + self.d[m] * w
+            P[:, c] = p
+            ms[c] = m
+        return P, ms
+
     def dots(self, Q, X):
         """s[j, col] = <X[:, col], w_j[:, col]> for j = 0..m, w_0 = X (DOT form)."""
         W = np.array(X, dtype=np.float64, copy=True)
@@ -90,3 +115,11 @@ def apply_log(Q, V, lmin: float, lmax: float, degree: int):
     """log(Q) V ~= P_m(Q~) V + log(sigma) V."""
     plan = NewtonPlan(lmin, lmax, degree)
     return plan.apply_poly(Q, V) + math.log(plan.sigma) * np.asarray(V, dtype=np.float64)
+
+
+def apply_log_adaptive(Q, V, lmin: float, lmax: float, max_degree: int, tol: float):
+    """(log(Q) V by Alg. 2 with per-column stopping, per-column degrees); the log(sigma) V
+    term of the scaling is added after the loop."""
+    plan = NewtonPlan(lmin, lmax, max_degree)
+    P, ms = plan.apply_poly_adaptive(Q, V, tol)
+    return P + math.log(plan.sigma) * np.asarray(V, dtype=np.float64), ms

@@ -93,3 +93,57 @@ def test_dots_match_apply():
     X = rng.standard_normal((100, 3))
     s = plan.dots(Q, X)
     np.testing.assert_allclose(plan.d @ s, np.einsum("ij,ij->j", X, plan.apply_poly(Q, X)), rtol=1e-12)
+
+
+def _sine_mode(N, a, b):
+    i = np.arange(1, N + 1)
+    return np.outer(np.sin(np.pi * a * i / (N + 1)), np.sin(np.pi * b * i / (N + 1))).ravel()
+
+
+def test_adaptive_stopping_degree_closed_form():
+    # For an eigenvector v of Q with eigenvalue lam, w_m = pi_m(t) v with
+    # t = (lam/sigma - c)/gamma, so Alg. 2 stops at the first m with
+    # |d_m| |pi_m(t)| ||v|| <= tol and returns P_m(lam/sigma) v (+ log(sigma) v).
+    N, k2 = 24, 0.3
+    Q = w.to_scipy(w.grid_laplacian_2d(N, k2))
+    lmin, lmax = k2, k2 + 8.0
+    from oracle.newton import NewtonPlan as NP, apply_log_adaptive
+    plan = NP(lmin, lmax, 60)
+    modes = [(1, 1), (3, 7), (12, 12), (24, 23)]
+    V = np.stack([_sine_mode(N, a, b) for a, b in modes], axis=1)
+    lam = np.array([exact.grid_eigenvalue_2d(N, k2, a, b) for a, b in modes])
+    t = (lam / plan.sigma - plan.c) / plan.gamma
+    norms = np.linalg.norm(V, axis=0)
+    # e[m, col] = |d_m| |pi_m(t_col)| ||v_col|| by the scalar product formula
+    e = np.empty((61, len(modes)))
+    pi = np.ones_like(t)
+    for m in range(61):
+        e[m] = np.abs(plan.d[m]) * np.abs(pi) * norms
+        if m < 60:
+            pi = pi * (t - plan.xi[m])
+    for tol in (1e-3, 1e-7, 1e-11):
+        # expected stop: first m with e <= tol (a tol that sits exactly on some e would be a tie)
+        assert np.min(np.abs(np.log(e / tol))) > 1e-6
+        want = np.array([next((m for m in range(61) if e[m, c] <= tol), 60) for c in range(len(modes))])
+        P, ms = apply_log_adaptive(Q, V, lmin, lmax, 60, tol)
+        np.testing.assert_array_equal(ms, want)
+        for c in range(len(modes)):
+            ref = NP(lmin, lmax, max(int(ms[c]), 1))
+            val = ref.d[0] if ms[c] == 0 else ref.eval_scalar(lam[c])
+            np.testing.assert_allclose(P[:, c], (val + math.log(plan.sigma)) * V[:, c], rtol=1e-10,
+                                       atol=1e-12 * np.abs(V[:, c]).max())
+    assert len(set(want.tolist())) > 1          # the columns stopped at different degrees
+
+
+def test_adaptive_limits():
+    rng = np.random.default_rng(5)
+    Q = w.to_scipy(w.grid_laplacian_2d(10, 0.5))
+    V = rng.standard_normal((100, 3))
+    from oracle.newton import NewtonPlan as NP
+    plan = NP(0.5, 8.5, 30)
+    P, ms = plan.apply_poly_adaptive(Q, V, 0.0)          # never small enough: full degree
+    assert (ms == 30).all()
+    np.testing.assert_allclose(P, plan.apply_poly(Q, V), rtol=1e-14, atol=1e-14)
+    P, ms = plan.apply_poly_adaptive(Q, V, 1e30)         # stops before the first product
+    assert (ms == 0).all()
+    np.testing.assert_array_equal(P, plan.d[0] * V)
