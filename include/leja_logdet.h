@@ -163,8 +163,9 @@ int ld_squared_basis_coefficients(int32_t degree, const double* d_host, double* 
 /* ---- device entry points -------------------------------------------------- */
 
 /* Bytes of workspace needed by ld_logdet_estimate (want_grad = 0) or
- * ld_logdet_grad (want_grad = 1) for this matrix, degree and query count, or by
- * ld_apply_log when n_matvec is negative (then -n_matvec = number of columns).
+ * ld_logdet_grad (want_grad = 1) for this matrix, degree and query count, or,
+ * when n_matvec is negative (-n_matvec = number of columns), by ld_apply_log
+ * (want_grad = 0) or ld_apply_log_adaptive (want_grad = 1).
  * opts may be NULL.  Errors: LD_EINVAL. */
 int ld_workspace_size(const ld_csr* A, int32_t degree, int32_t n_matvec, int32_t want_grad,
                       const ld_options* opts, size_t* bytes);
@@ -178,6 +179,22 @@ int ld_workspace_size(const ld_csr* A, int32_t degree, int32_t n_matvec, int32_t
 int ld_apply_log(const ld_csr* A, double lmin, double lmax, int32_t degree, const void* V,
                  void* PV, int64_t ncols, const ld_options* opts, void* workspace,
                  size_t ws_bytes, void* stream);
+
+/* Alg. 2 with its adaptive degree, per column: column c starts from w_0 = v,
+ * P = d_0 w_0, m = 0 and, while |d_m| ||w_m||_2 > tol and m < max_degree,
+ * takes w_{m+1} = (T - xi_m) w_m, m += 1, P += d_m w_m (mapped variable
+ * T = (Q~ - cI)/gamma, forward order; tol absolute, as in Alg. 2).  Returns
+ * PV = P + log(sigma) V and, in degrees (host, ncols entries, may be NULL),
+ * the degree m at which each column stopped (max_degree if it never met tol).
+ * The norms are FP64 sums of the column's squares; the stopping test runs on
+ * the device after every step, and the host stops launching steps once every
+ * column has stopped (checked every 8 steps).
+ * V, PV: device, n x ncols row-major, dtype of A, must not overlap.
+ * Errors: LD_EINVAL (0 < lmin < lmax, max_degree >= 1, ncols >= 0, tol finite
+ * and >= 0), LD_ECSR, LD_EWORKSPACE, LD_EHIP. */
+int ld_apply_log_adaptive(const ld_csr* A, double lmin, double lmax, int32_t max_degree, double tol,
+                          const void* V, void* PV, int64_t ncols, const ld_options* opts,
+                          void* workspace, size_t ws_bytes, void* stream, int32_t* degrees);
 
 /* Léja + Hutch++ estimate of log det A (Alg. 3) with n_matvec queries:
  * k = floor(n_matvec/3) sketch columns (probe stream 0), k_G = n_matvec - 2k

@@ -239,6 +239,34 @@ def apply_log(A: CSR, lmin: float, lmax: float, degree: int, V, options=None):
     return out
 
 
+def apply_log_adaptive(A: CSR, lmin: float, lmax: float, max_degree: int, tol: float, V, options=None):
+    """Alg. 2 with per-column adaptive degree: (log(A) V, degrees), each column
+    stopping at the first m with |d_m| ||w_m||_2 <= tol (at most max_degree)."""
+    torch = _torch()
+    lib = nat.load()
+    V = V.contiguous()
+    if V.dtype != A.dtype or V.dim() != 2 or V.shape[0] != A.n:
+        raise ValueError("V must be n x ncols with the matrix dtype")
+    out = torch.empty_like(V)
+    ncols = int(V.shape[1])
+    degrees = np.zeros(ncols, dtype=np.int32)
+    c = A.c_struct()
+    o = _opts(options)
+    ws = None
+    if ncols > 0:
+        b = ctypes.c_size_t(0)
+        nat.check(lib.ld_workspace_size(ctypes.byref(c), int(max_degree), -ncols, 1, ctypes.byref(o),
+                                        ctypes.byref(b)), "ld_workspace_size")
+        ws = _workspace(int(b.value), V.device)
+    nat.check(lib.ld_apply_log_adaptive(
+        ctypes.byref(c), float(lmin), float(lmax), int(max_degree), float(tol),
+        ctypes.c_void_p(V.data_ptr() if ncols else None), ctypes.c_void_p(out.data_ptr() if ncols else None),
+        ncols, ctypes.byref(o), ctypes.c_void_p(ws.data_ptr() if ws is not None else None),
+        ws.numel() if ws is not None else 0, _stream_handle(V.device),
+        degrees.ctypes.data_as(ctypes.POINTER(ctypes.c_int32))), "ld_apply_log_adaptive")
+    return out, degrees
+
+
 def spectral_bounds(A: CSR, lanczos_steps: int = 0):
     """Gershgorin interval (lmin, lmax) computed on the GPU in FP64; with
     ``lanczos_steps`` > 0 the upper end is refined by Lanczos (App. A)."""

@@ -105,6 +105,11 @@ SIGNATURES = {
                                     ctypes.c_int32, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64,
                                     ctypes.POINTER(LdOptions), ctypes.c_void_p, ctypes.c_size_t,
                                     ctypes.c_void_p]),
+    "ld_apply_log_adaptive": (ctypes.c_int, [ctypes.POINTER(LdCsr), ctypes.c_double, ctypes.c_double,
+                                             ctypes.c_int32, ctypes.c_double, ctypes.c_void_p,
+                                             ctypes.c_void_p, ctypes.c_int64, ctypes.POINTER(LdOptions),
+                                             ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p,
+                                             ctypes.POINTER(ctypes.c_int32)]),
     "ld_logdet_estimate": (ctypes.c_int, [ctypes.POINTER(LdCsr), ctypes.c_double, ctypes.c_double,
                                           ctypes.c_int32, ctypes.c_int32, ctypes.c_uint64,
                                           ctypes.POINTER(LdOptions), ctypes.c_void_p, ctypes.c_size_t,

@@ -954,6 +954,19 @@ int lanczos_upper(const ld_csr* A_in, int steps, double abs_bound, hipStream_t s
     return LD_OK;
 }
 
+// Workspace of the adaptive apply: two n x ncols blocks, step partials for
+// 64 columns, Gram partials, small sums, the mask, degrees, flag, long rows.
+constexpr int kAdaptPoll = 8;   // steps between host checks of the active mask
+
+size_t adaptive_ws_bytes(const ld_csr* A, int ncols) {
+    const size_t elem = A->dtype == LD_F64 ? 8 : 4;
+    const int n = (int)A->n;
+    return 2 * align_up((size_t)n * ncols * elem) +
+           align_up((size_t)step_num_wg_any(n) * 64 * 8) +
+           align_up((size_t)cross_num_wg(n) * 64 * 64 * 8) + align_up(64 * 64 * 8) + align_up(256) +
+           align_up((size_t)ncols * 4) + align_up(256) + long_rows_bytes(A);
+}
+
 extern "C" {
 
 int ld_workspace_size(const ld_csr* A, int32_t degree, int32_t n_matvec, int32_t want_grad,
@@ -963,6 +976,10 @@ int ld_workspace_size(const ld_csr* A, int32_t degree, int32_t n_matvec, int32_t
     LD_CHECK(check_csr_args(A));
     if (degree < 1) return fail(LD_EINVAL, "degree must be >= 1");
     const ld_options o = resolve(opts);
+    if (n_matvec < 0 && want_grad) {
+        *bytes = adaptive_ws_bytes(A, (int)(-(int64_t)n_matvec));
+        return LD_OK;
+    }
     if (n_matvec < 0) {
         const size_t elem = A->dtype == LD_F64 ? 8 : 4;
         *bytes = 2 * align_up((size_t)A->n * (size_t)(-(int64_t)n_matvec) * elem) + align_up(256) +
@@ -1026,6 +1043,94 @@ int ld_apply_log(const ld_csr* A, double lmin, double lmax, int32_t degree, cons
         cur = out;
     }
     if (!workspace) LD_CHECK_HIP(hipStreamSynchronize(st));
+    return LD_OK;
+}
+
+int ld_apply_log_adaptive(const ld_csr* A, double lmin, double lmax, int32_t max_degree, double tol,
+                          const void* V, void* PV, int64_t ncols, const ld_options* opts, void* workspace,
+                          size_t ws_bytes, void* stream, int32_t* degrees) {
+    clear_error();
+    LD_CHECK(check_csr_args(A));
+    if (ncols < 0 || ncols > (1 << 20)) return fail(LD_EINVAL, "bad ncols");
+    if (ncols > 0 && (!V || !PV)) return fail(LD_EINVAL, "V or PV is null");
+    if (!(tol >= 0.0) || !std::isfinite(tol)) return fail(LD_EINVAL, "tol must be finite and >= 0");
+    const ld_options o = resolve(opts);
+    Plan p;
+    LD_CHECK(make_plan(lmin, lmax, max_degree, o, p));
+    if (ncols == 0) return LD_OK;
+    hipStream_t st = (hipStream_t)stream;
+    const bool f64 = A->dtype == LD_F64;
+    const size_t elem = f64 ? 8 : 4;
+    const int n = (int)A->n, nc = (int)ncols;
+    const size_t blk = (size_t)n * nc * elem;
+    const uint8_t* v8 = (const uint8_t*)V;
+    uint8_t* p8 = (uint8_t*)PV;
+    if (v8 < p8 + blk && p8 < v8 + blk) return fail(LD_EINVAL, "V and PV overlap");
+    OwnedWs own;
+    Arena ar;
+    LD_CHECK(get_workspace(workspace, ws_bytes, adaptive_ws_bytes(A, nc), own, ar));
+    uint8_t* W[2] = {(uint8_t*)ar.take(blk), (uint8_t*)ar.take(blk)};
+    const int nwg_max = step_num_wg_any(n);
+    double* part = (double*)ar.take((size_t)nwg_max * 64 * 8);
+    double* gpart = (double*)ar.take((size_t)cross_num_wg(n) * 64 * 64 * 8);
+    double* sums = (double*)ar.take(64 * 64 * 8);
+    uint64_t* mask = (uint64_t*)ar.take(256);
+    int* deg = (int*)ar.take((size_t)nc * 4);
+    int* flag = (int*)ar.take(256);
+    if (!o.trusted_csr) LD_CHECK(validate_csr(A, flag, st));
+    LongRows lr;
+    LD_CHECK(build_long_rows(A, ar, st, lr));
+    const int m = p.degree;
+    const std::vector<int> deg0((size_t)nc, m);   // columns that never meet tol stop at the cap
+    LD_CHECK_HIP(hipMemcpyAsync(deg, deg0.data(), (size_t)nc * 4, hipMemcpyHostToDevice, st));
+    const uint64_t all = ~0ull;
+    for (int q0 = 0; q0 < nc; q0 += 64) {
+        const int qc = std::min(64, nc - q0);
+        const uint8_t* Vq = v8 + (size_t)q0 * elem;
+        uint8_t* Pq = p8 + (size_t)q0 * elem;
+        // P_0 = d_0 w_0 (+ log(sigma) v, the scaling term), w_0 = v
+        LD_CHECK_HIP(launch_scale_copy(f64, n, qc, Vq, nc, p.d[0] + std::log(p.sigma), Pq, nc, st));
+        // e_0 = |d_0| ||v||: the diagonal of the chunk's Gram matrix
+        LD_CHECK(cross_product(f64, n, Vq, Blk::plain(nc), qc, Vq, Blk::plain(nc), qc, false, 0, gpart, sums,
+                               st));
+        LD_CHECK_HIP(hipMemcpyAsync(mask, &all, 8, hipMemcpyHostToDevice, st));
+        LD_CHECK_HIP(launch_adapt_decide(sums, qc + 1, qc, std::fabs(p.d[0]), tol, 0, mask, deg + q0, st));
+        const uint8_t* cur = Vq;
+        for (int j = 0; j < m; ++j) {
+            uint8_t* out = W[j % 2] + (size_t)q0 * elem;
+            StepArgs s{};
+            s.kind = STEP_ACC_NORM;
+            s.win = cur;
+            s.wout = out;
+            s.ld = nc;
+            s.alpha = p.alpha;
+            s.beta = p.beta[j];
+            s.dj = p.d[j + 1];
+            s.acc = Pq;
+            s.ldacc = nc;
+            s.acc_cols = qc;
+            s.active = mask;
+            s.ps1 = part;
+            s.part_ld = 64;
+            int nwg = 0;
+            LD_CHECK(run_step(f64, A, s, qc, qc, st, &nwg, lr));
+            if (nwg > nwg_max) return fail(LD_EINVAL, "internal: partial sums overflow");
+            LD_CHECK_HIP(launch_reduce(part, nwg, qc, 64, 1, 0, sums, qc, st));
+            LD_CHECK_HIP(launch_adapt_decide(sums, 1, qc, std::fabs(p.d[j + 1]), tol, j + 1, mask, deg + q0, st));
+            cur = out;
+            if ((j + 1) % kAdaptPoll == 0 && j + 1 < m) {   // stop launching once every column is done
+                uint64_t h = 0;
+                LD_CHECK_HIP(hipMemcpyAsync(&h, mask, 8, hipMemcpyDeviceToHost, st));
+                LD_CHECK_HIP(hipStreamSynchronize(st));
+                if (h == 0) break;
+            }
+        }
+    }
+    std::vector<int> hdeg((size_t)nc);
+    LD_CHECK_HIP(hipMemcpyAsync(hdeg.data(), deg, (size_t)nc * 4, hipMemcpyDeviceToHost, st));
+    LD_CHECK_HIP(hipStreamSynchronize(st));   // also keeps deg0 and `all` alive until their copies ran
+    if (degrees)
+        for (int c = 0; c < nc; ++c) degrees[c] = hdeg[(size_t)c];
     return LD_OK;
 }
 

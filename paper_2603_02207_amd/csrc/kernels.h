@@ -16,6 +16,7 @@ enum StepKind : int {
     STEP_DOT_SQ = 3,        // out = alpha*A*in - beta*in; <in,out>, <out,out> (and <in,in>)
     STEP_PLAIN = 4,         // out = alpha*A*in - beta*in
     STEP_PLAIN_ACC = 5,     // PLAIN, and acc[r, c] += dj*out[r, c] for columns c < acc_cols
+    STEP_ACC_NORM = 6,      // PLAIN, acc += dj*out on the columns active in *active, <out,out>
 };
 
 // A dense n x cols matrix stored as column blocks of width bw: element
@@ -65,8 +66,9 @@ struct StepArgs {
     // regular ones: kLongWgs of them).
     const int* long_rows;      // device list of long rows (ascending), or null
     const int* long_count;     // device count of the list
-    void* acc;                 // PLAIN_ACC: row-major accumulator (column c of the step = column c)
+    void* acc;                 // PLAIN_ACC / ACC_NORM: row-major accumulator (column c of the step = column c)
     int ldacc, acc_cols;
+    const uint64_t* active;    // ACC_NORM: device word, bit (c - c0) set = column c still accumulates
 };
 
 constexpr int kLongRow = 64;     // entries above which a row is "long"
@@ -82,6 +84,7 @@ int step_num_wg(bool f64, int n, const StepArgs& s);
 // Widest column range of one launch (a row group spans at most one wave).
 int step_max_cols(bool f64, const StepArgs& s);
 int step_num_wg_bound(int n, int bcols, int elem_bytes);
+int step_num_wg_any(int n);   // bound for the column-sum kinds at any layout
 
 hipError_t launch_step(bool f64, const CsrDev& A, const StepArgs& s, hipStream_t st);
 
@@ -138,6 +141,13 @@ struct AdjArgs {
     bool last;       // no lam_out needed (only the SDDMM)
 };
 hipError_t launch_adjoint(bool f64, const CsrDev& A, const AdjArgs& a, hipStream_t st);
+
+// Alg. 2's stopping test after the step that produced w_m: for columns c < qc
+// still active in *mask, e = |d_m| sqrt(sums[c*stride]) <= tol clears the bit
+// and sets deg[c] = m (deg of the columns that never stop is left as set by
+// the caller).  One wave; sums are FP64 column sums of w_m^2.
+hipError_t launch_adapt_decide(const double* sums, int stride, int qc, double dm_abs, double tol, int m,
+                               uint64_t* mask, int* deg, hipStream_t st);
 
 // y[i] = (double)x[i], i < len.
 hipError_t launch_widen(long long len, const float* x, double* y, hipStream_t st);

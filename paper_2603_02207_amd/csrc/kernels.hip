@@ -75,7 +75,7 @@ constexpr int kMaxDotCols = 64;    // columns of one launch of the kinds with co
 constexpr int kAdjBatch = 4;       // CSR entries of a row whose gathers the adjoint issues together
 constexpr int kAdjStageNz = 1536;  // CSR entries one adjoint workgroup stages in LDS
 
-constexpr bool is_dot(int kind) { return kind == STEP_DOT_FWD || kind == STEP_DOT_SQ; }
+constexpr bool is_dot(int kind) { return kind == STEP_DOT_FWD || kind == STEP_DOT_SQ || kind == STEP_ACC_NORM; }
 constexpr int threads_of(int) { return 256; }
 // Kinds with column sums run a fixed grid of at most kDotWgs workgroups (all
 // resident on the 256 CUs), each looping over row tiles and reducing its
@@ -107,10 +107,11 @@ __global__ __launch_bounds__(NT) void step_kernel(
     int bcols, int gshift, T alpha, T beta, T dj, const T* __restrict__ vsrc, int ldv,
     const uint64_t* __restrict__ mask, double* __restrict__ ps0, double* __restrict__ ps1,
     double* __restrict__ ps2, int part_ld, int lpr, int rpw, int skip_long, T* __restrict__ accum,
-    int ldacc, int acc_cols, int ntiles) {
+    int ldacc, int acc_cols, int ntiles, const uint64_t* __restrict__ active) {
     constexpr bool kDot = is_dot(KIND);
     constexpr int NW = NT / 64;
     constexpr int kSums = kDot ? ((FIRST ? 1 : 0) + 1 + (KIND == STEP_DOT_SQ ? 1 : 0)) : 0;
+    static_assert(KIND != STEP_ACC_NORM || !FIRST, "ACC_NORM has no first-step variant");
     constexpr int kStageBytes = kWaveNz * (int)(sizeof(T) + 4);
     constexpr int kLaneBytes = 64 * VEC * 8;                  // per-lane sums of one wave
     constexpr int kWaveBytes = kStageBytes > kLaneBytes ? kStageBytes : kLaneBytes;
@@ -237,21 +238,30 @@ __global__ __launch_bounds__(NT) void step_kernel(
                 s1[e] += (double)w.v[e] * (double)o.v[e];
                 s2[e] += (double)o.v[e] * (double)o.v[e];
             }
+        } else if constexpr (KIND == STEP_ACC_NORM) {
+#pragma unroll
+            for (int e = 0; e < VEC; ++e) s1[e] += (double)o.v[e] * (double)o.v[e];
+        }
+        if constexpr (KIND == STEP_PLAIN_ACC || KIND == STEP_ACC_NORM) {
+            if (col < acc_cols) {
+                // ACC_NORM: only the columns still active in Alg. 2's loop accumulate
+                const uint64_t bits = KIND == STEP_ACC_NORM ? *active : ~0ull;
+                T* const pa = accum + (size_t)row * ldacc + col;
+                const Pack<T, VEC> a0 = load_pack<T, VEC>(pa);
+                Pack<T, VEC> a1;
+#pragma unroll
+                for (int e = 0; e < VEC; ++e) {
+                    const int b = col - c0 + e;
+                    const bool on = KIND == STEP_PLAIN_ACC || (b < 64 && ((bits >> (b & 63)) & 1ull));
+                    a1.v[e] = on ? fma(dj, o.v[e], a0.v[e]) : a0.v[e];
+                }
+                store_pack<T, VEC>(pa, a1);
+            }
         }
         // Every lane stores its whole vector: ld and c0 are multiples of VEC, so
         // the vector never leaves the row, and columns past c0+bcols in it get
         // the value of the same recurrence (real columns of a wider block, or
         // padding that no one reads).
-        if constexpr (KIND == STEP_PLAIN_ACC) {
-            if (col < acc_cols) {
-                T* const pa = accum + (size_t)row * ldacc + col;
-                const Pack<T, VEC> a0 = load_pack<T, VEC>(pa);
-                Pack<T, VEC> a1;
-#pragma unroll
-                for (int e = 0; e < VEC; ++e) a1.v[e] = fma(dj, o.v[e], a0.v[e]);
-                store_pack<T, VEC>(pa, a1);
-            }
-        }
         store_pack<T, VEC>(wout + (size_t)row * ld + col, o);
     }
     }   // tiles
@@ -313,7 +323,8 @@ __global__ __launch_bounds__(256) void long_row_kernel(
     int bcols, int gshift, T alpha, T beta, T dj, const T* __restrict__ vsrc, int ldv,
     const uint64_t* __restrict__ mask, double* __restrict__ ps0, double* __restrict__ ps1,
     double* __restrict__ ps2, int part_ld, int lpr, int rpw, const int* __restrict__ list,
-    const int* __restrict__ count, int part_row0, T* __restrict__ accum, int ldacc, int acc_cols) {
+    const int* __restrict__ count, int part_row0, T* __restrict__ accum, int ldacc, int acc_cols,
+    const uint64_t* __restrict__ active) {
     constexpr int NW = 4;
     __shared__ T s_acc[NW * 64 * VEC];
     const int lane = threadIdx.x & 63;
@@ -401,14 +412,22 @@ __global__ __launch_bounds__(256) void long_row_kernel(
                     s1[e] += (double)w.v[e] * (double)o.v[e];
                     s2[e] += (double)o.v[e] * (double)o.v[e];
                 }
+            } else if constexpr (KIND == STEP_ACC_NORM) {
+#pragma unroll
+                for (int e = 0; e < VEC; ++e) s1[e] += (double)o.v[e] * (double)o.v[e];
             }
-            if constexpr (KIND == STEP_PLAIN_ACC) {
+            if constexpr (KIND == STEP_PLAIN_ACC || KIND == STEP_ACC_NORM) {
                 if (col < acc_cols) {
+                    const uint64_t bits = KIND == STEP_ACC_NORM ? *active : ~0ull;
                     T* const pa = accum + (size_t)row * ldacc + col;
                     const Pack<T, VEC> a0 = load_pack<T, VEC>(pa);
                     Pack<T, VEC> a1;
 #pragma unroll
-                    for (int e = 0; e < VEC; ++e) a1.v[e] = fma(dj, o.v[e], a0.v[e]);
+                    for (int e = 0; e < VEC; ++e) {
+                        const int b = col - c0 + e;
+                        const bool on = KIND == STEP_PLAIN_ACC || (b < 64 && ((bits >> (b & 63)) & 1ull));
+                        a1.v[e] = on ? fma(dj, o.v[e], a0.v[e]) : a0.v[e];
+                    }
                     store_pack<T, VEC>(pa, a1);
                 }
             }
@@ -448,14 +467,14 @@ hipError_t launch_step_t(const CsrDev& A, const StepArgs& s, hipStream_t st) {
                        A.n, A.row_ptr, A.col_idx, (const T*)A.val, (const T*)s.win, (T*)s.wout, s.ld,
                        s.c0, s.bcols, s.gshift, (T)s.alpha, (T)s.beta, (T)s.dj, (const T*)s.vsrc,
                        s.ldv, s.mask, s.ps0, s.ps1, s.ps2, s.part_ld, lpr, rpw, skip, (T*)s.acc,
-                       s.ldacc, s.acc_cols, ntiles);
+                       s.ldacc, s.acc_cols, ntiles, s.active);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess || !skip) return e;
     hipLaunchKernelGGL((long_row_kernel<T, VEC, KIND, FIRST>), dim3(kLongWgs), dim3(256), 0, st,
                        A.n, A.row_ptr, A.col_idx, (const T*)A.val, (const T*)s.win, (T*)s.wout, s.ld,
                        s.c0, s.bcols, s.gshift, (T)s.alpha, (T)s.beta, (T)s.dj, (const T*)s.vsrc,
                        s.ldv, s.mask, s.ps0, s.ps1, s.ps2, s.part_ld, lpr, rpw, s.long_rows,
-                       s.long_count, nwg, (T*)s.acc, s.ldacc, s.acc_cols);
+                       s.long_count, nwg, (T*)s.acc, s.ldacc, s.acc_cols, s.active);
     return hipGetLastError();
 }
 
@@ -466,6 +485,9 @@ hipError_t launch_step_v(const CsrDev& A, const StepArgs& s, hipStream_t st) {
         case STEP_HORNER_VEC: return launch_step_t<T, VEC, STEP_HORNER_VEC, false>(A, s, st);
         case STEP_PLAIN: return launch_step_t<T, VEC, STEP_PLAIN, false>(A, s, st);
         case STEP_PLAIN_ACC: return launch_step_t<T, VEC, STEP_PLAIN_ACC, false>(A, s, st);
+        case STEP_ACC_NORM:
+            if (!s.active || !s.acc) return hipErrorInvalidValue;
+            return launch_step_t<T, VEC, STEP_ACC_NORM, false>(A, s, st);
         case STEP_DOT_FWD:
             return s.first ? launch_step_t<T, VEC, STEP_DOT_FWD, true>(A, s, st)
                            : launch_step_t<T, VEC, STEP_DOT_FWD, false>(A, s, st);
@@ -502,6 +524,11 @@ int step_num_wg_bound(int n, int bcols, int elem_bytes) {
 }
 
 int step_max_cols(bool f64, const StepArgs& s) { return 64 * pick_vec(s, f64 ? 8 : 4); }
+
+int step_num_wg_any(int n) {
+    // any vector width and column count: at most 8 rows per tile, at most kDotWgs tiles' workgroups
+    return grid_of(STEP_DOT_SQ, div_up(n, (threads_of(STEP_PLAIN) / 64) * kStepIters)) + kLongWgs;
+}
 
 int step_num_wg(bool f64, int n, const StepArgs& s) {
     const int vec = pick_vec(s, f64 ? 8 : 4);
@@ -1062,6 +1089,30 @@ __global__ __launch_bounds__(kThreads) void axpby_kernel(long long len, T a, con
                                                          T b, T* __restrict__ y) {
     const long long i = (long long)blockIdx.x * kThreads + threadIdx.x;
     if (i < len) y[i] = a * x[i] + b * y[i];
+}
+
+__global__ __launch_bounds__(64) void adapt_decide_kernel(const double* __restrict__ sums, int stride, int qc,
+                                                          double dm_abs, double tol, int m,
+                                                          uint64_t* __restrict__ mask, int* __restrict__ deg) {
+    const int c = threadIdx.x;
+    const uint64_t old = *mask;
+    const bool was = c < qc && ((old >> c) & 1ull);
+    bool keep = false;
+    if (was) {
+        const double e = dm_abs * sqrt(fmax(sums[(size_t)c * stride], 0.0));
+        keep = e > tol;
+        if (!keep) deg[c] = m;
+    }
+    const uint64_t now = __ballot(keep);
+    if (c == 0) *mask = now;
+}
+
+hipError_t launch_adapt_decide(const double* sums, int stride, int qc, double dm_abs, double tol, int m,
+                               uint64_t* mask, int* deg, hipStream_t st) {
+    if (qc < 1 || qc > 64) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(adapt_decide_kernel, dim3(1), dim3(64), 0, st, sums, stride, qc, dm_abs, tol, m, mask,
+                       deg);
+    return hipGetLastError();
 }
 
 __global__ __launch_bounds__(kThreads) void widen_kernel(long long len, const float* __restrict__ x,
