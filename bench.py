@@ -44,6 +44,12 @@ def parse():
                    help="also time the gradient entry point against the estimate alone")
     p.add_argument("--calibrate-copy", action="store_true",
                    help="only run a 1 GiB device-to-device copy (reference for the memory counters)")
+    p.add_argument("--adaptive-tol", type=float, default=0.0,
+                   help="also time Alg. 2's adaptive loop (ld_apply_log_adaptive) on k Rademacher columns "
+                        "with tol = this value times sqrt(n) (the norm of a probe), against the fixed degree")
+    p.add_argument("--sweep", action="store_true",
+                   help="only the theta sweep of the 5000 x 5000 GMRF I + theta*Adj (Sec. 5.2): one FP32 "
+                        "estimate per theta against the closed-form log det, one JSON line")
     p.add_argument("--all", action="store_true",
                    help="one JSON line per workload (FP32 and FP64, no CPU baseline), about 2 s of "
                         "timed work per precision each")
@@ -73,6 +79,9 @@ def describe(name, cfg, n, nnz):
     elif cfg["kind"] == "grid3d":
         shape = f"7-point Dirichlet Laplacian {cfg['N']}^3 grid"
         shift = f"L + {cfg['kappa2']} I"
+    elif cfg["kind"] == "gmrf_theta":
+        shape = f"GMRF precision I + theta*Adj (4 neighbours) on a {cfg['N']}x{cfg['N']} grid"
+        shift = f"theta = {cfg['theta']}"
     else:
         shape = "Chung-Lu power-law graph Laplacian (exponent 2.5, mean degree 16)"
         shift = "Lap + 0.01 I"
@@ -95,6 +104,69 @@ def time_estimates(ld, A, lmin, lmax, degree, m_vec, seed, opts, steps, warmup):
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
     return est, stats, dt
+
+
+def theta_sweep(args):
+    """log det Q(theta), Q = I + theta*Adj on 5000 x 5000, for the thetas of the stored sweep."""
+    import numpy as np
+    import torch
+
+    import paper_2603_02207_amd as ld
+    import workloads
+    from tests.gpu_common import golden
+
+    cfg = workloads.CONFIGS["gmrf5000_theta"]
+    N, degree, m_vec = cfg["N"], cfg["degree"], cfg["m_vec"]
+    row_ptr, col_idx, val, n = workloads.gmrf_theta(N, workloads.GMRF_THETAS[0])
+    A = ld.CSR.from_arrays(row_ptr, col_idx, val.astype(np.float32), n, device="cuda:0", dtype=torch.float32)
+    diag = torch.tensor(val == 1.0, device="cuda:0")
+    g = golden("gmrf5000_theta_sweep")
+    opts = ld.Options(trusted_csr=1)
+    rows = []
+    t_all = time.perf_counter()
+    for th in workloads.GMRF_THETAS:
+        At = A.with_values(torch.where(diag, torch.ones_like(A.val), torch.full_like(A.val, th)))
+        lmin, lmax = ld.spectral_bounds(At)
+        est, st, dt = time_estimates(ld, At, lmin, lmax, degree, m_vec, args.seed, opts, 3, 1)
+        r = g["results"][repr(th)] if g else None
+        row = {"theta": th, "lmin": lmin, "lmax": lmax, "estimate_f32": est, "ms_per_estimate": dt / 3 * 1e3}
+        if r is not None:
+            row.update(logdet_exact=r["logdet_exact"], rel_err_vs_exact=abs(est - r["logdet_exact"]) /
+                       abs(r["logdet_exact"]), z=(est - r["expectation"]) / r["sd_hutchinson"])
+        rows.append(row)
+    ms = [r["ms_per_estimate"] for r in rows]
+    return {"metric": "theta sweep of log det Q(theta), GMRF of Sec. 5.2", "workload":
+            describe("gmrf5000_theta", cfg, n, int(len(col_idx))), "n": n, "nnz": int(len(col_idx)),
+            "degree": degree, "m_vec": m_vec, "dtype": "f32", "estimates_per_s": 1e3 / float(np.mean(ms)),
+            "sweep_seconds": time.perf_counter() - t_all, "points": rows}
+
+
+def time_adaptive(ld, A, lmin, lmax, degree, ncols, rel_tol, n, nnz, reps=5):
+    """Alg. 2's adaptive loop against the fixed-degree apply on the same Rademacher block."""
+    import numpy as np
+    import torch
+
+    g = torch.Generator(device="cpu").manual_seed(1)
+    V = (torch.randint(0, 2, (n, ncols), generator=g, dtype=torch.int8) * 2 - 1).to(A.val.device, A.dtype)
+    tol = rel_tol * math.sqrt(n)
+    out = {}
+    for name, fn in (("adaptive", lambda: ld.apply_log_adaptive(A, lmin, lmax, degree, tol, V)),
+                     ("fixed", lambda: (ld.apply_log(A, lmin, lmax, degree, V), None))):
+        fn()
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        for _ in range(reps):
+            _, deg = fn()
+        torch.cuda.synchronize()
+        out[name] = (time.perf_counter() - t) / reps
+        if deg is not None:
+            degs = np.asarray(deg)
+    steps = min(degree, -(-int(degs.max()) // 8) * 8)        # steps launched: until the 8-step poll sees all stopped
+    step_bytes = 8.0 * nnz + 4.0 * (n + 1) + 16.0 * n * ncols   # A + read w, write w, read and write P
+    return {"tol": tol, "tol_over_sqrt_n": rel_tol, "columns": ncols, "max_degree": degree,
+            "degree_min": int(degs.min()), "degree_median": float(np.median(degs)), "degree_max": int(degs.max()),
+            "ms_adaptive": out["adaptive"] * 1e3, "ms_fixed_degree_horner": out["fixed"] * 1e3,
+            "steps_launched": steps, "adaptive_GBps": steps * step_bytes / out["adaptive"] / 1e9}
 
 
 def cpu_baseline(csr, lmin, lmax, degree, m_vec, seed):
@@ -174,6 +246,9 @@ def main():
     import workloads
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
+    if args.sweep:
+        print(json.dumps(theta_sweep(args)), flush=True)
+        return
     if not args.all:
         print(json.dumps(run_workload(args, args.workload, args.steps)), flush=True)
         return
@@ -275,6 +350,13 @@ def run_workload(args, workload, steps):
 
     from tests.gpu_common import golden
 
+    if cfg["kind"] == "gmrf_theta":   # closed form of the stored sweep (exact log det, expectation, sd)
+        gs = golden("gmrf5000_theta_sweep")
+        r = gs["results"].get(repr(cfg["theta"])) if gs and gs["N"] == cfg["N"] else None
+        if r is not None:
+            out["parity"] = {"logdet_exact": r["logdet_exact"], "expectation": r["expectation"],
+                             "rel_err_f32_vs_exact": abs(est32 - r["logdet_exact"]) / abs(r["logdet_exact"]),
+                             "z_f32": (est32 - r["expectation"]) / r["sd_hutchinson"]}
     g = golden(args.workload)
     ref = None
     if g is not None and str(args.seed) in g["results"] and g["degree"] == degree:
@@ -307,6 +389,10 @@ def run_workload(args, workload, steps):
                            "call_over_estimate": dtg * 1e3 / t_est,
                            "extra_over_estimate": (dtg * 1e3 - t_est) / t_est,
                            "ckpt_stride": "auto (every forward vector kept when they fit 64 GiB)"}
+
+    if args.adaptive_tol > 0:
+        out["apply_log_adaptive"] = time_adaptive(ld, A32, lmin, lmax, degree, st["k"], args.adaptive_tol, n,
+                                                  nnz)
 
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline((row_ptr, col_idx, np.asarray(val), n), lmin, lmax, degree,

@@ -4,6 +4,9 @@
   the 5-point (7-point) Laplacian on an N^d grid has eigenvalues
   sum_axes 4 sin^2(pi a/(2(N+1))), a = 1..N per axis, so
   log det = sum log(tau*(kappa2 + sum_axes 4 sin^2(...))).
+* The GMRF precision Q(theta) = I + theta*Adj of Sec. 5.2 on the same grid
+  (Adj = 4I - L) has eigenvalues 1 + theta*(4 - mu_a - mu_b), i.e.
+  1 + 2 theta (cos(pi a/(N+1)) + cos(pi b/(N+1))).
 * Dense Cholesky log det = 2 sum log diag(chol(Q)) for small n (the paper's
   exact reference is a Cholesky factorisation, Sec. 5).
 
@@ -48,6 +51,29 @@ def grid_logdet_2d(N: int, kappa2: float, tau: float = 1.0) -> float:
 def grid_logdet_3d(N: int, kappa2: float, tau: float = 1.0) -> float:
     lam = grid_eigenvalues_3d(N, kappa2, tau)
     return math.fsum(np.log(lam).tolist())
+
+
+def gmrf_theta_eigenvalues(N: int, theta: float) -> np.ndarray:
+    a = np.arange(1, N + 1)
+    cs = np.cos(np.pi * a / (N + 1))
+    return (1.0 + 2.0 * theta * (cs[:, None] + cs[None, :])).reshape(-1)
+
+
+def gmrf_theta_logdet(N: int, theta: float) -> float:
+    return math.fsum(np.log(gmrf_theta_eigenvalues(N, theta)).tolist())
+
+
+def grid_matfun_diag_2d(N: int, fvals: np.ndarray) -> np.ndarray:
+    """Diagonal of f(Q) for any Q diagonalised by the 2-D Dirichlet sine modes.
+
+    fvals[a-1, b-1] = f(lambda_ab).  The unit eigenvectors are separable,
+    u_ab(i, j) = u_a(i) u_b(j) with u_a(i) = sqrt(2/(N+1)) sin(pi a i/(N+1)), so
+    f(Q)_(i,j),(i,j) = sum_ab u_a(i)^2 u_b(j)^2 f_ab = (S f S^T)[i, j] with
+    S[i, a] = u_a(i)^2.  Returned in grid (row-major) order.
+    """
+    a = np.arange(1, N + 1)
+    S = 2.0 / (N + 1) * np.sin(np.pi * np.outer(a, a) / (N + 1)) ** 2
+    return (S @ np.asarray(fvals, dtype=np.float64).reshape(N, N) @ S.T).reshape(-1)
 
 
 def grid_logdet_2d_dkappa(N: int, kappa2: float, tau: float = 1.0) -> float:

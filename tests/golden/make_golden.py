@@ -18,7 +18,7 @@ sys.path.insert(0, ROOT)
 import numpy as np  # noqa: E402
 
 import workloads  # noqa: E402
-from oracle import bounds, hutchpp  # noqa: E402
+from oracle import bounds, exact, hutchpp, newton  # noqa: E402
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 
@@ -51,6 +51,46 @@ def make(name: str):
         json.dump(out, f, indent=1)
 
 
+def make_gmrf_theta_sweep(name="gmrf5000_theta_sweep"):
+    """Closed-form references for the theta sweep of Sec. 5.2 at full size (N = 5000).
+
+    For each theta: the exact log det; the estimator's expectation
+    n log(sigma) + sum_i P_m(lambda_i / sigma) (Hutch++ is unbiased for the
+    trace of the polynomial); and a bound on its standard deviation,
+    sqrt(2 sum_i P_m(lambda_i/sigma)^2 / k_G) (Rademacher Hutchinson on the
+    deflated residual, whose Frobenius norm is at most that of P_m).  Also the
+    standard deviation of plain Hutchinson with k_G Rademacher probes,
+    sqrt(2 (||F||_F^2 - sum_i F_ii^2) / k_G), F = P_m(Q~), whose diagonal
+    comes from the separable sine eigenvectors (exact.grid_matfun_diag_2d).
+    The interval is Gershgorin's, [1 - 4|theta|, 1 + 4|theta|].
+    """
+    cfg = workloads.CONFIGS["gmrf5000_theta"]
+    N, degree, m_vec = cfg["N"], cfg["degree"], cfg["m_vec"]
+    n = N * N
+    k_g = m_vec - 2 * (m_vec // 3)
+    out = dict(workload="gmrf5000_theta", N=N, n=n, degree=degree, m_vec=m_vec, results={})
+    for th in workloads.GMRF_THETAS:
+        t = time.perf_counter()
+        lmin, lmax = 1.0 - 4.0 * abs(th), 1.0 + 4.0 * abs(th)
+        lam = exact.gmrf_theta_eigenvalues(N, th)
+        plan = newton.NewtonPlan(lmin, lmax, degree)
+        pm = plan.eval_scalar(lam)
+        fdiag = exact.grid_matfun_diag_2d(N, pm)
+        off = float(np.sum(pm * pm) - np.sum(fdiag * fdiag))
+        out["results"][repr(th)] = dict(
+            theta=th, lmin=lmin, lmax=lmax, logdet_exact=exact.gmrf_theta_logdet(N, th),
+            expectation=n * float(np.log(plan.sigma)) + float(np.sum(pm)),
+            sd_bound=float(np.sqrt(2.0 * np.sum(pm * pm) / k_g)),
+            sd_hutchinson=float(np.sqrt(2.0 * max(off, 0.0) / k_g)), seconds=time.perf_counter() - t)
+        print(name, th, out["results"][repr(th)], flush=True)
+    with open(os.path.join(HERE, f"{name}.json"), "w") as f:
+        json.dump(out, f, indent=1)
+
+
 if __name__ == "__main__":
-    for nm in sys.argv[1:] or list(ENTRIES):
-        make(nm)
+    names = sys.argv[1:] or list(ENTRIES) + ["gmrf5000_theta_sweep"]
+    for nm in names:
+        if nm == "gmrf5000_theta_sweep":
+            make_gmrf_theta_sweep()
+        else:
+            make(nm)

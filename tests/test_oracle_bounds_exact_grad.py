@@ -34,6 +34,26 @@ def test_lanczos_lmax():
     assert est == pytest.approx(ev[-1], rel=1e-6)
 
 
+def test_gmrf_theta_closed_form():
+    # I + theta*Adj: closed-form eigenvalues and log det against dense algebra
+    for N, th in ((7, -0.22), (10, -0.24), (9, 0.1)):
+        Q = w.to_scipy(w.gmrf_theta(N, th)).toarray()
+        np.testing.assert_allclose(np.sort(exact.gmrf_theta_eigenvalues(N, th)), np.linalg.eigvalsh(Q),
+                                   rtol=1e-13, atol=1e-13)
+        assert exact.gmrf_theta_logdet(N, th) == pytest.approx(exact.cholesky_logdet(Q), rel=1e-12)
+        assert bounds.gershgorin(w.gmrf_theta(N, th)) == pytest.approx((1 - 4 * abs(th), 1 + 4 * abs(th)))
+
+
+def test_grid_matfun_diag_against_dense():
+    import scipy.linalg as sla
+    for N, th in ((12, -0.22), (9, 0.15)):
+        Q = w.to_scipy(w.gmrf_theta(N, th)).toarray()
+        lam = exact.gmrf_theta_eigenvalues(N, th)
+        for f, fm in ((np.log, lambda M: sla.logm(M).real), (np.exp, sla.expm)):
+            np.testing.assert_allclose(exact.grid_matfun_diag_2d(N, f(lam)), np.diag(fm(Q)), rtol=1e-12,
+                                       atol=1e-13)
+
+
 def test_lanczos_upper_brackets_top_eigenvalue():
     from oracle import rng
     for A, steps in ((w.chung_lu_laplacian(1500, seed=1), 40), (w.grid_laplacian_2d(30, 0.5), 25),

@@ -23,6 +23,7 @@ __all__ = [
     "grid_laplacian_3d",
     "chung_lu_laplacian",
     "pentadiagonal",
+    "gmrf_theta",
     "dirichlet_sine_vector_2d",
     "dirichlet_sine_vector_3d",
     "to_scipy",
@@ -129,6 +130,21 @@ def chung_lu_laplacian(n: int, seed: int = 0, beta: float = 2.5, mean_degree: fl
     return _assemble(n, rows, cols, vals)
 
 
+def gmrf_theta(N: int, theta: float):
+    """Q(theta) = I + theta * Adj on an N x N grid, Adj the 4-nearest-neighbour adjacency.
+
+    The GMRF precision of the paper's maximum-likelihood study (Sec. 5.2):
+    unit diagonal, theta on the four neighbours; Dirichlet boundary (a border
+    node has fewer neighbours).  Its spectrum lies in [1 - 4|theta|, 1 + 4|theta|].
+    Same pattern and order as ``grid_laplacian_2d``; since L = 4I - Adj this is
+    (1 + 4 theta) I - theta L.
+    """
+    row_ptr, col_idx, _, n = grid_laplacian_2d(N, 0.0)
+    rows = np.repeat(np.arange(n, dtype=np.int64), np.diff(row_ptr))
+    val = np.where(col_idx == rows, 1.0, float(theta))
+    return row_ptr, col_idx, val, n
+
+
 def pentadiagonal(n: int, seed: int = 0):
     """Symmetric pentadiagonal SPD matrix of the paper's synthetic study (Section 5.1).
 
@@ -180,7 +196,13 @@ CONFIGS = {
     "grid128c_k0.05": dict(kind="grid3d", N=128, kappa2=0.05, degree=120, m_vec=96),
     "chunglu_4M": dict(kind="chunglu", n=1 << 22, degree=150, m_vec=64),
     "gmrf2048": dict(kind="grid2d", N=2048, kappa2=0.1, tau=1.5, degree=100, m_vec=32),
+    # Sec. 5.2's GMRF, I + theta*Adj on 5000 x 5000 at the hidden theta = -0.22
+    # (spectrum [0.12, 1.88]); the sweep over theta uses the same pattern
+    "gmrf5000_theta": dict(kind="gmrf_theta", N=5000, theta=-0.22, degree=80, m_vec=30),
 }
+
+# the theta values of the likelihood sweep over the paper's range [-0.25, 0]
+GMRF_THETAS = (-0.24, -0.22, -0.2, -0.16, -0.12, -0.08, -0.04)
 
 
 def build(name: str, **override):
@@ -196,4 +218,6 @@ def build(name: str, **override):
         return chung_lu_laplacian(cfg["n"], seed=cfg.get("seed", 0), permute=cfg.get("permute", False))
     if kind == "penta":
         return pentadiagonal(cfg["n"], seed=cfg.get("seed", 0))
+    if kind == "gmrf_theta":
+        return gmrf_theta(cfg["N"], cfg["theta"])
     raise ValueError(kind)
