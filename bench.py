@@ -79,6 +79,9 @@ def describe(name, cfg, n, nnz):
     elif cfg["kind"] == "grid3d":
         shape = f"7-point Dirichlet Laplacian {cfg['N']}^3 grid"
         shift = f"L + {cfg['kappa2']} I"
+    elif cfg["kind"] == "penta":
+        shape = "pentadiagonal Q + Q^T + n I with U(0,1) diagonals (Sec. 5.1)"
+        shift = f"seed {cfg.get('seed', 0)}"
     elif cfg["kind"] == "gmrf_theta":
         shape = f"GMRF precision I + theta*Adj (4 neighbours) on a {cfg['N']}x{cfg['N']} grid"
         shift = f"theta = {cfg['theta']}"
@@ -161,7 +164,8 @@ def time_adaptive(ld, A, lmin, lmax, degree, ncols, rel_tol, n, nnz, reps=5):
         out[name] = (time.perf_counter() - t) / reps
         if deg is not None:
             degs = np.asarray(deg)
-    steps = min(degree, -(-int(degs.max()) // 8) * 8)        # steps launched: until the 8-step poll sees all stopped
+    mx = int(degs.max())                                        # steps launched: until a poll sees all stopped
+    steps = min(degree, next(p for p in (1, 2, 4) if p >= mx) if mx <= 4 else -(-mx // 8) * 8)
     step_bytes = 8.0 * nnz + 4.0 * (n + 1) + 16.0 * n * ncols   # A + read w, write w, read and write P
     return {"tol": tol, "tol_over_sqrt_n": rel_tol, "columns": ncols, "max_degree": degree,
             "degree_min": int(degs.min()), "degree_median": float(np.median(degs)), "degree_max": int(degs.max()),
@@ -350,6 +354,12 @@ def run_workload(args, workload, steps):
 
     from tests.gpu_common import golden
 
+    if cfg["kind"] == "penta":        # banded-Cholesky log det of the same values (stored)
+        gp = golden(args.workload)
+        if gp is not None and "logdet_exact_f32_values" in gp:
+            out["parity_exact"] = {"logdet_exact_f32_values": gp["logdet_exact_f32_values"],
+                                   "rel_err_f32_vs_exact": abs(est32 - gp["logdet_exact_f32_values"]) /
+                                   abs(gp["logdet_exact_f32_values"])}
     if cfg["kind"] == "gmrf_theta":   # closed form of the stored sweep (exact log det, expectation, sd)
         gs = golden("gmrf5000_theta_sweep")
         r = gs["results"].get(repr(cfg["theta"])) if gs and gs["N"] == cfg["N"] else None

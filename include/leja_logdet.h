@@ -188,7 +188,7 @@ int ld_apply_log(const ld_csr* A, double lmin, double lmax, int32_t degree, cons
  * the degree m at which each column stopped (max_degree if it never met tol).
  * The norms are FP64 sums of the column's squares; the stopping test runs on
  * the device after every step, and the host stops launching steps once every
- * column has stopped (checked every 8 steps).
+ * column has stopped (checked after steps 1, 2 and 4, then every 8 steps).
  * V, PV: device, n x ncols row-major, dtype of A, must not overlap.
  * Errors: LD_EINVAL (0 < lmin < lmax, max_degree >= 1, ncols >= 0, tol finite
  * and >= 0), LD_ECSR, LD_EWORKSPACE, LD_EHIP. */

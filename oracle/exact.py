@@ -7,6 +7,8 @@
 * The GMRF precision Q(theta) = I + theta*Adj of Sec. 5.2 on the same grid
   (Adj = 4I - L) has eigenvalues 1 + theta*(4 - mu_a - mu_b), i.e.
   1 + 2 theta (cos(pi a/(N+1)) + cos(pi b/(N+1))).
+* Banded Cholesky log det for the pentadiagonal matrices of Sec. 5.1 at full
+  size.
 * Dense Cholesky log det = 2 sum log diag(chol(Q)) for small n (the paper's
   exact reference is a Cholesky factorisation, Sec. 5).
 
@@ -81,6 +83,29 @@ def grid_logdet_2d_dkappa(N: int, kappa2: float, tau: float = 1.0) -> float:
     mu = grid_eigenvalues_2d(N, kappa2, 1.0) - kappa2
     kappa = math.sqrt(kappa2)
     return math.fsum((2.0 * kappa / (kappa2 + mu)).tolist())
+
+
+def banded_logdet(csr, bandwidth: int) -> float:
+    """log det of a symmetric banded SPD matrix from its banded Cholesky factor.
+
+    csr = (row_ptr, col_idx, val, n) with |i - j| <= bandwidth for every entry;
+    the lower band is packed as ab[k, j] = Q[j + k, j] (LAPACK lower banded
+    storage) and factored by scipy.linalg.cholesky_banded; log det is
+    2 sum log diag(L), summed with math.fsum.  O(n bandwidth^2): used at the
+    full size of the paper's pentadiagonal study (Sec. 5.1).
+    """
+    import scipy.linalg as sla
+
+    row_ptr, col_idx, val, n = csr
+    rows = np.repeat(np.arange(n, dtype=np.int64), np.diff(np.asarray(row_ptr, dtype=np.int64)))
+    cols = np.asarray(col_idx, dtype=np.int64)
+    if np.any(np.abs(rows - cols) > bandwidth):
+        raise ValueError("entry outside the band")
+    low = rows >= cols
+    ab = np.zeros((bandwidth + 1, n))
+    ab[rows[low] - cols[low], cols[low]] = np.asarray(val, dtype=np.float64)[low]
+    c = sla.cholesky_banded(ab, lower=True, overwrite_ab=True, check_finite=False)
+    return 2.0 * math.fsum(np.log(c[0]).tolist())
 
 
 def cholesky_logdet(Q_dense) -> float:

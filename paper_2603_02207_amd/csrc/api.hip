@@ -956,7 +956,7 @@ int lanczos_upper(const ld_csr* A_in, int steps, double abs_bound, hipStream_t s
 
 // Workspace of the adaptive apply: two n x ncols blocks, step partials for
 // 64 columns, Gram partials, small sums, the mask, degrees, flag, long rows.
-constexpr int kAdaptPoll = 8;   // steps between host checks of the active mask
+constexpr int kAdaptPoll = 8;   // steps between host checks of the active mask (after the first few)
 
 size_t adaptive_ws_bytes(const ld_csr* A, int ncols) {
     const size_t elem = A->dtype == LD_F64 ? 8 : 4;
@@ -1118,7 +1118,8 @@ int ld_apply_log_adaptive(const ld_csr* A, double lmin, double lmax, int32_t max
             LD_CHECK_HIP(launch_reduce(part, nwg, qc, 64, 1, 0, sums, qc, st));
             LD_CHECK_HIP(launch_adapt_decide(sums, 1, qc, std::fabs(p.d[j + 1]), tol, j + 1, mask, deg + q0, st));
             cur = out;
-            if ((j + 1) % kAdaptPoll == 0 && j + 1 < m) {   // stop launching once every column is done
+            const int done = j + 1;   // poll after steps 1, 2, 4, then every kAdaptPoll: stop once all columns are done
+            if (done < m && (done == 1 || done == 2 || done == 4 || done % kAdaptPoll == 0)) {
                 uint64_t h = 0;
                 LD_CHECK_HIP(hipMemcpyAsync(&h, mask, 8, hipMemcpyDeviceToHost, st));
                 LD_CHECK_HIP(hipStreamSynchronize(st));

@@ -29,6 +29,7 @@ ENTRIES = {
     "gmrf2048": ("gmrf2048", {}, [0]),
     "grid128c_k0.05": ("grid128c_k0.05", {}, [0]),
     "chunglu_1M": ("chunglu_4M", {"n": 1 << 20}, [0]),
+    "penta_1e7": ("penta_1e7", {}, [0]),
 }
 
 
@@ -41,6 +42,11 @@ def make(name: str):
     lmin, lmax = bounds.gershgorin(csr)
     out = dict(workload=wl, overrides=over, n=int(csr[3]), nnz=int(len(csr[1])), lmin=lmin, lmax=lmax,
                degree=cfg["degree"], m_vec=cfg["m_vec"], results={})
+    if cfg["kind"] == "penta":   # exact references by banded Cholesky, FP64 values and FP32-rounded values
+        v32 = np.asarray(csr[2], dtype=np.float32).astype(np.float64)
+        out["logdet_exact"] = exact.banded_logdet(csr, 2)
+        out["logdet_exact_f32_values"] = exact.banded_logdet((csr[0], csr[1], v32, csr[3]), 2)
+        out["lmin_f32_values"], out["lmax_f32_values"] = bounds.gershgorin((csr[0], csr[1], v32, csr[3]))
     for s in seeds:
         t = time.perf_counter()
         parts = hutchpp.logdet_estimate(Q, lmin, lmax, cfg["degree"], cfg["m_vec"], s, return_parts=True)

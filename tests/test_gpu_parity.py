@@ -192,6 +192,31 @@ def test_estimate_grid1024_full_size():
     assert rel(e64, ref) < 1e-10
 
 
+def test_estimate_pentadiagonal_1e7_full_size():
+    # Sec. 5.1's pentadiagonal study at its largest size (n = 1e7): parity with the
+    # oracle's estimate on the same probes, and the exact log det by banded
+    # Cholesky within the estimator's own error.  For Q ~ n I the Monte-Carlo
+    # error is dominated by log(lambda) * (||u_j||^2 - n) of the deflated
+    # residual probes, ||u_j||^2 = n - ||Q_b^T g_j||^2 with ||Q_b^T g_j||^2 ~ chi^2_k,
+    # so sd ~ log(lmax) sqrt(2k/k_G); six of those bound |estimate - exact|.
+    g = golden("penta_1e7")
+    csr = w.build("penta_1e7")
+    k, kg = g["m_vec"] // 3, g["m_vec"] - 2 * (g["m_vec"] // 3)
+    sd = math.log(g["lmax"]) * math.sqrt(2.0 * k / kg)
+    ref = g["results"]["0"]["logdet"]
+    A64, _ = to_gpu(csr, torch.float64)
+    e64 = ld.logdet(A64, g["lmin"], g["lmax"], g["degree"], g["m_vec"], 0)
+    assert rel(e64, ref) < 1e-12
+    assert abs(e64 - g["logdet_exact"]) < 6 * sd
+    del A64
+    A32, _ = to_gpu(csr, torch.float32)
+    lo, hi = ld.spectral_bounds(A32)
+    assert lo == pytest.approx(g["lmin_f32_values"], rel=1e-12) and hi == pytest.approx(g["lmax_f32_values"], rel=1e-12)
+    e32 = ld.logdet(A32, lo, hi, g["degree"], g["m_vec"], 0)
+    assert rel(e32, ref) < 1e-7
+    assert abs(e32 - g["logdet_exact_f32_values"]) < 6 * sd
+
+
 # ---------------------------------------------------------------- bounds and errors
 
 def test_spectral_bounds_match_oracle():

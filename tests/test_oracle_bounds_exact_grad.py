@@ -44,6 +44,18 @@ def test_gmrf_theta_closed_form():
         assert bounds.gershgorin(w.gmrf_theta(N, th)) == pytest.approx((1 - 4 * abs(th), 1 + 4 * abs(th)))
 
 
+def test_banded_logdet_against_dense():
+    for n, seed in ((50, 0), (333, 4)):
+        csr = w.pentadiagonal(n, seed)
+        Q = w.to_scipy(csr).toarray()
+        assert exact.banded_logdet(csr, 2) == pytest.approx(exact.cholesky_logdet(Q), rel=1e-14)
+        assert exact.banded_logdet(csr, 5) == pytest.approx(exact.cholesky_logdet(Q), rel=1e-14)
+    g = w.grid_laplacian_2d(6, 0.3)                     # bandwidth N
+    assert exact.banded_logdet(g, 6) == pytest.approx(exact.grid_logdet_2d(6, 0.3), rel=1e-13)
+    with pytest.raises(ValueError):
+        exact.banded_logdet(g, 5)
+
+
 def test_grid_matfun_diag_against_dense():
     import scipy.linalg as sla
     for N, th in ((12, -0.22), (9, 0.15)):

@@ -199,6 +199,9 @@ CONFIGS = {
     # Sec. 5.2's GMRF, I + theta*Adj on 5000 x 5000 at the hidden theta = -0.22
     # (spectrum [0.12, 1.88]); the sweep over theta uses the same pattern
     "gmrf5000_theta": dict(kind="gmrf_theta", N=5000, theta=-0.22, degree=80, m_vec=30),
+    # Sec. 5.1's pentadiagonal matrices at their largest size; the spectrum sits in
+    # [n - 8, n + 10], so a low degree already interpolates log to rounding level
+    "penta_1e7": dict(kind="penta", n=10_000_000, degree=8, m_vec=30),
 }
 
 # the theta values of the likelihood sweep over the paper's range [-0.25, 0]
