@@ -331,6 +331,8 @@ def run_workload(args, workload, steps):
             "lmin": lmin,
             "lmax": lmax,
             "dot_mode": {1: "forward", 2: "squared"}[st["dot_mode_used"]],
+            "matrix_storage": (f"diagonal ({st['dia_diagonals']} diagonals)" if st.get("dia_diagonals")
+                               else "csr"),
             "block_cols": args.block_cols,
             "seed": args.seed,
             "parallelism": "single GPU",

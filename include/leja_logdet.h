@@ -85,7 +85,12 @@ typedef struct {
                                 fits, at least ceil(sqrt(m))                    */
     int32_t dot_mode;        /* LD_DOT_AUTO / LD_DOT_FORWARD / LD_DOT_SQUARED  */
     int32_t trusted_csr;     /* nonzero: skip the device CSR structure check    */
-    int32_t reserved[3];
+    int32_t csr_only;        /* nonzero: never use the diagonal storage (the
+                                library otherwise builds it, once per call, when
+                                every entry lies on one of at most 9 diagonals,
+                                and gathers from it instead of the CSR arrays;
+                                same sums in the same order)                    */
+    int32_t reserved[2];
 } ld_options;
 
 typedef struct {
@@ -109,6 +114,8 @@ typedef struct {
     double ms_steps23;       /* phase-2+3 step launches (quadratic forms)      */
     int32_t launches1, launches23;
     double bytes1, bytes23;  /* algorithmic bytes of those launches            */
+    int32_t dia_diagonals;   /* diagonals of the diagonal storage used, 0: CSR */
+    int32_t reserved_stats;
 } ld_stats;
 
 /* Defaults for ld_options (all zero except as documented). */

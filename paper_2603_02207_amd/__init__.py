@@ -50,6 +50,7 @@ class Options:
     ckpt_stride: int = 0
     dot_mode: int = LD_DOT_AUTO
     trusted_csr: int = 0
+    csr_only: int = 0
 
     def to_c(self) -> nat.LdOptions:
         o = nat.LdOptions()
@@ -60,6 +61,7 @@ class Options:
         o.ckpt_stride = self.ckpt_stride
         o.dot_mode = self.dot_mode
         o.trusted_csr = self.trusted_csr
+        o.csr_only = self.csr_only
         return o
 
 

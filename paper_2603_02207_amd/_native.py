@@ -48,7 +48,8 @@ class LdOptions(ctypes.Structure):
         ("ckpt_stride", ctypes.c_int32),
         ("dot_mode", ctypes.c_int32),
         ("trusted_csr", ctypes.c_int32),
-        ("reserved", ctypes.c_int32 * 3),
+        ("csr_only", ctypes.c_int32),
+        ("reserved", ctypes.c_int32 * 2),
     ]
 
 
@@ -76,6 +77,8 @@ class LdStats(ctypes.Structure):
         ("launches23", ctypes.c_int32),
         ("bytes1", ctypes.c_double),
         ("bytes23", ctypes.c_double),
+        ("dia_diagonals", ctypes.c_int32),
+        ("reserved_stats", ctypes.c_int32),
     ]
 
     def as_dict(self):

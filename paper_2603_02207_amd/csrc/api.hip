@@ -64,6 +64,13 @@ size_t long_rows_bytes(const ld_csr* A) {
     return align_up((size_t)A->n * 4) + align_up(((size_t)A->n / 256 + 4) * 4) + align_up(16);
 }
 
+// Workspace of the diagonal storage (taken whether or not the matrix turns out to have it).
+size_t dia_bytes(const ld_csr* A, const ld_options& o) {
+    if (o.csr_only) return 0;
+    return align_up((size_t)A->n * kMaxDiag * (A->dtype == LD_F64 ? 8 : 4)) + align_up(256);
+}
+
+
 // Bump allocator over the caller's (or our own) workspace.
 struct Arena {
     char* base = nullptr;
@@ -223,7 +230,7 @@ EstLayout layout_estimate(const ld_csr* A, int degree, int n_matvec, bool grad,
     L.small = (size_t)kSmallSlots * 64 * 64 * 8;
     L.nu = (size_t)L.nslots * L.nc * 8;
     L.flag = 256;
-    L.longb = long_rows_bytes(A);
+    L.longb = long_rows_bytes(A) + dia_bytes(A, o);
     if (grad) {
         L.gcols = L.nc + L.k;                               // R = [Q_b, U, S] / L = [Q_b, cU, 2Z]
         const int v = 16 / (int)L.elem;
@@ -279,7 +286,7 @@ struct Timer {
 
 // bytes the recurrence kernels must move (FP values, int32 indices; the
 // matrix once per launch, blocks as listed per step kind)
-double alg_bytes_step(const ld_csr* A, int cols, int kind, size_t elem) {
+double alg_bytes_step(const ld_csr* A, int cols, int kind, size_t elem, int dia_nd = 0) {
     double per = 0;
     switch (kind) {
         case STEP_HORNER_SIGNS: per = 2.0 * elem * cols + 8.0; break;   // + sign-mask word
@@ -288,7 +295,9 @@ double alg_bytes_step(const ld_csr* A, int cols, int kind, size_t elem) {
         case STEP_DOT_SQ: per = 2.0 * elem * cols; break;
         default: per = 2.0 * elem * cols; break;
     }
-    return matrix_bytes(A, elem) + per * (double)A->n;
+    // diagonal storage: the values only, n x nd
+    const double mat = dia_nd > 0 ? (double)A->n * dia_nd * elem : matrix_bytes(A, elem);
+    return mat + per * (double)A->n;
 }
 
 // Launch one Newton step over all columns of a row-major block, in column
@@ -296,6 +305,11 @@ double alg_bytes_step(const ld_csr* A, int cols, int kind, size_t elem) {
 struct LongRows {
     const int* list = nullptr;    // null: the matrix has no row above kLongRow entries
     const int* count = nullptr;
+    // diagonal storage of A, when every stored entry lies on one of at most
+    // kMaxDiag diagonals (stencils, banded matrices); dia_nd = 0: CSR only
+    const void* dia = nullptr;
+    int dia_nd = 0;
+    int dia_off[kMaxDiag] = {};
 };
 
 int run_step(bool f64, const ld_csr* A, StepArgs s, int ncols, int col_block, hipStream_t st,
@@ -303,6 +317,9 @@ int run_step(bool f64, const ld_csr* A, StepArgs s, int ncols, int col_block, hi
     const CsrDev d = dev_of(A);
     s.long_rows = lr.list;
     s.long_count = lr.count;
+    s.dia = lr.dia;
+    s.dia_nd = lr.dia_nd;
+    for (int q = 0; q < kMaxDiag; ++q) s.dia_off[q] = lr.dia_off[q];
     int nwg = 0;
     const int gshift = s.gshift;
     // one row group spans at most a wave: 64 lanes of the launch's vector width
@@ -334,6 +351,29 @@ int build_long_rows(const ld_csr* A, Arena& ar, hipStream_t st, LongRows& lr) {
         lr.list = list;
         lr.count = count;
     }
+    return LD_OK;
+}
+
+// Diagonal storage: the offsets of the middle row are the candidates; the
+// build kernel places every entry and flags any off those diagonals, in which
+// case the call keeps the CSR path.  Two small host syncs.
+int build_dia(const ld_csr* A, const ld_options& o, Arena& ar, hipStream_t st, LongRows& lr) {
+    lr.dia = nullptr;
+    lr.dia_nd = 0;
+    if (o.csr_only) return LD_OK;
+    void* buf = ar.take((size_t)A->n * kMaxDiag * (A->dtype == LD_F64 ? 8 : 4));
+    int* info = (int*)ar.take(256);
+    if (A->n < 3 || A->nnz == 0) return LD_OK;
+    int h[16] = {};
+    LD_CHECK_HIP(hipMemcpyAsync(info, h, sizeof(h), hipMemcpyHostToDevice, st));
+    LD_CHECK_HIP(launch_dia_build(A->dtype == LD_F64, dev_of(A), buf, info, st));
+    LD_CHECK_HIP(hipMemcpyAsync(h, info, sizeof(h), hipMemcpyDeviceToHost, st));
+    LD_CHECK_HIP(hipStreamSynchronize(st));   // also orders the upload of h before its reuse
+    const int nd = h[0];
+    if (nd < 1 || nd > kMaxDiag || h[12]) return LD_OK;
+    lr.dia = buf;
+    lr.dia_nd = nd;
+    for (int q = 0; q < kMaxDiag; ++q) lr.dia_off[q] = q < nd ? h[1 + q] : 0;
     return LD_OK;
 }
 
@@ -445,7 +485,7 @@ int sketch_phase(const ld_csr* A, EstimateState& S, hipStream_t st) {
             s.mask = (const uint64_t*)S.mask;
             LD_CHECK(run_step(f64, A, s, cols, cols, st, nullptr, S.longrows));
             S.launches1 += 1;
-            S.bytes1 += alg_bytes_step(A, cols, STEP_HORNER_SIGNS, S.L.elem);
+            S.bytes1 += alg_bytes_step(A, cols, STEP_HORNER_SIGNS, S.L.elem, S.longrows.dia_nd);
         }
     }
     return LD_OK;
@@ -516,7 +556,7 @@ int estimate_dots(const ld_csr* A, EstimateState& S, hipStream_t st, std::vector
                 s.part_ld = X.bw;
                 LD_CHECK(run_step(f64, A, s, cols, cols, st, &nwg, S.longrows));
                 S.launches23 += 1;
-                S.bytes23 += alg_bytes_step(A, cols, STEP_DOT_SQ, L.elem);
+                S.bytes23 += alg_bytes_step(A, cols, STEP_DOT_SQ, L.elem, S.longrows.dia_nd);
                 cur = nxt;
             }
         } else {
@@ -538,7 +578,7 @@ int estimate_dots(const ld_csr* A, EstimateState& S, hipStream_t st, std::vector
                 s.part_ld = X.bw;
                 LD_CHECK(run_step(f64, A, s, cols, cols, st, &nwg, S.longrows));
                 S.launches23 += 1;
-                S.bytes23 += alg_bytes_step(A, cols, STEP_DOT_FWD, L.elem);
+                S.bytes23 += alg_bytes_step(A, cols, STEP_DOT_FWD, L.elem, S.longrows.dia_nd);
                 cur = pp[j % 2];
             }
         }
@@ -807,6 +847,7 @@ int run_logdet(const ld_csr* A, double lmin, double lmax, int degree, int n_matv
         return fail(LD_EINVAL, "internal: workspace layout overflow");
     if (!o.trusted_csr) LD_CHECK(validate_csr(A, S.flag, st));
     LD_CHECK(build_long_rows(A, ar, st, S.longrows));
+    LD_CHECK(build_dia(A, o, ar, st, S.longrows));
     Timer tm(st);
     tm.mark();
     LD_CHECK(estimate_front(A, seed, S, st, tm));
@@ -854,6 +895,7 @@ int run_logdet(const ld_csr* A, double lmin, double lmax, int degree, int n_matv
         stats->k = L.k;
         stats->k_G = L.kg;
         stats->dot_mode_used = want_grad ? LD_DOT_FORWARD : S.mode;
+        stats->dia_diagonals = S.longrows.dia_nd;
         stats->spmm_launches = S.spmm_launches;
         stats->t_low = t_low;
         stats->t_res = t_res;
@@ -958,13 +1000,13 @@ int lanczos_upper(const ld_csr* A_in, int steps, double abs_bound, hipStream_t s
 // 64 columns, Gram partials, small sums, the mask, degrees, flag, long rows.
 constexpr int kAdaptPoll = 8;   // steps between host checks of the active mask (after the first few)
 
-size_t adaptive_ws_bytes(const ld_csr* A, int ncols) {
+size_t adaptive_ws_bytes(const ld_csr* A, int ncols, const ld_options& o) {
     const size_t elem = A->dtype == LD_F64 ? 8 : 4;
     const int n = (int)A->n;
     return 2 * align_up((size_t)n * ncols * elem) +
            align_up((size_t)step_num_wg_any(n) * 64 * 8) +
            align_up((size_t)cross_num_wg(n) * 64 * 64 * 8) + align_up(64 * 64 * 8) + align_up(256) +
-           align_up((size_t)ncols * 4) + align_up(256) + long_rows_bytes(A);
+           align_up((size_t)ncols * 4) + align_up(256) + long_rows_bytes(A) + dia_bytes(A, o);
 }
 
 extern "C" {
@@ -977,13 +1019,13 @@ int ld_workspace_size(const ld_csr* A, int32_t degree, int32_t n_matvec, int32_t
     if (degree < 1) return fail(LD_EINVAL, "degree must be >= 1");
     const ld_options o = resolve(opts);
     if (n_matvec < 0 && want_grad) {
-        *bytes = adaptive_ws_bytes(A, (int)(-(int64_t)n_matvec));
+        *bytes = adaptive_ws_bytes(A, (int)(-(int64_t)n_matvec), o);
         return LD_OK;
     }
     if (n_matvec < 0) {
         const size_t elem = A->dtype == LD_F64 ? 8 : 4;
         *bytes = 2 * align_up((size_t)A->n * (size_t)(-(int64_t)n_matvec) * elem) + align_up(256) +
-                 long_rows_bytes(A);
+                 long_rows_bytes(A) + dia_bytes(A, o);
         return LD_OK;
     }
     if (n_matvec < 3) return fail(LD_EINVAL, "n_matvec must be >= 3");
@@ -1011,7 +1053,7 @@ int ld_apply_log(const ld_csr* A, double lmin, double lmax, int32_t degree, cons
     const uint8_t* v8 = (const uint8_t*)V;
     const uint8_t* p8 = (const uint8_t*)PV;
     if (v8 < p8 + blk && p8 < v8 + blk) return fail(LD_EINVAL, "V and PV overlap");
-    const size_t need = 2 * align_up(blk) + align_up(256) + long_rows_bytes(A);
+    const size_t need = 2 * align_up(blk) + align_up(256) + long_rows_bytes(A) + dia_bytes(A, o);
     OwnedWs own;
     Arena ar;
     LD_CHECK(get_workspace(workspace, ws_bytes, need, own, ar));
@@ -1021,6 +1063,7 @@ int ld_apply_log(const ld_csr* A, double lmin, double lmax, int32_t degree, cons
     if (!o.trusted_csr) LD_CHECK(validate_csr(A, flag, st));
     LongRows lr;
     LD_CHECK(build_long_rows(A, ar, st, lr));
+    LD_CHECK(build_dia(A, o, ar, st, lr));
     const int m = p.degree;
     const int cb = (o.block_cols > 0 && o.block_cols < std::min(nc, 64)) ? o.block_cols : std::min(nc, 64);
     // Horner: r_m = d_m V; r_j = (T - xi_j) r_{j+1} + d_j V, with d_0 carrying
@@ -1068,7 +1111,7 @@ int ld_apply_log_adaptive(const ld_csr* A, double lmin, double lmax, int32_t max
     if (v8 < p8 + blk && p8 < v8 + blk) return fail(LD_EINVAL, "V and PV overlap");
     OwnedWs own;
     Arena ar;
-    LD_CHECK(get_workspace(workspace, ws_bytes, adaptive_ws_bytes(A, nc), own, ar));
+    LD_CHECK(get_workspace(workspace, ws_bytes, adaptive_ws_bytes(A, nc, o), own, ar));
     uint8_t* W[2] = {(uint8_t*)ar.take(blk), (uint8_t*)ar.take(blk)};
     const int nwg_max = step_num_wg_any(n);
     double* part = (double*)ar.take((size_t)nwg_max * 64 * 8);
@@ -1080,6 +1123,7 @@ int ld_apply_log_adaptive(const ld_csr* A, double lmin, double lmax, int32_t max
     if (!o.trusted_csr) LD_CHECK(validate_csr(A, flag, st));
     LongRows lr;
     LD_CHECK(build_long_rows(A, ar, st, lr));
+    LD_CHECK(build_dia(A, o, ar, st, lr));
     const int m = p.degree;
     const std::vector<int> deg0((size_t)nc, m);   // columns that never meet tol stop at the cap
     LD_CHECK_HIP(hipMemcpyAsync(deg, deg0.data(), (size_t)nc * 4, hipMemcpyHostToDevice, st));

@@ -44,6 +44,8 @@ struct CsrDev {
     const void* val;
 };
 
+constexpr int kMaxDiag = 9;      // diagonals of the diagonal storage (9-point stencils, 7-point 3-D)
+
 // Geometry of a Newton step launch over columns [c0, c0+bcols) of row-major
 // blocks with leading dimension ld (elements).
 struct StepArgs {
@@ -69,6 +71,12 @@ struct StepArgs {
     void* acc;                 // PLAIN_ACC / ACC_NORM: row-major accumulator (column c of the step = column c)
     int ldacc, acc_cols;
     const uint64_t* active;    // ACC_NORM: device word, bit (c - c0) set = column c still accumulates
+    // Diagonal storage of A (dia_nd > 0): row r holds dia[r*dia_nd + q] at
+    // column r + dia_off[q] (offsets ascending; 0 where absent); replaces the
+    // CSR arrays in the gather.
+    const void* dia;
+    int dia_nd;
+    int dia_off[kMaxDiag];
 };
 
 constexpr int kLongRow = 64;     // entries above which a row is "long"
@@ -141,6 +149,13 @@ struct AdjArgs {
     bool last;       // no lam_out needed (only the SDDMM)
 };
 hipError_t launch_adjoint(bool f64, const CsrDev& A, const AdjArgs& a, hipStream_t st);
+
+// Diagonal storage of A.  info (device, 16 ints, info[12] preset to 0 by the
+// caller): info[0] = number of diagonals nd (distinct offsets col - row of 64
+// sampled rows, ascending, in info[1..nd]; -1 if more than kMaxDiag);
+// dia[r*nd + q] = A[r, r + info[1+q]] or 0; info[12] = 1 when some stored
+// entry lies on none of the diagonals (the storage is then unusable).
+hipError_t launch_dia_build(bool f64, const CsrDev& A, void* dia, int* info, hipStream_t st);
 
 // Alg. 2's stopping test after the step that produced w_m: for columns c < qc
 // still active in *mask, e = |d_m| sqrt(sums[c*stride]) <= tol clears the bit

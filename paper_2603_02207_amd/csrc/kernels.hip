@@ -100,14 +100,19 @@ inline int grid_of(int kind, int ntiles) { return is_dot(kind) && ntiles > kDotW
 // partial row.  No wave ever waits at a barrier, and the order of every
 // addition is fixed.  Global column of local column c: c + gshift.
 // ---------------------------------------------------------------------------
-template <typename T, int VEC, int KIND, bool FIRST, int ITERS, int NT>
+struct DiaOff {
+    int o[kMaxDiag];
+};
+
+template <typename T, int VEC, int KIND, bool FIRST, int ITERS, int NT, bool DIA>
 __global__ __launch_bounds__(NT) void step_kernel(
     int n, const int* __restrict__ row_ptr, const int* __restrict__ col_idx,
     const T* __restrict__ val, const T* __restrict__ win, T* __restrict__ wout, int ld, int c0,
     int bcols, int gshift, T alpha, T beta, T dj, const T* __restrict__ vsrc, int ldv,
     const uint64_t* __restrict__ mask, double* __restrict__ ps0, double* __restrict__ ps1,
     double* __restrict__ ps2, int part_ld, int lpr, int rpw, int skip_long, T* __restrict__ accum,
-    int ldacc, int acc_cols, int ntiles, const uint64_t* __restrict__ active) {
+    int ldacc, int acc_cols, int ntiles, const uint64_t* __restrict__ active, const T* __restrict__ dia, int nd,
+    DiaOff off) {
     constexpr bool kDot = is_dot(KIND);
     constexpr int NW = NT / 64;
     constexpr int kSums = kDot ? ((FIRST ? 1 : 0) + 1 + (KIND == STEP_DOT_SQ ? 1 : 0)) : 0;
@@ -153,17 +158,26 @@ __global__ __launch_bounds__(NT) void step_kernel(
     const int nrows = max(0, min(rows_per_wave, n - W0));
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");   // the previous tile's LDS reads come first
     __builtin_amdgcn_wave_barrier();
-    if (nrows > 0)   // waves past the last row read nothing
-        for (int t2 = lane; t2 <= nrows; t2 += 64) rp[t2] = row_ptr[W0 + t2];
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    const int K0 = nrows > 0 ? rp[0] : 0;
-    const int K1 = nrows > 0 ? rp[nrows] : 0;
-    const bool staged = (K1 - K0) <= kWaveNz;
-    if (staged) {
-        for (int k = K0 + lane; k < K1; k += 64) {
-            s_col[k - K0] = col_idx[k];
-            s_val[k - K0] = val[k];
+    int K0 = 0;
+    bool staged;
+    if constexpr (DIA) {
+        // the wave's rows are one contiguous run of nrows*nd diagonal values
+        staged = nrows * nd <= kWaveNz;
+        if (staged)
+            for (int k = lane; k < nrows * nd; k += 64) s_val[k] = dia[(size_t)W0 * nd + k];
+    } else {
+        if (nrows > 0)   // waves past the last row read nothing
+            for (int t2 = lane; t2 <= nrows; t2 += 64) rp[t2] = row_ptr[W0 + t2];
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        K0 = nrows > 0 ? rp[0] : 0;
+        const int K1 = nrows > 0 ? rp[nrows] : 0;
+        staged = (K1 - K0) <= kWaveNz;
+        if (staged) {
+            for (int k = K0 + lane; k < K1; k += 64) {
+                s_col[k - K0] = col_idx[k];
+                s_val[k - K0] = val[k];
+            }
         }
     }
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
@@ -174,11 +188,25 @@ __global__ __launch_bounds__(NT) void step_kernel(
         const int lr = it * rpw + g;
         if (!lane_ok || lr >= nrows) continue;
         const int row = W0 + lr;
-        const int beg = rp[lr], end = rp[lr + 1];
-        if (skip_long && end - beg > kLongRow) continue;   // done by long_row_kernel
         T acc[VEC];
 #pragma unroll
         for (int e = 0; e < VEC; ++e) acc[e] = T(0);
+        if constexpr (DIA) {
+            // offsets ascending = the CSR column order: the same sums in the same order
+#pragma unroll
+            for (int q = 0; q < kMaxDiag; ++q) {
+                if (q >= nd) break;
+                const int c = row + off.o[q];
+                const T a = staged ? s_val[lr * nd + q] : dia[(size_t)row * nd + q];
+                if ((unsigned)c < (unsigned)n && a != T(0)) {
+                    const Pack<T, VEC> x = load_pack<T, VEC>(win + (size_t)c * ld + col);
+#pragma unroll
+                    for (int e = 0; e < VEC; ++e) acc[e] = fma(a, x.v[e], acc[e]);
+                }
+            }
+        } else {
+        const int beg = rp[lr], end = rp[lr + 1];
+        if (skip_long && end - beg > kLongRow) continue;   // done by long_row_kernel
         if (staged) {
             for (int k = beg - K0; k < end - K0; ++k) {
                 const Pack<T, VEC> x = load_pack<T, VEC>(win + (size_t)s_col[k] * ld + col);
@@ -209,6 +237,7 @@ __global__ __launch_bounds__(NT) void step_kernel(
                 }
             }
         }
+        }   // CSR
         const Pack<T, VEC> w = load_pack<T, VEC>(win + (size_t)row * ld + col);
         Pack<T, VEC> o;
 #pragma unroll
@@ -462,12 +491,23 @@ hipError_t launch_step_t(const CsrDev& A, const StepArgs& s, hipStream_t st) {
     const int ntiles = div_up(A.n, rows_per_wg);
     const int nwg = grid_of(KIND, ntiles);
     if (nwg == 0) return hipSuccess;
+    DiaOff off{};
+    for (int q = 0; q < kMaxDiag; ++q) off.o[q] = q < s.dia_nd ? s.dia_off[q] : 0;
+    if (s.dia_nd > 0) {   // no row has more than kMaxDiag entries: no long rows either
+        if (s.dia_nd > kMaxDiag || !s.dia) return hipErrorInvalidValue;
+        hipLaunchKernelGGL((step_kernel<T, VEC, KIND, FIRST, kIters, NT, true>), dim3(nwg), dim3(NT), 0, st,
+                           A.n, A.row_ptr, A.col_idx, (const T*)A.val, (const T*)s.win, (T*)s.wout, s.ld,
+                           s.c0, s.bcols, s.gshift, (T)s.alpha, (T)s.beta, (T)s.dj, (const T*)s.vsrc,
+                           s.ldv, s.mask, s.ps0, s.ps1, s.ps2, s.part_ld, lpr, rpw, 0, (T*)s.acc,
+                           s.ldacc, s.acc_cols, ntiles, s.active, (const T*)s.dia, s.dia_nd, off);
+        return hipGetLastError();
+    }
     const int skip = s.long_rows != nullptr;
-    hipLaunchKernelGGL((step_kernel<T, VEC, KIND, FIRST, kIters, NT>), dim3(nwg), dim3(NT), 0, st,
+    hipLaunchKernelGGL((step_kernel<T, VEC, KIND, FIRST, kIters, NT, false>), dim3(nwg), dim3(NT), 0, st,
                        A.n, A.row_ptr, A.col_idx, (const T*)A.val, (const T*)s.win, (T*)s.wout, s.ld,
                        s.c0, s.bcols, s.gshift, (T)s.alpha, (T)s.beta, (T)s.dj, (const T*)s.vsrc,
                        s.ldv, s.mask, s.ps0, s.ps1, s.ps2, s.part_ld, lpr, rpw, skip, (T*)s.acc,
-                       s.ldacc, s.acc_cols, ntiles, s.active);
+                       s.ldacc, s.acc_cols, ntiles, s.active, (const T*)nullptr, 0, off);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess || !skip) return e;
     hipLaunchKernelGGL((long_row_kernel<T, VEC, KIND, FIRST>), dim3(kLongWgs), dim3(256), 0, st,
@@ -533,7 +573,7 @@ int step_num_wg_any(int n) {
 int step_num_wg(bool f64, int n, const StepArgs& s) {
     const int vec = pick_vec(s, f64 ? 8 : 4);
     const int rows = (threads_of(s.kind) / 64) * (64 / lanes_per_row(s.bcols, vec)) * kStepIters;
-    return grid_of(s.kind, div_up(n, rows)) + (s.long_rows ? kLongWgs : 0);   // partial rows written
+    return grid_of(s.kind, div_up(n, rows)) + (s.long_rows && s.dia_nd == 0 ? kLongWgs : 0);   // partial rows written
 }
 
 hipError_t launch_step(bool f64, const CsrDev& A, const StepArgs& s, hipStream_t st) {
@@ -1089,6 +1129,96 @@ __global__ __launch_bounds__(kThreads) void axpby_kernel(long long len, T a, con
                                                          T b, T* __restrict__ y) {
     const long long i = (long long)blockIdx.x * kThreads + threadIdx.x;
     if (i < len) y[i] = a * x[i] + b * y[i];
+}
+
+// Candidate diagonals: the distinct offsets col - row of 64 rows scattered
+// over the matrix, merged in ascending order by one lane; info[0] = their number,
+// or -1 when a sampled row or the union exceeds kMaxDiag.
+__global__ __launch_bounds__(64) void dia_probe_kernel(int n, const int* __restrict__ row_ptr,
+                                                       const int* __restrict__ col_idx, int* __restrict__ info) {
+    __shared__ int offs[64][kMaxDiag];
+    __shared__ int cnt[64];
+    const int t = threadIdx.x;
+    // golden-ratio stride: no alignment with a grid's rows, whatever its width
+    const int r = (int)(((uint64_t)(t + 1) * 0x9E3779B97F4A7C15ull) % (uint64_t)n);
+    const int b = row_ptr[r], e = row_ptr[r + 1];
+    cnt[t] = e - b <= kMaxDiag ? e - b : -1;
+    for (int k = b; k < e && k - b < kMaxDiag; ++k) offs[t][k - b] = col_idx[k] - r;
+    __syncthreads();
+    if (t != 0) return;
+    int u[kMaxDiag];
+    int nu = 0;
+    for (int i = 0; i < 64 && nu >= 0; ++i) {
+        if (cnt[i] < 0) {
+            nu = -1;
+            break;
+        }
+        for (int j = 0; j < cnt[i]; ++j) {
+            const int o = offs[i][j];
+            int p = 0;
+            while (p < nu && u[p] < o) ++p;
+            if (p < nu && u[p] == o) continue;
+            if (nu == kMaxDiag) {
+                nu = -1;
+                break;
+            }
+            for (int q = nu; q > p; --q) u[q] = u[q - 1];
+            u[p] = o;
+            ++nu;
+        }
+    }
+    info[0] = nu;
+    for (int q = 0; q < kMaxDiag; ++q) info[1 + q] = (nu > 0 && q < nu) ? u[q] : 0;
+}
+
+// Diagonal storage for the offsets of info (ascending): dia[r*nd + q] =
+// A[r, r + off[q]] or 0; info[kDiaFlag] = 1 when a stored entry lies on none
+// of them (or there are no candidates).
+constexpr int kDiaFlag = 12;
+
+template <typename T>
+__global__ __launch_bounds__(kThreads) void dia_build_kernel(int n, const int* __restrict__ row_ptr,
+                                                             const int* __restrict__ col_idx,
+                                                             const T* __restrict__ val, T* __restrict__ dia,
+                                                             int* __restrict__ info) {
+    const int r = blockIdx.x * kThreads + threadIdx.x;
+    if (r >= n) return;
+    const int nd = info[0];
+    if (nd <= 0) {
+        if (r == 0) info[kDiaFlag] = 1;
+        return;
+    }
+    int off[kMaxDiag];
+#pragma unroll
+    for (int q = 0; q < kMaxDiag; ++q) off[q] = info[1 + q];
+    T* const out = dia + (size_t)r * nd;
+    for (int q = 0; q < nd; ++q) out[q] = T(0);
+    bool bad = false;
+    for (int k = row_ptr[r]; k < row_ptr[r + 1]; ++k) {
+        const int o = col_idx[k] - r;
+        int hit = -1;
+#pragma unroll
+        for (int q = 0; q < kMaxDiag; ++q)
+            if (q < nd && off[q] == o) hit = q;
+        if (hit >= 0)
+            out[hit] = val[k];
+        else
+            bad = true;
+    }
+    if (bad) info[kDiaFlag] = 1;
+}
+
+hipError_t launch_dia_build(bool f64, const CsrDev& A, void* dia, int* info, hipStream_t st) {
+    if (A.n == 0) return hipSuccess;
+    hipLaunchKernelGGL(dia_probe_kernel, dim3(1), dim3(64), 0, st, A.n, A.row_ptr, A.col_idx, info);
+    const int nb = div_up(A.n, kThreads);
+    if (f64)
+        hipLaunchKernelGGL(dia_build_kernel<double>, dim3(nb), dim3(kThreads), 0, st, A.n, A.row_ptr, A.col_idx,
+                           (const double*)A.val, (double*)dia, info);
+    else
+        hipLaunchKernelGGL(dia_build_kernel<float>, dim3(nb), dim3(kThreads), 0, st, A.n, A.row_ptr, A.col_idx,
+                           (const float*)A.val, (float*)dia, info);
+    return hipGetLastError();
 }
 
 __global__ __launch_bounds__(64) void adapt_decide_kernel(const double* __restrict__ sums, int stride, int qc,

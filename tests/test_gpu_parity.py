@@ -318,3 +318,49 @@ def test_estimate_full_size_workloads(name, tol32):
     assert rel(e32, ref) < tol32, (e32, ref, st["dot_mode_used"])
     e64 = ld.logdet(A64, g["lmin"], g["lmax"], g["degree"], g["m_vec"], 0)
     assert rel(e64, ref) < 1e-10
+
+
+# ---------------------------------------------------------------- diagonal storage
+
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
+def test_diagonal_storage_matches_csr_bitwise(dtype):
+    # Stencil and banded matrices are gathered from the diagonal storage, with
+    # the offsets in column order: the same products summed in the same order
+    # as the CSR path, hence bit-identical results.
+    for csr, lo, hi in ((w.grid_laplacian_2d(96, 0.3), 0.3, 8.3), (w.grid_laplacian_3d(20, 0.2), 0.2, 12.2),
+                        (w.pentadiagonal(5000, 1), None, None)):
+        A, vals = to_gpu(csr, dtype)
+        if lo is None:
+            lo, hi = bounds.gershgorin((csr[0], csr[1], vals, csr[3]))
+        est_d, st_d = ld.logdet(A, lo, hi, 30, 24, 5, return_stats=True)
+        est_c, st_c = ld.logdet(A, lo, hi, 30, 24, 5, options=ld.Options(csr_only=1), return_stats=True)
+        rows = np.repeat(np.arange(csr[3]), np.diff(csr[0]))
+        assert st_d["dia_diagonals"] == len(np.unique(np.asarray(csr[1]) - rows))
+        assert st_c["dia_diagonals"] == 0
+        assert est_d == est_c
+        V = torch.tensor(np.random.default_rng(3).standard_normal((csr[3], 6)), dtype=dtype, device=DEV)
+        assert torch.equal(ld.apply_log(A, lo, hi, 25, V), ld.apply_log(A, lo, hi, 25, V, ld.Options(csr_only=1)))
+        e1, g1 = ld.logdet_with_grad(A, lo, hi, 12, 9, 2)
+        e2, g2 = ld.logdet_with_grad(A, lo, hi, 12, 9, 2, options=ld.Options(csr_only=1))
+        assert e1 == e2 and torch.equal(g1, g2)
+
+
+def test_diagonal_storage_falls_back_to_csr():
+    # one entry off the stencil's diagonals, and an irregular matrix: CSR path
+    row_ptr, col_idx, val, n = w.grid_laplacian_2d(40, 0.5)
+    rows = np.repeat(np.arange(n), np.diff(row_ptr))
+    keep_r, keep_c, keep_v = list(rows), list(col_idx), list(val)
+    keep_r += [0, 777]
+    keep_c += [777, 0]
+    keep_v += [-0.25, -0.25]
+    order = np.lexsort((keep_c, keep_r))
+    r2, c2, v2 = np.asarray(keep_r)[order], np.asarray(keep_c)[order], np.asarray(keep_v)[order]
+    rp2 = np.concatenate([[0], np.cumsum(np.bincount(r2, minlength=n))]).astype(np.int32)
+    for csr in ((rp2, c2.astype(np.int32), v2, n), random_spd_csr(900, 2, long_rows=1)):
+        A, vals = to_gpu(csr, torch.float64)
+        lo, hi = bounds.gershgorin((csr[0], csr[1], vals, csr[3]))
+        lo = max(lo, 0.1)
+        est, st = ld.logdet(A, lo, hi, 20, 12, 1, return_stats=True)
+        assert st["dia_diagonals"] == 0
+        ref = hutchpp.logdet_estimate(w.to_scipy((csr[0], csr[1], vals, csr[3])), lo, hi, 20, 12, 1)
+        assert rel(est, ref) < 1e-10
