@@ -329,8 +329,9 @@ int run_step(bool f64, const ld_csr* A, StepArgs s, int ncols, int col_block, hi
         s.c0 = c0;
         s.bcols = std::min(col_block, ncols - c0);
         s.gshift = gshift;
-        nwg = std::max(nwg, step_num_wg(f64, (int)A->n, s));
-        LD_CHECK_HIP(launch_step(f64, d, s, st));
+        int used = 0;
+        LD_CHECK_HIP(launch_step(f64, d, s, st, &used));
+        nwg = std::max(nwg, used);
     }
     if (nwg_used) *nwg_used = nwg;
     return LD_OK;
@@ -554,7 +555,10 @@ int estimate_dots(const ld_csr* A, EstimateState& S, hipStream_t st, std::vector
                 s.ps1 = part + (size_t)(2 * a + 1) * slot_stride;
                 s.ps2 = part + (size_t)(2 * a + 2) * slot_stride;
                 s.part_ld = X.bw;
-                LD_CHECK(run_step(f64, A, s, cols, cols, st, &nwg, S.longrows));
+                int used = 0;
+                LD_CHECK(run_step(f64, A, s, cols, cols, st, &used, S.longrows));
+                if (a > 0 && used != nwg) return fail(LD_EINVAL, "internal: partial rows differ between steps");
+                nwg = used;
                 S.launches23 += 1;
                 S.bytes23 += alg_bytes_step(A, cols, STEP_DOT_SQ, L.elem, S.longrows.dia_nd);
                 cur = nxt;
@@ -576,7 +580,10 @@ int estimate_dots(const ld_csr* A, EstimateState& S, hipStream_t st, std::vector
                 s.ps0 = part;
                 s.ps1 = part + (size_t)(j + 1) * slot_stride;
                 s.part_ld = X.bw;
-                LD_CHECK(run_step(f64, A, s, cols, cols, st, &nwg, S.longrows));
+                int used = 0;
+                LD_CHECK(run_step(f64, A, s, cols, cols, st, &used, S.longrows));
+                if (j > 0 && used != nwg) return fail(LD_EINVAL, "internal: partial rows differ between steps");
+                nwg = used;
                 S.launches23 += 1;
                 S.bytes23 += alg_bytes_step(A, cols, STEP_DOT_FWD, L.elem, S.longrows.dia_nd);
                 cur = pp[j % 2];

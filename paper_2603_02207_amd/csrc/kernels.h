@@ -94,7 +94,10 @@ int step_max_cols(bool f64, const StepArgs& s);
 int step_num_wg_bound(int n, int bcols, int elem_bytes);
 int step_num_wg_any(int n);   // bound for the column-sum kinds at any layout
 
-hipError_t launch_step(bool f64, const CsrDev& A, const StepArgs& s, hipStream_t st);
+// *nwg_out (may be null): workgroup partial rows the launch wrote (dot kinds:
+// the grid, which is the number of resident workgroups or less, plus the
+// long-row launch's kLongWgs).
+hipError_t launch_step(bool f64, const CsrDev& A, const StepArgs& s, hipStream_t st, int* nwg_out = nullptr);
 
 // Sign mask of stream `key`: bit c of word r = (probe(r, c) == -1), c < k <= 64.
 hipError_t launch_sign_mask(int n, int k, uint64_t key, uint64_t* mask, hipStream_t st);

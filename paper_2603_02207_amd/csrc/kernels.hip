@@ -18,6 +18,8 @@
 
 #include <algorithm>
 #include <cstdint>
+#include <mutex>
+#include <unordered_map>
 
 #include "kernels.h"
 
@@ -104,7 +106,9 @@ struct DiaOff {
     int o[kMaxDiag];
 };
 
-template <typename T, int VEC, int KIND, bool FIRST, int ITERS, int NT, bool DIA>
+// ND > 0: gather from the diagonal storage, at most ND diagonals (compile-time
+// width of the per-row gather batch); ND = 0: from the CSR arrays.
+template <typename T, int VEC, int KIND, bool FIRST, int ITERS, int NT, int ND>
 __global__ __launch_bounds__(NT) void step_kernel(
     int n, const int* __restrict__ row_ptr, const int* __restrict__ col_idx,
     const T* __restrict__ val, const T* __restrict__ win, T* __restrict__ wout, int ld, int c0,
@@ -160,7 +164,7 @@ __global__ __launch_bounds__(NT) void step_kernel(
     __builtin_amdgcn_wave_barrier();
     int K0 = 0;
     bool staged;
-    if constexpr (DIA) {
+    if constexpr (ND > 0) {
         // the wave's rows are one contiguous run of nrows*nd diagonal values
         staged = nrows * nd <= kWaveNz;
         if (staged)
@@ -191,18 +195,27 @@ __global__ __launch_bounds__(NT) void step_kernel(
         T acc[VEC];
 #pragma unroll
         for (int e = 0; e < VEC; ++e) acc[e] = T(0);
-        if constexpr (DIA) {
-            // offsets ascending = the CSR column order: the same sums in the same order
+        if constexpr (ND > 0) {
+            // offsets ascending = the CSR column order: the same sums in the same
+            // order (a diagonal absent from the row, or leaving the matrix, adds an
+            // exact zero product of the row's own vector).  All gathers are issued
+            // before the first product.
+            int cq[ND];
+            T aq[ND];
 #pragma unroll
-            for (int q = 0; q < kMaxDiag; ++q) {
-                if (q >= nd) break;
+            for (int q = 0; q < ND; ++q) {
                 const int c = row + off.o[q];
-                const T a = staged ? s_val[lr * nd + q] : dia[(size_t)row * nd + q];
-                if ((unsigned)c < (unsigned)n && a != T(0)) {
-                    const Pack<T, VEC> x = load_pack<T, VEC>(win + (size_t)c * ld + col);
+                const bool ok = q < nd && (unsigned)c < (unsigned)n;
+                cq[q] = ok ? c : row;
+                aq[q] = ok ? (staged ? s_val[lr * nd + q] : dia[(size_t)row * nd + q]) : T(0);
+            }
+            Pack<T, VEC> xq[ND];
 #pragma unroll
-                    for (int e = 0; e < VEC; ++e) acc[e] = fma(a, x.v[e], acc[e]);
-                }
+            for (int q = 0; q < ND; ++q) xq[q] = load_pack<T, VEC>(win + (size_t)cq[q] * ld + col);
+#pragma unroll
+            for (int q = 0; q < ND; ++q) {
+#pragma unroll
+                for (int e = 0; e < VEC; ++e) acc[e] = fma(aq[q], xq[q].v[e], acc[e]);
             }
         } else {
         const int beg = rp[lr], end = rp[lr + 1];
@@ -479,31 +492,73 @@ __global__ __launch_bounds__(256) void long_row_kernel(
     }
 }
 
+// Workgroups of a kernel that are resident at once on the device (blocks per
+// CU at full occupancy x CUs), at most kDotWgs; cached per kernel (one device).
+int resident_wgs(const void* fn, int nt) {
+    static std::mutex mu;
+    static std::unordered_map<const void*, int> cache;
+    std::lock_guard<std::mutex> lock(mu);
+    const auto it = cache.find(fn);
+    if (it != cache.end()) return it->second;
+    int dev = 0, cus = 0, per_cu = 0;
+    int r = kDotWgs;
+    if (hipGetDevice(&dev) == hipSuccess &&
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess &&
+        hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, nt, 0) == hipSuccess && per_cu > 0 && cus > 0)
+        r = std::max(kXcds, std::min(kDotWgs, per_cu * cus));
+    cache[fn] = r;
+    return r;
+}
+
 template <typename T, int VEC, int KIND, bool FIRST>
-hipError_t launch_step_t(const CsrDev& A, const StepArgs& s, hipStream_t st) {
+hipError_t launch_step_t(const CsrDev& A, const StepArgs& s, hipStream_t st, int* nwg_out) {
     constexpr int kIters = kStepIters;
     constexpr int NT = threads_of(KIND);
+    if (nwg_out) *nwg_out = 0;
     if (is_dot(KIND) && s.bcols > kMaxDotCols) return hipErrorInvalidValue;
     const int lpr = lanes_per_row(s.bcols, VEC);
     if (lpr > 64) return hipErrorInvalidValue;
     const int rpw = 64 / lpr;
     const int rows_per_wg = (NT / 64) * rpw * kIters;
     const int ntiles = div_up(A.n, rows_per_wg);
-    const int nwg = grid_of(KIND, ntiles);
-    if (nwg == 0) return hipSuccess;
+    if (ntiles == 0) return hipSuccess;
+    // the kinds with column sums run as many workgroups as are resident at once
+    // (each loops over its tiles); the others one workgroup per tile.  The
+    // occupancy is that of the non-first variant, so every step of a phase
+    // writes the same number of partial rows (they are reduced together).
+    auto grid = [&](const void* fn_rest) {
+        return is_dot(KIND) ? std::min(ntiles, resident_wgs(fn_rest, NT)) : ntiles;
+    };
     DiaOff off{};
     for (int q = 0; q < kMaxDiag; ++q) off.o[q] = q < s.dia_nd ? s.dia_off[q] : 0;
     if (s.dia_nd > 0) {   // no row has more than kMaxDiag entries: no long rows either
         if (s.dia_nd > kMaxDiag || !s.dia) return hipErrorInvalidValue;
-        hipLaunchKernelGGL((step_kernel<T, VEC, KIND, FIRST, kIters, NT, true>), dim3(nwg), dim3(NT), 0, st,
-                           A.n, A.row_ptr, A.col_idx, (const T*)A.val, (const T*)s.win, (T*)s.wout, s.ld,
-                           s.c0, s.bcols, s.gshift, (T)s.alpha, (T)s.beta, (T)s.dj, (const T*)s.vsrc,
-                           s.ldv, s.mask, s.ps0, s.ps1, s.ps2, s.part_ld, lpr, rpw, 0, (T*)s.acc,
-                           s.ldacc, s.acc_cols, ntiles, s.active, (const T*)s.dia, s.dia_nd, off);
+#define LD_DIA_LAUNCH(ND_)                                                                                     \
+    {                                                                                                          \
+        const auto fn = step_kernel<T, VEC, KIND, FIRST, kIters, NT, ND_>;                                     \
+        const int nwg = grid(reinterpret_cast<const void*>(step_kernel<T, VEC, KIND, false, kIters, NT, ND_>)); \
+        hipLaunchKernelGGL(fn, dim3(nwg), dim3(NT), 0, st, A.n, A.row_ptr, A.col_idx, (const T*)A.val,         \
+                           (const T*)s.win, (T*)s.wout, s.ld, s.c0, s.bcols, s.gshift, (T)s.alpha, (T)s.beta,   \
+                           (T)s.dj, (const T*)s.vsrc, s.ldv, s.mask, s.ps0, s.ps1, s.ps2, s.part_ld, lpr, rpw, \
+                           0, (T*)s.acc, s.ldacc, s.acc_cols, ntiles, s.active, (const T*)s.dia, s.dia_nd, off); \
+        if (nwg_out) *nwg_out = nwg;                                                                           \
+    }
+        if (s.dia_nd <= 3)
+            LD_DIA_LAUNCH(3)
+        else if (s.dia_nd <= 5)
+            LD_DIA_LAUNCH(5)
+        else if (s.dia_nd <= 7)
+            LD_DIA_LAUNCH(7)
+        else
+            LD_DIA_LAUNCH(9)
+#undef LD_DIA_LAUNCH
         return hipGetLastError();
     }
     const int skip = s.long_rows != nullptr;
-    hipLaunchKernelGGL((step_kernel<T, VEC, KIND, FIRST, kIters, NT, false>), dim3(nwg), dim3(NT), 0, st,
+    const auto fn = step_kernel<T, VEC, KIND, FIRST, kIters, NT, 0>;
+    const int nwg = grid(reinterpret_cast<const void*>(step_kernel<T, VEC, KIND, false, kIters, NT, 0>));
+    if (nwg_out) *nwg_out = nwg + (skip ? kLongWgs : 0);
+    hipLaunchKernelGGL(fn, dim3(nwg), dim3(NT), 0, st,
                        A.n, A.row_ptr, A.col_idx, (const T*)A.val, (const T*)s.win, (T*)s.wout, s.ld,
                        s.c0, s.bcols, s.gshift, (T)s.alpha, (T)s.beta, (T)s.dj, (const T*)s.vsrc,
                        s.ldv, s.mask, s.ps0, s.ps1, s.ps2, s.part_ld, lpr, rpw, skip, (T*)s.acc,
@@ -519,21 +574,21 @@ hipError_t launch_step_t(const CsrDev& A, const StepArgs& s, hipStream_t st) {
 }
 
 template <typename T, int VEC>
-hipError_t launch_step_v(const CsrDev& A, const StepArgs& s, hipStream_t st) {
+hipError_t launch_step_v(const CsrDev& A, const StepArgs& s, hipStream_t st, int* nw) {
     switch (s.kind) {
-        case STEP_HORNER_SIGNS: return launch_step_t<T, VEC, STEP_HORNER_SIGNS, false>(A, s, st);
-        case STEP_HORNER_VEC: return launch_step_t<T, VEC, STEP_HORNER_VEC, false>(A, s, st);
-        case STEP_PLAIN: return launch_step_t<T, VEC, STEP_PLAIN, false>(A, s, st);
-        case STEP_PLAIN_ACC: return launch_step_t<T, VEC, STEP_PLAIN_ACC, false>(A, s, st);
+        case STEP_HORNER_SIGNS: return launch_step_t<T, VEC, STEP_HORNER_SIGNS, false>(A, s, st, nw);
+        case STEP_HORNER_VEC: return launch_step_t<T, VEC, STEP_HORNER_VEC, false>(A, s, st, nw);
+        case STEP_PLAIN: return launch_step_t<T, VEC, STEP_PLAIN, false>(A, s, st, nw);
+        case STEP_PLAIN_ACC: return launch_step_t<T, VEC, STEP_PLAIN_ACC, false>(A, s, st, nw);
         case STEP_ACC_NORM:
             if (!s.active || !s.acc) return hipErrorInvalidValue;
-            return launch_step_t<T, VEC, STEP_ACC_NORM, false>(A, s, st);
+            return launch_step_t<T, VEC, STEP_ACC_NORM, false>(A, s, st, nw);
         case STEP_DOT_FWD:
-            return s.first ? launch_step_t<T, VEC, STEP_DOT_FWD, true>(A, s, st)
-                           : launch_step_t<T, VEC, STEP_DOT_FWD, false>(A, s, st);
+            return s.first ? launch_step_t<T, VEC, STEP_DOT_FWD, true>(A, s, st, nw)
+                           : launch_step_t<T, VEC, STEP_DOT_FWD, false>(A, s, st, nw);
         case STEP_DOT_SQ:
-            return s.first ? launch_step_t<T, VEC, STEP_DOT_SQ, true>(A, s, st)
-                           : launch_step_t<T, VEC, STEP_DOT_SQ, false>(A, s, st);
+            return s.first ? launch_step_t<T, VEC, STEP_DOT_SQ, true>(A, s, st, nw)
+                           : launch_step_t<T, VEC, STEP_DOT_SQ, false>(A, s, st, nw);
         default: return hipErrorInvalidValue;
     }
 }
@@ -576,15 +631,15 @@ int step_num_wg(bool f64, int n, const StepArgs& s) {
     return grid_of(s.kind, div_up(n, rows)) + (s.long_rows && s.dia_nd == 0 ? kLongWgs : 0);   // partial rows written
 }
 
-hipError_t launch_step(bool f64, const CsrDev& A, const StepArgs& s, hipStream_t st) {
+hipError_t launch_step(bool f64, const CsrDev& A, const StepArgs& s, hipStream_t st, int* nwg_out) {
     if (f64) {
         const int vec = pick_vec(s, 8);
-        return vec == 2 ? launch_step_v<double, 2>(A, s, st) : launch_step_v<double, 1>(A, s, st);
+        return vec == 2 ? launch_step_v<double, 2>(A, s, st, nwg_out) : launch_step_v<double, 1>(A, s, st, nwg_out);
     }
     const int vec = pick_vec(s, 4);
-    if (vec == 4) return launch_step_v<float, 4>(A, s, st);
-    if (vec == 2) return launch_step_v<float, 2>(A, s, st);
-    return launch_step_v<float, 1>(A, s, st);
+    if (vec == 4) return launch_step_v<float, 4>(A, s, st, nwg_out);
+    if (vec == 2) return launch_step_v<float, 2>(A, s, st, nwg_out);
+    return launch_step_v<float, 1>(A, s, st, nwg_out);
 }
 
 // ---------------------------------------------------------------------------
