@@ -221,7 +221,22 @@ __global__ __launch_bounds__(NT) void step_kernel(
         const int beg = rp[lr], end = rp[lr + 1];
         if (skip_long && end - beg > kLongRow) continue;   // done by long_row_kernel
         if (staged) {
-            for (int k = beg - K0; k < end - K0; ++k) {
+            // batches of four entries: their gathers are issued before their
+            // products (same order of the sums as one entry at a time)
+            int k = beg - K0;
+            const int kend = end - K0;
+            for (; k + 4 <= kend; k += 4) {
+                Pack<T, VEC> x[4];
+#pragma unroll
+                for (int u = 0; u < 4; ++u) x[u] = load_pack<T, VEC>(win + (size_t)s_col[k + u] * ld + col);
+#pragma unroll
+                for (int u = 0; u < 4; ++u) {
+                    const T a = s_val[k + u];
+#pragma unroll
+                    for (int e = 0; e < VEC; ++e) acc[e] = fma(a, x[u].v[e], acc[e]);
+                }
+            }
+            for (; k < kend; ++k) {
                 const Pack<T, VEC> x = load_pack<T, VEC>(win + (size_t)s_col[k] * ld + col);
                 const T a = s_val[k];
 #pragma unroll
