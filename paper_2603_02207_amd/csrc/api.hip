@@ -125,7 +125,8 @@ int validate_csr(const ld_csr* A, int* dflag, hipStream_t st) {
 // after another (Blk), so every step reads contiguous memory.
 // ---------------------------------------------------------------------------
 constexpr double kMallBudget = 240e6;
-constexpr int kSmallSlots = 10;   // k x k (<= 64 x 64) FP64 scratch matrices
+constexpr int kSmallSlots = 12;   // k x k (<= 64 x 64) FP64 scratch matrices
+constexpr int kSlotR1 = 10, kSlotR2 = 11;   // CholQR factors, Y = Q_b R2 R1
 constexpr int kMaxDotBlock = 64;  // widest column block of the quadratic-form launches
 
 double matrix_bytes(const ld_csr* A, size_t elem) {
@@ -338,43 +339,40 @@ int run_step(bool f64, const ld_csr* A, StepArgs s, int ncols, int col_block, hi
 }
 
 
-// Lists the rows with more than kLongRow entries (one host sync for the count).
-int build_long_rows(const ld_csr* A, Arena& ar, hipStream_t st, LongRows& lr) {
+// Per-call matrix preparation, with one host sync for both results:
+// the list of rows with more than kLongRow entries, and diagonal storage when
+// every stored entry lies on one of at most kMaxDiag diagonals (stencils,
+// banded matrices).  The diagonal build takes its candidate offsets from a
+// sample of rows and flags any entry off them, in which case the call keeps
+// the CSR path.
+int prepare_rows(const ld_csr* A, const ld_options& o, Arena& ar, hipStream_t st, LongRows& lr) {
     int* list = (int*)ar.take((size_t)A->n * 4);
     int* tmp = (int*)ar.take(((size_t)A->n / 256 + 4) * 4);
     int* count = (int*)ar.take(16);
+    void* buf = o.csr_only ? nullptr : ar.take((size_t)A->n * kMaxDiag * (A->dtype == LD_F64 ? 8 : 4));
+    int* info = o.csr_only ? nullptr : (int*)ar.take(256);
+    const bool want_dia = buf && A->n >= 3 && A->nnz > 0;
+    int hcount = 0;
+    int h[16] = {};
     LD_CHECK_HIP(launch_long_rows(dev_of(A), tmp, list, count, st));
-    int h = 0;
-    LD_CHECK_HIP(hipMemcpyAsync(&h, count, sizeof(int), hipMemcpyDeviceToHost, st));
-    LD_CHECK_HIP(hipStreamSynchronize(st));
+    if (want_dia) {
+        LD_CHECK_HIP(hipMemcpyAsync(info, h, sizeof(h), hipMemcpyHostToDevice, st));
+        LD_CHECK_HIP(launch_dia_build(A->dtype == LD_F64, dev_of(A), buf, info, st));
+        LD_CHECK_HIP(hipMemcpyAsync(h, info, sizeof(h), hipMemcpyDeviceToHost, st));
+    }
+    LD_CHECK_HIP(hipMemcpyAsync(&hcount, count, sizeof(int), hipMemcpyDeviceToHost, st));
+    LD_CHECK_HIP(hipStreamSynchronize(st));   // also orders the upload of h before its reuse
     lr = LongRows{};
-    if (h > 0) {
+    if (hcount > 0) {
         lr.list = list;
         lr.count = count;
     }
-    return LD_OK;
-}
-
-// Diagonal storage: the offsets of the middle row are the candidates; the
-// build kernel places every entry and flags any off those diagonals, in which
-// case the call keeps the CSR path.  Two small host syncs.
-int build_dia(const ld_csr* A, const ld_options& o, Arena& ar, hipStream_t st, LongRows& lr) {
-    lr.dia = nullptr;
-    lr.dia_nd = 0;
-    if (o.csr_only) return LD_OK;
-    void* buf = ar.take((size_t)A->n * kMaxDiag * (A->dtype == LD_F64 ? 8 : 4));
-    int* info = (int*)ar.take(256);
-    if (A->n < 3 || A->nnz == 0) return LD_OK;
-    int h[16] = {};
-    LD_CHECK_HIP(hipMemcpyAsync(info, h, sizeof(h), hipMemcpyHostToDevice, st));
-    LD_CHECK_HIP(launch_dia_build(A->dtype == LD_F64, dev_of(A), buf, info, st));
-    LD_CHECK_HIP(hipMemcpyAsync(h, info, sizeof(h), hipMemcpyDeviceToHost, st));
-    LD_CHECK_HIP(hipStreamSynchronize(st));   // also orders the upload of h before its reuse
     const int nd = h[0];
-    if (nd < 1 || nd > kMaxDiag || h[12]) return LD_OK;
-    lr.dia = buf;
-    lr.dia_nd = nd;
-    for (int q = 0; q < kMaxDiag; ++q) lr.dia_off[q] = q < nd ? h[1 + q] : 0;
+    if (want_dia && nd >= 1 && nd <= kMaxDiag && !h[12]) {
+        lr.dia = buf;
+        lr.dia_nd = nd;
+        for (int q = 0; q < kMaxDiag; ++q) lr.dia_off[q] = q < nd ? h[1 + q] : 0;
+    }
     return LD_OK;
 }
 
@@ -386,24 +384,15 @@ int cross_product(bool f64, int n, const void* X, Blk bx, int kx, const void* Z,
     return LD_OK;
 }
 
-// One CholQR pass: R from the Gram of Y, then Q = Y R^{-1} (into Q, global
+// One CholQR pass: R from the Gram of Y (factored on the device, breakdown
+// code in *dflag, read with the results), then Q = Y R^{-1} (into Q, global
 // columns [0, k)).
 int cholqr_pass(bool f64, int n, const BlkMat& Y, int k, const BlkMat& Q, double* part, double* dG,
-                double* dRinv, double* Rh, hipStream_t st) {
+                double* dR, double* dRinv, int* dflag, hipStream_t st) {
     LD_CHECK(cross_product(f64, n, Y.base, Y.desc(), k, Y.base, Y.desc(), k, false, 0, part, dG, st));
-    std::vector<double> G((size_t)k * k), R((size_t)k * k), Rinv((size_t)k * k);
-    LD_CHECK_HIP(hipMemcpyAsync(G.data(), dG, sizeof(double) * k * k, hipMemcpyDeviceToHost, st));
-    LD_CHECK_HIP(hipStreamSynchronize(st));
-    for (double g : G)
-        if (!std::isfinite(g)) return fail(LD_EBREAKDOWN, "non-finite Gram entry in CholQR");
-    if (!cholesky_upper(G.data(), k, R.data(), Rinv.data()))
-        return fail(LD_EBREAKDOWN, "CholQR Gram matrix is not positive definite (rank-deficient sketch)");
-    if (Rh) std::memcpy(Rh, R.data(), sizeof(double) * k * k);
-    LD_CHECK_HIP(hipMemcpyAsync(dRinv, Rinv.data(), sizeof(double) * k * k, hipMemcpyHostToDevice, st));
+    LD_CHECK_HIP(launch_chol_factor(dG, k, dR, dRinv, dflag, st));
     LD_CHECK_HIP(launch_rowmat(f64, n, Y.base, Y.desc(), k, dRinv, k, 1.0, false, 0, nullptr,
                                Blk::plain(1), Q.base, Q.desc(), st));
-    // the host vectors die at return; make sure the copy has consumed them
-    LD_CHECK_HIP(hipStreamSynchronize(st));
     return LD_OK;
 }
 
@@ -415,7 +404,6 @@ struct EstimateState {
     void *mask, *W0, *W1;
     double *part, *small, *nu;
     int* flag;
-    double R1[64 * 64], R2[64 * 64];   // CholQR factors (host), Y = Q_b * R2 * R1
     int spmm_launches = 0;
     double bytes_alg = 0;
     int launches1 = 0, launches23 = 0;
@@ -427,6 +415,16 @@ struct EstimateState {
             if (e) (void)hipEventDestroy(e);
     }
 };
+
+// Breakdown codes the two CholQR factorisations left in flag[1], flag[2].
+int cholqr_status(const int* h) {
+    for (int i = 0; i < 2; ++i) {
+        if (h[i] == 1) return fail(LD_EBREAKDOWN, "non-finite Gram entry in CholQR");
+        if (h[i] != 0)
+            return fail(LD_EBREAKDOWN, "CholQR Gram matrix is not positive definite (rank-deficient sketch)");
+    }
+    return LD_OK;
+}
 
 int record(EstimateState& S, int i, hipStream_t st) {
     if (!S.ev[i]) LD_CHECK_HIP(hipEventCreate(&S.ev[i]));
@@ -511,8 +509,10 @@ int estimate_front(const ld_csr* A, uint64_t seed, EstimateState& S, hipStream_t
     double* dG = S.small;
     double* dRinv = S.small + 64 * 64;
     double* dC = S.small + 2 * 64 * 64;
-    LD_CHECK(cholqr_pass(f64, n, L.Y, L.k, L.Q1, S.part, dG, dRinv, S.R1, st));
-    LD_CHECK(cholqr_pass(f64, n, L.Q1, L.k, L.X, S.part, dG, dRinv, S.R2, st));
+    double* dR1 = S.small + (size_t)kSlotR1 * 64 * 64;
+    double* dR2 = S.small + (size_t)kSlotR2 * 64 * 64;
+    LD_CHECK(cholqr_pass(f64, n, L.Y, L.k, L.Q1, S.part, dG, dR1, dRinv, S.flag + 1, st));
+    LD_CHECK(cholqr_pass(f64, n, L.Q1, L.k, L.X, S.part, dG, dR2, dRinv, S.flag + 2, st));
     // ---- deflation: C = Q_b^T G, U = G - Q_b C (G = probe stream 1) into X[:, k:]
     LD_CHECK(cross_product(f64, n, L.X.base, L.X.desc(), L.k, nullptr, Blk::plain(1), L.kg, true, key1,
                            S.part, dC, st));
@@ -597,10 +597,12 @@ int estimate_dots(const ld_csr* A, EstimateState& S, hipStream_t st, std::vector
     S.spmm_launches += S.launches23;
     S.bytes_alg += S.bytes23;
     nu_host.assign((size_t)nslots * L.nc, 0.0);
+    int hflag[2] = {0, 0};
     LD_CHECK_HIP(hipMemcpyAsync(nu_host.data(), S.nu, sizeof(double) * nu_host.size(),
                                 hipMemcpyDeviceToHost, st));
+    LD_CHECK_HIP(hipMemcpyAsync(hflag, S.flag + 1, sizeof(hflag), hipMemcpyDeviceToHost, st));
     LD_CHECK_HIP(hipStreamSynchronize(st));
-    return LD_OK;
+    return cholqr_status(hflag);
 }
 
 int carve(Arena& ar, EstLayout& L, EstimateState& S) {
@@ -679,6 +681,15 @@ int estimate_and_gradient(const ld_csr* A, uint64_t seed, EstimateState& S, Grad
     const Blk X = L.X.desc(), FXd = L.FX.desc(), Gd = L.Gm.desc(), Td = L.T1.desc();
     const Blk Gb = Blk::plain(L.ldg);
     const int gcols = L.gcols, ldg = L.ldg, stride = L.stride;
+    // the CholQR factors: Y = Q_b R2 R1
+    std::vector<double> R1((size_t)k * k), R2((size_t)k * k);
+    {
+        int hflag[2] = {0, 0};
+        LD_CHECK_HIP(hipMemcpyAsync(hflag, S.flag + 1, sizeof(hflag), hipMemcpyDeviceToHost, st));
+        LD_CHECK(download(slot[kSlotR1], R1, st));
+        LD_CHECK(download(slot[kSlotR2], R2, st));
+        LD_CHECK(cholqr_status(hflag));
+    }
 
     // ---- R = [Q_b, U, S]
     auto diag = [](int q, double v) {
@@ -766,7 +777,7 @@ int estimate_and_gradient(const ld_csr* A, uint64_t seed, EstimateState& S, Grad
     for (int i = 0; i < k; ++i)
         for (int j = 0; j < k; ++j) {
             double v = 0.0;
-            for (int t = 0; t < k; ++t) v += S.R2[i * k + t] * S.R1[t * k + j];
+            for (int t = 0; t < k; ++t) v += R2[(size_t)i * k + t] * R1[(size_t)t * k + j];
             R[(size_t)i * k + j] = v;
         }
     for (int j = k - 1; j >= 0; --j) {   // inverse of the upper-triangular R by back substitution
@@ -853,8 +864,7 @@ int run_logdet(const ld_csr* A, double lmin, double lmax, int degree, int n_matv
     if (ar.base && ar.used > layout_bytes(S.L, want_grad))
         return fail(LD_EINVAL, "internal: workspace layout overflow");
     if (!o.trusted_csr) LD_CHECK(validate_csr(A, S.flag, st));
-    LD_CHECK(build_long_rows(A, ar, st, S.longrows));
-    LD_CHECK(build_dia(A, o, ar, st, S.longrows));
+    LD_CHECK(prepare_rows(A, o, ar, st, S.longrows));
     Timer tm(st);
     tm.mark();
     LD_CHECK(estimate_front(A, seed, S, st, tm));
@@ -1069,8 +1079,7 @@ int ld_apply_log(const ld_csr* A, double lmin, double lmax, int32_t degree, cons
     int* flag = (int*)ar.take(256);
     if (!o.trusted_csr) LD_CHECK(validate_csr(A, flag, st));
     LongRows lr;
-    LD_CHECK(build_long_rows(A, ar, st, lr));
-    LD_CHECK(build_dia(A, o, ar, st, lr));
+    LD_CHECK(prepare_rows(A, o, ar, st, lr));
     const int m = p.degree;
     const int cb = (o.block_cols > 0 && o.block_cols < std::min(nc, 64)) ? o.block_cols : std::min(nc, 64);
     // Horner: r_m = d_m V; r_j = (T - xi_j) r_{j+1} + d_j V, with d_0 carrying
@@ -1129,8 +1138,7 @@ int ld_apply_log_adaptive(const ld_csr* A, double lmin, double lmax, int32_t max
     int* flag = (int*)ar.take(256);
     if (!o.trusted_csr) LD_CHECK(validate_csr(A, flag, st));
     LongRows lr;
-    LD_CHECK(build_long_rows(A, ar, st, lr));
-    LD_CHECK(build_dia(A, o, ar, st, lr));
+    LD_CHECK(prepare_rows(A, o, ar, st, lr));
     const int m = p.degree;
     const std::vector<int> deg0((size_t)nc, m);   // columns that never meet tol stop at the cap
     LD_CHECK_HIP(hipMemcpyAsync(deg, deg0.data(), (size_t)nc * 4, hipMemcpyHostToDevice, st));

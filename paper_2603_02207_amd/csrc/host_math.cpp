@@ -237,37 +237,6 @@ uint64_t probe_stream_key(uint64_t seed, int stream) {
     return splitmix_mix(seed + (uint64_t)(stream + 1) * 0x9E3779B97F4A7C15ull);
 }
 
-// ---------------------------------------------------------------------------
-// Cholesky G = R^T R (R upper), FP64, and R^{-1}.
-// ---------------------------------------------------------------------------
-bool cholesky_upper(const double* G, int k, double* R, double* Rinv) {
-    std::memset(R, 0, sizeof(double) * k * k);
-    for (int j = 0; j < k; ++j) {
-        double s = G[j * k + j];
-        for (int t = 0; t < j; ++t) s -= R[t * k + j] * R[t * k + j];
-        if (!(s > 0.0) || !std::isfinite(s)) return false;
-        const double rjj = std::sqrt(s);
-        // relative pivot test: a pivot this small means rank deficiency
-        if (rjj <= 1e-7 * std::sqrt(std::fabs(G[j * k + j])) ) return false;
-        R[j * k + j] = rjj;
-        for (int i = j + 1; i < k; ++i) {
-            double v = G[j * k + i];
-            for (int t = 0; t < j; ++t) v -= R[t * k + j] * R[t * k + i];
-            R[j * k + i] = v / rjj;
-        }
-    }
-    std::memset(Rinv, 0, sizeof(double) * k * k);
-    for (int j = k - 1; j >= 0; --j) {
-        Rinv[j * k + j] = 1.0 / R[j * k + j];
-        for (int i = j + 1; i < k; ++i) {
-            double v = 0.0;
-            for (int t = j + 1; t <= i; ++t) v += R[j * k + t] * Rinv[t * k + i];
-            Rinv[j * k + i] = -v / R[j * k + j];
-        }
-    }
-    return true;
-}
-
 void tridiag_top_eigenpair(const std::vector<double>& a, const std::vector<double>& b, double* theta,
                            double* last) {
     const int k = (int)a.size();

@@ -122,6 +122,12 @@ hipError_t launch_cross(bool f64, int n, const void* X, Blk bx, int kx, const vo
 hipError_t launch_reduce(const double* part, int nwg, int len, int part_ld, int outer,
                          long long outer_stride, double* out, int out_ld, hipStream_t st);
 
+// G = R^T R for a k x k FP64 Gram (k <= 64, row-major): R (may be null) and
+// R^{-1}, both upper triangular; *flag = 0, 1 (non-finite entry) or 2 (pivot
+// not positive or below 1e-7 sqrt(G_jj)), R^{-1} zero unless 0.
+hipError_t launch_chol_factor(const double* G, int k, double* R, double* Rinv, int* flag,
+                              hipStream_t st);
+
 // out[r, j] = (base ? base[r, j] : 0) + (signs ? S_key[r, j] : 0)
 //             + sign_m * sum_i Y[r, i] M[i, j],
 // M k_y x k_out FP64 (device), j < k_out; Y, base and out column-blocked

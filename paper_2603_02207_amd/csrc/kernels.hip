@@ -1002,6 +1002,85 @@ hipError_t launch_reduce(const double* part, int nwg, int len, int part_ld, int 
 }
 
 // ---------------------------------------------------------------------------
+// CholQR's small factorisation on the device: G = R^T R (upper R) and R^{-1},
+// k <= 64, one workgroup.  Right-looking elimination subtracts the rank-one
+// terms R[t][i] R[t][l] in increasing t, the order of the textbook
+// column-oriented Cholesky; R^{-1} is formed by back substitution, one thread
+// per column.  A non-finite Gram entry sets *flag = 1 and a non-positive or
+// relatively tiny pivot (rank-deficient sketch: r_jj <= 1e-7 sqrt(G_jj))
+// sets 2; then R^{-1} is left zero.  *flag is written on every call.
+// ---------------------------------------------------------------------------
+constexpr int kCholMax = 64;
+constexpr int kCholLd = kCholMax + 1;
+
+__global__ __launch_bounds__(kThreads) void chol_factor_kernel(const double* __restrict__ G, int k,
+                                                               double* __restrict__ R,
+                                                               double* __restrict__ Rinv,
+                                                               int* __restrict__ flag) {
+    // R in the upper triangle of a; R^{-1} transposed in its strict lower
+    // triangle, inv(j, i) at a[i][j], with the diagonal of R^{-1} in invd
+    __shared__ double a[kCholMax * kCholLd];
+    __shared__ double invd[kCholMax];
+    __shared__ int bad;
+    const int tid = threadIdx.x;
+    if (tid == 0) bad = 0;
+    __syncthreads();
+    for (int e = tid; e < k * k; e += kThreads) {
+        const double v = G[e];
+        if (!isfinite(v)) bad = 1;
+        a[(e / k) * kCholLd + e % k] = v;
+    }
+    __syncthreads();
+    for (int j = 0; j < k && bad == 0; ++j) {
+        const double s = a[j * kCholLd + j];
+        const double rjj = sqrt(s);
+        const bool ok = s > 0.0 && isfinite(s) && rjj > 1e-7 * sqrt(fabs(G[j * k + j]));
+        __syncthreads();   // every lane has read the pivot before row j changes
+        if (!ok) {
+            if (tid == 0) bad = 2;
+            __syncthreads();
+            break;
+        }
+        for (int i = j + tid; i < k; i += kThreads)
+            a[j * kCholLd + i] = i == j ? rjj : a[j * kCholLd + i] / rjj;
+        __syncthreads();
+        const int m = k - j - 1;
+        for (int e = tid; e < m * m; e += kThreads) {
+            const int r = j + 1 + e / m, c = j + 1 + e % m;
+            if (c >= r) a[r * kCholLd + c] -= a[j * kCholLd + r] * a[j * kCholLd + c];
+        }
+        __syncthreads();
+    }
+    const int ok = bad == 0;
+    if (ok && tid < k) {   // column i of R^{-1}, rows i, i-1, ..., 0
+        const int i = tid;
+        const double di = 1.0 / a[i * kCholLd + i];
+        invd[i] = di;
+        for (int j = i - 1; j >= 0; --j) {
+            double sacc = 0.0;
+            for (int t = j + 1; t < i; ++t) sacc += a[j * kCholLd + t] * a[i * kCholLd + t];
+            sacc += a[j * kCholLd + i] * di;
+            a[i * kCholLd + j] = -sacc / a[j * kCholLd + j];
+        }
+    }
+    __syncthreads();
+    for (int e = tid; e < k * k; e += kThreads) {
+        const int r = e / k, c = e % k;
+        const bool on = ok && c >= r;
+        if (R) R[e] = on ? a[r * kCholLd + c] : 0.0;
+        Rinv[e] = on ? (c == r ? invd[r] : a[c * kCholLd + r]) : 0.0;
+    }
+    if (tid == 0) *flag = bad;
+}
+
+hipError_t launch_chol_factor(const double* G, int k, double* R, double* Rinv, int* flag,
+                              hipStream_t st) {
+    if (k < 1 || k > kCholMax) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(chol_factor_kernel, dim3(1), dim3(kThreads), 0, st, G, k, R, Rinv, flag);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
 // row block times a small FP64 matrix (TRSM with R^{-1}; deflation G - Q C)
 // ---------------------------------------------------------------------------
 // Tiles of RT rows (one row per thread); a grid of at most kRowmatWgs

@@ -31,11 +31,6 @@ void squared_basis(const std::vector<double>& xi, const std::vector<double>& d,
 uint64_t splitmix_mix(uint64_t z);
 uint64_t probe_stream_key(uint64_t seed, int stream);
 
-// Cholesky of a k x k symmetric matrix (row-major, FP64); on success R is the
-// upper factor (G = R^T R) and Rinv its inverse.  Returns false if G is not
-// numerically positive definite.
-bool cholesky_upper(const double* G, int k, double* R, double* Rinv);
-
 // Largest eigenvalue of the symmetric tridiagonal matrix with diagonal a[0..k)
 // and off-diagonal b[0..k-1) (cyclic Jacobi on the dense k x k matrix), and
 // the last component of its unit eigenvector.
