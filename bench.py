@@ -38,6 +38,8 @@ def parse():
     p.add_argument("--seed", type=int, default=0)
     p.add_argument("--block-cols", type=int, default=0)
     p.add_argument("--dot-mode", choices=["auto", "forward", "squared"], default="auto")
+    p.add_argument("--tile-order", choices=["auto", "bands", "interleaved"], default="auto",
+                   help="row-tile order of the Newton-step launches (default: by working set)")
     p.add_argument("--no-fp64", action="store_true")
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--grad", action="store_true",
@@ -242,7 +244,7 @@ def main():
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
         print("bench.py: this build runs on exactly one GPU; --gpus must be 1 "
-              "(multi-GPU sharding is described in DESIGN.md, not implemented)", file=sys.stderr)
+              "(sharding across GPUs is not implemented)", file=sys.stderr)
         sys.exit(2)
 
     import torch
@@ -283,7 +285,8 @@ def run_workload(args, workload, steps):
     A32 = ld.CSR.from_arrays(row_ptr, col_idx, val, n, device=dev, dtype=torch.float32)
     lmin, lmax = ld.spectral_bounds(A32)           # Gershgorin on the device (also checks the CSR)
     A64 = ld.CSR.from_arrays(row_ptr, col_idx, val, n, device=dev, dtype=torch.float64)
-    opts = ld.Options(block_cols=args.block_cols, dot_mode=mode, trusted_csr=1)
+    tiles = {"auto": 0, "bands": 1, "interleaved": 2}[args.tile_order]
+    opts = ld.Options(block_cols=args.block_cols, dot_mode=mode, trusted_csr=1, tile_order=tiles)
     t = time.perf_counter()
     ld.logdet(A32, lmin, lmax, degree, m_vec, args.seed)   # validated call
     torch.cuda.synchronize()
@@ -334,6 +337,7 @@ def run_workload(args, workload, steps):
             "matrix_storage": (f"diagonal ({st['dia_diagonals']} diagonals)" if st.get("dia_diagonals")
                                else "csr"),
             "block_cols": args.block_cols,
+            "tile_order": {1: "bands", 2: "interleaved"}[st["tile_order_used"]],
             "seed": args.seed,
             "parallelism": "single GPU",
         },

@@ -66,6 +66,11 @@ extern "C" {
 #define LD_DOT_FORWARD 1    /* Alg. 2 forward: m steps, <x, w_j> every step    */
 #define LD_DOT_SQUARED 2    /* ceil(m/2) steps: <w_a,w_a>, <w_a,w_a+1>          */
 
+/* ld_options.tile_order */
+#define LD_TILES_AUTO        0
+#define LD_TILES_XCD_BANDS   1  /* XCD x walks the x-th contiguous band of tiles */
+#define LD_TILES_INTERLEAVED 2  /* workgroup w takes tiles w, w + grid, ...      */
+
 typedef struct {
     int64_t n;               /* rows = columns                                 */
     int64_t nnz;             /* stored entries, < 2^31                         */
@@ -90,7 +95,14 @@ typedef struct {
                                 every entry lies on one of at most 9 diagonals,
                                 and gathers from it instead of the CSR arrays;
                                 same sums in the same order)                    */
-    int32_t reserved[2];
+    int32_t tile_order;      /* LD_TILES_AUTO / LD_TILES_XCD_BANDS /
+                                LD_TILES_INTERLEAVED: how the workgroups of a
+                                Newton-step launch walk the row tiles (auto:
+                                XCD bands when the launch's working set fits
+                                the 256 MB Infinity Cache, else interleaved);
+                                the sums' grouping, hence the last bits of the
+                                quadratic forms, depend on it                 */
+    int32_t reserved[1];
 } ld_options;
 
 typedef struct {
@@ -115,7 +127,7 @@ typedef struct {
     int32_t launches1, launches23;
     double bytes1, bytes23;  /* algorithmic bytes of those launches            */
     int32_t dia_diagonals;   /* diagonals of the diagonal storage used, 0: CSR */
-    int32_t reserved_stats;
+    int32_t tile_order_used; /* LD_TILES_XCD_BANDS or LD_TILES_INTERLEAVED      */
 } ld_stats;
 
 /* Defaults for ld_options (all zero except as documented). */

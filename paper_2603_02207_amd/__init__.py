@@ -51,6 +51,7 @@ class Options:
     dot_mode: int = LD_DOT_AUTO
     trusted_csr: int = 0
     csr_only: int = 0
+    tile_order: int = 0
 
     def to_c(self) -> nat.LdOptions:
         o = nat.LdOptions()
@@ -62,6 +63,7 @@ class Options:
         o.dot_mode = self.dot_mode
         o.trusted_csr = self.trusted_csr
         o.csr_only = self.csr_only
+        o.tile_order = self.tile_order
         return o
 
 

@@ -49,7 +49,8 @@ class LdOptions(ctypes.Structure):
         ("dot_mode", ctypes.c_int32),
         ("trusted_csr", ctypes.c_int32),
         ("csr_only", ctypes.c_int32),
-        ("reserved", ctypes.c_int32 * 2),
+        ("tile_order", ctypes.c_int32),
+        ("reserved", ctypes.c_int32 * 1),
     ]
 
 
@@ -78,7 +79,7 @@ class LdStats(ctypes.Structure):
         ("bytes1", ctypes.c_double),
         ("bytes23", ctypes.c_double),
         ("dia_diagonals", ctypes.c_int32),
-        ("reserved_stats", ctypes.c_int32),
+        ("tile_order_used", ctypes.c_int32),
     ]
 
     def as_dict(self):

@@ -44,7 +44,8 @@ struct CsrDev {
     const void* val;
 };
 
-constexpr int kMaxDiag = 9;      // diagonals of the diagonal storage (9-point stencils, 7-point 3-D)
+constexpr int kMaxDiag = 9;
+constexpr int kXcds = 8;     // XCDs of the MI355X; workgroup w runs on XCD w % 8      // diagonals of the diagonal storage (9-point stencils, 7-point 3-D)
 
 // Geometry of a Newton step launch over columns [c0, c0+bcols) of row-major
 // blocks with leading dimension ld (elements).
@@ -77,6 +78,11 @@ struct StepArgs {
     const void* dia;
     int dia_nd;
     int dia_off[kMaxDiag];
+    // tile order: 0 = XCD x (blockIdx % 8) walks the x-th contiguous band of
+    // row tiles (stencil neighbours stay in that XCD's L2); 1 = workgroup w
+    // takes tiles w, w + grid, ... (spreads each tile's neighbours over the
+    // XCDs; faster once the blocks stream from HBM)
+    int interleave;
 };
 
 constexpr int kLongRow = 64;     // entries above which a row is "long"
@@ -159,11 +165,15 @@ struct AdjArgs {
 };
 hipError_t launch_adjoint(bool f64, const CsrDev& A, const AdjArgs& a, hipStream_t st);
 
-// Diagonal storage of A.  info (device, 16 ints, info[12] preset to 0 by the
-// caller): info[0] = number of diagonals nd (distinct offsets col - row of 64
-// sampled rows, ascending, in info[1..nd]; -1 if more than kMaxDiag);
-// dia[r*nd + q] = A[r, r + info[1+q]] or 0; info[12] = 1 when some stored
-// entry lies on none of the diagonals (the storage is then unusable).
+// Row probe (info: device, 32 ints, info[12] preset to 0 by the caller):
+// info[0] = number of diagonals nd (distinct offsets col - row of 64 sampled
+// rows, ascending, in info[1..nd]; -1 if more than kMaxDiag), and
+// info[kBandInfo + i] = row_ptr[i*n/8], i = 0..8 (entries per XCD band).
+// Then the diagonal storage: dia[r*nd + q] = A[r, r + info[1+q]] or 0;
+// info[12] = 1 when some stored entry lies on none of the diagonals (the
+// storage is then unusable).
+constexpr int kBandInfo = 16;
+hipError_t launch_rows_probe(const CsrDev& A, int* info, hipStream_t st);
 hipError_t launch_dia_build(bool f64, const CsrDev& A, void* dia, int* info, hipStream_t st);
 
 // Alg. 2's stopping test after the step that produced w_m: for columns c < qc

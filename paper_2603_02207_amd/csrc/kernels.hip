@@ -17,6 +17,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <climits>
 #include <cstdint>
 #include <mutex>
 #include <unordered_map>
@@ -29,7 +30,6 @@ namespace {
 
 constexpr int kThreads = 256;
 constexpr int kWaves = kThreads / 64;
-constexpr int kXcds = 8;
 
 template <typename T, int V>
 struct alignas(sizeof(T) * V) Pack {
@@ -116,7 +116,7 @@ __global__ __launch_bounds__(NT) void step_kernel(
     const uint64_t* __restrict__ mask, double* __restrict__ ps0, double* __restrict__ ps1,
     double* __restrict__ ps2, int part_ld, int lpr, int rpw, int skip_long, T* __restrict__ accum,
     int ldacc, int acc_cols, int ntiles, const uint64_t* __restrict__ active, const T* __restrict__ dia, int nd,
-    DiaOff off) {
+    DiaOff off, int interleave) {
     constexpr bool kDot = is_dot(KIND);
     constexpr int NW = NT / 64;
     constexpr int kSums = kDot ? ((FIRST ? 1 : 0) + 1 + (KIND == STEP_DOT_SQ ? 1 : 0)) : 0;
@@ -148,16 +148,18 @@ __global__ __launch_bounds__(NT) void step_kernel(
 #pragma unroll
     for (int e = 0; e < VEC; ++e) s0[e] = s1[e] = s2[e] = 0.0;
 
-    // Tiles of NW*rows_per_wave rows.  XCD x (= blockIdx % 8) owns the
-    // contiguous band of tiles [x*base + min(x, rem), ...) and its workgroups
-    // take the band's tiles round-robin in order, so the XCD's active rows
-    // stay a narrow window; with one workgroup per tile each takes one.
+    // Tiles of NW*rows_per_wave rows.  Banded order: XCD x (= blockIdx % 8)
+    // owns the contiguous band of tiles [x*base + min(x, rem), ...) and its
+    // workgroups take the band's tiles round-robin in order, so the XCD's
+    // active rows stay a narrow window.  Interleaved order: workgroup w takes
+    // tiles w, w + grid, ...  With one workgroup per tile each takes one.
     const int xcd = blockIdx.x % kXcds;
     const int base = ntiles / kXcds, rem = ntiles % kXcds;
-    const int band0 = xcd * base + (xcd < rem ? xcd : rem);
-    const int band_len = base + (xcd < rem ? 1 : 0);
-    const int wgs_here = gridDim.x / kXcds + (xcd < (int)(gridDim.x % kXcds) ? 1 : 0);
-    for (int t = blockIdx.x / kXcds; t < band_len; t += wgs_here) {
+    const int band0 = interleave ? 0 : xcd * base + (xcd < rem ? xcd : rem);
+    const int band_len = interleave ? ntiles : base + (xcd < rem ? 1 : 0);
+    const int wgs_here =
+        interleave ? (int)gridDim.x : (int)(gridDim.x / kXcds) + (xcd < (int)(gridDim.x % kXcds) ? 1 : 0);
+    for (int t = interleave ? (int)blockIdx.x : (int)(blockIdx.x / kXcds); t < band_len; t += wgs_here) {
     const int W0 = (band0 + t) * (NW * rows_per_wave) + wave * rows_per_wave;   // first row of this wave
     const int nrows = max(0, min(rows_per_wave, n - W0));
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");   // the previous tile's LDS reads come first
@@ -555,7 +557,8 @@ hipError_t launch_step_t(const CsrDev& A, const StepArgs& s, hipStream_t st, int
         hipLaunchKernelGGL(fn, dim3(nwg), dim3(NT), 0, st, A.n, A.row_ptr, A.col_idx, (const T*)A.val,         \
                            (const T*)s.win, (T*)s.wout, s.ld, s.c0, s.bcols, s.gshift, (T)s.alpha, (T)s.beta,   \
                            (T)s.dj, (const T*)s.vsrc, s.ldv, s.mask, s.ps0, s.ps1, s.ps2, s.part_ld, lpr, rpw, \
-                           0, (T*)s.acc, s.ldacc, s.acc_cols, ntiles, s.active, (const T*)s.dia, s.dia_nd, off); \
+                           0, (T*)s.acc, s.ldacc, s.acc_cols, ntiles, s.active, (const T*)s.dia, s.dia_nd, off, \
+                           s.interleave);                                                                      \
         if (nwg_out) *nwg_out = nwg;                                                                           \
     }
         if (s.dia_nd <= 3)
@@ -577,7 +580,7 @@ hipError_t launch_step_t(const CsrDev& A, const StepArgs& s, hipStream_t st, int
                        A.n, A.row_ptr, A.col_idx, (const T*)A.val, (const T*)s.win, (T*)s.wout, s.ld,
                        s.c0, s.bcols, s.gshift, (T)s.alpha, (T)s.beta, (T)s.dj, (const T*)s.vsrc,
                        s.ldv, s.mask, s.ps0, s.ps1, s.ps2, s.part_ld, lpr, rpw, skip, (T*)s.acc,
-                       s.ldacc, s.acc_cols, ntiles, s.active, (const T*)nullptr, 0, off);
+                       s.ldacc, s.acc_cols, ntiles, s.active, (const T*)nullptr, 0, off, s.interleave);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess || !skip) return e;
     hipLaunchKernelGGL((long_row_kernel<T, VEC, KIND, FIRST>), dim3(kLongWgs), dim3(256), 0, st,
@@ -1005,8 +1008,8 @@ hipError_t launch_reduce(const double* part, int nwg, int len, int part_ld, int 
 // CholQR's small factorisation on the device: G = R^T R (upper R) and R^{-1},
 // k <= 64, one workgroup.  Right-looking elimination subtracts the rank-one
 // terms R[t][i] R[t][l] in increasing t, the order of the textbook
-// column-oriented Cholesky; R^{-1} is formed by back substitution, one thread
-// per column.  A non-finite Gram entry sets *flag = 1 and a non-positive or
+// column-oriented Cholesky; R^{-1} solves R X = I row by row from the last,
+// each row's contribution subtracted from all rows above it at once.  A non-finite Gram entry sets *flag = 1 and a non-positive or
 // relatively tiny pivot (rank-deficient sketch: r_jj <= 1e-7 sqrt(G_jj))
 // sets 2; then R^{-1} is left zero.  *flag is written on every call.
 // ---------------------------------------------------------------------------
@@ -1021,6 +1024,7 @@ __global__ __launch_bounds__(kThreads) void chol_factor_kernel(const double* __r
     // triangle, inv(j, i) at a[i][j], with the diagonal of R^{-1} in invd
     __shared__ double a[kCholMax * kCholLd];
     __shared__ double invd[kCholMax];
+    __shared__ double gdiag[kCholMax];   // the Gram's diagonal, for the relative pivot test
     __shared__ int bad;
     const int tid = threadIdx.x;
     if (tid == 0) bad = 0;
@@ -1029,12 +1033,13 @@ __global__ __launch_bounds__(kThreads) void chol_factor_kernel(const double* __r
         const double v = G[e];
         if (!isfinite(v)) bad = 1;
         a[(e / k) * kCholLd + e % k] = v;
+        if (e % (k + 1) == 0) gdiag[e / (k + 1)] = v;
     }
     __syncthreads();
     for (int j = 0; j < k && bad == 0; ++j) {
         const double s = a[j * kCholLd + j];
         const double rjj = sqrt(s);
-        const bool ok = s > 0.0 && isfinite(s) && rjj > 1e-7 * sqrt(fabs(G[j * k + j]));
+        const bool ok = s > 0.0 && isfinite(s) && rjj > 1e-7 * sqrt(fabs(gdiag[j]));
         __syncthreads();   // every lane has read the pivot before row j changes
         if (!ok) {
             if (tid == 0) bad = 2;
@@ -1052,15 +1057,33 @@ __global__ __launch_bounds__(kThreads) void chol_factor_kernel(const double* __r
         __syncthreads();
     }
     const int ok = bad == 0;
-    if (ok && tid < k) {   // column i of R^{-1}, rows i, i-1, ..., 0
-        const int i = tid;
-        const double di = 1.0 / a[i * kCholLd + i];
-        invd[i] = di;
-        for (int j = i - 1; j >= 0; --j) {
-            double sacc = 0.0;
-            for (int t = j + 1; t < i; ++t) sacc += a[j * kCholLd + t] * a[i * kCholLd + t];
-            sacc += a[j * kCholLd + i] * di;
-            a[i * kCholLd + j] = -sacc / a[j * kCholLd + j];
+    // R X = I solved by rows, last first: row j of X is final once the rows
+    // below it have been subtracted from the right-hand side B (= I at the
+    // start); then every row i < j takes away R[i][j] X[j][:].  B and X are
+    // upper triangular: B[i][c] (i < c) lives at a[c][i], its diagonal in invd.
+    if (ok) {
+        for (int e = tid; e < k * k; e += kThreads) {
+            const int r = e / k, c = e % k;
+            if (r > c) a[r * kCholLd + c] = 0.0;
+        }
+        for (int i = tid; i < k; i += kThreads) invd[i] = 1.0;
+        __syncthreads();
+        for (int j = k - 1; j >= 0; --j) {
+            const double rjj = a[j * kCholLd + j];
+            for (int c = j + tid; c < k; c += kThreads) {
+                if (c == j)
+                    invd[j] = invd[j] / rjj;
+                else
+                    a[c * kCholLd + j] = a[c * kCholLd + j] / rjj;
+            }
+            __syncthreads();
+            const int w = k - j;
+            for (int e = tid; e < j * w; e += kThreads) {
+                const int i = e / w, c = j + e % w;
+                const double xjc = c == j ? invd[j] : a[c * kCholLd + j];
+                a[c * kCholLd + i] -= a[i * kCholLd + j] * xjc;
+            }
+            __syncthreads();
         }
     }
     __syncthreads();
@@ -1285,39 +1308,45 @@ __global__ __launch_bounds__(kThreads) void axpby_kernel(long long len, T a, con
 // or -1 when a sampled row or the union exceeds kMaxDiag.
 __global__ __launch_bounds__(64) void dia_probe_kernel(int n, const int* __restrict__ row_ptr,
                                                        const int* __restrict__ col_idx, int* __restrict__ info) {
-    __shared__ int offs[64][kMaxDiag];
-    __shared__ int cnt[64];
+    // one wave: lane t samples one row (golden-ratio stride: no alignment with
+    // a grid's rows, whatever its width) and holds its column offsets
     const int t = threadIdx.x;
-    // golden-ratio stride: no alignment with a grid's rows, whatever its width
     const int r = (int)(((uint64_t)(t + 1) * 0x9E3779B97F4A7C15ull) % (uint64_t)n);
     const int b = row_ptr[r], e = row_ptr[r + 1];
-    cnt[t] = e - b <= kMaxDiag ? e - b : -1;
-    for (int k = b; k < e && k - b < kMaxDiag; ++k) offs[t][k - b] = col_idx[k] - r;
-    __syncthreads();
-    if (t != 0) return;
+    const bool fits = e - b <= kMaxDiag;
+    int off[kMaxDiag];
+#pragma unroll
+    for (int q = 0; q < kMaxDiag; ++q) off[q] = (fits && b + q < e) ? col_idx[b + q] - r : INT_MAX;
+    // the distinct offsets in increasing order: repeatedly the wave's smallest
+    // offset above the last one found
+    int nu = __any(!fits) ? -1 : 0;
     int u[kMaxDiag];
-    int nu = 0;
-    for (int i = 0; i < 64 && nu >= 0; ++i) {
-        if (cnt[i] < 0) {
+    long long last = LLONG_MIN;
+    while (nu >= 0) {
+        int m = INT_MAX;
+#pragma unroll
+        for (int q = 0; q < kMaxDiag; ++q)
+            if ((long long)off[q] > last && off[q] < m) m = off[q];
+        for (int d = 32; d >= 1; d >>= 1) m = min(m, __shfl_xor(m, d, 64));
+        if (m == INT_MAX) break;
+        if (nu == kMaxDiag) {
             nu = -1;
             break;
         }
-        for (int j = 0; j < cnt[i]; ++j) {
-            const int o = offs[i][j];
-            int p = 0;
-            while (p < nu && u[p] < o) ++p;
-            if (p < nu && u[p] == o) continue;
-            if (nu == kMaxDiag) {
-                nu = -1;
-                break;
-            }
-            for (int q = nu; q > p; --q) u[q] = u[q - 1];
-            u[p] = o;
-            ++nu;
-        }
+#pragma unroll
+        for (int q = 0; q < kMaxDiag; ++q)
+            if (q == nu) u[q] = m;
+        ++nu;
+        last = m;
     }
-    info[0] = nu;
-    for (int q = 0; q < kMaxDiag; ++q) info[1 + q] = (nu > 0 && q < nu) ? u[q] : 0;
+    if (t == 0) {
+        info[0] = nu;
+#pragma unroll
+        for (int q = 0; q < kMaxDiag; ++q) info[1 + q] = (nu > 0 && q < nu) ? u[q] : 0;
+    }
+    // row_ptr at the boundaries of eight equal row bands (balance of the
+    // entries over the XCD bands)
+    if (t <= kXcds) info[kBandInfo + t] = row_ptr[(int)((long long)t * n / kXcds)];
 }
 
 // Diagonal storage for the offsets of info (ascending): dia[r*nd + q] =
@@ -1357,9 +1386,14 @@ __global__ __launch_bounds__(kThreads) void dia_build_kernel(int n, const int* _
     if (bad) info[kDiaFlag] = 1;
 }
 
-hipError_t launch_dia_build(bool f64, const CsrDev& A, void* dia, int* info, hipStream_t st) {
+hipError_t launch_rows_probe(const CsrDev& A, int* info, hipStream_t st) {
     if (A.n == 0) return hipSuccess;
     hipLaunchKernelGGL(dia_probe_kernel, dim3(1), dim3(64), 0, st, A.n, A.row_ptr, A.col_idx, info);
+    return hipGetLastError();
+}
+
+hipError_t launch_dia_build(bool f64, const CsrDev& A, void* dia, int* info, hipStream_t st) {
+    if (A.n == 0) return hipSuccess;
     const int nb = div_up(A.n, kThreads);
     if (f64)
         hipLaunchKernelGGL(dia_build_kernel<double>, dim3(nb), dim3(kThreads), 0, st, A.n, A.row_ptr, A.col_idx,

@@ -364,3 +364,45 @@ def test_diagonal_storage_falls_back_to_csr():
         assert st["dia_diagonals"] == 0
         ref = hutchpp.logdet_estimate(w.to_scipy((csr[0], csr[1], vals, csr[3])), lo, hi, 20, 12, 1)
         assert rel(est, ref) < 1e-10
+
+
+@pytest.mark.parametrize("dtype,tol", [(torch.float64, 1e-11), (torch.float32, 2e-5)])
+def test_tile_orders_agree_with_oracle(dtype, tol):
+    # Both row-tile orders of the Newton-step launches: the recurrence vectors
+    # are per-row results (bit-identical), the quadratic forms regroup their
+    # workgroup sums (same value to rounding); both against the oracle.  A
+    # 3-D stencil (diagonal storage) and an irregular matrix with long rows
+    # (CSR path), several hundred tiles each.
+    for csr in (w.grid_laplacian_3d(40, 0.2), random_spd_csr(60000, 9, long_rows=3)):
+        A, vals = to_gpu(csr, dtype)
+        csr_v = (csr[0], csr[1], vals, csr[3])
+        lo, hi = bounds.gershgorin(csr_v)
+        lo = max(lo, 0.2)
+        ref = hutchpp.logdet_estimate(w.to_scipy(csr_v), lo, hi, 30, 24, 4)
+        V = torch.tensor(np.random.default_rng(8).standard_normal((csr[3], 7)), dtype=dtype, device=DEV)
+        outs = []
+        for order in (1, 2):
+            o = ld.Options(tile_order=order)
+            est = ld.logdet(A, lo, hi, 30, 24, 4, options=o)
+            assert rel(est, ref) < tol, (order, est, ref)
+            outs.append(ld.apply_log(A, lo, hi, 25, V, o))
+        assert torch.equal(outs[0], outs[1])
+    with pytest.raises(ld.NativeError):
+        ld.logdet(A, lo, hi, 30, 24, 4, options=ld.Options(tile_order=3))
+
+
+def test_tile_order_follows_band_balance():
+    # auto: XCD bands for a stencil, interleaved tiles for a power-law graph
+    # whose hubs come first (most entries in the first row band); the estimate
+    # matches the oracle either way.
+    for csr, want in ((w.grid_laplacian_2d(300, 0.5), 1), (w.chung_lu_laplacian(1 << 16), 2)):
+        A, vals = to_gpu(csr, torch.float64)
+        csr_v = (csr[0], csr[1], vals, csr[3])
+        lo, hi = bounds.gershgorin(csr_v)
+        lo = max(lo, 1e-2)
+        est, st = ld.logdet(A, lo, hi, 30, 24, 2, return_stats=True)
+        assert st["tile_order_used"] == want
+        forced = ld.logdet(A, lo, hi, 30, 24, 2, options=ld.Options(tile_order=3 - want), return_stats=True)[1]
+        assert forced["tile_order_used"] == 3 - want
+        ref = hutchpp.logdet_estimate(w.to_scipy(csr_v), lo, hi, 30, 24, 2)
+        assert rel(est, ref) < 1e-10
