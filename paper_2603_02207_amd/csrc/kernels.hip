@@ -1109,13 +1109,20 @@ hipError_t launch_chol_factor(const double* G, int k, double* R, double* Rinv, i
 // Tiles of RT rows (one row per thread); a grid of at most kRowmatWgs
 // workgroups loops over them, staging M once per workgroup.  The tile of Y is
 // loaded into LDS with coalesced accesses (consecutive threads read
-// consecutive columns), each thread multiplies its row by M (read from LDS at
-// the same address by every lane), the results go back into the tile, and
-// the tile is written out coalesced, adding the optional base matrix and
-// probe signs.  Y, base and out are column-blocked (Blk).
+// consecutive columns; each thread issues all its loads before it stores any,
+// so a tile costs one memory round trip), each thread multiplies its row by M
+// (one row of M per step, read from LDS at the same address by every lane),
+// the results go back into the tile, and the tile is written out
+// coalesced, adding the optional base matrix and probe signs.  Y, base and
+// out are column-blocked (Blk).
 constexpr int kRowmatWgs = 1024;
+constexpr int kRowmatBatch = 16;   // loads a thread keeps in flight while staging
 
-template <typename T, int KY, int KO, bool SIGNS, int RT>
+// FAST: Y's columns lie in one block whose rows (ld <= max(KY, KO), 16-byte
+// multiple) the tile holds whole, and out (and base) cover whole rows of
+// their block: a tile is then one contiguous run in each, moved with 16-byte
+// vectors in a single batch per thread.
+template <typename T, int KY, int KO, bool SIGNS, int RT, bool FAST>
 __global__ __launch_bounds__(RT) void rowmat_kernel(int n, const T* __restrict__ Y, Blk by,
                                                     int ky, const double* __restrict__ M,
                                                     int kout, double sign_m, uint64_t key,
@@ -1135,37 +1142,151 @@ __global__ __launch_bounds__(RT) void rowmat_kernel(int n, const T* __restrict__
     }
     __syncthreads();
     const int ntiles = div_up_dev(n, RT);
+    // element e = tid + u*RT of a tile is (row e / k, column e % k); RT = qa*k + qb
+    const int qa_y = RT / ky, qb_y = RT - qa_y * ky;
+    const int qa_o = RT / kout, qb_o = RT - qa_o * kout;
+    const int cy = FAST ? by.c0 % by.bw : 0;   // first column of Y's view within a staged row
     for (int t = blockIdx.x; t < ntiles; t += gridDim.x) {
     const int row0 = t * RT;
     const int nr = min(RT, n - row0);
-    for (int e = threadIdx.x; e < nr * ky; e += RT) {
-        const int r = e / ky, i = e - r * ky;
-        tile[r * KS + i] = Y[yoff[i] + (size_t)(row0 + r) * by.ld];
-    }
-    __syncthreads();
-    if (threadIdx.x < nr) {
-        T y[KY];
+    constexpr int V = 16 / (int)sizeof(T);
+    using P = Pack<T, V>;
+    if constexpr (FAST) {   // the tile is rows [row0, row0+nr) of Y's block, whole
+        constexpr int NV = (KS - 1 + V - 1) / V;
+        const int ldy = by.ld;
+        const T* src = Y + (size_t)(by.c0 / by.bw) * (size_t)by.bstride + (size_t)row0 * ldy;
+        const int nvec = nr * ldy / V;
+        P v[NV];
 #pragma unroll
-        for (int i = 0; i < KY; ++i) y[i] = i < ky ? tile[threadIdx.x * KS + i] : T(0);
+        for (int u = 0; u < NV; ++u) {
+            const int e = threadIdx.x + u * RT;
+            if (e < nvec) v[u] = load_pack<T, V>(src + (size_t)e * V);
+        }
+#pragma unroll
+        for (int u = 0; u < NV; ++u) {
+            const int e = threadIdx.x + u * RT;
+            if (e < nvec) {
+                const int x = e * V, r = x / ldy, c = x - r * ldy;
+#pragma unroll
+                for (int q = 0; q < V; ++q) tile[r * KS + c + q] = v[u].v[q];
+            }
+        }
+    } else
+    {   // stage the tile of Y: a batch of loads in flight, then their LDS stores
+        int r = threadIdx.x / ky, i = threadIdx.x - (threadIdx.x / ky) * ky;
 #pragma nounroll
-        for (int j = 0; j < kout; ++j) {
-            T acc = T(0);
+        for (int u0 = 0; u0 < KY && u0 * RT < nr * ky; u0 += kRowmatBatch) {
+            T v[kRowmatBatch];
+            const int r0 = r, i0 = i;
 #pragma unroll
-            for (int i = 0; i < KY; ++i) acc = fma(y[i], ms[i * KO + j], acc);
-            tile[threadIdx.x * KS + j] = acc;
+            for (int u = 0; u < kRowmatBatch; ++u) {
+                v[u] = r < nr ? Y[yoff[i] + (size_t)(row0 + r) * by.ld] : T(0);
+                r += qa_y;
+                i += qb_y;
+                if (i >= ky) {
+                    i -= ky;
+                    ++r;
+                }
+            }
+            r = r0;
+            i = i0;
+#pragma unroll
+            for (int u = 0; u < kRowmatBatch; ++u) {
+                if (r < nr) tile[r * KS + i] = v[u];
+                r += qa_y;
+                i += qb_y;
+                if (i >= ky) {
+                    i -= ky;
+                    ++r;
+                }
+            }
         }
     }
     __syncthreads();
-    for (int e = threadIdx.x; e < nr * kout; e += RT) {
-        const int r = e / kout, j = e - r * kout;
-        const int row = row0 + r;
-        T v = tile[r * KS + j];
-        if constexpr (SIGNS) {
-            const uint64_t x = probe_bits(key, (uint64_t)j * (uint64_t)n + (uint64_t)row + 1ull);
-            v += (x >> 63) ? T(-1) : T(1);
+    if (threadIdx.x < nr) {   // row times M: one row of M (LDS broadcast) per step
+        T acc[KO];
+#pragma unroll
+        for (int j = 0; j < KO; ++j) acc[j] = T(0);
+#pragma nounroll
+        for (int i = 0; i < ky; ++i) {
+            const T yi = tile[threadIdx.x * KS + cy + i];
+#pragma unroll
+            for (int j = 0; j < KO; ++j) acc[j] = fma(yi, ms[i * KO + j], acc[j]);
         }
-        if (base) v += base[boff[j] + (size_t)row * bb.ld];
-        out[ooff[j] + (size_t)row * bo.ld] = v;
+#pragma unroll
+        for (int j = 0; j < KO; ++j)
+            if (j < kout) tile[threadIdx.x * KS + j] = acc[j];
+    }
+    __syncthreads();
+    if constexpr (FAST) {   // out's tile is rows [row0, row0+nr) of its block, kout == ld
+        constexpr int NV = (KO + V - 1) / V;
+        T* dst = out + (size_t)(bo.c0 / bo.bw) * (size_t)bo.bstride + (size_t)row0 * kout;
+        const T* bsrc = base ? base + (size_t)(bb.c0 / bb.bw) * (size_t)bb.bstride + (size_t)row0 * kout : nullptr;
+        const int nvec = nr * kout / V;
+        P b[NV];
+#pragma unroll
+        for (int u = 0; u < NV; ++u) {
+            const int e = threadIdx.x + u * RT;
+#pragma unroll
+            for (int q = 0; q < V; ++q) b[u].v[q] = T(0);
+            if (bsrc && e < nvec) b[u] = load_pack<T, V>(bsrc + (size_t)e * V);
+        }
+#pragma unroll
+        for (int u = 0; u < NV; ++u) {
+            const int e = threadIdx.x + u * RT;
+            if (e < nvec) {
+                const int x = e * V, r = x / kout, c = x - r * kout;
+                P o;
+#pragma unroll
+                for (int q = 0; q < V; ++q) {
+                    T v = tile[r * KS + c + q] + b[u].v[q];
+                    if constexpr (SIGNS) {
+                        const uint64_t z = probe_bits(key, (uint64_t)(c + q) * (uint64_t)n + (uint64_t)(row0 + r) + 1ull);
+                        v += (z >> 63) ? T(-1) : T(1);
+                    }
+                    o.v[q] = v;
+                }
+                store_pack<T, V>(dst + (size_t)x, o);
+            }
+        }
+    } else
+    {   // write out: a batch of base values loaded first (base may alias out), then the stores
+        int r = threadIdx.x / kout, j = threadIdx.x - (threadIdx.x / kout) * kout;
+#pragma nounroll
+        for (int u0 = 0; u0 < KO && u0 * RT < nr * kout; u0 += kRowmatBatch) {
+            T b[kRowmatBatch];
+            const int r0 = r, j0 = j;
+#pragma unroll
+            for (int u = 0; u < kRowmatBatch; ++u) {
+                b[u] = (base && r < nr) ? base[boff[j] + (size_t)(row0 + r) * bb.ld] : T(0);
+                r += qa_o;
+                j += qb_o;
+                if (j >= kout) {
+                    j -= kout;
+                    ++r;
+                }
+            }
+            r = r0;
+            j = j0;
+#pragma unroll
+            for (int u = 0; u < kRowmatBatch; ++u) {
+                if (r < nr) {
+                    const int row = row0 + r;
+                    T v = tile[r * KS + j] + b[u];
+                    if constexpr (SIGNS) {
+                        const uint64_t x = probe_bits(key, (uint64_t)j * (uint64_t)n + (uint64_t)row + 1ull);
+                        v += (x >> 63) ? T(-1) : T(1);
+                    }
+                    out[ooff[j] + (size_t)row * bo.ld] = v;
+                }
+                r += qa_o;
+                j += qb_o;
+                if (j >= kout) {
+                    j -= kout;
+                    ++r;
+                }
+            }
+        }
     }
     __syncthreads();   // the tile is reused by the next iteration
     }
@@ -1177,12 +1298,32 @@ void launch_rowmat_t(int n, hipStream_t st, const void* Y, Blk by, int ky, const
                      void* out, Blk bo) {
     constexpr int RT = (sizeof(T) == 8 && KY == 64 && KO == 64) ? 128 : 256;
     const int nwg = std::min(div_up(n, RT), kRowmatWgs);
+    constexpr int V = 16 / (int)sizeof(T);
+    auto aligned = [](const void* p) { return ((uintptr_t)p & 15) == 0; };
+    // a view covers whole rows of its block: starts a block, as wide as its rows
+    auto whole_rows = [&](const Blk& b, int k) { return b.c0 % b.bw == 0 && k == b.ld && k <= b.bw && b.ld % V == 0; };
+    // at most 16 vectors per thread in a batch (FP64 with 64 columns keeps the general path)
+    constexpr bool kFastFits = (KY > KO ? KY : KO) / V <= 16;
+    const bool fast = kFastFits && aligned(Y) && aligned(out) && by.ld % V == 0 && by.ld <= (KY > KO ? KY : KO) &&
+                      by.c0 % by.bw + ky <= by.bw && whole_rows(bo, kout) &&
+                      (!base || (aligned(base) && whole_rows(bb, kout)));
+#define LD_RM_GO(S_, F_)                                                                                     \
+    hipLaunchKernelGGL((rowmat_kernel<T, KY, KO, S_, RT, F_>), dim3(nwg), dim3(RT), 0, st, n, (const T*)Y, by, \
+                       ky, M, kout, sign_m, key, (const T*)base, bb, (T*)out, bo)
+    if constexpr (kFastFits) {
+        if (fast) {
+            if (signs)
+                LD_RM_GO(true, true);
+            else
+                LD_RM_GO(false, true);
+            return;
+        }
+    }
     if (signs)
-        hipLaunchKernelGGL((rowmat_kernel<T, KY, KO, true, RT>), dim3(nwg), dim3(RT), 0, st, n,
-                           (const T*)Y, by, ky, M, kout, sign_m, key, (const T*)base, bb, (T*)out, bo);
+        LD_RM_GO(true, false);
     else
-        hipLaunchKernelGGL((rowmat_kernel<T, KY, KO, false, RT>), dim3(nwg), dim3(RT), 0, st, n,
-                           (const T*)Y, by, ky, M, kout, sign_m, key, (const T*)base, bb, (T*)out, bo);
+        LD_RM_GO(false, false);
+#undef LD_RM_GO
 }
 
 template <typename T>
