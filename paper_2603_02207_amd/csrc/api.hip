@@ -397,8 +397,8 @@ int prepare_rows(const ld_csr* A, const ld_options& o, Arena& ar, hipStream_t st
 
 // Gram / cross product X^T Z reduced to a kx x kz FP64 matrix on the device.
 int cross_product(bool f64, int n, const void* X, Blk bx, int kx, const void* Z, Blk bz, int kz,
-                  bool zsigns, uint64_t key, double* part, double* out, hipStream_t st) {
-    LD_CHECK_HIP(launch_cross(f64, n, X, bx, kx, Z, bz, kz, zsigns, key, part, st));
+                  const uint64_t* zmask, double* part, double* out, hipStream_t st) {
+    LD_CHECK_HIP(launch_cross(f64, n, X, bx, kx, Z, bz, kz, zmask, part, st));
     LD_CHECK_HIP(launch_reduce(part, cross_num_wg(n), kx * kz, kx * kz, 1, 0, out, kx * kz, st));
     return LD_OK;
 }
@@ -408,9 +408,9 @@ int cross_product(bool f64, int n, const void* X, Blk bx, int kx, const void* Z,
 // columns [0, k)).
 int cholqr_pass(bool f64, int n, const BlkMat& Y, int k, const BlkMat& Q, double* part, double* dG,
                 double* dR, double* dRinv, int* dflag, hipStream_t st) {
-    LD_CHECK(cross_product(f64, n, Y.base, Y.desc(), k, Y.base, Y.desc(), k, false, 0, part, dG, st));
+    LD_CHECK(cross_product(f64, n, Y.base, Y.desc(), k, Y.base, Y.desc(), k, nullptr, part, dG, st));
     LD_CHECK_HIP(launch_chol_factor(dG, k, dR, dRinv, dflag, st));
-    LD_CHECK_HIP(launch_rowmat(f64, n, Y.base, Y.desc(), k, dRinv, k, 1.0, false, 0, nullptr,
+    LD_CHECK_HIP(launch_rowmat(f64, n, Y.base, Y.desc(), k, dRinv, k, 1.0, nullptr, nullptr,
                                Blk::plain(1), Q.base, Q.desc(), st));
     return LD_OK;
 }
@@ -532,11 +532,14 @@ int estimate_front(const ld_csr* A, uint64_t seed, EstimateState& S, hipStream_t
     double* dR2 = S.small + (size_t)kSlotR2 * 64 * 64;
     LD_CHECK(cholqr_pass(f64, n, L.Y, L.k, L.Q1, S.part, dG, dR1, dRinv, S.flag + 1, st));
     LD_CHECK(cholqr_pass(f64, n, L.Q1, L.k, L.X, S.part, dG, dR2, dRinv, S.flag + 2, st));
-    // ---- deflation: C = Q_b^T G, U = G - Q_b C (G = probe stream 1) into X[:, k:]
-    LD_CHECK(cross_product(f64, n, L.X.base, L.X.desc(), L.k, nullptr, Blk::plain(1), L.kg, true, key1,
-                           S.part, dC, st));
-    LD_CHECK_HIP(launch_rowmat(f64, n, L.X.base, L.X.desc(), L.k, dC, L.kg, -1.0, true, key1, nullptr,
-                               Blk::plain(1), L.X.base, L.X.desc().shifted(L.k), st));
+    // ---- deflation: C = Q_b^T G, U = G - Q_b C (G = probe stream 1) into X[:, k:].
+    //      The sketch is done with S's sign words: the buffer now takes G's.
+    const uint64_t* gmask = (const uint64_t*)S.mask;
+    LD_CHECK_HIP(launch_sign_mask(n, L.kg, key1, (uint64_t*)S.mask, st));
+    LD_CHECK(cross_product(f64, n, L.X.base, L.X.desc(), L.k, nullptr, Blk::plain(1), L.kg, gmask, S.part, dC,
+                           st));
+    LD_CHECK_HIP(launch_rowmat(f64, n, L.X.base, L.X.desc(), L.k, dC, L.kg, -1.0, gmask, nullptr, Blk::plain(1),
+                               L.X.base, L.X.desc().shifted(L.k), st));
     tm.mark();
     return LD_OK;
 }
@@ -719,9 +722,9 @@ int estimate_and_gradient(const ld_csr* A, uint64_t seed, EstimateState& S, Grad
     LD_CHECK(upload(diag(k, 1.0), slot[7], st));
     LD_CHECK(upload(diag(kg, c), slot[8], st));
     LD_CHECK(upload(diag(kg, 1.0), slot[9], st));
-    LD_CHECK_HIP(launch_rowmat(f64, n, L.X.base, X, k, slot[7], k, 1.0, false, 0, nullptr, Blk::plain(1),
+    LD_CHECK_HIP(launch_rowmat(f64, n, L.X.base, X, k, slot[7], k, 1.0, nullptr, nullptr, Blk::plain(1),
                                B.Rg, Gb, st));
-    LD_CHECK_HIP(launch_rowmat(f64, n, L.X.base, X.shifted(k), kg, slot[9], kg, 1.0, false, 0, nullptr,
+    LD_CHECK_HIP(launch_rowmat(f64, n, L.X.base, X.shifted(k), kg, slot[9], kg, 1.0, nullptr, nullptr,
                                Blk::plain(1), B.Rg, Gb.shifted(k), st));
     LD_CHECK_HIP(launch_sign_mask(n, k, key0, (uint64_t*)S.mask, st));
     LD_CHECK_HIP(launch_fill_signs(f64, n, k, ldg, 0, (const uint64_t*)S.mask, 1.0,
@@ -759,8 +762,8 @@ int estimate_and_gradient(const ld_csr* A, uint64_t seed, EstimateState& S, Grad
 
     // ---- the estimate's traces: diag(Q_b^T F Q_b), diag(U^T F U)
     {
-        LD_CHECK(cross_product(f64, n, L.X.base, X, k, L.FX.base, FXd, k, false, 0, S.part, slot[0], st));
-        LD_CHECK(cross_product(f64, n, L.X.base, X.shifted(k), kg, L.FX.base, FXd.shifted(k), kg, false, 0,
+        LD_CHECK(cross_product(f64, n, L.X.base, X, k, L.FX.base, FXd, k, nullptr, S.part, slot[0], st));
+        LD_CHECK(cross_product(f64, n, L.X.base, X.shifted(k), kg, L.FX.base, FXd.shifted(k), kg, nullptr,
                                S.part, slot[1], st));
         std::vector<double> ql((size_t)k * k), qr((size_t)kg * kg);
         LD_CHECK(download(slot[0], ql, st));
@@ -780,16 +783,16 @@ int estimate_and_gradient(const ld_csr* A, uint64_t seed, EstimateState& S, Grad
     for (int i = 0; i < k; ++i)
         for (int j = 0; j < kg; ++j) Ct[(size_t)j * k + i] = C[(size_t)i * kg + j];
     LD_CHECK(upload(Ct, slot[3], st));
-    LD_CHECK(cross_product(f64, n, L.X.base, X.shifted(k), kg, L.FX.base, FXd, k, false, 0, S.part,
+    LD_CHECK(cross_product(f64, n, L.X.base, X.shifted(k), kg, L.FX.base, FXd, k, nullptr, S.part,
                            slot[4], st));
     // T1 = F Q_b - c F U C^T ; then T1 -= c G M1  (= X Q_b of the derivation)
-    LD_CHECK_HIP(launch_rowmat(f64, n, L.FX.base, FXd.shifted(k), kg, slot[3], k, -c, false, 0,
+    LD_CHECK_HIP(launch_rowmat(f64, n, L.FX.base, FXd.shifted(k), kg, slot[3], k, -c, nullptr,
                                L.FX.base, FXd, L.T1.base, Td, st));
-    LD_CHECK_HIP(launch_rowmat(f64, n, L.Gm.base, Gd, kg, slot[4], k, -c, false, 0, L.T1.base, Td,
+    LD_CHECK_HIP(launch_rowmat(f64, n, L.Gm.base, Gd, kg, slot[4], k, -c, nullptr, L.T1.base, Td,
                                L.T1.base, Td, st));
     // P = T1 - Q_b (Q_b^T T1)
-    LD_CHECK(cross_product(f64, n, L.X.base, X, k, L.T1.base, Td, k, false, 0, S.part, slot[5], st));
-    LD_CHECK_HIP(launch_rowmat(f64, n, L.X.base, X, k, slot[5], k, -1.0, false, 0, L.T1.base, Td,
+    LD_CHECK(cross_product(f64, n, L.X.base, X, k, L.T1.base, Td, k, nullptr, S.part, slot[5], st));
+    LD_CHECK_HIP(launch_rowmat(f64, n, L.X.base, X, k, slot[5], k, -1.0, nullptr, L.T1.base, Td,
                                L.T1.base, Td, st));
     // Z = P R^{-T}, R = R2 R1 (upper triangular)
     std::vector<double> R((size_t)k * k, 0.0), Rinv((size_t)k * k, 0.0), RinvT((size_t)k * k);
@@ -811,11 +814,11 @@ int estimate_and_gradient(const ld_csr* A, uint64_t seed, EstimateState& S, Grad
         for (int j = 0; j < k; ++j) RinvT[(size_t)i * k + j] = Rinv[(size_t)j * k + i];
     LD_CHECK(upload(RinvT, slot[6], st));
     // L = [Q_b, c U, 2 Z]
-    LD_CHECK_HIP(launch_rowmat(f64, n, L.T1.base, Td, k, slot[6], k, 2.0, false, 0, nullptr, Blk::plain(1),
+    LD_CHECK_HIP(launch_rowmat(f64, n, L.T1.base, Td, k, slot[6], k, 2.0, nullptr, nullptr, Blk::plain(1),
                                B.Lg, Gb.shifted(nc), st));
-    LD_CHECK_HIP(launch_rowmat(f64, n, L.X.base, X, k, slot[7], k, 1.0, false, 0, nullptr, Blk::plain(1),
+    LD_CHECK_HIP(launch_rowmat(f64, n, L.X.base, X, k, slot[7], k, 1.0, nullptr, nullptr, Blk::plain(1),
                                B.Lg, Gb, st));
-    LD_CHECK_HIP(launch_rowmat(f64, n, L.X.base, X.shifted(k), kg, slot[8], kg, 1.0, false, 0, nullptr,
+    LD_CHECK_HIP(launch_rowmat(f64, n, L.X.base, X.shifted(k), kg, slot[8], kg, 1.0, nullptr, nullptr,
                                Blk::plain(1), B.Lg, Gb.shifted(k), st));
 
     // ---- reverse sweep, segment by segment (recomputing a segment's vectors
@@ -999,7 +1002,7 @@ int lanczos_upper(const ld_csr* A_in, int steps, double abs_bound, hipStream_t s
     std::vector<double> a, b;   // diagonal, off-diagonal of the projection
     double beta = 0.0;
     auto dot = [&](const void* x, const void* y, double* r) -> int {
-        LD_CHECK(cross_product(f64, (int)n, x, one, 1, y, one, 1, false, 0, part, scal, st));
+        LD_CHECK(cross_product(f64, (int)n, x, one, 1, y, one, 1, nullptr, part, scal, st));
         LD_CHECK_HIP(hipMemcpyAsync(r, scal, sizeof(double), hipMemcpyDeviceToHost, st));
         LD_CHECK_HIP(hipStreamSynchronize(st));
         return LD_OK;
@@ -1173,7 +1176,7 @@ int ld_apply_log_adaptive(const ld_csr* A, double lmin, double lmax, int32_t max
         // P_0 = d_0 w_0 (+ log(sigma) v, the scaling term), w_0 = v
         LD_CHECK_HIP(launch_scale_copy(f64, n, qc, Vq, nc, p.d[0] + std::log(p.sigma), Pq, nc, st));
         // e_0 = |d_0| ||v||: the diagonal of the chunk's Gram matrix
-        LD_CHECK(cross_product(f64, n, Vq, Blk::plain(nc), qc, Vq, Blk::plain(nc), qc, false, 0, gpart, sums,
+        LD_CHECK(cross_product(f64, n, Vq, Blk::plain(nc), qc, Vq, Blk::plain(nc), qc, nullptr, gpart, sums,
                                st));
         LD_CHECK_HIP(hipMemcpyAsync(mask, &all, 8, hipMemcpyHostToDevice, st));
         LD_CHECK_HIP(launch_adapt_decide(sums, qc + 1, qc, std::fabs(p.d[0]), tol, 0, mask, deg + q0, st));

@@ -116,12 +116,12 @@ hipError_t launch_fill_signs(bool f64, int n, int k, int ld, int gshift, const u
 hipError_t launch_scale_copy(bool f64, int n, int ncols, const void* V, int ldv, double scale,
                              void* out, int ldo, hipStream_t st);
 
-// Partial cross products X^T Z per workgroup on FP64 MFMA: part[wg][i*kz+j].
-// Z is either a second block (zsigns_key ignored) or, with zsigns, the probe
-// signs of stream key for columns [0, kz).
+// Partial cross products X^T Z per workgroup, FP64: part[wg][i*kz+j],
+// cross_num_wg(n) rows.  Z is a second block, or, with zmask (one word per
+// row, bit j set = -1), the signs of columns [0, kz); Z is then ignored.
 int cross_num_wg(int n);
 hipError_t launch_cross(bool f64, int n, const void* X, Blk bx, int kx, const void* Z, Blk bz,
-                        int kz, bool zsigns, uint64_t key, double* part, hipStream_t st);
+                        int kz, const uint64_t* zmask, double* part, hipStream_t st);
 
 // out[o*out_ld + j] = sum_wg part[o*outer_stride + wg*part_ld + j], j < len
 // (Neumaier, fixed order).
@@ -134,12 +134,12 @@ hipError_t launch_reduce(const double* part, int nwg, int len, int part_ld, int 
 hipError_t launch_chol_factor(const double* G, int k, double* R, double* Rinv, int* flag,
                               hipStream_t st);
 
-// out[r, j] = (base ? base[r, j] : 0) + (signs ? S_key[r, j] : 0)
+// out[r, j] = (base ? base[r, j] : 0) + (zmask ? sign of bit j of zmask[r] : 0)
 //             + sign_m * sum_i Y[r, i] M[i, j],
 // M k_y x k_out FP64 (device), j < k_out; Y, base and out column-blocked
 // (base may alias out: each element is read before it is written).
 hipError_t launch_rowmat(bool f64, int n, const void* Y, Blk by, int ky, const double* M, int kout,
-                         double sign_m, bool signs, uint64_t key, const void* base, Blk bb,
+                         double sign_m, const uint64_t* zmask, const void* base, Blk bb,
                          void* out, Blk bo, hipStream_t st);
 
 // CSR structure check: *flag (device int) set to 1 on any violation.

@@ -815,7 +815,7 @@ typedef double double4_t __attribute__((ext_vector_type(4)));
 template <typename T, int TX, int TZ, bool ZSIGNS, bool SAME>
 __global__ __launch_bounds__(kThreads) void cross_kernel(int n, const T* __restrict__ X, Blk bx,
                                                          int kx, const T* __restrict__ Z, Blk bz,
-                                                         int kz, uint64_t key,
+                                                         int kz, const uint64_t* __restrict__ zmask,
                                                          double* __restrict__ part) {
     const int lane = threadIdx.x & 63;
     const int wave = threadIdx.x >> 6;
@@ -855,8 +855,7 @@ __global__ __launch_bounds__(kThreads) void cross_kernel(int n, const T* __restr
                         double z = 0.0;
                         if (rok && c < kz) {
                             if constexpr (ZSIGNS) {
-                                const uint64_t x = probe_bits(key, (uint64_t)c * (uint64_t)n + (uint64_t)r + 1ull);
-                                z = (x >> 63) ? -1.0 : 1.0;
+                                z = ((zmask[r] >> c) & 1ull) ? -1.0 : 1.0;
                             } else {
                                 z = (double)Z[zoff[b] + (size_t)r * bz.ld];
                             }
@@ -915,29 +914,30 @@ __global__ __launch_bounds__(kThreads) void cross_kernel(int n, const T* __restr
 
 template <typename T, int TX, int TZ>
 hipError_t launch_cross_t(int n, const void* X, Blk bx, int kx, const void* Z, Blk bz, int kz,
-                          bool zsigns, uint64_t key, double* part, hipStream_t st) {
+                          const uint64_t* zmask, double* part, hipStream_t st) {
+    const bool zsigns = zmask != nullptr;
     const int nwg = cross_num_wg(n);
     if (nwg == 0) return hipSuccess;
     const bool same = !zsigns && X == Z && kx == kz && bx.ld == bz.ld && bx.bw == bz.bw &&
                       bx.bstride == bz.bstride && bx.c0 == bz.c0;
     if (zsigns)
         hipLaunchKernelGGL((cross_kernel<T, TX, TZ, true, false>), dim3(nwg), dim3(kThreads), 0, st, n,
-                           (const T*)X, bx, kx, (const T*)Z, bz, kz, key, part);
+                           (const T*)X, bx, kx, (const T*)Z, bz, kz, zmask, part);
     else if (same && TX == TZ)
         hipLaunchKernelGGL((cross_kernel<T, TX, TZ, false, TX == TZ>), dim3(nwg), dim3(kThreads), 0, st, n,
-                           (const T*)X, bx, kx, (const T*)Z, bz, kz, key, part);
+                           (const T*)X, bx, kx, (const T*)Z, bz, kz, zmask, part);
     else
         hipLaunchKernelGGL((cross_kernel<T, TX, TZ, false, false>), dim3(nwg), dim3(kThreads), 0, st, n,
-                           (const T*)X, bx, kx, (const T*)Z, bz, kz, key, part);
+                           (const T*)X, bx, kx, (const T*)Z, bz, kz, zmask, part);
     return hipGetLastError();
 }
 
 template <typename T>
 hipError_t launch_cross_tx(int n, const void* X, Blk bx, int kx, const void* Z, Blk bz, int kz,
-                           bool zsigns, uint64_t key, double* part, hipStream_t st) {
+                           const uint64_t* zmask, double* part, hipStream_t st) {
     const int tx = (kx + 15) / 16, tz = (kz + 15) / 16;
 #define LD_CROSS_CASE(A, B) \
-    if (tx == A && tz == B) return launch_cross_t<T, A, B>(n, X, bx, kx, Z, bz, kz, zsigns, key, part, st);
+    if (tx == A && tz == B) return launch_cross_t<T, A, B>(n, X, bx, kx, Z, bz, kz, zmask, part, st);
     LD_CROSS_CASE(1, 1) LD_CROSS_CASE(1, 2) LD_CROSS_CASE(1, 3) LD_CROSS_CASE(1, 4)
     LD_CROSS_CASE(2, 1) LD_CROSS_CASE(2, 2) LD_CROSS_CASE(2, 3) LD_CROSS_CASE(2, 4)
     LD_CROSS_CASE(3, 1) LD_CROSS_CASE(3, 2) LD_CROSS_CASE(3, 3) LD_CROSS_CASE(3, 4)
@@ -948,11 +948,187 @@ hipError_t launch_cross_tx(int n, const void* X, Blk bx, int kx, const void* Z, 
 
 int cross_num_wg(int n) { return (int)std::min<long long>(div_up(n, kCrossRows), kCrossWgs); }
 
+// ---------------------------------------------------------------------------
+// Narrow cross products (kx, kz <= 32) from LDS-staged tiles on the FP64
+// vector units.  A tile of RT rows is staged whole (X's block rows with
+// 16-byte vectors; generated signs written once per element), and each
+// thread accumulates one 4x4 block of X^T Z in FP64 over a fixed subset of
+// the tile's rows (its phase).  The phases are summed in order at the end,
+// so partial row wg (one per workgroup, as cross_kernel's) is repeatable.
+// At 20 columns the FP64 MFMA tiles of cross_kernel are 61% padding; here
+// the padding is at most 3 columns per side.
+// ---------------------------------------------------------------------------
+constexpr int kGramMaxK = 32;
+constexpr int kGramKS = kGramMaxK + 5;   // LDS row stride: odd, and room for a 4-column block past a view's end
+
+template <typename T, bool SAME, bool ZSIGNS, int RT>
+__global__ __launch_bounds__(kThreads) void gram_kernel(int n, const T* __restrict__ X, Blk bx, int kx,
+                                                        const T* __restrict__ Z, Blk bz, int kz,
+                                                        const uint64_t* __restrict__ zmask, double* __restrict__ part) {
+    constexpr int V = 16 / (int)sizeof(T);
+    using P = Pack<T, V>;
+    constexpr int NV = (RT * kGramMaxK / V + kThreads - 1) / kThreads;   // vectors per thread and tile
+    constexpr int kTileBytes = (SAME ? 1 : 2) * RT * kGramKS * (int)sizeof(T);
+    constexpr int kRedBytes = kThreads * 17 * 8;
+    __shared__ __align__(16) unsigned char smem[kTileBytes > kRedBytes ? kTileBytes : kRedBytes];
+    T* const xs = reinterpret_cast<T*>(smem);
+    T* const zs = SAME ? xs : xs + RT * kGramKS;
+    double* const red = reinterpret_cast<double*>(smem);
+
+    const int tid = threadIdx.x;
+    const int bix = (kx + 3) / 4, biz = (kz + 3) / 4;
+    const int nblk = SAME ? bix * (bix + 1) / 2 : bix * biz;
+    const int nph = kThreads / nblk;   // row phases, >= 4
+    const int blk = tid % nblk, phase = tid / nblk;
+    int bi, bj;
+    if (SAME) {   // upper-triangular blocks in row order
+        int b = blk;
+        bi = 0;
+        while (b >= bix - bi) {
+            b -= bix - bi;
+            ++bi;
+        }
+        bj = bi + b;
+    } else {
+        bi = blk / biz;
+        bj = blk - bi * biz;
+    }
+    const int ldx = bx.ld, cx = bx.c0 % bx.bw;
+    const T* const xblk = X + (size_t)(bx.c0 / bx.bw) * (size_t)bx.bstride;
+    const int ldz = bz.ld, cz = (SAME || ZSIGNS) ? 0 : bz.c0 % bz.bw;
+    const T* const zblk = (SAME || ZSIGNS) ? nullptr : Z + (size_t)(bz.c0 / bz.bw) * (size_t)bz.bstride;
+    const int xcol = cx + 4 * bi, zcol = (SAME ? cx : cz) + 4 * bj;
+
+    double acc[16];
+#pragma unroll
+    for (int q = 0; q < 16; ++q) acc[q] = 0.0;
+    const int ntiles = div_up_dev(n, RT);
+    for (int t = blockIdx.x; t < ntiles; t += gridDim.x) {
+        const int row0 = t * RT, nr = min(RT, n - row0);
+        {   // X's block rows [row0, row0 + nr), whole
+            const int nvec = nr * ldx / V;
+            const T* src = xblk + (size_t)row0 * ldx;
+            P v[NV];
+#pragma unroll
+            for (int u = 0; u < NV; ++u) {
+                const int e = tid + u * kThreads;
+                if (e < nvec) v[u] = load_pack<T, V>(src + (size_t)e * V);
+            }
+#pragma unroll
+            for (int u = 0; u < NV; ++u) {
+                const int e = tid + u * kThreads;
+                if (e < nvec) {
+                    const int x = e * V, r = x / ldx, c = x - r * ldx;
+#pragma unroll
+                    for (int q = 0; q < V; ++q) xs[r * kGramKS + c + q] = v[u].v[q];
+                }
+            }
+        }
+        if constexpr (ZSIGNS) {   // one thread per row expands the row's sign word
+            for (int r = tid; r < nr; r += kThreads) {
+                const uint64_t w = zmask[row0 + r];
+                for (int j = 0; j < kz; ++j) zs[r * kGramKS + j] = ((w >> j) & 1ull) ? T(-1) : T(1);
+            }
+        } else if constexpr (!SAME) {
+            const int nvec = nr * ldz / V;
+            const T* src = zblk + (size_t)row0 * ldz;
+            P v[NV];
+#pragma unroll
+            for (int u = 0; u < NV; ++u) {
+                const int e = tid + u * kThreads;
+                if (e < nvec) v[u] = load_pack<T, V>(src + (size_t)e * V);
+            }
+#pragma unroll
+            for (int u = 0; u < NV; ++u) {
+                const int e = tid + u * kThreads;
+                if (e < nvec) {
+                    const int x = e * V, r = x / ldz, c = x - r * ldz;
+#pragma unroll
+                    for (int q = 0; q < V; ++q) zs[r * kGramKS + c + q] = v[u].v[q];
+                }
+            }
+        }
+        __syncthreads();
+        if (phase < nph) {
+            for (int r = phase; r < nr; r += nph) {
+                double xv[4], zv[4];
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    xv[q] = (double)xs[r * kGramKS + xcol + q];
+                    zv[q] = (double)zs[r * kGramKS + zcol + q];
+                }
+#pragma unroll
+                for (int a = 0; a < 4; ++a)
+#pragma unroll
+                    for (int b = 0; b < 4; ++b) acc[a * 4 + b] = fma(xv[a], zv[b], acc[a * 4 + b]);
+            }
+        }
+        __syncthreads();   // the tiles are restaged (or become the reduction buffer)
+    }
+    // phases of each block summed in order; entries past kx / kz are dropped
+#pragma unroll
+    for (int q = 0; q < 16; ++q) red[tid * 17 + q] = acc[q];
+    __syncthreads();
+    for (int e = tid; e < kx * kz; e += kThreads) {
+        const int i = e / kz, j = e - i * kz;
+        int a = i, b = j;
+        if (SAME && a / 4 > b / 4) {   // below the diagonal blocks: the mirror entry
+            a = j;
+            b = i;
+        }
+        const int pi = a / 4, pj = b / 4;
+        const int pb = SAME ? pi * bix - pi * (pi - 1) / 2 + (pj - pi) : pi * biz + pj;
+        double s = 0.0;
+        for (int p = 0; p < nph; ++p) s += red[(p * nblk + pb) * 17 + (a % 4) * 4 + (b % 4)];
+        part[(size_t)blockIdx.x * kx * kz + e] = s;
+    }
+}
+
+// The staged kernel applies when both views lie in one block each whose rows
+// (16-byte multiple, at most kGramMaxK wide) can be staged whole.
+template <typename T>
+bool gram_fits(const void* X, Blk bx, int kx, const void* Z, Blk bz, int kz, bool zsigns) {
+    constexpr int V = 16 / (int)sizeof(T);
+    auto view_ok = [](const void* p, const Blk& b, int k) {
+        return ((uintptr_t)p & 15) == 0 && b.ld % V == 0 && b.ld <= kGramMaxK && b.c0 % b.bw + k <= b.bw &&
+               b.bw <= b.ld;
+    };
+    return kx <= kGramMaxK && kz <= kGramMaxK && view_ok(X, bx, kx) && (zsigns || view_ok(Z, bz, kz));
+}
+
+template <typename T>
+void launch_gram_t(int n, const void* X, Blk bx, int kx, const void* Z, Blk bz, int kz,
+                   const uint64_t* zmask, double* part, int nwg, hipStream_t st) {
+    const bool zsigns = zmask != nullptr;
+    constexpr int RT = sizeof(T) == 8 ? 64 : 128;
+    const bool same = !zsigns && X == Z && kx == kz && bx.ld == bz.ld && bx.bw == bz.bw &&
+                      bx.bstride == bz.bstride && bx.c0 == bz.c0;
+    if (zsigns)
+        hipLaunchKernelGGL((gram_kernel<T, false, true, RT>), dim3(nwg), dim3(kThreads), 0, st, n, (const T*)X,
+                           bx, kx, (const T*)Z, bz, kz, zmask, part);
+    else if (same)
+        hipLaunchKernelGGL((gram_kernel<T, true, false, RT>), dim3(nwg), dim3(kThreads), 0, st, n, (const T*)X,
+                           bx, kx, (const T*)Z, bz, kz, zmask, part);
+    else
+        hipLaunchKernelGGL((gram_kernel<T, false, false, RT>), dim3(nwg), dim3(kThreads), 0, st, n, (const T*)X,
+                           bx, kx, (const T*)Z, bz, kz, zmask, part);
+}
+
 hipError_t launch_cross(bool f64, int n, const void* X, Blk bx, int kx, const void* Z, Blk bz,
-                        int kz, bool zsigns, uint64_t key, double* part, hipStream_t st) {
+                        int kz, const uint64_t* zmask, double* part, hipStream_t st) {
     if (kx < 1 || kz < 1 || kx > 64 || kz > 64) return hipErrorInvalidValue;
-    return f64 ? launch_cross_tx<double>(n, X, bx, kx, Z, bz, kz, zsigns, key, part, st)
-               : launch_cross_tx<float>(n, X, bx, kx, Z, bz, kz, zsigns, key, part, st);
+    const int nwg = cross_num_wg(n);
+    if (nwg == 0) return hipSuccess;
+    const bool zsigns = zmask != nullptr;
+    if (f64 ? gram_fits<double>(X, bx, kx, Z, bz, kz, zsigns) : gram_fits<float>(X, bx, kx, Z, bz, kz, zsigns)) {
+        if (f64)
+            launch_gram_t<double>(n, X, bx, kx, Z, bz, kz, zmask, part, nwg, st);
+        else
+            launch_gram_t<float>(n, X, bx, kx, Z, bz, kz, zmask, part, nwg, st);
+        return hipGetLastError();
+    }
+    return f64 ? launch_cross_tx<double>(n, X, bx, kx, Z, bz, kz, zmask, part, st)
+               : launch_cross_tx<float>(n, X, bx, kx, Z, bz, kz, zmask, part, st);
 }
 
 // ---------------------------------------------------------------------------
@@ -1125,7 +1301,7 @@ constexpr int kRowmatBatch = 16;   // loads a thread keeps in flight while stagi
 template <typename T, int KY, int KO, bool SIGNS, int RT, bool FAST>
 __global__ __launch_bounds__(RT) void rowmat_kernel(int n, const T* __restrict__ Y, Blk by,
                                                     int ky, const double* __restrict__ M,
-                                                    int kout, double sign_m, uint64_t key,
+                                                    int kout, double sign_m, const uint64_t* __restrict__ zmask,
                                                     const T* base, Blk bb, T* out, Blk bo) {
     constexpr int KS = (KY > KO ? KY : KO) + 1;      // padded row stride of the tile
     __shared__ T ms[KY * KO];
@@ -1224,12 +1400,14 @@ __global__ __launch_bounds__(RT) void rowmat_kernel(int n, const T* __restrict__
         const T* bsrc = base ? base + (size_t)(bb.c0 / bb.bw) * (size_t)bb.bstride + (size_t)row0 * kout : nullptr;
         const int nvec = nr * kout / V;
         P b[NV];
+        uint64_t w[SIGNS ? NV : 1];   // sign words, loaded with the base values before any store
 #pragma unroll
         for (int u = 0; u < NV; ++u) {
             const int e = threadIdx.x + u * RT;
 #pragma unroll
             for (int q = 0; q < V; ++q) b[u].v[q] = T(0);
             if (bsrc && e < nvec) b[u] = load_pack<T, V>(bsrc + (size_t)e * V);
+            if constexpr (SIGNS) w[u] = e < nvec ? zmask[row0 + (e * V) / kout] : 0ull;
         }
 #pragma unroll
         for (int u = 0; u < NV; ++u) {
@@ -1240,10 +1418,7 @@ __global__ __launch_bounds__(RT) void rowmat_kernel(int n, const T* __restrict__
 #pragma unroll
                 for (int q = 0; q < V; ++q) {
                     T v = tile[r * KS + c + q] + b[u].v[q];
-                    if constexpr (SIGNS) {
-                        const uint64_t z = probe_bits(key, (uint64_t)(c + q) * (uint64_t)n + (uint64_t)(row0 + r) + 1ull);
-                        v += (z >> 63) ? T(-1) : T(1);
-                    }
+                    if constexpr (SIGNS) v += ((w[u] >> (c + q)) & 1ull) ? T(-1) : T(1);
                     o.v[q] = v;
                 }
                 store_pack<T, V>(dst + (size_t)x, o);
@@ -1255,10 +1430,12 @@ __global__ __launch_bounds__(RT) void rowmat_kernel(int n, const T* __restrict__
 #pragma nounroll
         for (int u0 = 0; u0 < KO && u0 * RT < nr * kout; u0 += kRowmatBatch) {
             T b[kRowmatBatch];
+            uint64_t w[SIGNS ? kRowmatBatch : 1];
             const int r0 = r, j0 = j;
 #pragma unroll
             for (int u = 0; u < kRowmatBatch; ++u) {
                 b[u] = (base && r < nr) ? base[boff[j] + (size_t)(row0 + r) * bb.ld] : T(0);
+                if constexpr (SIGNS) w[u] = r < nr ? zmask[row0 + r] : 0ull;
                 r += qa_o;
                 j += qb_o;
                 if (j >= kout) {
@@ -1273,10 +1450,7 @@ __global__ __launch_bounds__(RT) void rowmat_kernel(int n, const T* __restrict__
                 if (r < nr) {
                     const int row = row0 + r;
                     T v = tile[r * KS + j] + b[u];
-                    if constexpr (SIGNS) {
-                        const uint64_t x = probe_bits(key, (uint64_t)j * (uint64_t)n + (uint64_t)row + 1ull);
-                        v += (x >> 63) ? T(-1) : T(1);
-                    }
+                    if constexpr (SIGNS) v += ((w[u] >> j) & 1ull) ? T(-1) : T(1);
                     out[ooff[j] + (size_t)row * bo.ld] = v;
                 }
                 r += qa_o;
@@ -1294,7 +1468,7 @@ __global__ __launch_bounds__(RT) void rowmat_kernel(int n, const T* __restrict__
 
 template <typename T, int KY, int KO>
 void launch_rowmat_t(int n, hipStream_t st, const void* Y, Blk by, int ky, const double* M,
-                     int kout, double sign_m, bool signs, uint64_t key, const void* base, Blk bb,
+                     int kout, double sign_m, const uint64_t* zmask, const void* base, Blk bb,
                      void* out, Blk bo) {
     constexpr int RT = (sizeof(T) == 8 && KY == 64 && KO == 64) ? 128 : 256;
     const int nwg = std::min(div_up(n, RT), kRowmatWgs);
@@ -1309,17 +1483,17 @@ void launch_rowmat_t(int n, hipStream_t st, const void* Y, Blk by, int ky, const
                       (!base || (aligned(base) && whole_rows(bb, kout)));
 #define LD_RM_GO(S_, F_)                                                                                     \
     hipLaunchKernelGGL((rowmat_kernel<T, KY, KO, S_, RT, F_>), dim3(nwg), dim3(RT), 0, st, n, (const T*)Y, by, \
-                       ky, M, kout, sign_m, key, (const T*)base, bb, (T*)out, bo)
+                       ky, M, kout, sign_m, zmask, (const T*)base, bb, (T*)out, bo)
     if constexpr (kFastFits) {
         if (fast) {
-            if (signs)
+            if (zmask)
                 LD_RM_GO(true, true);
             else
                 LD_RM_GO(false, true);
             return;
         }
     }
-    if (signs)
+    if (zmask)
         LD_RM_GO(true, false);
     else
         LD_RM_GO(false, false);
@@ -1328,12 +1502,12 @@ void launch_rowmat_t(int n, hipStream_t st, const void* Y, Blk by, int ky, const
 
 template <typename T>
 hipError_t launch_rowmat_ty(hipStream_t st, int n, const void* Y, Blk by, int ky,
-                            const double* M, int kout, double sign_m, bool signs, uint64_t key,
+                            const double* M, int kout, double sign_m, const uint64_t* zmask,
                             const void* base, Blk bb, void* out, Blk bo) {
     const int a = ky <= 16 ? 16 : ky <= 32 ? 32 : 64;
     const int b = kout <= 16 ? 16 : kout <= 32 ? 32 : 64;
 #define LD_RM(A_, B_) \
-    if (a == A_ && b == B_) launch_rowmat_t<T, A_, B_>(n, st, Y, by, ky, M, kout, sign_m, signs, key, base, bb, out, bo);
+    if (a == A_ && b == B_) launch_rowmat_t<T, A_, B_>(n, st, Y, by, ky, M, kout, sign_m, zmask, base, bb, out, bo);
     LD_RM(16, 16) LD_RM(16, 32) LD_RM(16, 64) LD_RM(32, 16) LD_RM(32, 32) LD_RM(32, 64)
     LD_RM(64, 16) LD_RM(64, 32) LD_RM(64, 64)
 #undef LD_RM
@@ -1341,12 +1515,12 @@ hipError_t launch_rowmat_ty(hipStream_t st, int n, const void* Y, Blk by, int ky
 }
 
 hipError_t launch_rowmat(bool f64, int n, const void* Y, Blk by, int ky, const double* M, int kout,
-                         double sign_m, bool signs, uint64_t key, const void* base, Blk bb,
+                         double sign_m, const uint64_t* zmask, const void* base, Blk bb,
                          void* out, Blk bo, hipStream_t st) {
     if (ky < 1 || kout < 1 || ky > 64 || kout > 64) return hipErrorInvalidValue;
     if (n == 0) return hipSuccess;
-    return f64 ? launch_rowmat_ty<double>(st, n, Y, by, ky, M, kout, sign_m, signs, key, base, bb, out, bo)
-               : launch_rowmat_ty<float>(st, n, Y, by, ky, M, kout, sign_m, signs, key, base, bb, out, bo);
+    return f64 ? launch_rowmat_ty<double>(st, n, Y, by, ky, M, kout, sign_m, zmask, base, bb, out, bo)
+               : launch_rowmat_ty<float>(st, n, Y, by, ky, M, kout, sign_m, zmask, base, bb, out, bo);
 }
 
 // ---------------------------------------------------------------------------
