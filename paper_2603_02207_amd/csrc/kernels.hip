@@ -78,6 +78,8 @@ constexpr int kAdjBatch = 4;       // CSR entries of a row whose gathers the adj
 constexpr int kAdjStageNz = 1536;  // CSR entries one adjoint workgroup stages in LDS
 
 constexpr bool is_dot(int kind) { return kind == STEP_DOT_FWD || kind == STEP_DOT_SQ || kind == STEP_ACC_NORM; }
+// kinds with a first-step variant (it adds the sums of the input block itself)
+constexpr bool has_first(int kind) { return kind == STEP_DOT_FWD || kind == STEP_DOT_SQ; }
 constexpr int threads_of(int) { return 256; }
 // Kinds with column sums run a fixed grid of at most kDotWgs workgroups (all
 // resident on the 256 CUs), each looping over row tiles and reducing its
@@ -541,10 +543,11 @@ hipError_t launch_step_t(const CsrDev& A, const StepArgs& s, hipStream_t st, int
     if (ntiles == 0) return hipSuccess;
     // the kinds with column sums run as many workgroups as are resident at once
     // (each loops over its tiles); the others one workgroup per tile.  The
-    // occupancy is that of the non-first variant, so every step of a phase
-    // writes the same number of partial rows (they are reduced together).
-    auto grid = [&](const void* fn_rest) {
-        return is_dot(KIND) ? std::min(ntiles, resident_wgs(fn_rest, NT)) : ntiles;
+    // occupancy is the smaller of the first and the other steps' variants, so
+    // every step of a phase writes the same number of partial rows (they are
+    // reduced together) and every launch's workgroups are all resident.
+    auto grid = [&](const void* fn_first, const void* fn_rest) {
+        return is_dot(KIND) ? std::min({ntiles, resident_wgs(fn_first, NT), resident_wgs(fn_rest, NT)}) : ntiles;
     };
     DiaOff off{};
     for (int q = 0; q < kMaxDiag; ++q) off.o[q] = q < s.dia_nd ? s.dia_off[q] : 0;
@@ -553,7 +556,8 @@ hipError_t launch_step_t(const CsrDev& A, const StepArgs& s, hipStream_t st, int
 #define LD_DIA_LAUNCH(ND_)                                                                                     \
     {                                                                                                          \
         const auto fn = step_kernel<T, VEC, KIND, FIRST, kIters, NT, ND_>;                                     \
-        const int nwg = grid(reinterpret_cast<const void*>(step_kernel<T, VEC, KIND, false, kIters, NT, ND_>)); \
+        const int nwg = grid(reinterpret_cast<const void*>(step_kernel<T, VEC, KIND, has_first(KIND), kIters, NT, ND_>), \
+                             reinterpret_cast<const void*>(step_kernel<T, VEC, KIND, false, kIters, NT, ND_>));  \
         hipLaunchKernelGGL(fn, dim3(nwg), dim3(NT), 0, st, A.n, A.row_ptr, A.col_idx, (const T*)A.val,         \
                            (const T*)s.win, (T*)s.wout, s.ld, s.c0, s.bcols, s.gshift, (T)s.alpha, (T)s.beta,   \
                            (T)s.dj, (const T*)s.vsrc, s.ldv, s.mask, s.ps0, s.ps1, s.ps2, s.part_ld, lpr, rpw, \
@@ -574,7 +578,8 @@ hipError_t launch_step_t(const CsrDev& A, const StepArgs& s, hipStream_t st, int
     }
     const int skip = s.long_rows != nullptr;
     const auto fn = step_kernel<T, VEC, KIND, FIRST, kIters, NT, 0>;
-    const int nwg = grid(reinterpret_cast<const void*>(step_kernel<T, VEC, KIND, false, kIters, NT, 0>));
+    const int nwg = grid(reinterpret_cast<const void*>(step_kernel<T, VEC, KIND, has_first(KIND), kIters, NT, 0>),
+                         reinterpret_cast<const void*>(step_kernel<T, VEC, KIND, false, kIters, NT, 0>));
     if (nwg_out) *nwg_out = nwg + (skip ? kLongWgs : 0);
     hipLaunchKernelGGL(fn, dim3(nwg), dim3(NT), 0, st,
                        A.n, A.row_ptr, A.col_idx, (const T*)A.val, (const T*)s.win, (T*)s.wout, s.ld,
@@ -749,27 +754,42 @@ hipError_t launch_sign_mask(int n, int k, uint64_t key, uint64_t* mask, hipStrea
     return hipGetLastError();
 }
 
+// One thread per 16-byte chunk of a row (VEC columns): a vector store when the
+// chunk lies inside [0, k) and out's rows are 16-byte aligned, else per column.
 template <typename T>
 __global__ __launch_bounds__(kThreads) void fill_signs_kernel(int n, int k, int ld, int gshift,
                                                               const uint64_t* __restrict__ mask,
-                                                              T scale, T* __restrict__ out) {
+                                                              T scale, T* __restrict__ out, int chunks,
+                                                              int vec_ok) {
+    constexpr int V = 16 / (int)sizeof(T);
     const long long i = (long long)blockIdx.x * kThreads + threadIdx.x;
-    if (i >= (long long)n * k) return;
-    const int r = (int)(i / k), c = (int)(i - (long long)r * k);
-    out[(size_t)r * ld + c] = ((mask[r] >> ((c + gshift) & 63)) & 1ull) ? -scale : scale;
+    if (i >= (long long)n * chunks) return;
+    const int r = (int)(i / chunks), c0 = (int)(i - (long long)r * chunks) * V;
+    const uint64_t w = mask[r];
+    T* const dst = out + (size_t)r * ld + c0;
+    if (vec_ok && c0 + V <= k) {
+        Pack<T, V> p;
+#pragma unroll
+        for (int q = 0; q < V; ++q) p.v[q] = ((w >> ((c0 + q + gshift) & 63)) & 1ull) ? -scale : scale;
+        store_pack<T, V>(dst, p);
+    } else {
+        for (int q = 0; q < V && c0 + q < k; ++q) dst[q] = ((w >> ((c0 + q + gshift) & 63)) & 1ull) ? -scale : scale;
+    }
 }
 
 hipError_t launch_fill_signs(bool f64, int n, int k, int ld, int gshift, const uint64_t* mask,
                              double scale, void* out, hipStream_t st) {
-    const long long tot = (long long)n * k;
-    if (tot == 0) return hipSuccess;
-    const int nb = div_up(tot, kThreads);
+    if ((long long)n * k == 0) return hipSuccess;
+    const int v = f64 ? 2 : 4;
+    const int chunks = (k + v - 1) / v;
+    const int vec_ok = ((uintptr_t)out % 16 == 0) && ld % v == 0;
+    const int nb = div_up((long long)n * chunks, kThreads);
     if (f64)
         hipLaunchKernelGGL(fill_signs_kernel<double>, dim3(nb), dim3(kThreads), 0, st, n, k, ld,
-                           gshift, mask, scale, (double*)out);
+                           gshift, mask, scale, (double*)out, chunks, vec_ok);
     else
         hipLaunchKernelGGL(fill_signs_kernel<float>, dim3(nb), dim3(kThreads), 0, st, n, k, ld,
-                           gshift, mask, (float)scale, (float*)out);
+                           gshift, mask, (float)scale, (float*)out, chunks, vec_ok);
     return hipGetLastError();
 }
 
@@ -1190,27 +1210,30 @@ hipError_t launch_reduce(const double* part, int nwg, int len, int part_ld, int 
 // sets 2; then R^{-1} is left zero.  *flag is written on every call.
 // ---------------------------------------------------------------------------
 constexpr int kCholMax = 64;
+constexpr int kCholThreads = 256;   // a 16 x 16 grid over the entries
 constexpr int kCholLd = kCholMax + 1;
 
-__global__ __launch_bounds__(kThreads) void chol_factor_kernel(const double* __restrict__ G, int k,
-                                                               double* __restrict__ R,
-                                                               double* __restrict__ Rinv,
-                                                               int* __restrict__ flag) {
+__global__ __launch_bounds__(kCholThreads) void chol_factor_kernel(const double* __restrict__ G, int k,
+                                                                   double* __restrict__ R,
+                                                                   double* __restrict__ Rinv,
+                                                                   int* __restrict__ flag) {
     // R in the upper triangle of a; R^{-1} transposed in its strict lower
-    // triangle, inv(j, i) at a[i][j], with the diagonal of R^{-1} in invd
+    // triangle, inv(j, i) at a[i][j], with the diagonal of R^{-1} in invd.
+    // Threads form a 16 x 16 grid (tx, ty) over the matrix entries.
     __shared__ double a[kCholMax * kCholLd];
     __shared__ double invd[kCholMax];
     __shared__ double gdiag[kCholMax];   // the Gram's diagonal, for the relative pivot test
     __shared__ int bad;
-    const int tid = threadIdx.x;
+    const int tid = threadIdx.x, tx = tid & 15, ty = tid >> 4;
     if (tid == 0) bad = 0;
     __syncthreads();
-    for (int e = tid; e < k * k; e += kThreads) {
-        const double v = G[e];
-        if (!isfinite(v)) bad = 1;
-        a[(e / k) * kCholLd + e % k] = v;
-        if (e % (k + 1) == 0) gdiag[e / (k + 1)] = v;
-    }
+    for (int r = ty; r < k; r += 16)
+        for (int c = tx; c < k; c += 16) {
+            const double v = G[r * k + c];
+            if (!isfinite(v)) bad = 1;
+            a[r * kCholLd + c] = v;
+            if (r == c) gdiag[r] = v;
+        }
     __syncthreads();
     for (int j = 0; j < k && bad == 0; ++j) {
         const double s = a[j * kCholLd + j];
@@ -1222,14 +1245,12 @@ __global__ __launch_bounds__(kThreads) void chol_factor_kernel(const double* __r
             __syncthreads();
             break;
         }
-        for (int i = j + tid; i < k; i += kThreads)
+        for (int i = j + tid; i < k; i += kCholThreads)
             a[j * kCholLd + i] = i == j ? rjj : a[j * kCholLd + i] / rjj;
         __syncthreads();
-        const int m = k - j - 1;
-        for (int e = tid; e < m * m; e += kThreads) {
-            const int r = j + 1 + e / m, c = j + 1 + e % m;
-            if (c >= r) a[r * kCholLd + c] -= a[j * kCholLd + r] * a[j * kCholLd + c];
-        }
+        for (int r = j + 1 + ty; r < k; r += 16)
+            for (int c = j + 1 + tx; c < k; c += 16)
+                if (c >= r) a[r * kCholLd + c] -= a[j * kCholLd + r] * a[j * kCholLd + c];
         __syncthreads();
     }
     const int ok = bad == 0;
@@ -1238,44 +1259,41 @@ __global__ __launch_bounds__(kThreads) void chol_factor_kernel(const double* __r
     // start); then every row i < j takes away R[i][j] X[j][:].  B and X are
     // upper triangular: B[i][c] (i < c) lives at a[c][i], its diagonal in invd.
     if (ok) {
-        for (int e = tid; e < k * k; e += kThreads) {
-            const int r = e / k, c = e % k;
-            if (r > c) a[r * kCholLd + c] = 0.0;
-        }
-        for (int i = tid; i < k; i += kThreads) invd[i] = 1.0;
+        for (int r = ty; r < k; r += 16)
+            for (int c = tx; c < r; c += 16) a[r * kCholLd + c] = 0.0;
+        for (int i = tid; i < k; i += kCholThreads) invd[i] = 1.0;
         __syncthreads();
         for (int j = k - 1; j >= 0; --j) {
             const double rjj = a[j * kCholLd + j];
-            for (int c = j + tid; c < k; c += kThreads) {
+            for (int c = j + tid; c < k; c += kCholThreads) {
                 if (c == j)
                     invd[j] = invd[j] / rjj;
                 else
                     a[c * kCholLd + j] = a[c * kCholLd + j] / rjj;
             }
             __syncthreads();
-            const int w = k - j;
-            for (int e = tid; e < j * w; e += kThreads) {
-                const int i = e / w, c = j + e % w;
-                const double xjc = c == j ? invd[j] : a[c * kCholLd + j];
-                a[c * kCholLd + i] -= a[i * kCholLd + j] * xjc;
-            }
+            for (int i = ty; i < j; i += 16)
+                for (int c = j + tx; c < k; c += 16) {
+                    const double xjc = c == j ? invd[j] : a[c * kCholLd + j];
+                    a[c * kCholLd + i] -= a[i * kCholLd + j] * xjc;
+                }
             __syncthreads();
         }
     }
     __syncthreads();
-    for (int e = tid; e < k * k; e += kThreads) {
-        const int r = e / k, c = e % k;
-        const bool on = ok && c >= r;
-        if (R) R[e] = on ? a[r * kCholLd + c] : 0.0;
-        Rinv[e] = on ? (c == r ? invd[r] : a[c * kCholLd + r]) : 0.0;
-    }
+    for (int r = ty; r < k; r += 16)
+        for (int c = tx; c < k; c += 16) {
+            const bool on = ok && c >= r;
+            if (R) R[r * k + c] = on ? a[r * kCholLd + c] : 0.0;
+            Rinv[r * k + c] = on ? (c == r ? invd[r] : a[c * kCholLd + r]) : 0.0;
+        }
     if (tid == 0) *flag = bad;
 }
 
 hipError_t launch_chol_factor(const double* G, int k, double* R, double* Rinv, int* flag,
                               hipStream_t st) {
     if (k < 1 || k > kCholMax) return hipErrorInvalidValue;
-    hipLaunchKernelGGL(chol_factor_kernel, dim3(1), dim3(kThreads), 0, st, G, k, R, Rinv, flag);
+    hipLaunchKernelGGL(chol_factor_kernel, dim3(1), dim3(kCholThreads), 0, st, G, k, R, Rinv, flag);
     return hipGetLastError();
 }
 
