@@ -38,13 +38,14 @@ import scipy.linalg as sla
 from .hutchpp import logdet_estimate
 
 
-def logdet_grad(csr, lmin: float, lmax: float, degree: int, m_vec: int, seed: int):
+def logdet_grad(csr, lmin: float, lmax: float, degree: int, m_vec: int, seed: int,
+                probes: str = "rademacher"):
     """(estimate, d estimate / d val) for a CSR matrix (row_ptr, col_idx, val, n)."""
     import scipy.sparse as sp
 
     row_ptr, col_idx, val, n = csr
     Q = sp.csr_matrix((np.asarray(val, dtype=np.float64), col_idx, row_ptr), shape=(n, n))
-    parts = logdet_estimate(Q, lmin, lmax, degree, m_vec, seed, return_parts=True)
+    parts = logdet_estimate(Q, lmin, lmax, degree, m_vec, seed, return_parts=True, probes=probes)
     plan = parts["plan"]
     A, U, S, G, Y = parts["A"], parts["U"], parts["S"], parts["G"], parts["Y"]
     c = 1.0 / parts["k_G"]
@@ -72,7 +73,7 @@ def logdet_grad(csr, lmin: float, lmax: float, degree: int, m_vec: int, seed: in
     return parts["logdet"], grad
 
 
-def fd_directional(csr, direction, lmin, lmax, degree, m_vec, seed, h):
+def fd_directional(csr, direction, lmin, lmax, degree, m_vec, seed, h, probes: str = "rademacher"):
     """Central difference of the FP64 estimate along ``direction`` over the nonzeros."""
     import scipy.sparse as sp
 
@@ -81,6 +82,6 @@ def fd_directional(csr, direction, lmin, lmax, degree, m_vec, seed, h):
 
     def est(v):
         Q = sp.csr_matrix((v, col_idx, row_ptr), shape=(n, n))
-        return logdet_estimate(Q, lmin, lmax, degree, m_vec, seed)
+        return logdet_estimate(Q, lmin, lmax, degree, m_vec, seed, probes=probes)
 
     return (est(val + h * direction) - est(val - h * direction)) / (2.0 * h)

@@ -3,12 +3,13 @@
 Steps (Sec. 4.1, Alg. 3), with F = P_m(Q~) the Léja interpolant of log(Q~):
   1. sigma and Q~ (Eq. scaled_sigma_matrix; input lower bound, see newton.py)
   2. S in {+-1}^{n x k}, k = floor(m_vec/3), from stream 0 of the probe
-     generator (Rademacher; the Gaussian option is not on this path)
+     generator (Rademacher; or standard normal entries, the paper's other
+     choice, with probes="gaussian")
   3. Y = F S  (Eq. eq_lejdetc_onstruction, Alg. 2 per column)
   4. A = orth(Y): Householder QR (any orthonormal basis of span(Y) gives the
      same estimate)
   5. t_low = tr(A^T F A) = sum_i a_i^T F a_i  (Eq. eq_lej_deterministic_part)
-  6. G in {+-1}^{n x k_G}, k_G = m_vec - 2k, from stream 1;
+  6. G in {+-1}^{n x k_G} (or Gaussian), k_G = m_vec - 2k, from stream 1;
      u_j = (I - A A^T) g_j;  t_res = (1/k_G) sum_j u_j^T F u_j
      (Eq. eq_lej_residual_def; reading: weight 1/k_G, equal to 3/m_vec when 3
      divides m_vec, and the sum index runs over j = 1..k_G)
@@ -30,7 +31,7 @@ import math
 import numpy as np
 
 from .newton import NewtonPlan
-from .rng import rademacher
+from .rng import probes as draw_probes, rademacher
 
 
 def split_queries(m_vec: int):
@@ -42,15 +43,15 @@ def split_queries(m_vec: int):
 
 
 def logdet_estimate(Q, lmin: float, lmax: float, degree: int, m_vec: int, seed: int,
-                    orth=None, return_parts: bool = False):
+                    orth=None, return_parts: bool = False, probes: str = "rademacher"):
     """Alg. 3 in FP64 on a scipy sparse (or dense) symmetric Q."""
     n = Q.shape[0]
     plan = NewtonPlan(lmin, lmax, degree)
     k, k_g = split_queries(m_vec)
     if k > n:
         raise ValueError("sketch wider than the matrix")
-    S = rademacher(seed, 0, n, k)
-    G = rademacher(seed, 1, n, k_g)
+    S = draw_probes(probes, seed, 0, n, k)
+    G = draw_probes(probes, seed, 1, n, k_g)
     Y = plan.apply_poly(Q, S)
     if orth is None:
         A, _ = np.linalg.qr(Y)               # Householder (LAPACK geqrf/orgqr)

@@ -145,3 +145,11 @@ def test_gradient_gmrf_hyperparameters_and_exact_limit():
     # estimator derivatives approximate the exact ones (n/tau and the closed form)
     assert d_tau == pytest.approx(n / tau, rel=0.05)
     assert d_kappa == pytest.approx(tau * 0 + exact.grid_logdet_2d_dkappa(N, k2), rel=0.1)
+
+
+def test_gradient_gaussian_probes_against_finite_differences():
+    A = w.grid_laplacian_2d(8, 0.5)
+    est, g = grad.logdet_grad(A, 0.5, 8.5, 20, 12, 4, probes="gaussian")
+    E = np.random.default_rng(21).standard_normal(len(A[2]))
+    fd = grad.fd_directional(A, E, 0.5, 8.5, 20, 12, 4, 1e-5, probes="gaussian")
+    assert g @ E == pytest.approx(fd, rel=1e-7)

@@ -109,3 +109,22 @@ def test_sigma_split():
     lam = exact.grid_eigenvalues_2d(8, 3.0)
     assert hutchpp.exact_trace(lam, 3.0, 11.0, 30) == pytest.approx(ex, rel=1e-9)
     assert hutchpp.exact_trace(lam / 4, 0.75, 2.75, 30) == pytest.approx(ex - 64 * math.log(4.0), rel=1e-9)
+
+
+def test_gaussian_probes_exact_span_and_unbiased():
+    # The paper's other probe distribution: the same two pins as Rademacher
+    # (sketch spanning the space gives the exact trace; mean over seeds).
+    rng_ = np.random.default_rng(1)
+    n = 6
+    B = rng_.standard_normal((n, n))
+    Qd = B @ B.T + n * np.eye(n)
+    ev = np.linalg.eigvalsh(Qd)
+    lmin, lmax = 0.9 * ev[0], 1.1 * ev[-1]
+    est = hutchpp.logdet_estimate(sp.csr_matrix(Qd), lmin, lmax, 25, 18, 9, probes="gaussian")
+    assert est == pytest.approx(hutchpp.exact_trace(ev, lmin, lmax, 25), rel=1e-12)
+    Q = w.to_scipy(w.grid_laplacian_2d(16, 0.5))
+    et = hutchpp.exact_trace(exact.grid_eigenvalues_2d(16, 0.5), 0.5, 8.5, 30)
+    hpp = np.array([hutchpp.logdet_estimate(Q, 0.5, 8.5, 30, 12, s, probes="gaussian") for s in range(60)])
+    assert abs(hpp.mean() - et) < 3.5 * hpp.std(ddof=1) / math.sqrt(len(hpp))
+    with pytest.raises(ValueError):
+        hutchpp.logdet_estimate(Q, 0.5, 8.5, 30, 12, 0, probes="uniform")

@@ -39,3 +39,23 @@ def test_rademacher_entry_definition():
     x = int(rng.splitmix64_outputs(key, 1, start=2 * n + 5 + 1)[0])
     S = rng.rademacher(11, 1, n, 3)
     assert S[5, 2] == (-1.0 if x >> 63 else 1.0)
+
+
+def test_gaussian_entries_are_standard_normal():
+    # Kolmogorov-Smirnov against N(0, 1), moments, and no correlation between
+    # columns or streams; entries depend on (seed, stream, row, col) only.
+    from scipy import stats
+
+    n, c = 40000, 3
+    G = rng.gaussian(11, 1, n, c)
+    for j in range(c):
+        assert stats.kstest(G[:, j], "norm").pvalue > 1e-3
+    x = G.ravel()
+    se = 1.0 / np.sqrt(x.size)
+    assert abs(x.mean()) < 5 * se
+    assert abs(x.var() - 1.0) < 5 * np.sqrt(2.0) * se
+    assert abs(stats.kurtosis(x, fisher=False) - 3.0) < 5 * np.sqrt(24.0) * se
+    C = np.corrcoef(np.hstack([G, rng.gaussian(11, 0, n, 1)]).T)
+    assert np.abs(C - np.eye(c + 1)).max() < 5.0 / np.sqrt(n)
+    assert np.array_equal(rng.gaussian(11, 1, 500, 2)[:, 1], rng.gaussian(11, 1, 500, 3)[:, 1])
+    assert not np.array_equal(rng.gaussian(11, 1, 500, 1), rng.gaussian(12, 1, 500, 1))
