@@ -66,6 +66,10 @@ extern "C" {
 #define LD_DOT_FORWARD 1    /* Alg. 2 forward: m steps, <x, w_j> every step    */
 #define LD_DOT_SQUARED 2    /* ceil(m/2) steps: <w_a,w_a>, <w_a,w_a+1>          */
 
+/* ld_options.probe_dist */
+#define LD_PROBE_RADEMACHER 0  /* +-1: sign of SplitMix64 output (col*n + row + 1)  */
+#define LD_PROBE_GAUSSIAN   1  /* Box-Muller on the two 32-bit halves of that output */
+
 /* ld_options.tile_order */
 #define LD_TILES_AUTO        0
 #define LD_TILES_XCD_BANDS   1  /* XCD x walks the x-th contiguous band of tiles */
@@ -102,7 +106,10 @@ typedef struct {
                                 the 256 MB Infinity Cache, else interleaved);
                                 the sums' grouping, hence the last bits of the
                                 quadratic forms, depend on it                 */
-    int32_t reserved[1];
+    int32_t probe_dist;      /* LD_PROBE_RADEMACHER (default) / LD_PROBE_GAUSSIAN:
+                                the distribution of the probe entries of S and
+                                G (Alg. 3 step 2 allows either); see
+                                ld_logdet_estimate for the generator          */
 } ld_options;
 
 typedef struct {

@@ -52,6 +52,7 @@ class Options:
     trusted_csr: int = 0
     csr_only: int = 0
     tile_order: int = 0
+    probe_dist: int = 0     # 0: Rademacher, 1: Gaussian
 
     def to_c(self) -> nat.LdOptions:
         o = nat.LdOptions()
@@ -64,6 +65,7 @@ class Options:
         o.trusted_csr = self.trusted_csr
         o.csr_only = self.csr_only
         o.tile_order = self.tile_order
+        o.probe_dist = self.probe_dist
         return o
 
 

@@ -50,7 +50,7 @@ class LdOptions(ctypes.Structure):
         ("trusted_csr", ctypes.c_int32),
         ("csr_only", ctypes.c_int32),
         ("tile_order", ctypes.c_int32),
-        ("reserved", ctypes.c_int32 * 1),
+        ("probe_dist", ctypes.c_int32),
     ]
 
 

@@ -419,6 +419,8 @@ struct EstimateState {
     Plan plan;
     EstLayout L;
     int mode;                       // LD_DOT_FORWARD / LD_DOT_SQUARED
+    int probe = LD_PROBE_RADEMACHER;   // distribution of the entries of S and G
+    uint64_t key0 = 0;                 // stream key of S
     std::vector<double> coef;       // d (forward) or c (squared)
     void *mask, *W0, *W1;
     double *part, *small, *nu;
@@ -484,15 +486,25 @@ int sketch_phase(const ld_csr* A, EstimateState& S, hipStream_t st) {
     const Plan& p = S.plan;
     const BlkMat& Y = S.L.Y;
     const int m = p.degree;
+    // Gaussian S is stored (in Q1's block, free until CholQR) and read by
+    // every step; Rademacher S is regenerated from its sign words
+    const bool gauss = S.probe == LD_PROBE_GAUSSIAN;
+    const int kind = gauss ? STEP_HORNER_VEC : STEP_HORNER_SIGNS;
     for (int b = 0; b < Y.nblocks(); ++b) {
         const int cols = Y.bcols(b), gcol = b * Y.bw;
         // step j (= m-1 .. 0) writes (j even ? block : W0); r_m sits in the other one
         void* bufs[2] = {Y.block(b), S.W0};
-        LD_CHECK_HIP(launch_fill_signs(f64, n, cols, Y.ld, gcol, (const uint64_t*)S.mask, p.d[m],
-                                       bufs[(m - 1) % 2 == 0 ? 1 : 0], st));
+        void* const rm = bufs[(m - 1) % 2 == 0 ? 1 : 0];
+        void* const sblk = S.L.Q1.block(b);
+        if (gauss) {
+            LD_CHECK_HIP(launch_gauss_fill(f64, n, cols, S.key0, gcol, 1.0, sblk, Blk::plain(S.L.Q1.ld), st));
+            LD_CHECK_HIP(launch_scale_copy(f64, n, cols, sblk, S.L.Q1.ld, p.d[m], rm, Y.ld, st));
+        } else {
+            LD_CHECK_HIP(launch_fill_signs(f64, n, cols, Y.ld, gcol, (const uint64_t*)S.mask, p.d[m], rm, st));
+        }
         for (int j = m - 1; j >= 0; --j) {
             StepArgs s{};
-            s.kind = STEP_HORNER_SIGNS;
+            s.kind = kind;
             s.win = bufs[j % 2 == 0 ? 1 : 0];
             s.wout = bufs[j % 2 == 0 ? 0 : 1];
             s.ld = Y.ld;
@@ -501,9 +513,11 @@ int sketch_phase(const ld_csr* A, EstimateState& S, hipStream_t st) {
             s.beta = p.beta[j];
             s.dj = p.d[j];
             s.mask = (const uint64_t*)S.mask;
+            s.vsrc = gauss ? sblk : nullptr;
+            s.ldv = S.L.Q1.ld;
             LD_CHECK(run_step(f64, A, s, cols, cols, st, nullptr, S.longrows));
             S.launches1 += 1;
-            S.bytes1 += alg_bytes_step(A, cols, STEP_HORNER_SIGNS, S.L.elem, S.longrows.dia_nd);
+            S.bytes1 += alg_bytes_step(A, cols, kind, S.L.elem, S.longrows.dia_nd);
         }
     }
     return LD_OK;
@@ -515,8 +529,10 @@ int estimate_front(const ld_csr* A, uint64_t seed, EstimateState& S, hipStream_t
     const int n = (int)A->n;
     const EstLayout& L = S.L;
     const uint64_t key0 = probe_stream_key(seed, 0), key1 = probe_stream_key(seed, 1);
+    const bool gauss = S.probe == LD_PROBE_GAUSSIAN;
+    S.key0 = key0;
 
-    LD_CHECK_HIP(launch_sign_mask(n, L.k, key0, (uint64_t*)S.mask, st));
+    if (!gauss) LD_CHECK_HIP(launch_sign_mask(n, L.k, key0, (uint64_t*)S.mask, st));
     LD_CHECK(record(S, 0, st));
     LD_CHECK(sketch_phase(A, S, st));
     LD_CHECK(record(S, 1, st));
@@ -533,13 +549,20 @@ int estimate_front(const ld_csr* A, uint64_t seed, EstimateState& S, hipStream_t
     LD_CHECK(cholqr_pass(f64, n, L.Y, L.k, L.Q1, S.part, dG, dR1, dRinv, S.flag + 1, st));
     LD_CHECK(cholqr_pass(f64, n, L.Q1, L.k, L.X, S.part, dG, dR2, dRinv, S.flag + 2, st));
     // ---- deflation: C = Q_b^T G, U = G - Q_b C (G = probe stream 1) into X[:, k:].
-    //      The sketch is done with S's sign words: the buffer now takes G's.
-    const uint64_t* gmask = (const uint64_t*)S.mask;
-    LD_CHECK_HIP(launch_sign_mask(n, L.kg, key1, (uint64_t*)S.mask, st));
-    LD_CHECK(cross_product(f64, n, L.X.base, L.X.desc(), L.k, nullptr, Blk::plain(1), L.kg, gmask, S.part, dC,
-                           st));
-    LD_CHECK_HIP(launch_rowmat(f64, n, L.X.base, L.X.desc(), L.k, dC, L.kg, -1.0, gmask, nullptr, Blk::plain(1),
-                               L.X.base, L.X.desc().shifted(L.k), st));
+    if (gauss) {   // G stored where U goes, then U = G - Q_b C in place
+        const Blk ud = L.X.desc().shifted(L.k);
+        LD_CHECK_HIP(launch_gauss_fill(f64, n, L.kg, key1, 0, 1.0, L.X.base, ud, st));
+        LD_CHECK(cross_product(f64, n, L.X.base, L.X.desc(), L.k, L.X.base, ud, L.kg, nullptr, S.part, dC, st));
+        LD_CHECK_HIP(launch_rowmat(f64, n, L.X.base, L.X.desc(), L.k, dC, L.kg, -1.0, nullptr, L.X.base, ud,
+                                   L.X.base, ud, st));
+    } else {   // the sketch is done with S's sign words: the buffer now takes G's
+        const uint64_t* gmask = (const uint64_t*)S.mask;
+        LD_CHECK_HIP(launch_sign_mask(n, L.kg, key1, (uint64_t*)S.mask, st));
+        LD_CHECK(cross_product(f64, n, L.X.base, L.X.desc(), L.k, nullptr, Blk::plain(1), L.kg, gmask, S.part,
+                               dC, st));
+        LD_CHECK_HIP(launch_rowmat(f64, n, L.X.base, L.X.desc(), L.k, dC, L.kg, -1.0, gmask, nullptr,
+                                   Blk::plain(1), L.X.base, L.X.desc().shifted(L.k), st));
+    }
     tm.mark();
     return LD_OK;
 }
@@ -726,9 +749,14 @@ int estimate_and_gradient(const ld_csr* A, uint64_t seed, EstimateState& S, Grad
                                B.Rg, Gb, st));
     LD_CHECK_HIP(launch_rowmat(f64, n, L.X.base, X.shifted(k), kg, slot[9], kg, 1.0, nullptr, nullptr,
                                Blk::plain(1), B.Rg, Gb.shifted(k), st));
-    LD_CHECK_HIP(launch_sign_mask(n, k, key0, (uint64_t*)S.mask, st));
-    LD_CHECK_HIP(launch_fill_signs(f64, n, k, ldg, 0, (const uint64_t*)S.mask, 1.0,
-                                   (char*)B.Rg + (size_t)nc * L.elem, st));
+    if (S.probe == LD_PROBE_GAUSSIAN) {
+        LD_CHECK_HIP(launch_gauss_fill(f64, n, k, key0, 0, 1.0, (char*)B.Rg + (size_t)nc * L.elem, Blk::plain(ldg),
+                                       st));
+    } else {
+        LD_CHECK_HIP(launch_sign_mask(n, k, key0, (uint64_t*)S.mask, st));
+        LD_CHECK_HIP(launch_fill_signs(f64, n, k, ldg, 0, (const uint64_t*)S.mask, 1.0,
+                                       (char*)B.Rg + (size_t)nc * L.elem, st));
+    }
 
     // ---- forward Newton vectors of R; FX = sum_j d_j w_j[:, :nc] on the way
     LD_CHECK_HIP(launch_scale_copy(f64, n, nc, B.Rg, ldg, p.d[0], L.FX.base, L.FX.ld, st));
@@ -776,8 +804,12 @@ int estimate_and_gradient(const ld_csr* A, uint64_t seed, EstimateState& S, Grad
     }
 
     // ---- Z: small matrices C = Q_b^T G (slot 2, from the deflation), M1 = U^T F Q_b
-    LD_CHECK_HIP(launch_sign_mask(n, kg, key1, (uint64_t*)B.mask2, st));
-    LD_CHECK_HIP(launch_fill_signs(f64, n, kg, L.Gm.ld, 0, (const uint64_t*)B.mask2, 1.0, L.Gm.base, st));
+    if (S.probe == LD_PROBE_GAUSSIAN) {
+        LD_CHECK_HIP(launch_gauss_fill(f64, n, kg, key1, 0, 1.0, L.Gm.base, Gd, st));
+    } else {
+        LD_CHECK_HIP(launch_sign_mask(n, kg, key1, (uint64_t*)B.mask2, st));
+        LD_CHECK_HIP(launch_fill_signs(f64, n, kg, L.Gm.ld, 0, (const uint64_t*)B.mask2, 1.0, L.Gm.base, st));
+    }
     std::vector<double> C((size_t)k * kg), Ct((size_t)kg * k);
     LD_CHECK(download(slot[2], C, st));
     for (int i = 0; i < k; ++i)
@@ -866,6 +898,9 @@ int run_logdet(const ld_csr* A, double lmin, double lmax, int degree, int n_matv
     LD_CHECK(make_plan(lmin, lmax, degree, o, S.plan));
     S.L = layout_estimate(A, degree, n_matvec, want_grad, o);
     S.mode = choose_dot_mode(S.plan, o.dot_mode, S.coef);
+    if (o.probe_dist != LD_PROBE_RADEMACHER && o.probe_dist != LD_PROBE_GAUSSIAN)
+        return fail(LD_EINVAL, "probe_dist must be LD_PROBE_RADEMACHER or LD_PROBE_GAUSSIAN");
+    S.probe = o.probe_dist;
     OwnedWs own;
     Arena ar;
     LD_CHECK(get_workspace(workspace, ws_bytes, layout_bytes(S.L, want_grad), own, ar));

@@ -112,6 +112,12 @@ hipError_t launch_sign_mask(int n, int k, uint64_t key, uint64_t* mask, hipStrea
 hipError_t launch_fill_signs(bool f64, int n, int k, int ld, int gshift, const uint64_t* mask,
                              double scale, void* out, hipStream_t st);
 
+// out[r, c] = scale * g(key, (c + col0)*n + r + 1), c < k, out column-blocked:
+// standard normal entries by Box-Muller (FP64) on the two 32-bit halves of
+// SplitMix64 output number (c + col0)*n + r + 1 of the stream key.
+hipError_t launch_gauss_fill(bool f64, int n, int k, uint64_t key, int col0, double scale, void* out, Blk bo,
+                             hipStream_t st);
+
 // out[r, c] = scale * V[r, c] (row-major, V with ldv, out with ldo), c < ncols.
 hipError_t launch_scale_copy(bool f64, int n, int ncols, const void* V, int ldv, double scale,
                              void* out, int ldo, hipStream_t st);

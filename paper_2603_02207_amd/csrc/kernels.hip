@@ -777,6 +777,34 @@ __global__ __launch_bounds__(kThreads) void fill_signs_kernel(int n, int k, int 
     }
 }
 
+// Gaussian probe entries: one thread per row of a column (grid.y = column).
+template <typename T>
+__global__ __launch_bounds__(kThreads) void gauss_fill_kernel(int n, uint64_t key, int col0, double scale,
+                                                              T* __restrict__ out, Blk bo) {
+    const int r = blockIdx.x * kThreads + threadIdx.x;
+    const int c = blockIdx.y;
+    if (r >= n) return;
+    const uint64_t x = probe_bits(key, (uint64_t)(c + col0) * (uint64_t)n + (uint64_t)r + 1ull);
+    const double u1 = ((double)(x >> 32) + 0.5) * 0x1p-32;
+    const double u2 = ((double)(x & 0xFFFFFFFFull) + 0.5) * 0x1p-32;
+    const double g = sqrt(-2.0 * log(u1)) * cos(6.283185307179586 * u2);
+    out[bo.offset(c) + (size_t)r * bo.ld] = (T)(scale * g);
+}
+
+hipError_t launch_gauss_fill(bool f64, int n, int k, uint64_t key, int col0, double scale, void* out, Blk bo,
+                             hipStream_t st) {
+    if ((long long)n * k == 0) return hipSuccess;
+    if (k > 65535) return hipErrorInvalidValue;
+    const dim3 grid(div_up(n, kThreads), k);
+    if (f64)
+        hipLaunchKernelGGL(gauss_fill_kernel<double>, grid, dim3(kThreads), 0, st, n, key, col0, scale,
+                           (double*)out, bo);
+    else
+        hipLaunchKernelGGL(gauss_fill_kernel<float>, grid, dim3(kThreads), 0, st, n, key, col0, scale,
+                           (float*)out, bo);
+    return hipGetLastError();
+}
+
 hipError_t launch_fill_signs(bool f64, int n, int k, int ld, int gshift, const uint64_t* mask,
                              double scale, void* out, hipStream_t st) {
     if ((long long)n * k == 0) return hipSuccess;

@@ -124,3 +124,18 @@ def test_grad_gmrf2048_finite_difference_full_size():
 
     fdk = (at_kappa(kap + hk) - at_kappa(kap - hk)) / (2 * hk)
     assert d_kap == pytest.approx(fdk, rel=1e-5)
+
+
+@pytest.mark.parametrize("dtype,tol", [(torch.float64, 1e-9), (torch.float32, 2e-4)])
+def test_grad_gaussian_probes(dtype, tol):
+    # Gaussian S and G (the paper's other probe choice): stored probe blocks
+    # in the forward pass and the reverse sweep alike
+    csr = random_spd_csr(300, 5, long_rows=2)
+    A, vals = to_gpu(csr, dtype)
+    csr_v = (csr[0], csr[1], vals, csr[3])
+    lmin, lmax = bounds.gershgorin(csr_v)
+    est, g = ld.logdet_with_grad(A, lmin, lmax, 30, 21, 6, options=ld.Options(probe_dist=1))
+    ref_est, ref_g = ograd.logdet_grad(csr_v, lmin, lmax, 30, 21, 6, probes="gaussian")
+    assert abs(est - ref_est) / abs(ref_est) < (1e-10 if dtype == torch.float64 else 1e-5)
+    g = g.double().cpu().numpy()
+    assert np.linalg.norm(g - ref_g) / np.linalg.norm(ref_g) < tol

@@ -406,3 +406,26 @@ def test_tile_order_follows_band_balance():
         assert forced["tile_order_used"] == 3 - want
         ref = hutchpp.logdet_estimate(w.to_scipy(csr_v), lo, hi, 30, 24, 2)
         assert rel(est, ref) < 1e-10
+
+
+@pytest.mark.parametrize("dtype,tol", [(torch.float64, 1e-10), (torch.float32, 2e-5)])
+def test_gaussian_probes_against_oracle(dtype, tol):
+    # Gaussian probe entries from the same counter generator (Box-Muller in
+    # FP64 on both sides): a stencil in diagonal storage with several sketch
+    # blocks, and an irregular matrix with long rows; the sketch goes
+    # through the stored-probe Horner step, the deflation through the
+    # general cross product.
+    cases = ((w.grid_laplacian_2d(200, 0.3), 48, dict(block_cols=8)),
+             (random_spd_csr(20000, 9, long_rows=3), 30, {}))
+    for csr, m_vec, extra in cases:
+        A, vals = to_gpu(csr, dtype)
+        csr_v = (csr[0], csr[1], vals, csr[3])
+        lo, hi = bounds.gershgorin(csr_v)
+        lo = max(lo, 0.3)
+        est, st = ld.logdet(A, lo, hi, 30, m_vec, 7, options=ld.Options(probe_dist=1, **extra), return_stats=True)
+        ref = hutchpp.logdet_estimate(w.to_scipy(csr_v), lo, hi, 30, m_vec, 7, probes="gaussian")
+        assert rel(est, ref) < tol, (est, ref)
+        if dtype == torch.float64:   # not the Rademacher estimate
+            assert rel(est, hutchpp.logdet_estimate(w.to_scipy(csr_v), lo, hi, 30, m_vec, 7)) > 1e-8
+    with pytest.raises(ld.NativeError):
+        ld.logdet(A, lo, hi, 30, 24, 4, options=ld.Options(probe_dist=2))
