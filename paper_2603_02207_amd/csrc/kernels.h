@@ -83,6 +83,8 @@ struct StepArgs {
     // takes tiles w, w + grid, ... (spreads each tile's neighbours over the
     // XCDs; faster once the blocks stream from HBM)
     int interleave;
+    // 1: the output block is written with non-temporal (streaming) stores
+    int nt_out;
 };
 
 constexpr int kLongRow = 64;     // entries above which a row is "long"

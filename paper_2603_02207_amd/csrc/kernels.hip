@@ -44,6 +44,16 @@ template <typename T, int V>
 __device__ __forceinline__ void store_pack(T* p, const Pack<T, V>& x) {
     *reinterpret_cast<Pack<T, V>*>(p) = x;
 }
+// Streaming store (non-temporal hint): the line is not kept in L2, which then
+// holds more of the rows the next tiles gather.
+template <typename T, int V>
+__device__ __forceinline__ void store_pack_nt(T* p, const Pack<T, V>& x) {
+    typedef T vt __attribute__((ext_vector_type(V)));
+    vt v;
+#pragma unroll
+    for (int e = 0; e < V; ++e) v[e] = x.v[e];
+    __builtin_nontemporal_store(v, reinterpret_cast<vt*>(p));
+}
 
 // Logical tile of this workgroup: XCD x (= blockIdx % 8) gets the contiguous
 // tile range [x*(nwg/8) + min(x, nwg%8), ...).
@@ -118,7 +128,7 @@ __global__ __launch_bounds__(NT) void step_kernel(
     const uint64_t* __restrict__ mask, double* __restrict__ ps0, double* __restrict__ ps1,
     double* __restrict__ ps2, int part_ld, int lpr, int rpw, int skip_long, T* __restrict__ accum,
     int ldacc, int acc_cols, int ntiles, const uint64_t* __restrict__ active, const T* __restrict__ dia, int nd,
-    DiaOff off, int interleave) {
+    DiaOff off, int interleave, int nt_out) {
     constexpr bool kDot = is_dot(KIND);
     constexpr int NW = NT / 64;
     constexpr int kSums = kDot ? ((FIRST ? 1 : 0) + 1 + (KIND == STEP_DOT_SQ ? 1 : 0)) : 0;
@@ -323,7 +333,10 @@ __global__ __launch_bounds__(NT) void step_kernel(
         // the vector never leaves the row, and columns past c0+bcols in it get
         // the value of the same recurrence (real columns of a wider block, or
         // padding that no one reads).
-        store_pack<T, VEC>(wout + (size_t)row * ld + col, o);
+        if (nt_out)
+            store_pack_nt<T, VEC>(wout + (size_t)row * ld + col, o);
+        else
+            store_pack<T, VEC>(wout + (size_t)row * ld + col, o);
     }
     }   // tiles
 
@@ -562,7 +575,7 @@ hipError_t launch_step_t(const CsrDev& A, const StepArgs& s, hipStream_t st, int
                            (const T*)s.win, (T*)s.wout, s.ld, s.c0, s.bcols, s.gshift, (T)s.alpha, (T)s.beta,   \
                            (T)s.dj, (const T*)s.vsrc, s.ldv, s.mask, s.ps0, s.ps1, s.ps2, s.part_ld, lpr, rpw, \
                            0, (T*)s.acc, s.ldacc, s.acc_cols, ntiles, s.active, (const T*)s.dia, s.dia_nd, off, \
-                           s.interleave);                                                                      \
+                           s.interleave, s.nt_out);                                                            \
         if (nwg_out) *nwg_out = nwg;                                                                           \
     }
         if (s.dia_nd <= 3)
@@ -585,7 +598,7 @@ hipError_t launch_step_t(const CsrDev& A, const StepArgs& s, hipStream_t st, int
                        A.n, A.row_ptr, A.col_idx, (const T*)A.val, (const T*)s.win, (T*)s.wout, s.ld,
                        s.c0, s.bcols, s.gshift, (T)s.alpha, (T)s.beta, (T)s.dj, (const T*)s.vsrc,
                        s.ldv, s.mask, s.ps0, s.ps1, s.ps2, s.part_ld, lpr, rpw, skip, (T*)s.acc,
-                       s.ldacc, s.acc_cols, ntiles, s.active, (const T*)nullptr, 0, off, s.interleave);
+                       s.ldacc, s.acc_cols, ntiles, s.active, (const T*)nullptr, 0, off, s.interleave, s.nt_out);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess || !skip) return e;
     hipLaunchKernelGGL((long_row_kernel<T, VEC, KIND, FIRST>), dim3(kLongWgs), dim3(256), 0, st,
