@@ -887,6 +887,8 @@ int estimate_and_gradient(const ld_csr* A, uint64_t seed, EstimateState& S, Grad
             a.dj = p.d[i];
             a.first = i == m - 1;
             a.last = i == 0;
+            // as the Newton steps: streaming stores once the sweep works beyond the Infinity Cache
+            a.nt_out = matrix_bytes(A, L.elem) + 4.0 * (double)n * ldg * L.elem > kMallBudget;
             LD_CHECK_HIP(launch_adjoint(f64, d, a, st));
             std::swap(lam_in, lam_out);
         }

@@ -170,6 +170,7 @@ struct AdjArgs {
     double alpha, beta, dj;
     bool first;      // grad is overwritten instead of accumulated
     bool last;       // no lam_out needed (only the SDDMM)
+    bool nt_out;     // lam_out written with non-temporal (streaming) stores
 };
 hipError_t launch_adjoint(bool f64, const CsrDev& A, const AdjArgs& a, hipStream_t st);
 

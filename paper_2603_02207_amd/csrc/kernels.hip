@@ -1848,7 +1848,7 @@ __global__ __launch_bounds__(kThreads) void adjoint_kernel(
     int n, const int* __restrict__ row_ptr, const int* __restrict__ col_idx,
     const T* __restrict__ val, const T* __restrict__ lam_in, T* __restrict__ lam_out,
     const T* __restrict__ w, const T* __restrict__ L, T* __restrict__ grad, int ld, int ncols,
-    T alpha, T beta, T dj, int first, int last) {
+    T alpha, T beta, T dj, int first, int last, int nt_out) {
     constexpr int RPW = 64 / LPR;
     constexpr int NB = LPR < kAdjBatch ? LPR : kAdjBatch;
     constexpr int rows_per_wg = kWaves * RPW;
@@ -1953,7 +1953,10 @@ __global__ __launch_bounds__(kThreads) void adjoint_kernel(
 #pragma unroll
             for (int e = 0; e < VEC; ++e)
                 o.v[e] = fma(dj, Lr[q].v[e], alpha * acc[q][e] - beta * own[q].v[e]);
-            store_pack<T, VEC>(lam_out + off, o);
+            if (nt_out)
+                store_pack_nt<T, VEC>(lam_out + off, o);
+            else
+                store_pack<T, VEC>(lam_out + off, o);
         }
     }
 }
@@ -1966,7 +1969,7 @@ hipError_t launch_adjoint_t(const CsrDev& A, const AdjArgs& a, hipStream_t st) {
     hipLaunchKernelGGL((adjoint_kernel<T, VEC, LPR, CPL>), dim3(nwg), dim3(kThreads), 0, st, A.n,
                        A.row_ptr, A.col_idx, (const T*)A.val, (const T*)a.lam_in, (T*)a.lam_out,
                        (const T*)a.w, (const T*)a.L, (T*)a.grad, a.ld, a.ncols, (T)a.alpha, (T)a.beta,
-                       (T)a.dj, (int)a.first, (int)a.last);
+                       (T)a.dj, (int)a.first, (int)a.last, (int)a.nt_out);
     return hipGetLastError();
 }
 
