@@ -181,8 +181,12 @@ __global__ __launch_bounds__(NT) void step_kernel(
     if constexpr (ND > 0) {
         // the wave's rows are one contiguous run of nrows*nd diagonal values
         staged = nrows * nd <= kWaveNz;
-        if (staged)
-            for (int k = lane; k < nrows * nd; k += 64) s_val[k] = dia[(size_t)W0 * nd + k];
+        if (staged) {   // read once per step: streamed past L2 when the launch works from HBM
+            if (nt_out)
+                for (int k = lane; k < nrows * nd; k += 64) s_val[k] = __builtin_nontemporal_load(dia + (size_t)W0 * nd + k);
+            else
+                for (int k = lane; k < nrows * nd; k += 64) s_val[k] = dia[(size_t)W0 * nd + k];
+        }
     } else {
         if (nrows > 0)   // waves past the last row read nothing
             for (int t2 = lane; t2 <= nrows; t2 += 64) rp[t2] = row_ptr[W0 + t2];
@@ -191,10 +195,17 @@ __global__ __launch_bounds__(NT) void step_kernel(
         K0 = nrows > 0 ? rp[0] : 0;
         const int K1 = nrows > 0 ? rp[nrows] : 0;
         staged = (K1 - K0) <= kWaveNz;
-        if (staged) {
-            for (int k = K0 + lane; k < K1; k += 64) {
-                s_col[k - K0] = col_idx[k];
-                s_val[k - K0] = val[k];
+        if (staged) {   // read once per step: streamed past L2 when the launch works from HBM
+            if (nt_out) {
+                for (int k = K0 + lane; k < K1; k += 64) {
+                    s_col[k - K0] = __builtin_nontemporal_load(col_idx + k);
+                    s_val[k - K0] = __builtin_nontemporal_load(val + k);
+                }
+            } else {
+                for (int k = K0 + lane; k < K1; k += 64) {
+                    s_col[k - K0] = col_idx[k];
+                    s_val[k - K0] = val[k];
+                }
             }
         }
     }
