@@ -1744,31 +1744,46 @@ __global__ __launch_bounds__(kThreads) void dia_build_kernel(int n, const int* _
                                                              const int* __restrict__ col_idx,
                                                              const T* __restrict__ val, T* __restrict__ dia,
                                                              int* __restrict__ info) {
-    const int r = blockIdx.x * kThreads + threadIdx.x;
-    if (r >= n) return;
+    // each thread places its row's entries in registers; the workgroup's rows
+    // are one contiguous run of the storage, written through LDS with
+    // consecutive threads on consecutive elements
+    __shared__ T sv[kThreads * kMaxDiag];
     const int nd = info[0];
-    if (nd <= 0) {
-        if (r == 0) info[kDiaFlag] = 1;
+    if (nd <= 0) {   // uniform: no candidate diagonals
+        if (blockIdx.x == 0 && threadIdx.x == 0) info[kDiaFlag] = 1;
         return;
     }
-    int off[kMaxDiag];
+    const int r0 = blockIdx.x * kThreads;
+    const int nr = min(kThreads, n - r0);
+    const int r = r0 + threadIdx.x;
+    if (threadIdx.x < nr) {
+        int off[kMaxDiag];
 #pragma unroll
-    for (int q = 0; q < kMaxDiag; ++q) off[q] = info[1 + q];
-    T* const out = dia + (size_t)r * nd;
-    for (int q = 0; q < nd; ++q) out[q] = T(0);
-    bool bad = false;
-    for (int k = row_ptr[r]; k < row_ptr[r + 1]; ++k) {
-        const int o = col_idx[k] - r;
-        int hit = -1;
+        for (int q = 0; q < kMaxDiag; ++q) off[q] = info[1 + q];
+        T v[kMaxDiag];
+#pragma unroll
+        for (int q = 0; q < kMaxDiag; ++q) v[q] = T(0);
+        bool bad = false;
+        for (int k = row_ptr[r]; k < row_ptr[r + 1]; ++k) {
+            const int o = col_idx[k] - r;
+            const T x = val[k];
+            bool hit = false;
+#pragma unroll
+            for (int q = 0; q < kMaxDiag; ++q)
+                if (q < nd && off[q] == o) {
+                    v[q] = x;
+                    hit = true;
+                }
+            bad |= !hit;
+        }
+        if (bad) info[kDiaFlag] = 1;
 #pragma unroll
         for (int q = 0; q < kMaxDiag; ++q)
-            if (q < nd && off[q] == o) hit = q;
-        if (hit >= 0)
-            out[hit] = val[k];
-        else
-            bad = true;
+            if (q < nd) sv[threadIdx.x * nd + q] = v[q];
     }
-    if (bad) info[kDiaFlag] = 1;
+    __syncthreads();
+    T* const out = dia + (size_t)r0 * nd;
+    for (int e = threadIdx.x; e < nr * nd; e += kThreads) out[e] = sv[e];
 }
 
 hipError_t launch_rows_probe(const CsrDev& A, int* info, hipStream_t st) {
