@@ -354,12 +354,13 @@ int run_step(bool f64, const ld_csr* A, StepArgs s, int ncols, int col_block, hi
 }
 
 
-// Per-call matrix preparation, with one host sync for both results:
-// the list of rows with more than kLongRow entries, and diagonal storage when
-// every stored entry lies on one of at most kMaxDiag diagonals (stencils,
-// banded matrices).  The diagonal build takes its candidate offsets from a
-// sample of rows and flags any entry off them, in which case the call keeps
-// the CSR path.
+// Per-call matrix preparation, with one host sync for all results: the list
+// of rows with more than kLongRow entries, the balance of the entries over
+// the eight row bands (tile order), and diagonal storage when every stored
+// entry lies on one of at most kMaxDiag diagonals (stencils, banded
+// matrices).  The diagonal build takes its candidate offsets from a sample of
+// rows and flags any entry off them, in which case the call keeps the CSR
+// path.
 int prepare_rows(const ld_csr* A, const ld_options& o, Arena& ar, hipStream_t st, LongRows& lr) {
     if (o.tile_order < LD_TILES_AUTO || o.tile_order > LD_TILES_INTERLEAVED)
         return fail(LD_EINVAL, "tile_order must be LD_TILES_AUTO, LD_TILES_XCD_BANDS or LD_TILES_INTERLEAVED");
@@ -485,7 +486,8 @@ int choose_dot_mode(const Plan& p, int requested, std::vector<double>& coef) {
     return LD_DOT_SQUARED;
 }
 
-// Horner evaluation of Y = P_m(Q~) S, block by block; S from the sign mask.
+// Horner evaluation of Y = P_m(Q~) S, block by block; S from the sign words
+// (Rademacher) or stored (Gaussian).
 int sketch_phase(const ld_csr* A, EstimateState& S, hipStream_t st) {
     const bool f64 = A->dtype == LD_F64;
     const int n = (int)A->n;

@@ -9,7 +9,8 @@
 // Work distribution is XCD-aware: workgroups are issued round-robin over the
 // 8 XCDs, so the logical row tile of a workgroup is remapped such that each
 // XCD walks one contiguous band of rows.  Stencil neighbours (rows r +- N)
-// are then mostly found in that XCD's own L2.
+// are then mostly found in that XCD's own L2.  Matrices whose entries crowd
+// into a few bands take interleaved tiles instead (balanced XCD load).
 //
 // Reductions never use atomics: each workgroup writes FP64 partial sums and a
 // separate kernel adds them in a fixed order (Neumaier), so every result is
@@ -1023,7 +1024,7 @@ int cross_num_wg(int n) { return (int)std::min<long long>(div_up(n, kCrossRows),
 // ---------------------------------------------------------------------------
 // Narrow cross products (kx, kz <= 32) from LDS-staged tiles on the FP64
 // vector units.  A tile of RT rows is staged whole (X's block rows with
-// 16-byte vectors; generated signs written once per element), and each
+// 16-byte vectors; probe signs expanded once per row from its sign word), and each
 // thread accumulates one 4x4 block of X^T Z in FP64 over a fixed subset of
 // the tile's rows (its phase).  The phases are summed in order at the end,
 // so partial row wg (one per workgroup, as cross_kernel's) is repeatable.
