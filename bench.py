@@ -338,8 +338,9 @@ def run_workload(args, workload, steps):
             "lmin": lmin,
             "lmax": lmax,
             "dot_mode": {1: "forward", 2: "squared"}[st["dot_mode_used"]],
-            "matrix_storage": (f"diagonal ({st['dia_diagonals']} diagonals)" if st.get("dia_diagonals")
-                               else "csr"),
+            "matrix_storage": ((f"diagonal ({st['dia_diagonals']} diagonals" +
+                                (", one value each, presence bits per row)" if st.get("dia_constant") else ")"))
+                               if st.get("dia_diagonals") else "csr"),
             "block_cols": args.block_cols,
             "tile_order": {1: "bands", 2: "interleaved"}[st["tile_order_used"]],
             "probes": args.probe_dist,

@@ -135,6 +135,9 @@ typedef struct {
     double bytes1, bytes23;  /* algorithmic bytes of those launches            */
     int32_t dia_diagonals;   /* diagonals of the diagonal storage used, 0: CSR */
     int32_t tile_order_used; /* LD_TILES_XCD_BANDS or LD_TILES_INTERLEAVED      */
+    int32_t dia_constant;    /* 1: every diagonal holds one value (stored once,
+                                with 16 presence bits per row)                */
+    int32_t reserved_stats;
 } ld_stats;
 
 /* Defaults for ld_options (all zero except as documented). */

@@ -80,6 +80,8 @@ class LdStats(ctypes.Structure):
         ("bytes23", ctypes.c_double),
         ("dia_diagonals", ctypes.c_int32),
         ("tile_order_used", ctypes.c_int32),
+        ("dia_constant", ctypes.c_int32),
+        ("reserved_stats", ctypes.c_int32),
     ]
 
     def as_dict(self):

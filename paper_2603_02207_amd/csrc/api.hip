@@ -68,7 +68,8 @@ size_t long_rows_bytes(const ld_csr* A) {
 // the matrix turns out to have it).
 size_t dia_bytes(const ld_csr* A, const ld_options& o) {
     if (o.csr_only) return align_up(256);
-    return align_up((size_t)A->n * kMaxDiag * (A->dtype == LD_F64 ? 8 : 4)) + align_up(256);
+    return align_up((size_t)A->n * kMaxDiag * (A->dtype == LD_F64 ? 8 : 4)) + align_up((size_t)A->n * 2) +
+           align_up(256);
 }
 
 
@@ -288,7 +289,7 @@ struct Timer {
 
 // bytes the recurrence kernels must move (FP values, int32 indices; the
 // matrix once per launch, blocks as listed per step kind)
-double alg_bytes_step(const ld_csr* A, int cols, int kind, size_t elem, int dia_nd = 0) {
+double alg_bytes_step(const ld_csr* A, int cols, int kind, size_t elem, int dia_nd = 0, bool dia_const = false) {
     double per = 0;
     switch (kind) {
         case STEP_HORNER_SIGNS: per = 2.0 * elem * cols + 8.0; break;   // + sign-mask word
@@ -297,8 +298,10 @@ double alg_bytes_step(const ld_csr* A, int cols, int kind, size_t elem, int dia_
         case STEP_DOT_SQ: per = 2.0 * elem * cols; break;
         default: per = 2.0 * elem * cols; break;
     }
-    // diagonal storage: the values only, n x nd
-    const double mat = dia_nd > 0 ? (double)A->n * dia_nd * elem : matrix_bytes(A, elem);
+    // diagonal storage: the values only, n x nd; constant diagonals: 2 bytes
+    // of presence bits per row
+    const double mat = dia_nd > 0 ? (dia_const ? 2.0 * (double)A->n : (double)A->n * dia_nd * elem)
+                                  : matrix_bytes(A, elem);
     return mat + per * (double)A->n;
 }
 
@@ -312,6 +315,9 @@ struct LongRows {
     const void* dia = nullptr;
     int dia_nd = 0;
     int dia_off[kMaxDiag] = {};
+    // every diagonal one constant: per-row presence bits and the constants
+    const uint16_t* dia_pres = nullptr;
+    double dia_cval[kMaxDiag] = {};
     int tile_order = LD_TILES_AUTO;   // ld_options.tile_order
     bool skewed = false;              // entries far from even over the eight row bands
 };
@@ -324,6 +330,8 @@ int run_step(bool f64, const ld_csr* A, StepArgs s, int ncols, int col_block, hi
     s.dia = lr.dia;
     s.dia_nd = lr.dia_nd;
     for (int q = 0; q < kMaxDiag; ++q) s.dia_off[q] = lr.dia_off[q];
+    s.dia_pres = lr.dia_pres;
+    for (int q = 0; q < kMaxDiag; ++q) s.dia_cval[q] = lr.dia_cval[q];
     // XCD bands keep a stencil's neighbour rows in the XCD's L2 (measured on
     // gfx950: 1.45x faster steps while the blocks stream from the Infinity
     // Cache, within 3% of interleaved from HBM), but give one XCD most of
@@ -335,7 +343,8 @@ int run_step(bool f64, const ld_csr* A, StepArgs s, int ncols, int col_block, hi
     // input rows that neighbouring tiles gather (measured on gfx950: -7% on a
     // 7-point stencil step over 32 columns at 128^3).  Below that size the
     // next step reads the output back from the cache, and plain stores stay.
-    s.nt_out = alg_bytes_step(A, ncols, s.kind, A->dtype == LD_F64 ? 8 : 4, lr.dia_nd) > kMallBudget;
+    s.nt_out = alg_bytes_step(A, ncols, s.kind, A->dtype == LD_F64 ? 8 : 4, lr.dia_nd, lr.dia_pres != nullptr) >
+               kMallBudget;
     int nwg = 0;
     const int gshift = s.gshift;
     // one row group spans at most a wave: 64 lanes of the launch's vector width
@@ -368,16 +377,17 @@ int prepare_rows(const ld_csr* A, const ld_options& o, Arena& ar, hipStream_t st
     int* tmp = (int*)ar.take(((size_t)A->n / 256 + 4) * 4);
     int* count = (int*)ar.take(16);
     void* buf = o.csr_only ? nullptr : ar.take((size_t)A->n * kMaxDiag * (A->dtype == LD_F64 ? 8 : 4));
+    uint16_t* pres = o.csr_only ? nullptr : (uint16_t*)ar.take((size_t)A->n * 2);
     int* info = (int*)ar.take(256);
     const bool probe = A->n >= 3 && A->nnz > 0;
     const bool want_dia = buf && probe;
     int hcount = 0;
-    int h[kBandInfo + kXcds + 1] = {};
+    int h[64] = {};   // the 256-byte info block
     LD_CHECK_HIP(launch_long_rows(dev_of(A), tmp, list, count, st));
     if (probe) {
         LD_CHECK_HIP(hipMemcpyAsync(info, h, sizeof(h), hipMemcpyHostToDevice, st));
-        LD_CHECK_HIP(launch_rows_probe(dev_of(A), info, st));
-        if (want_dia) LD_CHECK_HIP(launch_dia_build(A->dtype == LD_F64, dev_of(A), buf, info, st));
+        LD_CHECK_HIP(launch_rows_probe(A->dtype == LD_F64, dev_of(A), info, st));
+        if (want_dia) LD_CHECK_HIP(launch_dia_build(A->dtype == LD_F64, dev_of(A), buf, pres, info, st));
         LD_CHECK_HIP(hipMemcpyAsync(h, info, sizeof(h), hipMemcpyDeviceToHost, st));
     }
     LD_CHECK_HIP(hipMemcpyAsync(&hcount, count, sizeof(int), hipMemcpyDeviceToHost, st));
@@ -398,6 +408,10 @@ int prepare_rows(const ld_csr* A, const ld_options& o, Arena& ar, hipStream_t st
         lr.dia = buf;
         lr.dia_nd = nd;
         for (int q = 0; q < kMaxDiag; ++q) lr.dia_off[q] = q < nd ? h[1 + q] : 0;
+        if (!h[kConstFlag] && !o.csr_only) {   // every diagonal holds one value
+            lr.dia_pres = pres;
+            std::memcpy(lr.dia_cval, h + kConstInfo, sizeof(double) * nd);
+        }
     }
     return LD_OK;
 }
@@ -525,7 +539,7 @@ int sketch_phase(const ld_csr* A, EstimateState& S, hipStream_t st) {
             s.ldv = S.L.Q1.ld;
             LD_CHECK(run_step(f64, A, s, cols, cols, st, nullptr, S.longrows));
             S.launches1 += 1;
-            S.bytes1 += alg_bytes_step(A, cols, kind, S.L.elem, S.longrows.dia_nd);
+            S.bytes1 += alg_bytes_step(A, cols, kind, S.L.elem, S.longrows.dia_nd, S.longrows.dia_pres != nullptr);
         }
     }
     return LD_OK;
@@ -613,7 +627,7 @@ int estimate_dots(const ld_csr* A, EstimateState& S, hipStream_t st, std::vector
                 if (a > 0 && used != nwg) return fail(LD_EINVAL, "internal: partial rows differ between steps");
                 nwg = used;
                 S.launches23 += 1;
-                S.bytes23 += alg_bytes_step(A, cols, STEP_DOT_SQ, L.elem, S.longrows.dia_nd);
+                S.bytes23 += alg_bytes_step(A, cols, STEP_DOT_SQ, L.elem, S.longrows.dia_nd, S.longrows.dia_pres != nullptr);
                 cur = nxt;
             }
         } else {
@@ -638,7 +652,7 @@ int estimate_dots(const ld_csr* A, EstimateState& S, hipStream_t st, std::vector
                 if (j > 0 && used != nwg) return fail(LD_EINVAL, "internal: partial rows differ between steps");
                 nwg = used;
                 S.launches23 += 1;
-                S.bytes23 += alg_bytes_step(A, cols, STEP_DOT_FWD, L.elem, S.longrows.dia_nd);
+                S.bytes23 += alg_bytes_step(A, cols, STEP_DOT_FWD, L.elem, S.longrows.dia_nd, S.longrows.dia_pres != nullptr);
                 cur = pp[j % 2];
             }
         }
@@ -980,6 +994,7 @@ int run_logdet(const ld_csr* A, double lmin, double lmax, int degree, int n_matv
         stats->k_G = L.kg;
         stats->dot_mode_used = want_grad ? LD_DOT_FORWARD : S.mode;
         stats->dia_diagonals = S.longrows.dia_nd;
+        stats->dia_constant = S.longrows.dia_pres != nullptr;
         stats->tile_order_used = S.longrows.tile_order == LD_TILES_INTERLEAVED ||
                                          (S.longrows.tile_order == LD_TILES_AUTO && S.longrows.skewed)
                                      ? LD_TILES_INTERLEAVED

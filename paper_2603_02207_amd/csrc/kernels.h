@@ -78,6 +78,10 @@ struct StepArgs {
     const void* dia;
     int dia_nd;
     int dia_off[kMaxDiag];
+    // every diagonal one constant (dia_pres non-null): row r holds dia_cval[q]
+    // on diagonal q when bit q of dia_pres[r] is set; dia is not read
+    const uint16_t* dia_pres;
+    double dia_cval[kMaxDiag];
     // tile order: 0 = XCD x (blockIdx % 8) walks the x-th contiguous band of
     // row tiles (stencil neighbours stay in that XCD's L2); 1 = workgroup w
     // takes tiles w, w + grid, ... (spreads each tile's neighbours over the
@@ -174,16 +178,21 @@ struct AdjArgs {
 };
 hipError_t launch_adjoint(bool f64, const CsrDev& A, const AdjArgs& a, hipStream_t st);
 
-// Row probe (info: device, 32 ints, info[12] preset to 0 by the caller):
-// info[0] = number of diagonals nd (distinct offsets col - row of 64 sampled
-// rows, ascending, in info[1..nd]; -1 if more than kMaxDiag), and
-// info[kBandInfo + i] = row_ptr[i*n/8], i = 0..8 (entries per XCD band).
-// Then the diagonal storage: dia[r*nd + q] = A[r, r + info[1+q]] or 0;
-// info[12] = 1 when some stored entry lies on none of the diagonals (the
-// storage is then unusable).
+// Row probe (info: device, 64 ints, preset to 0 by the caller): info[0] =
+// number of diagonals nd (distinct offsets col - row of 64 sampled rows,
+// ascending, in info[1..nd]; -1 if more than kMaxDiag),
+// info[kBandInfo + i] = row_ptr[i*n/8], i = 0..8 (entries per XCD band), and
+// at info + kConstInfo nd doubles: each diagonal's value in the first sampled
+// row that stores it.  Then the diagonal storage: dia[r*nd + q] =
+// A[r, r + info[1+q]] or 0, pres[r] bit q = row r stores diagonal q;
+// info[kDiaFlag] = 1 when some stored entry lies on none of the diagonals (the
+// storage is then unusable), info[kConstFlag] = 1 when some entry differs from
+// its diagonal's sampled value (else every diagonal is one constant).
 constexpr int kBandInfo = 16;
-hipError_t launch_rows_probe(const CsrDev& A, int* info, hipStream_t st);
-hipError_t launch_dia_build(bool f64, const CsrDev& A, void* dia, int* info, hipStream_t st);
+constexpr int kConstFlag = 13;
+constexpr int kConstInfo = 32;   // int index; 8-byte aligned doubles
+hipError_t launch_rows_probe(bool f64, const CsrDev& A, int* info, hipStream_t st);
+hipError_t launch_dia_build(bool f64, const CsrDev& A, void* dia, uint16_t* pres, int* info, hipStream_t st);
 
 // Alg. 2's stopping test after the step that produced w_m: for columns c < qc
 // still active in *mask, e = |d_m| sqrt(sums[c*stride]) <= tol clears the bit

@@ -118,6 +118,11 @@ inline int grid_of(int kind, int ntiles) { return is_dot(kind) && ntiles > kDotW
 struct DiaOff {
     int o[kMaxDiag];
 };
+// one value per diagonal (constant-coefficient storage)
+template <typename T>
+struct DiaVal {
+    T c[kMaxDiag];
+};
 
 // ND > 0: gather from the diagonal storage, at most ND diagonals (compile-time
 // width of the per-row gather batch); ND = 0: from the CSR arrays.
@@ -129,7 +134,7 @@ __global__ __launch_bounds__(NT) void step_kernel(
     const uint64_t* __restrict__ mask, double* __restrict__ ps0, double* __restrict__ ps1,
     double* __restrict__ ps2, int part_ld, int lpr, int rpw, int skip_long, T* __restrict__ accum,
     int ldacc, int acc_cols, int ntiles, const uint64_t* __restrict__ active, const T* __restrict__ dia, int nd,
-    DiaOff off, int interleave, int nt_out) {
+    DiaOff off, int interleave, int nt_out, const uint16_t* __restrict__ dpres, DiaVal<T> cv) {
     constexpr bool kDot = is_dot(KIND);
     constexpr int NW = NT / 64;
     constexpr int kSums = kDot ? ((FIRST ? 1 : 0) + 1 + (KIND == STEP_DOT_SQ ? 1 : 0)) : 0;
@@ -181,7 +186,7 @@ __global__ __launch_bounds__(NT) void step_kernel(
     bool staged;
     if constexpr (ND > 0) {
         // the wave's rows are one contiguous run of nrows*nd diagonal values
-        staged = nrows * nd <= kWaveNz;
+        staged = !dpres && nrows * nd <= kWaveNz;   // constant values: nothing to stage
         if (staged) {   // read once per step: streamed past L2 when the launch works from HBM
             if (nt_out)
                 for (int k = lane; k < nrows * nd; k += 64) s_val[k] = __builtin_nontemporal_load(dia + (size_t)W0 * nd + k);
@@ -228,12 +233,16 @@ __global__ __launch_bounds__(NT) void step_kernel(
             // before the first product.
             int cq[ND];
             T aq[ND];
+            const unsigned pbits = dpres ? dpres[row] : 0u;
 #pragma unroll
             for (int q = 0; q < ND; ++q) {
                 const int c = row + off.o[q];
                 const bool ok = q < nd && (unsigned)c < (unsigned)n;
                 cq[q] = ok ? c : row;
-                aq[q] = ok ? (staged ? s_val[lr * nd + q] : dia[(size_t)row * nd + q]) : T(0);
+                if (dpres)
+                    aq[q] = ok && ((pbits >> q) & 1u) ? cv.c[q] : T(0);
+                else
+                    aq[q] = ok ? (staged ? s_val[lr * nd + q] : dia[(size_t)row * nd + q]) : T(0);
             }
             Pack<T, VEC> xq[ND];
 #pragma unroll
@@ -576,6 +585,8 @@ hipError_t launch_step_t(const CsrDev& A, const StepArgs& s, hipStream_t st, int
     };
     DiaOff off{};
     for (int q = 0; q < kMaxDiag; ++q) off.o[q] = q < s.dia_nd ? s.dia_off[q] : 0;
+    DiaVal<T> cv{};
+    for (int q = 0; q < kMaxDiag; ++q) cv.c[q] = (T)(q < s.dia_nd ? s.dia_cval[q] : 0.0);
     if (s.dia_nd > 0) {   // no row has more than kMaxDiag entries: no long rows either
         if (s.dia_nd > kMaxDiag || !s.dia) return hipErrorInvalidValue;
 #define LD_DIA_LAUNCH(ND_)                                                                                     \
@@ -587,7 +598,7 @@ hipError_t launch_step_t(const CsrDev& A, const StepArgs& s, hipStream_t st, int
                            (const T*)s.win, (T*)s.wout, s.ld, s.c0, s.bcols, s.gshift, (T)s.alpha, (T)s.beta,   \
                            (T)s.dj, (const T*)s.vsrc, s.ldv, s.mask, s.ps0, s.ps1, s.ps2, s.part_ld, lpr, rpw, \
                            0, (T*)s.acc, s.ldacc, s.acc_cols, ntiles, s.active, (const T*)s.dia, s.dia_nd, off, \
-                           s.interleave, s.nt_out);                                                            \
+                           s.interleave, s.nt_out, s.dia_pres, cv);                                            \
         if (nwg_out) *nwg_out = nwg;                                                                           \
     }
         if (s.dia_nd <= 3)
@@ -610,7 +621,8 @@ hipError_t launch_step_t(const CsrDev& A, const StepArgs& s, hipStream_t st, int
                        A.n, A.row_ptr, A.col_idx, (const T*)A.val, (const T*)s.win, (T*)s.wout, s.ld,
                        s.c0, s.bcols, s.gshift, (T)s.alpha, (T)s.beta, (T)s.dj, (const T*)s.vsrc,
                        s.ldv, s.mask, s.ps0, s.ps1, s.ps2, s.part_ld, lpr, rpw, skip, (T*)s.acc,
-                       s.ldacc, s.acc_cols, ntiles, s.active, (const T*)nullptr, 0, off, s.interleave, s.nt_out);
+                       s.ldacc, s.acc_cols, ntiles, s.active, (const T*)nullptr, 0, off, s.interleave, s.nt_out,
+                       (const uint16_t*)nullptr, cv);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess || !skip) return e;
     hipLaunchKernelGGL((long_row_kernel<T, VEC, KIND, FIRST>), dim3(kLongWgs), dim3(256), 0, st,
@@ -1693,7 +1705,8 @@ __global__ __launch_bounds__(kThreads) void axpby_kernel(long long len, T a, con
 // over the matrix, merged in ascending order by one lane; info[0] = their number,
 // or -1 when a sampled row or the union exceeds kMaxDiag.
 __global__ __launch_bounds__(64) void dia_probe_kernel(int n, const int* __restrict__ row_ptr,
-                                                       const int* __restrict__ col_idx, int* __restrict__ info) {
+                                                       const int* __restrict__ col_idx, const void* __restrict__ val,
+                                                       int f64, int* __restrict__ info) {
     // one wave: lane t samples one row (golden-ratio stride: no alignment with
     // a grid's rows, whatever its width) and holds its column offsets
     const int t = threadIdx.x;
@@ -1730,21 +1743,41 @@ __global__ __launch_bounds__(64) void dia_probe_kernel(int n, const int* __restr
 #pragma unroll
         for (int q = 0; q < kMaxDiag; ++q) info[1 + q] = (nu > 0 && q < nu) ? u[q] : 0;
     }
+    // candidate constant of each diagonal: its value in the first sampled row
+    // that has it (the build checks every other entry against it)
+    double* const cval = reinterpret_cast<double*>(info + kConstInfo);
+#pragma unroll
+    for (int q = 0; q < kMaxDiag; ++q) {
+        if (q >= nu) break;   // uniform
+        int at = -1;
+#pragma unroll
+        for (int j = 0; j < kMaxDiag; ++j)
+            if (off[j] == u[q]) at = j;
+        const double v = at < 0 ? 0.0
+                                : (f64 ? static_cast<const double*>(val)[b + at]
+                                       : (double)static_cast<const float*>(val)[b + at]);
+        const uint64_t has = __ballot(at >= 0);
+        const int first = __ffsll((unsigned long long)has) - 1;   // at least one lane: u[q] came from a sample
+        const double c = __shfl(v, first, 64);
+        if (t == 0) cval[q] = c;
+    }
     // row_ptr at the boundaries of eight equal row bands (balance of the
     // entries over the XCD bands)
     if (t <= kXcds) info[kBandInfo + t] = row_ptr[(int)((long long)t * n / kXcds)];
 }
 
 // Diagonal storage for the offsets of info (ascending): dia[r*nd + q] =
-// A[r, r + off[q]] or 0; info[kDiaFlag] = 1 when a stored entry lies on none
-// of them (or there are no candidates).
+// A[r, r + off[q]] or 0, pres[r] bit q set when row r stores diagonal q;
+// info[kDiaFlag] = 1 when a stored entry lies on none of them (or there are
+// no candidates), info[kConstFlag] = 1 when some entry differs from its
+// diagonal's candidate constant.
 constexpr int kDiaFlag = 12;
 
 template <typename T>
 __global__ __launch_bounds__(kThreads) void dia_build_kernel(int n, const int* __restrict__ row_ptr,
                                                              const int* __restrict__ col_idx,
                                                              const T* __restrict__ val, T* __restrict__ dia,
-                                                             int* __restrict__ info) {
+                                                             uint16_t* __restrict__ pres, int* __restrict__ info) {
     // each thread places its row's entries in registers; the workgroup's rows
     // are one contiguous run of the storage, written through LDS with
     // consecutive threads on consecutive elements
@@ -1761,10 +1794,15 @@ __global__ __launch_bounds__(kThreads) void dia_build_kernel(int n, const int* _
         int off[kMaxDiag];
 #pragma unroll
         for (int q = 0; q < kMaxDiag; ++q) off[q] = info[1 + q];
-        T v[kMaxDiag];
+        T v[kMaxDiag], cv[kMaxDiag];
+        const double* const cinfo = reinterpret_cast<const double*>(info + kConstInfo);
 #pragma unroll
-        for (int q = 0; q < kMaxDiag; ++q) v[q] = T(0);
-        bool bad = false;
+        for (int q = 0; q < kMaxDiag; ++q) {
+            v[q] = T(0);
+            cv[q] = q < nd ? (T)cinfo[q] : T(0);
+        }
+        bool bad = false, varies = false;
+        unsigned bits = 0;
         for (int k = row_ptr[r]; k < row_ptr[r + 1]; ++k) {
             const int o = col_idx[k] - r;
             const T x = val[k];
@@ -1774,10 +1812,14 @@ __global__ __launch_bounds__(kThreads) void dia_build_kernel(int n, const int* _
                 if (q < nd && off[q] == o) {
                     v[q] = x;
                     hit = true;
+                    bits |= 1u << q;
+                    varies |= !(x == cv[q]);
                 }
             bad |= !hit;
         }
         if (bad) info[kDiaFlag] = 1;
+        if (varies) info[kConstFlag] = 1;
+        pres[r] = (uint16_t)bits;
 #pragma unroll
         for (int q = 0; q < kMaxDiag; ++q)
             if (q < nd) sv[threadIdx.x * nd + q] = v[q];
@@ -1787,21 +1829,21 @@ __global__ __launch_bounds__(kThreads) void dia_build_kernel(int n, const int* _
     for (int e = threadIdx.x; e < nr * nd; e += kThreads) out[e] = sv[e];
 }
 
-hipError_t launch_rows_probe(const CsrDev& A, int* info, hipStream_t st) {
+hipError_t launch_rows_probe(bool f64, const CsrDev& A, int* info, hipStream_t st) {
     if (A.n == 0) return hipSuccess;
-    hipLaunchKernelGGL(dia_probe_kernel, dim3(1), dim3(64), 0, st, A.n, A.row_ptr, A.col_idx, info);
+    hipLaunchKernelGGL(dia_probe_kernel, dim3(1), dim3(64), 0, st, A.n, A.row_ptr, A.col_idx, A.val, (int)f64, info);
     return hipGetLastError();
 }
 
-hipError_t launch_dia_build(bool f64, const CsrDev& A, void* dia, int* info, hipStream_t st) {
+hipError_t launch_dia_build(bool f64, const CsrDev& A, void* dia, uint16_t* pres, int* info, hipStream_t st) {
     if (A.n == 0) return hipSuccess;
     const int nb = div_up(A.n, kThreads);
     if (f64)
         hipLaunchKernelGGL(dia_build_kernel<double>, dim3(nb), dim3(kThreads), 0, st, A.n, A.row_ptr, A.col_idx,
-                           (const double*)A.val, (double*)dia, info);
+                           (const double*)A.val, (double*)dia, pres, info);
     else
         hipLaunchKernelGGL(dia_build_kernel<float>, dim3(nb), dim3(kThreads), 0, st, A.n, A.row_ptr, A.col_idx,
-                           (const float*)A.val, (float*)dia, info);
+                           (const float*)A.val, (float*)dia, pres, info);
     return hipGetLastError();
 }
 

@@ -326,9 +326,17 @@ def test_estimate_full_size_workloads(name, tol32):
 def test_diagonal_storage_matches_csr_bitwise(dtype):
     # Stencil and banded matrices are gathered from the diagonal storage, with
     # the offsets in column order: the same products summed in the same order
-    # as the CSR path, hence bit-identical results.
-    for csr, lo, hi in ((w.grid_laplacian_2d(96, 0.3), 0.3, 8.3), (w.grid_laplacian_3d(20, 0.2), 0.2, 12.2),
-                        (w.pentadiagonal(5000, 1), None, None)):
+    # as the CSR path, hence bit-identical results.  Constant-coefficient
+    # stencils keep one value per diagonal (presence bits per row); a grid
+    # with one diagonal entry changed and the random pentadiagonal matrix
+    # keep the stored values.
+    g2 = w.grid_laplacian_2d(96, 0.3)
+    bumped = np.array(g2[2], dtype=np.float64, copy=True)
+    r_b = 4321
+    bumped[g2[0][r_b] + list(g2[1][g2[0][r_b]:g2[0][r_b + 1]]).index(r_b)] += 0.5
+    for csr, lo, hi, const in ((g2, 0.3, 8.3, 1), (w.grid_laplacian_3d(20, 0.2), 0.2, 12.2, 1),
+                               ((g2[0], g2[1], bumped, g2[3]), 0.3, 8.8, 0),
+                               (w.pentadiagonal(5000, 1), None, None, 0)):
         A, vals = to_gpu(csr, dtype)
         if lo is None:
             lo, hi = bounds.gershgorin((csr[0], csr[1], vals, csr[3]))
@@ -336,7 +344,8 @@ def test_diagonal_storage_matches_csr_bitwise(dtype):
         est_c, st_c = ld.logdet(A, lo, hi, 30, 24, 5, options=ld.Options(csr_only=1), return_stats=True)
         rows = np.repeat(np.arange(csr[3]), np.diff(csr[0]))
         assert st_d["dia_diagonals"] == len(np.unique(np.asarray(csr[1]) - rows))
-        assert st_c["dia_diagonals"] == 0
+        assert st_d["dia_constant"] == const
+        assert st_c["dia_diagonals"] == 0 and st_c["dia_constant"] == 0
         assert est_d == est_c
         V = torch.tensor(np.random.default_rng(3).standard_normal((csr[3], 6)), dtype=dtype, device=DEV)
         assert torch.equal(ld.apply_log(A, lo, hi, 25, V), ld.apply_log(A, lo, hi, 25, V, ld.Options(csr_only=1)))
