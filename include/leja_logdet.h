@@ -97,19 +97,21 @@ typedef struct {
     int32_t csr_only;        /* nonzero: never use the diagonal storage (the
                                 library otherwise builds it, once per call, when
                                 every entry lies on one of at most 9 diagonals,
-                                and gathers from it instead of the CSR arrays;
-                                same sums in the same order)                    */
+                                and gathers from it instead of the CSR arrays,
+                                keeping one value per diagonal when each
+                                diagonal's entries are all equal; same sums in
+                                the same order)                                 */
     int32_t tile_order;      /* LD_TILES_AUTO / LD_TILES_XCD_BANDS /
                                 LD_TILES_INTERLEAVED: how the workgroups of a
                                 Newton-step launch walk the row tiles (auto:
-                                XCD bands when the launch's working set fits
-                                the 256 MB Infinity Cache, else interleaved);
-                                the sums' grouping, hence the last bits of the
-                                quadratic forms, depend on it                 */
+                                XCD bands, unless some eighth of the rows holds
+                                more than 1.25x its share of the entries, then
+                                interleaved); the sums' grouping, hence the
+                                last bits of the quadratic forms, depend on it */
     int32_t probe_dist;      /* LD_PROBE_RADEMACHER (default) / LD_PROBE_GAUSSIAN:
                                 the distribution of the probe entries of S and
-                                G (Alg. 3 step 2 allows either); see
-                                ld_logdet_estimate for the generator          */
+                                G (Alg. 3 step 2 allows either); ld_logdet_estimate
+                                gives the generator                           */
 } ld_options;
 
 typedef struct {
@@ -227,7 +229,11 @@ int ld_apply_log_adaptive(const ld_csr* A, double lmin, double lmax, int32_t max
 
 /* Léja + Hutch++ estimate of log det A (Alg. 3) with n_matvec queries:
  * k = floor(n_matvec/3) sketch columns (probe stream 0), k_G = n_matvec - 2k
- * residual probes (stream 1), degree = number of recurrence steps m.
+ * residual probes (stream 1), degree = number of recurrence steps m.  Probe
+ * entry (row, col) of a stream comes from SplitMix64 output x = number
+ * (col*n + row + 1) of the stream (see ld_rademacher_host): Rademacher: the
+ * sign of x's top bit; Gaussian (opts->probe_dist): sqrt(-2 ln u1) cos(2 pi u2)
+ * in FP64 with u1, u2 = (high, low 32 bits of x + 1/2) / 2^32.
  * out_logdet: host double.  stats: host, may be NULL.
  * Errors: LD_EINVAL (0 < lmin < lmax, degree >= 1, n_matvec >= 3, k <= n),
  * LD_ECSR, LD_EBREAKDOWN, LD_EWORKSPACE, LD_EHIP. */
