@@ -438,3 +438,23 @@ def test_gaussian_probes_against_oracle(dtype, tol):
             assert rel(est, hutchpp.logdet_estimate(w.to_scipy(csr_v), lo, hi, 30, m_vec, 7)) > 1e-8
     with pytest.raises(ld.NativeError):
         ld.logdet(A, lo, hi, 30, 24, 4, options=ld.Options(probe_dist=2))
+
+
+@pytest.mark.parametrize("dtype,tol", [(torch.float64, 1e-10), (torch.float32, 2e-5)])
+def test_estimate_parts_against_oracle(dtype, tol):
+    # The two traces of Alg. 3 (steps 5 and 6) separately, so that errors in
+    # the sketch basis and in the deflated residual cannot cancel in the sum;
+    # both quadratic-form modes.
+    for csr in (w.grid_laplacian_2d(70, 0.4), random_spd_csr(12000, 7, long_rows=2)):
+        A, vals = to_gpu(csr, dtype)
+        csr_v = (csr[0], csr[1], vals, csr[3])
+        lo, hi = bounds.gershgorin(csr_v)
+        lo = max(lo, 0.4)
+        ref = hutchpp.logdet_estimate(w.to_scipy(csr_v), lo, hi, 36, 30, 11, return_parts=True)
+        scale = abs(ref["logdet"])
+        for mode in (ld.LD_DOT_FORWARD, ld.LD_DOT_SQUARED):
+            est, st = ld.logdet(A, lo, hi, 36, 30, 11, options=ld.Options(dot_mode=mode), return_stats=True)
+            assert st["dot_mode_used"] == mode
+            assert abs(st["t_low"] - ref["t_low"]) < tol * scale, (mode, st["t_low"], ref["t_low"])
+            assert abs(st["t_res"] - ref["t_res"]) < tol * scale, (mode, st["t_res"], ref["t_res"])
+            assert rel(est, ref["logdet"]) < tol
