@@ -396,6 +396,11 @@ def test_tile_orders_agree_with_oracle(dtype, tol):
             assert rel(est, ref) < tol, (order, est, ref)
             outs.append(ld.apply_log(A, lo, hi, 25, V, o))
         assert torch.equal(outs[0], outs[1])
+        # the gradient call: per-row recurrence work and cross products that
+        # do not depend on the tile order, hence bit-identical
+        e1, g1 = ld.logdet_with_grad(A, lo, hi, 12, 9, 2, options=ld.Options(tile_order=1))
+        e2, g2 = ld.logdet_with_grad(A, lo, hi, 12, 9, 2, options=ld.Options(tile_order=2))
+        assert e1 == e2 and torch.equal(g1, g2)
     with pytest.raises(ld.NativeError):
         ld.logdet(A, lo, hi, 30, 24, 4, options=ld.Options(tile_order=3))
 
