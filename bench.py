@@ -246,7 +246,7 @@ def main():
         return
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
-        print("bench.py: this build runs on exactly one GPU; --gpus must be 1 "
+        print("bench.py: runs on exactly one GPU; --gpus must be 1 "
               "(sharding across GPUs is not implemented)", file=sys.stderr)
         sys.exit(2)
 
