@@ -5,6 +5,8 @@
 #include <algorithm>
 #include <chrono>
 #include <cmath>
+#include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <string>
 #include <vector>
@@ -979,37 +981,53 @@ int run_logdet(const ld_csr* A, double lmin, double lmax, int degree, int n_matv
     tot.add(t_res);
     *out_logdet = tot.value();
     LD_CHECK_HIP(hipStreamSynchronize(st));
-    if (stats) {
-        std::memset(stats, 0, sizeof(*stats));
-        stats->ms_phase1 = tm.ms(0, 1);
-        stats->ms_qr = tm.ms(1, 2);
-        stats->ms_phase23 = tm.ms(2, 3);
-        stats->ms_adjoint = want_grad ? tm.ms(3, 4) : 0.0;
-        stats->bytes_alg = S.bytes_alg;
-        stats->taylor_terms = S.plan.taylor_terms;
-        stats->sigma = S.plan.sigma;
-        stats->lo = S.plan.lo;
-        stats->hi = S.plan.hi;
-        stats->k = L.k;
-        stats->k_G = L.kg;
-        stats->dot_mode_used = want_grad ? LD_DOT_FORWARD : S.mode;
-        stats->dia_diagonals = S.longrows.dia_nd;
-        stats->dia_constant = S.longrows.dia_pres != nullptr;
-        stats->tile_order_used = S.longrows.tile_order == LD_TILES_INTERLEAVED ||
+    // statistics: to the caller, and one line on stderr when LD_PROFILE is set
+    const char* prof = std::getenv("LD_PROFILE");
+    const bool print = prof && prof[0] && std::strcmp(prof, "0") != 0;
+    if (stats || print) {
+        ld_stats local;
+        ld_stats* const out = stats ? stats : &local;
+        std::memset(out, 0, sizeof(*out));
+        out->ms_phase1 = tm.ms(0, 1);
+        out->ms_qr = tm.ms(1, 2);
+        out->ms_phase23 = tm.ms(2, 3);
+        out->ms_adjoint = want_grad ? tm.ms(3, 4) : 0.0;
+        out->bytes_alg = S.bytes_alg;
+        out->taylor_terms = S.plan.taylor_terms;
+        out->sigma = S.plan.sigma;
+        out->lo = S.plan.lo;
+        out->hi = S.plan.hi;
+        out->k = L.k;
+        out->k_G = L.kg;
+        out->dot_mode_used = want_grad ? LD_DOT_FORWARD : S.mode;
+        out->dia_diagonals = S.longrows.dia_nd;
+        out->dia_constant = S.longrows.dia_pres != nullptr;
+        out->tile_order_used = S.longrows.tile_order == LD_TILES_INTERLEAVED ||
                                          (S.longrows.tile_order == LD_TILES_AUTO && S.longrows.skewed)
                                      ? LD_TILES_INTERLEAVED
                                      : LD_TILES_XCD_BANDS;
-        stats->spmm_launches = S.spmm_launches;
-        stats->t_low = t_low;
-        stats->t_res = t_res;
-        stats->ms_steps1 = elapsed(S, 0, 1);
-        stats->ms_steps23 = elapsed(S, 2, 3);
-        stats->launches1 = S.launches1;
-        stats->launches23 = S.launches23;
-        stats->bytes1 = S.bytes1;
-        stats->bytes23 = S.bytes23;
-        stats->ms_total =
+        out->spmm_launches = S.spmm_launches;
+        out->t_low = t_low;
+        out->t_res = t_res;
+        out->ms_steps1 = elapsed(S, 0, 1);
+        out->ms_steps23 = elapsed(S, 2, 3);
+        out->launches1 = S.launches1;
+        out->launches23 = S.launches23;
+        out->bytes1 = S.bytes1;
+        out->bytes23 = S.bytes23;
+        out->ms_total =
             std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+        if (print)
+            std::fprintf(stderr,
+                         "ld_profile: %s n=%lld degree=%d m_vec=%d | sketch %.3f ms, CholQR+deflation %.3f ms, "
+                         "quadratic forms %.3f ms, gradient %.3f ms, call %.3f ms | steps %d+%d, %.1f GB/s "
+                         "(algorithmic) | storage %s%s, tiles %s\n",
+                         want_grad ? "estimate+gradient" : "estimate", (long long)A->n, degree, n_matvec,
+                         out->ms_phase1, out->ms_qr, out->ms_phase23, out->ms_adjoint, out->ms_total,
+                         out->launches1, out->launches23,
+                         (out->bytes1 + out->bytes23) / ((out->ms_steps1 + out->ms_steps23) * 1e-3 + 1e-30) / 1e9,
+                         out->dia_diagonals ? "diagonal" : "csr", out->dia_constant ? " (constant values)" : "",
+                         out->tile_order_used == LD_TILES_INTERLEAVED ? "interleaved" : "xcd-bands");
     }
     return LD_OK;
 }

@@ -463,3 +463,20 @@ def test_estimate_parts_against_oracle(dtype, tol):
             assert abs(st["t_low"] - ref["t_low"]) < tol * scale, (mode, st["t_low"], ref["t_low"])
             assert abs(st["t_res"] - ref["t_res"]) < tol * scale, (mode, st["t_res"], ref["t_res"])
             assert rel(est, ref["logdet"]) < tol
+
+
+def test_profile_line_on_request(capfd, monkeypatch):
+    # LD_PROFILE=1: one phase-breakdown line per estimate on stderr; the
+    # estimate itself is unchanged
+    csr = w.grid_laplacian_2d(40, 0.5)
+    A, _ = to_gpu(csr, torch.float32)
+    quiet = ld.logdet(A, 0.5, 8.5, 20, 12, 1)
+    capfd.readouterr()
+    monkeypatch.setenv("LD_PROFILE", "1")
+    loud = ld.logdet(A, 0.5, 8.5, 20, 12, 1)
+    err = capfd.readouterr().err
+    assert "ld_profile: estimate n=1600 degree=20 m_vec=12" in err and "storage diagonal" in err
+    assert loud == quiet
+    monkeypatch.setenv("LD_PROFILE", "0")
+    ld.logdet(A, 0.5, 8.5, 20, 12, 1)
+    assert "ld_profile" not in capfd.readouterr().err
