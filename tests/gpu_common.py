@@ -37,3 +37,31 @@ def random_spd_csr(n, seed, density=0.02, long_rows=0, shift=0.5):
     Q = (S + sp.diags(radius + shift + rng.uniform(0, 1, n))).tocsr()
     Q.sort_indices()
     return (Q.indptr.astype(np.int32), Q.indices.astype(np.int32), Q.data.astype(np.float64), n)
+
+
+def nine_point_grid(N, seed):
+    """Seeded SPD 9-point stencil on an N x N grid (row-major points).
+
+    Random symmetric weights on the eight neighbours (varying values, so the
+    diagonal storage keeps them), diagonal = sum of the row's |weights| + 0.5.
+    """
+    import scipy.sparse as sp
+
+    rng = np.random.default_rng(seed)
+    n = N * N
+    idx = np.arange(n)
+    i, j = idx // N, idx % N
+    rows, cols, vals = [], [], []
+    for di, dj in ((0, 1), (1, -1), (1, 0), (1, 1)):   # one of each mirrored pair
+        ii, jj = i + di, j + dj
+        ok = (ii >= 0) & (ii < N) & (jj >= 0) & (jj < N)
+        wgt = -rng.uniform(0.2, 1.0, int(ok.sum()))
+        rows += [idx[ok], (ii * N + jj)[ok]]
+        cols += [(ii * N + jj)[ok], idx[ok]]
+        vals += [wgt, wgt]
+    B = sp.coo_matrix((np.concatenate(vals), (np.concatenate(rows), np.concatenate(cols))), shape=(n, n)).tocsr()
+    radius = np.asarray(abs(B).sum(axis=1)).ravel()
+    Q = (B + sp.diags(radius + 0.5)).tocsr()
+    Q.sort_indices()
+    return (Q.indptr.astype(np.int32), Q.indices.astype(np.int32), Q.data.astype(np.float64), n)
+

@@ -10,7 +10,7 @@ import pytest
 
 import workloads as w
 from oracle import bounds, exact, hutchpp, newton
-from tests.gpu_common import golden, random_spd_csr
+from tests.gpu_common import golden, nine_point_grid, random_spd_csr
 
 pytestmark = pytest.mark.gpu
 
@@ -329,14 +329,15 @@ def test_diagonal_storage_matches_csr_bitwise(dtype):
     # as the CSR path, hence bit-identical results.  Constant-coefficient
     # stencils keep one value per diagonal (presence bits per row); a grid
     # with one diagonal entry changed and the random pentadiagonal matrix
-    # keep the stored values.
+    # keep the stored values, as does a 9-point stencil with random weights
+    # (nine diagonals: the widest gather of the diagonal storage).
     g2 = w.grid_laplacian_2d(96, 0.3)
     bumped = np.array(g2[2], dtype=np.float64, copy=True)
     r_b = 4321
     bumped[g2[0][r_b] + list(g2[1][g2[0][r_b]:g2[0][r_b + 1]]).index(r_b)] += 0.5
     for csr, lo, hi, const in ((g2, 0.3, 8.3, 1), (w.grid_laplacian_3d(20, 0.2), 0.2, 12.2, 1),
                                ((g2[0], g2[1], bumped, g2[3]), 0.3, 8.8, 0),
-                               (w.pentadiagonal(5000, 1), None, None, 0)):
+                               (w.pentadiagonal(5000, 1), None, None, 0), (nine_point_grid(61, 4), None, None, 0)):
         A, vals = to_gpu(csr, dtype)
         if lo is None:
             lo, hi = bounds.gershgorin((csr[0], csr[1], vals, csr[3]))
@@ -352,6 +353,24 @@ def test_diagonal_storage_matches_csr_bitwise(dtype):
         e1, g1 = ld.logdet_with_grad(A, lo, hi, 12, 9, 2)
         e2, g2 = ld.logdet_with_grad(A, lo, hi, 12, 9, 2, options=ld.Options(csr_only=1))
         assert e1 == e2 and torch.equal(g1, g2)
+
+
+@pytest.mark.parametrize("dtype,tol", [(torch.float64, 1e-10), (torch.float32, 2e-5)])
+def test_nine_point_stencil_against_oracle(dtype, tol):
+    # nine diagonals with varying values (the widest diagonal-storage gather),
+    # a grid ragged against the row tiles; estimate and Horner apply
+    csr = nine_point_grid(45, 7)
+    A, vals = to_gpu(csr, dtype)
+    csr_v = (csr[0], csr[1], vals, csr[3])
+    lo, hi = bounds.gershgorin(csr_v)
+    est, st = ld.logdet(A, lo, hi, 30, 24, 2, return_stats=True)
+    assert st["dia_diagonals"] == 9 and st["dia_constant"] == 0
+    Q = w.to_scipy(csr_v)
+    assert rel(est, hutchpp.logdet_estimate(Q, lo, hi, 30, 24, 2)) < tol
+    V = np.random.default_rng(5).standard_normal((csr[3], 5))
+    out = ld.apply_log(A, lo, hi, 25, torch.tensor(V, dtype=dtype, device=DEV)).double().cpu().numpy()
+    ref = newton.apply_log(Q, torch.tensor(V, dtype=dtype).double().numpy(), lo, hi, 25)
+    assert np.linalg.norm(out - ref) / np.linalg.norm(ref) < tol
 
 
 def test_diagonal_storage_falls_back_to_csr():
