@@ -31,7 +31,8 @@ def to_gpu(csr, dtype):
     return ld.CSR.from_arrays(row_ptr, col_idx, vals, n, device=DEV, dtype=dtype), vals.astype(np.float64)
 
 
-@pytest.mark.parametrize("m_vec,degree,stride", [(12, 20, 0), (30, 40, 1), (30, 40, 7), (9, 13, 5)])
+@pytest.mark.parametrize("m_vec,degree,stride", [(12, 20, 0), (30, 40, 1), (30, 40, 7), (9, 13, 5), (4, 11, 0),
+                                                 (100, 16, 3)])
 def test_grad_small_grid_fp64(m_vec, degree, stride):
     csr = w.grid_laplacian_2d(9, 0.5)
     A, vals = to_gpu(csr, torch.float64)

@@ -169,6 +169,27 @@ def test_estimate_power_law_hub_rows(dtype, tol, permute):
     assert np.linalg.norm(out - refv) / np.linalg.norm(refv) < (1e-10 if dtype == torch.float64 else 1e-5)
 
 
+@pytest.mark.parametrize("m_vec", [3, 4, 5, 32, 100, 192])
+def test_estimate_query_counts(m_vec):
+    # k = floor(m_vec/3) sketch columns and k_G = m_vec - 2k residual probes:
+    # the fewest queries, counts not divisible by three, and the widest
+    # sketch allowed (k = k_G = 64: the MFMA cross products, quadratic forms
+    # in two column blocks).  FP64 against the oracle; FP32 against the oracle
+    # run on the FP32-rounded values.
+    csr = random_spd_csr(2500, 11, long_rows=1)
+    for dtype, tol in ((torch.float64, 1e-10), (torch.float32, 2e-5)):
+        A, vals = to_gpu(csr, dtype)
+        csr_v = (csr[0], csr[1], vals, csr[3])
+        lo, hi = bounds.gershgorin(csr_v)
+        lo = max(lo, 0.2)
+        est, st = ld.logdet(A, lo, hi, 30, m_vec, 4, return_stats=True)
+        assert st["k"] == m_vec // 3 and st["k_G"] == m_vec - 2 * (m_vec // 3)
+        ref = hutchpp.logdet_estimate(w.to_scipy(csr_v), lo, hi, 30, m_vec, 4)
+        assert rel(est, ref) < tol, (dtype, est, ref)
+    with pytest.raises(ld.NativeError):   # k_G = 66 > 64
+        ld.logdet(A, lo, hi, 30, 194, 4)
+
+
 def test_estimate_small_and_sigma_one():
     # lmin >= 1 (sigma = 1), tiny n with k close to n
     csr = w.grid_laplacian_2d(4, 3.0)
