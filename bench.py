@@ -207,8 +207,19 @@ def cpu_baseline(csr, lmin, lmax, degree, m_vec, seed):
 
 KERNEL_SOURCES = ("paper_2603_02207_amd/csrc/kernels.hip", "paper_2603_02207_amd/csrc/api.hip")
 TRAFFIC_PROFILE = "profiles/step_kernel_grid1024_traffic.md"
-# step kernel template kinds: 0 sketch (Horner with probe signs), 3 / 2 quadratic forms
-KIND_OF = {"sketch_horner": (", 0, false",), "quadform": (", 3, false", ", 2, false")}
+# the step kernels of the two phases, as rocprofv3 names them: template kind 0
+# sketch (Horner with probe signs), 3 / 2 quadratic forms
+KERNEL_PREFIXES = {
+    ("sketch_horner", "step_kernel"): ("step_kernel<float, 4, 0, false",),
+    ("sketch_horner", "dia_flat_kernel"): ("dia_flat_kernel<float, 4, 0,",),
+    ("quadform", "step_kernel"): ("step_kernel<float, 4, 3, false", "step_kernel<float, 4, 2, false"),
+}
+
+
+def step_kernel_name(tag: str, st) -> str:
+    """Kernel of a phase's Newton steps: on diagonal storage the sketch's
+    steps (no column sums) take the one-chunk-per-thread kernel."""
+    return "dia_flat_kernel" if tag == "sketch_horner" and st.get("dia_diagonals") else "step_kernel"
 
 
 def kernel_hash() -> str:
@@ -221,7 +232,7 @@ def kernel_hash() -> str:
     return h.hexdigest()[:16]
 
 
-def measured_traffic(tag: str, workload: str):
+def measured_traffic(tag: str, workload: str, kernel: str):
     """Counter-measured bytes per launch of a step kernel, if taken on the current kernels."""
     path = os.path.join(ROOT, TRAFFIC_PROFILE)
     if workload != "grid1024_k0.1" or not os.path.exists(path):
@@ -234,7 +245,7 @@ def measured_traffic(tag: str, workload: str):
     if blob.get("kernel_hash") != kernel_hash():
         return None   # the kernels changed since the counters were taken
     for name, mb in blob.get("traffic_MB_per_launch", {}).items():
-        if "<float" in name and any(k in name for k in KIND_OF[tag]):
+        if any(name.startswith(p) for p in KERNEL_PREFIXES.get((tag, kernel), ())):
             return mb * 1e6
     return None
 
@@ -308,11 +319,13 @@ def run_workload(args, workload, steps):
                             ("quadform", st["ms_steps23"], st["launches23"], st["bytes23"])):
         if nl:
             avg_s = ms / 1e3 / nl
-            kernels[tag] = {"launches": nl, "avg_us": avg_s * 1e6, "bytes_per_launch": by / nl,
+            kernels[tag] = {"kernel": step_kernel_name(tag, st), "launches": nl, "avg_us": avg_s * 1e6,
+                            "bytes_per_launch": by / nl,
                             "GBps": by / nl / avg_s / 1e9, "total_ms": ms}
     dom = max(kernels, key=lambda k: kernels[k]["total_ms"])
     achieved = kernels[dom]["GBps"]
-    traffic = measured_traffic(dom, args.workload) if args.block_cols == 0 and args.dot_mode == "auto" else None
+    traffic = (measured_traffic(dom, args.workload, kernels[dom]["kernel"])
+               if args.block_cols == 0 and args.dot_mode == "auto" else None)
     total_bytes = st["bytes1"] + st["bytes23"]
     total_ms = st["ms_steps1"] + st["ms_steps23"]
 
@@ -349,7 +362,7 @@ def run_workload(args, workload, steps):
         },
         "roofline": {
             "bound": "hbm",
-            "kernel": f"step_kernel ({dom})",
+            "kernel": f"{kernels[dom]['kernel']} ({dom})",
             "achieved": achieved,
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
