@@ -551,7 +551,7 @@ __global__ __launch_bounds__(256) void long_row_kernel(
 // i = row*lpr + q over the whole block, so a wave's accesses are 64
 // consecutive chunks (no idle lanes, one contiguous 1 KB run per load) and a
 // workgroup is a single pass with no tile loop.  Measured on gfx950 at the
-// 1024^2 bench shape (20 FP32 columns, constant diagonals): 27.8 us per step
+// 1024^2 bench shape (20 FP32 columns, constant diagonals): 28.5 us per step
 // against 31.5 us for the row-group mapping of step_kernel, whose waves leave
 // 64 mod lpr lanes idle.  The rows r +- 1 share cache lines with r and cost no
 // extra traffic.  Per row the arithmetic and the order of the sums are those
