@@ -25,8 +25,9 @@
  *   - Work is ordered on the caller's HIP stream (`stream`, a hipStream_t
  *     passed as void*; NULL = the default stream).  Calls that return host
  *     scalars synchronise that stream before returning.
- *   - Scratch memory comes from the caller's workspace (ld_workspace_size);
- *     with workspace == NULL the library allocates and frees it itself.
+ *   - Scratch memory comes from the caller's workspace (ld_workspace_size),
+ *     which must be 256-byte aligned (LD_EINVAL otherwise); with
+ *     workspace == NULL the library allocates and frees it itself.
  *   - The matrix must be symmetric positive definite with sorted column
  *     indices in each row (CSR, int32 indices).  Symmetry is assumed, not
  *     checked; the CSR structure is checked unless opts->trusted_csr != 0.
@@ -145,7 +146,9 @@ typedef struct {
 /* Defaults for ld_options (all zero except as documented). */
 void ld_default_options(ld_options* opts);
 
-/* Library version string. */
+/* Library version string: "leja_logdet <version> (gfx950) src=<hash>", the hash
+ * being the first 16 hex digits of SHA-256 over the source files the library
+ * was built from (the build script computes it). */
 const char* ld_version(void);
 
 /* Name of an error code. */
@@ -235,7 +238,10 @@ int ld_apply_log_adaptive(const ld_csr* A, double lmin, double lmax, int32_t max
  * sign of x's top bit; Gaussian (opts->probe_dist): sqrt(-2 ln u1) cos(2 pi u2)
  * in FP64 with u1, u2 = (high, low 32 bits of x + 1/2) / 2^32.
  * out_logdet: host double.  stats: host, may be NULL.
- * Errors: LD_EINVAL (0 < lmin < lmax, degree >= 1, n_matvec >= 3, k <= n),
+ * Limits: 3 <= n_matvec <= 192, i.e. k, k_G <= 64 (the k x k Gram matrices
+ * of CholQR are factored by one workgroup on the device, and the quadratic
+ * forms take at most 64 columns per launch); k <= n.
+ * Errors: LD_EINVAL (0 < lmin < lmax, degree >= 1, the limits above),
  * LD_ECSR, LD_EBREAKDOWN, LD_EWORKSPACE, LD_EHIP. */
 int ld_logdet_estimate(const ld_csr* A, double lmin, double lmax, int32_t degree,
                        int32_t n_matvec, uint64_t seed, const ld_options* opts,

@@ -7,9 +7,18 @@ from __future__ import annotations
 
 import ctypes
 import os
+import re
+
+from .build import source_hash  # noqa: F401  (hash of the sources the library is built from)
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libleja_logdet.so")
+
+
+def built_source_hash() -> str:
+    """The source hash compiled into the loaded library (ld_version)."""
+    m = re.search(r"src=([0-9a-f]+|unknown)", load().ld_version().decode())
+    return m.group(1) if m else "unknown"
 
 LD_OK = 0
 LD_EINVAL = -1

@@ -5,6 +5,7 @@ The shared object is written next to this file, so it travels with the tree.
 """
 from __future__ import annotations
 
+import hashlib
 import os
 import shutil
 import subprocess
@@ -27,6 +28,27 @@ HIPCC_FLAGS = [
 ]
 
 
+def source_files():
+    """The files the library is built from: csrc/* and include/*.h (sorted relative paths)."""
+    out = []
+    for sub, keep in ((os.path.join("paper_2603_02207_amd", "csrc"), lambda f: True),
+                      ("include", lambda f: f.endswith(".h"))):
+        d = os.path.join(ROOT, sub)
+        out += [os.path.join(sub, f) for f in os.listdir(d) if keep(f) and os.path.isfile(os.path.join(d, f))]
+    return sorted(out)
+
+
+def source_hash() -> str:
+    """First 16 hex digits of SHA-256 over (path, contents) of every source file."""
+    h = hashlib.sha256()
+    for rel in source_files():
+        h.update(rel.replace(os.sep, "/").encode() + b"\0")
+        with open(os.path.join(ROOT, rel), "rb") as f:
+            h.update(f.read())
+        h.update(b"\0")
+    return h.hexdigest()[:16]
+
+
 def hipcc() -> str:
     for cand in (os.environ.get("HIPCC"), shutil.which("hipcc"), "/opt/rocm/bin/hipcc"):
         if cand and os.path.exists(cand):
@@ -35,24 +57,27 @@ def hipcc() -> str:
 
 
 def build(verbose: bool = False) -> str:
-    objs = []
+    # the library reports the hash of the sources it was built from (ld_version)
+    ident = ["-DLD_SOURCE_HASH=\"" + source_hash() + "\""]
     build_dir = os.path.join(HERE, "_build")
     os.makedirs(build_dir, exist_ok=True)
     inc = ["-I", os.path.join(ROOT, "include"), "-I", CSRC]
-    for src in SOURCES:
+    objs, jobs = [], []
+    for src in SOURCES:   # the three translation units compile in parallel
         obj = os.path.join(build_dir, os.path.splitext(src)[0] + ".o")
         lang = ["-x", "hip"] if src.endswith(".hip") else []
-        cmd = [hipcc()] + HIPCC_FLAGS + inc + lang + ["-c", os.path.join(CSRC, src), "-o", obj]
+        cmd = [hipcc()] + HIPCC_FLAGS + ident + inc + lang + ["-c", os.path.join(CSRC, src), "-o", obj]
         if verbose:
             print(" ".join(cmd), flush=True)
-        res = subprocess.run(cmd, capture_output=True, text=True)
-        msgs = "\n".join(l for l in (res.stdout + res.stderr).splitlines()
-                         if "packed-fp32-ops" not in l)
-        if res.returncode != 0:
+        jobs.append((src, subprocess.Popen(cmd, stdout=subprocess.PIPE, stderr=subprocess.STDOUT, text=True)))
+        objs.append(obj)
+    for src, proc in jobs:
+        out, _ = proc.communicate()
+        msgs = "\n".join(l for l in out.splitlines() if "packed-fp32-ops" not in l)
+        if proc.returncode != 0:
             raise RuntimeError(f"hipcc failed on {src}:\n{msgs}")
         if verbose and msgs.strip():
             print(msgs)
-        objs.append(obj)
     tmp = LIB + ".tmp"
     cmd = [hipcc(), "--offload-arch=gfx950", "-shared", "-fPIC", "-o", tmp] + objs
     res = subprocess.run(cmd, capture_output=True, text=True)

@@ -96,6 +96,9 @@ struct OwnedWs {
 
 int get_workspace(void* ws, size_t ws_bytes, size_t need, OwnedWs& own, Arena& ar) {
     if (ws) {
+        // the carved buffers keep the workspace's alignment, and the step
+        // kernels' vector width (hence their grids) assumes 256-byte buffers
+        if ((uintptr_t)ws % kAlign != 0) return fail(LD_EINVAL, "workspace must be 256-byte aligned");
         if (ws_bytes < need)
             return fail(LD_EWORKSPACE, "workspace has " + std::to_string(ws_bytes) + " bytes, needs " +
                                            std::to_string(need));

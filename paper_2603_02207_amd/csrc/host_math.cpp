@@ -3,6 +3,7 @@
 // squared Newton basis, the probe generator, a small Cholesky, and the
 // thread-local error detail.  Everything here is FP64 (or double-double)
 // scalar work done once per call or cached across calls.
+#include <algorithm>
 #include <cmath>
 #include <cstring>
 #include <map>
@@ -81,7 +82,10 @@ std::vector<double> compute_leja(int count) {
 }
 }  // namespace
 
-const std::vector<double>& leja_table(int count) {
+std::vector<double> leja_table(int count) {
+    // The table grows by reassignment; callers get a copy of their prefix,
+    // taken under the lock, so a concurrent call that grows the table never
+    // frees memory another thread is still reading.
     static std::mutex mu;
     static std::vector<double> table;
     std::lock_guard<std::mutex> lock(mu);
@@ -90,7 +94,7 @@ const std::vector<double>& leja_table(int count) {
         while (want < count) want *= 2;
         table = compute_leja(want);
     }
-    return table;
+    return std::vector<double>(table.begin(), table.begin() + std::max(count, 0));
 }
 
 // ---------------------------------------------------------------------------
@@ -102,7 +106,7 @@ const std::vector<double>& leja_table(int count) {
 // ---------------------------------------------------------------------------
 static int alg1(double lo, double hi, int degree, int s_mode, int64_t cap,
                 std::vector<double>& d, int64_t* terms) {
-    const std::vector<double>& xi_all = leja_table(degree + 1);
+    const std::vector<double> xi_all = leja_table(degree + 1);
     const int m1 = degree + 1;
     const double c = 0.5 * (lo + hi);
     const double gamma = 0.25 * (hi - lo);
@@ -313,8 +317,7 @@ int make_plan(double lmin, double lmax, int degree, const ld_options& o, Plan& p
     p.c = 0.5 * (p.lo + p.hi);
     p.gamma = 0.25 * (p.hi - p.lo);
     p.alpha = 1.0 / (p.sigma * p.gamma);
-    const std::vector<double>& t = leja_table(degree + 1);
-    p.xi.assign(t.begin(), t.begin() + degree + 1);
+    p.xi = leja_table(degree + 1);
     int rc = divided_differences(p.lo, p.hi, degree, o.s_val_mode, o.taylor_cap, p.d,
                                  &p.taylor_terms);
     if (rc != LD_OK) return rc;
@@ -330,7 +333,12 @@ int make_plan(double lmin, double lmax, int degree, const ld_options& o, Plan& p
 // ---------------------------------------------------------------------------
 extern "C" {
 
-const char* ld_version(void) { return "leja_logdet 0.1 (gfx950)"; }
+#ifndef LD_SOURCE_HASH
+#define LD_SOURCE_HASH "unknown"
+#endif
+// "src=" carries the hash of the source files the library was built from
+// (computed by the build script), so a run can tell which sources it loaded.
+const char* ld_version(void) { return "leja_logdet 0.2 (gfx950) src=" LD_SOURCE_HASH; }
 
 const char* ld_error_string(int code) {
     switch (code) {
@@ -359,7 +367,7 @@ int ld_leja_points(int32_t count, double* xi_host) {
     ld::clear_error();
     if (count < 0 || (count > 0 && !xi_host)) return ld::fail(LD_EINVAL, "bad count or null");
     if (count == 0) return LD_OK;
-    const std::vector<double>& t = ld::leja_table(count);
+    const std::vector<double> t = ld::leja_table(count);
     std::memcpy(xi_host, t.data(), sizeof(double) * count);
     return LD_OK;
 }
@@ -395,8 +403,7 @@ int ld_squared_basis_coefficients(int32_t degree, const double* d_host, double* 
     ld::clear_error();
     if (degree < 0 || !d_host || !c_host) return ld::fail(LD_EINVAL, "bad arguments");
     std::vector<double> d(d_host, d_host + degree + 1), c;
-    const std::vector<double>& t = ld::leja_table(degree + 1);
-    std::vector<double> xi(t.begin(), t.begin() + degree + 1);
+    const std::vector<double> xi = ld::leja_table(degree + 1);
     ld::squared_basis(xi, d, c);
     std::memcpy(c_host, c.data(), sizeof(double) * (degree + 1));
     return LD_OK;

@@ -15,9 +15,9 @@ int fail(int code, const std::string& detail);   // sets the thread-local detail
 void clear_error();
 
 // ---- host mathematics (host_math.cpp) ---------------------------------------
-// Fast Léja table on [-2, 2], cached and grown on demand; returns the first
-// `count` points.
-const std::vector<double>& leja_table(int count);
+// Fast Léja table on [-2, 2], cached and grown on demand; returns a copy of
+// the first `count` points (safe against concurrent growth of the table).
+std::vector<double> leja_table(int count);
 
 // Alg. 1 divided differences, cached by (lo, hi, degree, s-mode, cap).
 int divided_differences(double lo, double hi, int degree, int s_mode, int64_t cap,

@@ -36,6 +36,12 @@ def test_library_exports_every_declared_symbol():
     assert lib.ld_version().decode().startswith("leja_logdet")
 
 
+def test_library_built_from_these_sources():
+    # ld_version carries the hash of the csrc/ and include/ files the library
+    # was compiled from; it must be the hash of the files in this tree
+    assert nat.built_source_hash() == nat.source_hash()
+
+
 def test_error_strings():
     lib = nat.load()
     for code in range(0, -8, -1):

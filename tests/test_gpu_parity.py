@@ -33,6 +33,13 @@ def rel(a, b):
     return abs(a - b) / abs(b)
 
 
+def test_loaded_library_matches_sources():
+    # the library this GPU run loaded was built from the sources in this tree
+    from paper_2603_02207_amd import _native as nat
+
+    assert nat.built_source_hash() == nat.source_hash(), (nat.built_source_hash(), nat.source_hash())
+
+
 # ---------------------------------------------------------------- apply_log
 
 @pytest.mark.parametrize("dtype,tol", [(torch.float64, 1e-12), (torch.float32, 2e-5)])
@@ -320,6 +327,15 @@ def test_workspace_too_small():
     rc = nat.load().ld_logdet_estimate(ctypes.byref(c), 0.5, 8.5, 10, 9, 0, None, ctypes.c_void_p(ws.data_ptr()),
                                        16, None, ctypes.byref(out), None)
     assert rc == nat.LD_EWORKSPACE
+    # a workspace that is large enough but not 256-byte aligned is refused
+    need = ld.workspace_size(A, 10, 9)
+    big = torch.empty(need + 512, dtype=torch.uint8, device=DEV)
+    rc = nat.load().ld_logdet_estimate(ctypes.byref(c), 0.5, 8.5, 10, 9, 0, None,
+                                       ctypes.c_void_p(big.data_ptr() + 8), need, None, ctypes.byref(out), None)
+    assert rc == nat.LD_EINVAL and b"aligned" in nat.load().ld_last_error_detail()
+    rc = nat.load().ld_logdet_estimate(ctypes.byref(c), 0.5, 8.5, 10, 9, 0, None,
+                                       ctypes.c_void_p(big.data_ptr() + 256), need, None, ctypes.byref(out), None)
+    assert rc == nat.LD_OK
 
 
 # ---------------------------------------------------------------- the other workloads at full size
