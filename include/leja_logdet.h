@@ -248,6 +248,23 @@ int ld_logdet_estimate(const ld_csr* A, double lmin, double lmax, int32_t degree
                        void* workspace, size_t ws_bytes, void* stream, double* out_logdet,
                        ld_stats* stats);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, serving loops, harnesses that forbid hipMalloc): ld_logdet_estimate
+ * with the library's own static scratch instead of a workspace.  The scratch
+ * is a 64 MiB device array of the library, one per GPU, held until the
+ * process ends; an estimate whose workspace (ld_workspace_size with
+ * want_grad = 0) exceeds 64 MiB returns LD_EWORKSPACE.  The call makes no
+ * device allocation and creates no HIP events (so stats carries no kernel
+ * timings: its ms_phase and ms_steps fields are 0).  `stream` must belong to
+ * the current device (LD_EINVAL otherwise).  All calls on one GPU share its
+ * scratch: calls that overlap in time on the same GPU (other host threads,
+ * other streams) race and must be serialised by the caller.  Results are
+ * those of ld_logdet_estimate with the same arguments.
+ * Errors: as ld_logdet_estimate. */
+int ld_logdet_estimate_noalloc(const ld_csr* A, double lmin, double lmax, int32_t degree,
+                               int32_t n_matvec, uint64_t seed, const ld_options* opts, void* stream,
+                               double* out_logdet, ld_stats* stats);
+
 /* As ld_logdet_estimate, and the exact derivative of the returned estimate
  * with respect to each stored value of A (same probes, interval and sigma
  * held fixed; includes the dependence of the sketch basis on A), by a reverse

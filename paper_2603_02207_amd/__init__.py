@@ -8,6 +8,8 @@ Main entry points
 -----------------
 CSR.from_arrays(row_ptr, col_idx, val, n, device)   matrix on the GPU
 logdet(A, lmin, lmax, degree, n_matvec, seed)       Alg. 3 estimate of log det A
+logdet_noalloc(A, lmin, lmax, degree, n_matvec, seed) the same estimate from the library's
+                                                    static scratch (no device allocation)
 logdet_with_grad(...)                               estimate and d/d(values)
 LogdetFunction / logdet_autograd(values, ...)       torch.autograd wrapper
 apply_log(A, lmin, lmax, degree, V)                 P_m(Q~)V + log(sigma)V ~ log(A)V
@@ -26,7 +28,7 @@ from ._native import (LD_DOT_AUTO, LD_DOT_FORWARD, LD_DOT_SQUARED, LD_F32, LD_F6
                       LD_SVAL_CENTER, LD_SVAL_HALF_LMAX, NativeError)
 
 __all__ = [
-    "CSR", "Options", "logdet", "logdet_with_grad", "logdet_autograd", "LogdetFunction",
+    "CSR", "Options", "logdet", "logdet_noalloc", "logdet_with_grad", "logdet_autograd", "LogdetFunction",
     "apply_log", "spectral_bounds", "leja_points", "divided_differences", "rademacher_host",
     "squared_basis_coefficients", "workspace_size", "NativeError", "library_path",
 ]
@@ -156,6 +158,27 @@ def logdet(A: CSR, lmin: float, lmax: float, degree: int, n_matvec: int, seed: i
                                      ctypes.byref(o), ctypes.c_void_p(ws.data_ptr()), ws.numel(),
                                      _stream_handle(A.val.device), ctypes.byref(out),
                                      ctypes.byref(st)), "ld_logdet_estimate")
+    if return_stats:
+        return out.value, st.as_dict()
+    return out.value
+
+
+def logdet_noalloc(A: CSR, lmin: float, lmax: float, degree: int, n_matvec: int, seed: int = 0,
+                   options=None, return_stats: bool = False):
+    """As ``logdet``, from the library's static scratch: no device memory is
+    allocated (the estimate's workspace must fit the 64 MiB scratch)."""
+    torch = _torch()
+    lib = nat.load()
+    c = A.c_struct()
+    o = _opts(options)
+    out = ctypes.c_double(0.0)
+    st = nat.LdStats()
+    with torch.cuda.device(A.val.device):
+        nat.check(lib.ld_logdet_estimate_noalloc(ctypes.byref(c), float(lmin), float(lmax), int(degree),
+                                                 int(n_matvec), ctypes.c_uint64(int(seed) & (2**64 - 1)),
+                                                 ctypes.byref(o), _stream_handle(A.val.device),
+                                                 ctypes.byref(out), ctypes.byref(st)),
+                  "ld_logdet_estimate_noalloc")
     if return_stats:
         return out.value, st.as_dict()
     return out.value

@@ -130,6 +130,10 @@ SIGNATURES = {
                                           ctypes.POINTER(LdOptions), ctypes.c_void_p, ctypes.c_size_t,
                                           ctypes.c_void_p, ctypes.POINTER(ctypes.c_double),
                                           ctypes.POINTER(LdStats)]),
+    "ld_logdet_estimate_noalloc": (ctypes.c_int, [ctypes.POINTER(LdCsr), ctypes.c_double, ctypes.c_double,
+                                                  ctypes.c_int32, ctypes.c_int32, ctypes.c_uint64,
+                                                  ctypes.POINTER(LdOptions), ctypes.c_void_p,
+                                                  ctypes.POINTER(ctypes.c_double), ctypes.POINTER(LdStats)]),
     "ld_logdet_grad": (ctypes.c_int, [ctypes.POINTER(LdCsr), ctypes.c_double, ctypes.c_double,
                                       ctypes.c_int32, ctypes.c_int32, ctypes.c_uint64,
                                       ctypes.POINTER(LdOptions), ctypes.c_void_p, ctypes.c_size_t,

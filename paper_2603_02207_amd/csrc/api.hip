@@ -8,6 +8,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -273,11 +274,12 @@ struct Timer {
     hipEvent_t ev[8];
     int count = 0;
     hipStream_t st;
-    explicit Timer(hipStream_t s) : st(s) {
+    bool on;   // false: no events are created (the entry point that allocates nothing)
+    Timer(hipStream_t s, bool enabled) : st(s), on(enabled) {
         for (auto& e : ev) e = nullptr;
     }
     void mark() {
-        if (count < 8 && hipEventCreate(&ev[count]) == hipSuccess) {
+        if (on && count < 8 && hipEventCreate(&ev[count]) == hipSuccess) {
             (void)hipEventRecord(ev[count], st);
             ++count;
         }
@@ -456,6 +458,7 @@ struct EstimateState {
     int launches1 = 0, launches23 = 0;
     double bytes1 = 0, bytes23 = 0;
     hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};   // step-phase brackets
+    bool timed = true;              // false: no HIP events (ld_logdet_estimate_noalloc)
     LongRows longrows;
     ~EstimateState() {
         for (hipEvent_t e : ev)
@@ -474,6 +477,7 @@ int cholqr_status(const int* h) {
 }
 
 int record(EstimateState& S, int i, hipStream_t st) {
+    if (!S.timed) return LD_OK;
     if (!S.ev[i]) LD_CHECK_HIP(hipEventCreate(&S.ev[i]));
     LD_CHECK_HIP(hipEventRecord(S.ev[i], st));
     return LD_OK;
@@ -920,10 +924,11 @@ int estimate_and_gradient(const ld_csr* A, uint64_t seed, EstimateState& S, Grad
 // Estimate (and, with grad != nullptr, its gradient): the body of both entry points.
 int run_logdet(const ld_csr* A, double lmin, double lmax, int degree, int n_matvec, uint64_t seed,
                const ld_options& o, void* workspace, size_t ws_bytes, hipStream_t st,
-               double* out_logdet, void* grad, ld_stats* stats) {
+               double* out_logdet, void* grad, ld_stats* stats, bool timed = true) {
     const auto t0 = std::chrono::steady_clock::now();
     const bool want_grad = grad != nullptr;
     EstimateState S;
+    S.timed = timed;
     LD_CHECK(make_plan(lmin, lmax, degree, o, S.plan));
     S.L = layout_estimate(A, degree, n_matvec, want_grad, o);
     S.mode = choose_dot_mode(S.plan, o.dot_mode, S.coef);
@@ -951,7 +956,7 @@ int run_logdet(const ld_csr* A, double lmin, double lmax, int degree, int n_matv
         return fail(LD_EINVAL, "internal: workspace layout overflow");
     if (!o.trusted_csr) LD_CHECK(validate_csr(A, S.flag, st));
     LD_CHECK(prepare_rows(A, o, ar, st, S.longrows));
-    Timer tm(st);
+    Timer tm(st, timed);
     tm.mark();
     LD_CHECK(estimate_front(A, seed, S, st, tm));
     const EstLayout& L = S.L;
@@ -1039,6 +1044,41 @@ int run_logdet(const ld_csr* A, double lmin, double lmax, int degree, int n_matv
 }  // namespace ld
 
 using namespace ld;
+
+// ---------------------------------------------------------------------------
+// Scratch of ld_logdet_estimate_noalloc, for callers that cannot allocate
+// device memory: a file-scope device array of the library (each GPU the
+// library runs on holds its own copy, until the process ends).  Host code
+// never passes `scratch` itself to a kernel (in host code the name is only a
+// stand-in): its device address is looked up once per device with
+// hipGetSymbolAddress and that address is used everywhere.
+// ---------------------------------------------------------------------------
+constexpr size_t kNoAllocScratchBytes = 64ull << 20;
+static __device__ __align__(256) unsigned char scratch[kNoAllocScratchBytes];
+
+namespace {
+constexpr int kMaxScratchDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_addr[kMaxScratchDevices] = {};
+
+// Device address of `scratch` on the current device (looked up on the first
+// call made on that device, with it current).
+int scratch_address(void** out) {
+    int dev = -1;
+    LD_CHECK_HIP(hipGetDevice(&dev));
+    if (dev < 0 || dev >= kMaxScratchDevices) return fail(LD_EINVAL, "device ordinal out of range");
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_addr[dev]) {
+        void* p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p)
+            return fail(LD_EHIP, std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+        g_scratch_addr[dev] = p;
+    }
+    *out = g_scratch_addr[dev];
+    return LD_OK;
+}
+}  // namespace
 
 // ---------------------------------------------------------------------------
 // Lanczos refinement of the upper end of the spectrum (App. A): `steps`
@@ -1309,6 +1349,29 @@ int ld_logdet_estimate(const ld_csr* A, double lmin, double lmax, int32_t degree
     LD_CHECK(check_estimate_args(A, lmin, lmax, degree, n_matvec));
     return run_logdet(A, lmin, lmax, degree, n_matvec, seed, resolve(opts), workspace, ws_bytes,
                       (hipStream_t)stream, out_logdet, nullptr, stats);
+}
+
+int ld_logdet_estimate_noalloc(const ld_csr* A, double lmin, double lmax, int32_t degree,
+                               int32_t n_matvec, uint64_t seed, const ld_options* opts, void* stream,
+                               double* out_logdet, ld_stats* stats) {
+    clear_error();
+    if (!out_logdet) return fail(LD_EINVAL, "out_logdet is null");
+    LD_CHECK(check_estimate_args(A, lmin, lmax, degree, n_matvec));
+    const ld_options o = resolve(opts);
+    const size_t need = layout_bytes(layout_estimate(A, degree, n_matvec, false, o), false);
+    if (need > kNoAllocScratchBytes)
+        return fail(LD_EWORKSPACE, "the estimate needs " + std::to_string(need) +
+                                       " bytes of scratch; the library's static scratch holds " +
+                                       std::to_string(kNoAllocScratchBytes));
+    hipStream_t st = (hipStream_t)stream;
+    int dev = -1, sdev = -1;
+    LD_CHECK_HIP(hipGetDevice(&dev));
+    LD_CHECK_HIP(hipStreamGetDevice(st, &sdev));
+    if (sdev != dev) return fail(LD_EINVAL, "the stream must belong to the current device");
+    void* ws = nullptr;
+    LD_CHECK(scratch_address(&ws));
+    return run_logdet(A, lmin, lmax, degree, n_matvec, seed, o, ws, kNoAllocScratchBytes, st, out_logdet,
+                      nullptr, stats, /*timed=*/false);
 }
 
 int ld_spectral_bounds(const ld_csr* A, int32_t lanczos_steps, void* stream, double* lmin,
