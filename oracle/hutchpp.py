@@ -43,10 +43,12 @@ def split_queries(m_vec: int):
 
 
 def logdet_estimate(Q, lmin: float, lmax: float, degree: int, m_vec: int, seed: int,
-                    orth=None, return_parts: bool = False, probes: str = "rademacher"):
-    """Alg. 3 in FP64 on a scipy sparse (or dense) symmetric Q."""
+                    orth=None, return_parts: bool = False, probes: str = "rademacher",
+                    s_mode: str = "center", taylor_cap: int = 10**8):
+    """Alg. 3 in FP64 on a scipy sparse (or dense) symmetric Q (s_mode, taylor_cap:
+    Alg. 1's scaling value and Taylor cap, see NewtonPlan)."""
     n = Q.shape[0]
-    plan = NewtonPlan(lmin, lmax, degree)
+    plan = NewtonPlan(lmin, lmax, degree, s_mode, taylor_cap)
     k, k_g = split_queries(m_vec)
     if k > n:
         raise ValueError("sketch wider than the matrix")

@@ -33,7 +33,7 @@ import math
 
 import numpy as np
 
-from .divdiff import exact_dd, interval_map
+from .divdiff import alg1_dd, exact_dd, interval_map
 from .leja import fast_leja_vectorised
 
 
@@ -46,15 +46,31 @@ def scaling(lmin: float, lmax: float):
 
 
 class NewtonPlan:
-    """Everything the recurrence needs for an interval and a degree."""
+    """Everything the recurrence needs for an interval and a degree.
 
-    def __init__(self, lmin: float, lmax: float, degree: int):
+    ``s_mode`` is the scaling value of Alg. 1 (Sec. 3.1).  With the centre
+    ("center", the Lemma's optimum) Alg. 1 converges to the divided
+    differences of log to FP64 accuracy, so the plan takes their plain
+    definition (``exact_dd``).  With "half_lmax" (s = lambda_max/2, the
+    paper's other variant) Alg. 1's Taylor series converges only like 1/p at
+    xi_0 and the coefficients it returns after ``taylor_cap`` terms are not
+    those divided differences: the plan then takes Alg. 1's own output
+    (``alg1_dd``), which is what an estimate in that mode computes.
+    """
+
+    def __init__(self, lmin: float, lmax: float, degree: int, s_mode: str = "center",
+                 taylor_cap: int = 10**8):
         if degree < 1:
             raise ValueError("degree >= 1")
         self.sigma, self.lo, self.hi = scaling(lmin, lmax)
         self.degree = degree
         self.xi = fast_leja_vectorised(degree + 1)
-        self.d = exact_dd(self.lo, self.hi, self.xi)
+        if s_mode == "center":
+            self.d = exact_dd(self.lo, self.hi, self.xi)
+        elif s_mode == "half_lmax":
+            self.d, self.taylor_terms = alg1_dd(self.lo, self.hi, self.xi, "half_lmax", taylor_cap)
+        else:
+            raise ValueError(s_mode)
         self.c, self.gamma = interval_map(self.lo, self.hi)
         self.alpha = 1.0 / (self.sigma * self.gamma)
         self.beta = self.c / self.gamma + self.xi[:degree]
@@ -111,9 +127,9 @@ class NewtonPlan:
         return acc
 
 
-def apply_log(Q, V, lmin: float, lmax: float, degree: int):
+def apply_log(Q, V, lmin: float, lmax: float, degree: int, s_mode: str = "center", taylor_cap: int = 10**8):
     """log(Q) V ~= P_m(Q~) V + log(sigma) V."""
-    plan = NewtonPlan(lmin, lmax, degree)
+    plan = NewtonPlan(lmin, lmax, degree, s_mode, taylor_cap)
     return plan.apply_poly(Q, V) + math.log(plan.sigma) * np.asarray(V, dtype=np.float64)
 
 

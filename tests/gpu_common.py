@@ -65,3 +65,18 @@ def nine_point_grid(N, seed):
     Q.sort_indices()
     return (Q.indptr.astype(np.int32), Q.indices.astype(np.int32), Q.data.astype(np.float64), n)
 
+
+
+def assert_cols_close(out, ref, tol):
+    """Element by element: |out - ref| <= tol * max|ref[:, c]| for every entry of
+    every column c (a 1-D array is one column)."""
+    out = np.asarray(out, dtype=np.float64)
+    ref = np.asarray(ref, dtype=np.float64)
+    assert out.shape == ref.shape, (out.shape, ref.shape)
+    if ref.ndim == 1:
+        out, ref = out[:, None], ref[:, None]
+    scale = np.abs(ref).max(axis=0)
+    err = np.abs(out - ref) / np.where(scale > 0, scale, 1.0)
+    worst = float(err.max()) if err.size else 0.0
+    where = np.unravel_index(int(err.argmax()), err.shape) if err.size else None
+    assert worst <= tol, f"largest element error {worst:.3e} (tolerance {tol:.1e}) at row, column {where}"

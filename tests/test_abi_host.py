@@ -70,11 +70,17 @@ def test_alg1_ill_conditioned_interval():
     assert np.max(np.abs(d - ref)) < 1e-9 * np.max(np.abs(ref))
 
 
-def test_alg1_half_lmax_variant_and_cap():
-    d, terms = ld.divided_differences(1.0, 17.0, 40, ld.LD_SVAL_HALF_LMAX, 2000)
-    ref = divdiff.exact_dd(1.0, 17.0, leja.fast_leja_vectorised(41))
-    assert terms == 2000
-    assert 1e-6 < np.max(np.abs(d - ref)) < 1e-2
+@pytest.mark.parametrize("lo,hi,m,cap", [(1.0, 17.0, 40, 2000), (1.0, 81.0, 80, 5000), (2.5, 3.0, 30, 300)])
+def test_alg1_half_lmax_variant_matches_oracle(lo, hi, m, cap):
+    # s = lambda_max/2 (Sec. 3.1, Tab. 3/4's second variant): the library's
+    # Alg. 1 against the oracle's Alg. 1 after the same number of terms
+    d, terms = ld.divided_differences(lo, hi, m, ld.LD_SVAL_HALF_LMAX, cap)
+    ref, p = divdiff.alg1_dd(lo, hi, leja.fast_leja_vectorised(m + 1), "half_lmax", taylor_cap=cap)
+    assert terms == p == cap
+    assert np.max(np.abs(d - ref)) < 1e-13 * max(1.0, np.max(np.abs(ref)))
+    # and it is not the exact divided differences (the series has not converged)
+    exact = divdiff.exact_dd(lo, hi, leja.fast_leja_vectorised(m + 1))
+    assert np.max(np.abs(d - exact)) > 1e-6
 
 
 def test_probe_generator_bit_identical_to_oracle():

@@ -12,7 +12,7 @@ import pytest
 
 import workloads as w
 from oracle import bounds, grad as ograd, hutchpp
-from tests.gpu_common import random_spd_csr
+from tests.gpu_common import assert_cols_close, random_spd_csr
 
 pytestmark = pytest.mark.gpu
 
@@ -52,8 +52,7 @@ def test_grad_irregular(dtype, tol):
     est, g = ld.logdet_with_grad(A, lmin, lmax, 30, 21, 1)
     ref_est, ref_g = ograd.logdet_grad(csr_v, lmin, lmax, 30, 21, 1)
     assert abs(est - ref_est) / abs(ref_est) < (1e-10 if dtype == torch.float64 else 1e-5)
-    g = g.double().cpu().numpy()
-    assert np.linalg.norm(g - ref_g) / np.linalg.norm(ref_g) < tol
+    assert_cols_close(g.double().cpu().numpy(), ref_g, tol)
 
 
 def test_grad_fp32_grid32():
@@ -62,8 +61,7 @@ def test_grad_fp32_grid32():
     est, g = ld.logdet_with_grad(A, 0.5, 8.5, 40, 30, 0)
     ref_est, ref_g = ograd.logdet_grad((csr[0], csr[1], vals, csr[3]), 0.5, 8.5, 40, 30, 0)
     assert abs(est - ref_est) / abs(ref_est) < 1e-5
-    g = g.double().cpu().numpy()
-    assert np.linalg.norm(g - ref_g) / np.linalg.norm(ref_g) < 1e-4
+    assert_cols_close(g.double().cpu().numpy(), ref_g, 1e-4)
 
 
 def gmrf_values(kappa, tau, csr):
@@ -138,5 +136,65 @@ def test_grad_gaussian_probes(dtype, tol):
     est, g = ld.logdet_with_grad(A, lmin, lmax, 30, 21, 6, options=ld.Options(probe_dist=1))
     ref_est, ref_g = ograd.logdet_grad(csr_v, lmin, lmax, 30, 21, 6, probes="gaussian")
     assert abs(est - ref_est) / abs(ref_est) < (1e-10 if dtype == torch.float64 else 1e-5)
-    g = g.double().cpu().numpy()
-    assert np.linalg.norm(g - ref_g) / np.linalg.norm(ref_g) < tol
+    assert_cols_close(g.double().cpu().numpy(), ref_g, tol)
+
+
+@pytest.mark.parametrize("dtype,tol", [(torch.float64, 1e-11), (torch.float32, 2e-5)])
+@pytest.mark.parametrize("degree", [12, 30])
+def test_grad_equals_dense_inverse_when_sketch_spans_everything(dtype, tol, degree):
+    # k = n = 49 sketch columns: Q_b spans R^n, the residual probes deflate to
+    # zero and the estimate is the exact trace of P_m(Q~), whose derivative
+    # w.r.t. entry (r, c) is (P_m'(Q~)/sigma)_{cr}.  That is within the
+    # interpolant's derivative error max |P_m'(lam) - 1/lam| of the dense
+    # (Q^{-1})_{cr} (and equal to it to rounding at degree 30).
+    from oracle.newton import NewtonPlan
+
+    csr = w.grid_laplacian_2d(7, 3.0)              # spectrum in [3, 11]
+    A, vals = to_gpu(csr, dtype)
+    row_ptr, col_idx, _, n = csr
+    est, g = ld.logdet_with_grad(A, 3.0, 11.0, degree, 3 * n, 0)
+    Q = w.to_scipy((row_ptr, col_idx, vals, n)).toarray()
+    rows = np.repeat(np.arange(n), np.diff(row_ptr))
+    inv_t = np.linalg.inv(Q)[col_idx, rows]
+    plan = NewtonPlan(3.0, 11.0, degree)
+    lam = np.linspace(3.0, 11.0, 20001)
+    t = (lam - plan.c) / plan.gamma
+    pi, dpi, dp = np.ones_like(t), np.zeros_like(t), np.zeros_like(t)
+    for j in range(degree):
+        dpi = pi + (t - plan.xi[j]) * dpi
+        pi = pi * (t - plan.xi[j])
+        dp += plan.d[j + 1] * dpi
+    bound = float(np.max(np.abs(dp / plan.gamma - 1.0 / lam)))
+    err = np.abs(g.double().cpu().numpy() - inv_t)
+    assert err.max() <= bound + tol * np.abs(inv_t).max(), (err.max(), bound)
+
+
+def test_grad_gmrf2048_fp32_against_fp64_finite_differences():
+    """2048 x 2048 GMRF, degree 100, 32 probes, FP32 bulk: the hyperparameter
+    derivatives from the FP32 gradient against central differences of the FP64
+    estimate (same probes and interval), 1e-5 relative."""
+    N, k2, tau, deg, mv = 2048, 0.1, 1.5, 100, 32
+    csr = w.grid_laplacian_2d(N, k2, tau=tau)
+    A32, _ = to_gpu(csr, torch.float32)
+    A64, vals = to_gpu(csr, torch.float64)
+    lmin, lmax = tau * k2 * 0.999, tau * (k2 + 8.0)
+    est32, g = ld.logdet_with_grad(A32, lmin, lmax, deg, mv, 0)
+    g = g.double()
+    rows = np.repeat(np.arange(csr[3]), np.diff(csr[0]))
+    diag = torch.tensor(rows == csr[1], device=DEV)
+    d_tau = float((g * A32.val.double()).sum().item()) / tau
+    kap = math.sqrt(k2)
+    d_kap = 2 * kap * tau * float(g[diag].sum().item())
+    h = 1e-5 * tau
+    fd_tau = (ld.logdet(A64.with_values(A64.val * ((tau + h) / tau)), lmin, lmax, deg, mv, 0)
+              - ld.logdet(A64.with_values(A64.val * ((tau - h) / tau)), lmin, lmax, deg, mv, 0)) / (2 * h)
+    hk = 1e-6
+
+    def at_kappa(kk):
+        return ld.logdet(A64.with_values(torch.where(diag, A64.val + tau * (kk * kk - k2), A64.val)), lmin, lmax,
+                         deg, mv, 0)
+
+    fd_kap = (at_kappa(kap + hk) - at_kappa(kap - hk)) / (2 * hk)
+    assert abs(est32 - ld.logdet(A64, lmin, lmax, deg, mv, 0)) < 1e-4 * abs(est32)
+    assert d_tau == pytest.approx(fd_tau, rel=1e-5)
+    assert d_kap == pytest.approx(fd_kap, rel=1e-5)

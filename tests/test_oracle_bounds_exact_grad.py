@@ -153,3 +153,43 @@ def test_gradient_gaussian_probes_against_finite_differences():
     E = np.random.default_rng(21).standard_normal(len(A[2]))
     fd = grad.fd_directional(A, E, 0.5, 8.5, 20, 12, 4, 1e-5, probes="gaussian")
     assert g @ E == pytest.approx(fd, rel=1e-7)
+
+
+def interpolant_errors(plan, lmin, lmax):
+    """max over [lmin, lmax] of |P_m(lam/sigma) + log sigma - log lam| and of
+    |d/dlam P_m(lam/sigma) - 1/lam| (Newton form and its derivative by the
+    product rule, on a fine grid)."""
+    lam = np.linspace(lmin, lmax, 20001)
+    t = (lam / plan.sigma - plan.c) / plan.gamma
+    pi, dpi = np.ones_like(t), np.zeros_like(t)
+    p, dp = np.full_like(t, plan.d[0]), np.zeros_like(t)
+    for j in range(plan.degree):
+        dpi = pi + (t - plan.xi[j]) * dpi
+        pi = pi * (t - plan.xi[j])
+        p += plan.d[j + 1] * pi
+        dp += plan.d[j + 1] * dpi
+    value = np.max(np.abs(p + math.log(plan.sigma) - np.log(lam)))
+    deriv = np.max(np.abs(dp / (plan.sigma * plan.gamma) - 1.0 / lam))
+    return float(value), float(deriv)
+
+
+@pytest.mark.parametrize("degree", [12, 20, 40])
+def test_gradient_equals_dense_inverse_when_sketch_spans_everything(degree):
+    # With k = n sketch columns the basis Q_b spans R^n, the residual probes
+    # deflate to zero and the estimate is the exact trace n log sigma +
+    # tr P_m(Q~); its derivative w.r.t. the stored entry (r, c) is then
+    # (P_m'(Q~)/sigma)_{cr}, which differs from d log det / dQ_rc = (Q^{-1})_{cr}
+    # by at most the interpolant's derivative error max |P_m'(lam) - 1/lam|
+    # (spectral bound on each entry).
+    csr = w.grid_laplacian_2d(7, 3.0)              # n = 49, spectrum in [3, 11]
+    row_ptr, col_idx, val, n = csr
+    est, g = grad.logdet_grad(csr, 3.0, 11.0, degree, 3 * n, 0)
+    Q = w.to_scipy(csr).toarray()
+    rows = np.repeat(np.arange(n), np.diff(row_ptr))
+    inv_t = np.linalg.inv(Q)[col_idx, rows]
+    from oracle.newton import NewtonPlan
+    value_err, deriv_err = interpolant_errors(NewtonPlan(3.0, 11.0, degree), 3.0, 11.0)
+    assert np.max(np.abs(g - inv_t)) <= deriv_err + 1e-12
+    assert abs(est - exact.cholesky_logdet(Q)) <= n * value_err + 1e-10
+    if degree == 12:   # the bound is not vacuous: a visible polynomial error remains
+        assert np.max(np.abs(g - inv_t)) > 1e-3 * deriv_err

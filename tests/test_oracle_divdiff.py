@@ -28,6 +28,69 @@ def test_alg1_reaches_exact(lo, hi, m):
     assert p < 1.2 * (60 * math.log(2) / -math.log(r)) + 20
 
 
+def truncated_taylor_dd(lo, hi, xi, p, dps=80):
+    """Divided differences (Eq. Léja7, high precision) of f_p(c + gamma*xi),
+    f_p(z) = log s + sum_{k=1}^p (-1)^(k+1) ((z-s)/s)^k / k with s = hi/2:
+    the polynomial whose value at the Léja bidiagonal matrix Alg. 1 forms after
+    p Taylor terms, so that its first column holds these divided differences."""
+    import mpmath
+
+    with mpmath.workdps(dps):
+        c, g = mpmath.mpf(lo + hi) / 2, mpmath.mpf(hi - lo) / 4
+        s = mpmath.mpf(hi) / 2
+        X = [mpmath.mpf(float(x)) for x in xi]
+        vals = []
+        for x in X:
+            w = (c + g * x - s) / s
+            acc, pw = mpmath.log(s), mpmath.mpf(1)
+            for k in range(1, p + 1):
+                pw *= w
+                acc += (pw / k) if k % 2 else -(pw / k)
+            vals.append(acc)
+        out, table = [vals[0]], vals
+        for level in range(1, len(X)):
+            table = [(table[j + 1] - table[j]) / (X[j + level] - X[j]) for j in range(len(X) - level)]
+            out.append(table[0])
+        return np.array([float(v) for v in out])
+
+
+@pytest.mark.parametrize("lo,hi,m,p", [(1.0, 17.0, 40, 3000), (1.0, 81.0, 24, 1500), (2.5, 3.0, 30, 500)])
+def test_alg1_half_lmax_equals_truncated_taylor_divided_differences(lo, hi, m, p):
+    # Sec. 3.1 with s = lambda_max/2: after p terms Alg. 1 returns the divided
+    # differences of the truncated Taylor polynomial of log about s (no
+    # convergence test can stop it earlier: xi_0 sits on the Taylor disc's
+    # boundary), computed here independently by Eq. Léja7's recursion.
+    a, terms = divdiff.alg1_dd(lo, hi, XI[: m + 1], "half_lmax", taylor_cap=p)
+    assert terms == p
+    ref = truncated_taylor_dd(lo, hi, XI[: m + 1], p)
+    assert np.max(np.abs(a - ref)) < 1e-12 * max(1.0, np.max(np.abs(ref)))
+
+
+@pytest.mark.parametrize("p", [1, 2, 7, 100, 2001])
+def test_alg1_half_lmax_first_coefficient_closed_form(p):
+    # At xi_0 = 2 (z_0 = lambda_max) the Taylor variable is (z_0 - s)/s = 1, so
+    # d_0 = log(s) + S_p with S_p the p-th partial sum of the alternating
+    # harmonic series, S_p = log 2 + ((-1)^(p+1)/2) (psi((p+2)/2) - psi((p+1)/2)).
+    import mpmath
+
+    lo, hi = 1.0, 17.0
+    a, _ = divdiff.alg1_dd(lo, hi, XI[:5], "half_lmax", taylor_cap=p)
+    Sp = mpmath.log(2) + (-1) ** (p + 1) * (mpmath.digamma((p + 2) / mpmath.mpf(2))
+                                            - mpmath.digamma((p + 1) / mpmath.mpf(2))) / 2
+    assert a[0] == pytest.approx(math.log(hi / 2) + float(Sp), abs=1e-13)
+    # and the error against log(lambda_max) decays like 1/(2p)
+    if p > 50:
+        assert abs(a[0] - math.log(hi)) == pytest.approx(1 / (2 * p), rel=2 / p)
+
+
+def test_newton_plan_half_lmax_takes_alg1():
+    plan = NewtonPlan(0.5, 8.5, 30, "half_lmax", 1000)
+    a, _ = divdiff.alg1_dd(1.0, 17.0, XI[:31], "half_lmax", taylor_cap=1000)
+    np.testing.assert_array_equal(plan.d, a)
+    with pytest.raises(ValueError):
+        NewtonPlan(0.5, 8.5, 30, "lambda_min")
+
+
 def test_alg1_half_lmax_converges_slowly():
     # s = lambda_max/2 puts xi_0 = 2 on the boundary |w| = 1 of the Taylor
     # disc: the error decays only like 1/p.

@@ -1,5 +1,6 @@
 """Pins for the oracle's fast Léja points on [-2, 2] (Sec. 3, Eq. Léja5)."""
 import math
+from fractions import Fraction
 
 import numpy as np
 
@@ -56,3 +57,36 @@ def test_capacity_of_interval():
     assert all(a > b for a, b in zip(roots, roots[1:]))
     assert 1.0 < roots[-1] < 1.02
     assert roots[0] < 1.3
+
+
+def test_first_sixteen_points():
+    # The first points worked by hand from Eq. Léja5 over midpoint candidates:
+    # after 2, -2, 0 the product |x| |4 - x^2| ties at +-1 (larger x first);
+    # after {2, -2, 0, 1, -1} the product |x| |4 - x^2| |x^2 - 1| is even and
+    # ties at +-1.5 (3.28125) above +-0.5 (1.40625); on the symmetric set
+    # {0, +-1, +-1.5, +-2} the best midpoints are +-0.5 (2.8125 against
+    # 2.3262 at +-1.75), and so on; the later entries follow from the same
+    # rule in exact arithmetic (next test).
+    want = [2, -2, 0, 1, -1, 1.5, -1.5, 0.5, -1.75, 1.75, -0.5, 1.875, -1.875, 1.25, -1.25, 0.25]
+    assert list(leja.fast_leja(16)) == want
+    assert list(leja.fast_leja_vectorised(16)) == want
+
+
+def test_exact_arithmetic_brute_force():
+    # The same greedy rule in exact rational arithmetic: every candidate
+    # product is exact, ties are exact equalities (broken towards the larger
+    # x), so the FP64 products and the relative tie tolerance of the oracle
+    # must reproduce this sequence.
+    pts = [Fraction(2), Fraction(-2)]
+    while len(pts) < 96:
+        srt = sorted(pts)
+        cands = [(a + b) / 2 for a, b in zip(srt, srt[1:])]
+        best = None
+        for x in cands:
+            prod = Fraction(1)
+            for q in pts:
+                prod *= abs(x - q)
+            if best is None or prod > best[0] or (prod == best[0] and x > best[1]):
+                best = (prod, x)
+        pts.append(best[1])
+    np.testing.assert_array_equal(leja.fast_leja_vectorised(96), np.array([float(x) for x in pts]))
