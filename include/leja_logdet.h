@@ -140,7 +140,11 @@ typedef struct {
     int32_t tile_order_used; /* LD_TILES_XCD_BANDS or LD_TILES_INTERLEAVED      */
     int32_t dia_constant;    /* 1: every diagonal holds one value (stored once,
                                 with 16 presence bits per row)                */
-    int32_t reserved_stats;
+    int32_t xcd_chunk_rows;  /* with XCD bands: 0 = one contiguous band of rows
+                                per XCD; > 0 = the bands are cut into chunks of
+                                this many rows dealt to the XCDs in turn (a
+                                3-D stencil whose plane neighbours would not
+                                stay in an XCD's L2), for the quadratic forms */
 } ld_stats;
 
 /* Defaults for ld_options (all zero except as documented). */

@@ -90,7 +90,7 @@ class LdStats(ctypes.Structure):
         ("dia_diagonals", ctypes.c_int32),
         ("tile_order_used", ctypes.c_int32),
         ("dia_constant", ctypes.c_int32),
-        ("reserved_stats", ctypes.c_int32),
+        ("xcd_chunk_rows", ctypes.c_int32),
     ]
 
     def as_dict(self):

@@ -183,23 +183,46 @@ struct EstLayout {
     BlkMat Y, Q1, X;          // sketch, first CholQR factor, [Q_b | U]
     size_t mask, W, part, small, nu, flag;
     // gradient extras: F [Q_b|U], the materialised residual probes, a k-column
-    // temporary, and n x ldg blocks for L, R, checkpoints, segment and lambda
+    // temporary, the FP64 gradient accumulator of an FP32 matrix, then one of
+    // two regions: the squared-basis path's stored vectors (sqb bytes) or the
+    // Newton-form path's n x ldg blocks for L, R, lambdas, checkpoints and a
+    // segment (fwdb bytes at stride `stride`); the region is the larger one.
     BlkMat FX, Gm, T1;
-    int gcols = 0, ldg = 0, nckpt = 0, stride = 0;
-    size_t gblk = 0;
+    size_t grad64 = 0;
+    int H = 0, sq_stride = 0;        // squared path: forward steps ceil(m/2), checkpoint stride
+    size_t sqb = 0;
+    int gcols = 0, ldg = 0, nckpt = 0, stride = 0;   // Newton-form path
+    size_t gblk = 0, fwdb = 0;
     size_t longb = 0;          // long-row list
 };
 
-// Checkpoint stride of the reverse sweep: the smallest one whose stored
-// forward vectors (checkpoints + one segment) fit kCkptBudget, i.e. every
-// vector when memory allows (no recomputation); else the sqrt(m) stride that
-// minimises memory.
+// Vectors each gradient path keeps (checkpoints every `s` steps plus the
+// buffers a segment is recomputed into) and their bytes.
+//  Squared path: the sketch's Horner vectors r_t (t = 1..m; checkpoints at
+//  multiples of s and at m) and the forward vectors u_a of [Q_b | U] (a =
+//  1..H; the same rule), max(2, s-1) scratch blocks each when s > 1, two mu
+//  blocks of the reverse sweep and two rbar blocks of the sketch's adjoint.
+int sq_ckpts(int last, int s) { return last / s + (last % s != 0); }
+size_t sq_region(const EstLayout& L, int m, int s) {
+    const size_t yb = align_up(L.Y.bytes()), xb = align_up(L.X.bytes());
+    const size_t scratch = s > 1 ? (size_t)std::max(2, s - 1) : 0;
+    return yb * (sq_ckpts(m, s) + scratch + 2) + xb * (sq_ckpts(L.H, s) + scratch + 2);
+}
+//  Newton-form path: L, R, two lambdas, ceil(m/s)-1 checkpoints and a
+//  segment of s-1 vectors, all n x ldg.
+size_t fwd_region(const EstLayout& L, int m, int s) {
+    return align_up(L.gblk) * (size_t)(4 + ((m + s - 1) / s - 1) + (s - 1));
+}
+
+// Checkpoint stride: the smallest whose stored vectors fit kCkptBudget, i.e.
+// every vector when memory allows (no recomputation); else the sqrt(m)
+// stride, which minimises memory.
 constexpr double kCkptBudget = 64.0 * (1ull << 30);
 
-int auto_ckpt_stride(int degree, size_t gblk) {
+template <typename F>
+int auto_ckpt_stride(int degree, F region) {
     for (int s = 1; s <= degree; ++s) {
-        const double vecs = (double)((degree + s - 1) / s - 1 + (s - 1));
-        if (vecs * (double)align_up(gblk) <= kCkptBudget) return s;
+        if ((double)region(s) <= kCkptBudget) return s;
         if (s * s >= degree) break;   // past sqrt(m) memory only grows again
     }
     return std::max(1, (int)std::ceil(std::sqrt((double)degree)));
@@ -217,8 +240,10 @@ EstLayout layout_estimate(const ld_csr* A, int degree, int n_matvec, bool grad,
     L.k = n_matvec / 3;
     L.kg = n_matvec - 2 * L.k;
     L.nc = L.k + L.kg;
-    const int bw1 = choose_block_width(A, L.elem, L.k, o.block_cols);
-    int bw23 = choose_block_width(A, L.elem, L.nc, o.block_cols);
+    // the gradient keeps the sketch and [Q_b | U] as single blocks (its sweeps
+    // take every column of a vector in one row group)
+    const int bw1 = grad ? L.k : choose_block_width(A, L.elem, L.k, o.block_cols);
+    int bw23 = grad ? L.nc : choose_block_width(A, L.elem, L.nc, o.block_cols);
     if (bw23 > kMaxDotBlock) {   // the column-sum kernels take at most 64 columns per launch
         const int v = 16 / (int)L.elem, nb = (bw23 + kMaxDotBlock - 1) / kMaxDotBlock;
         bw23 = ((L.nc + nb - 1) / nb + v - 1) / v * v;
@@ -241,17 +266,34 @@ EstLayout layout_estimate(const ld_csr* A, int degree, int n_matvec, bool grad,
     L.flag = 256;
     L.longb = long_rows_bytes(A) + dia_bytes(A, o);
     if (grad) {
+        L.FX = make_blk(n, L.nc, L.nc, L.elem);             // F [Q_b | U], one row-major block
+        L.Gm = make_blk(n, L.kg, L.kg, L.elem);
+        L.T1 = make_blk(n, L.k, L.k, L.elem);
+        L.grad64 = L.elem == 8 ? 0 : (size_t)A->nnz * 8;
+        L.H = (degree + 1) / 2;
+        L.sq_stride = o.ckpt_stride > 0 ? std::min(o.ckpt_stride, degree)
+                                        : auto_ckpt_stride(degree, [&](int s) { return sq_region(L, degree, s); });
+        L.sqb = sq_region(L, degree, L.sq_stride);
         L.gcols = L.nc + L.k;                               // R = [Q_b, U, S] / L = [Q_b, cU, 2Z]
         const int v = 16 / (int)L.elem;
         int lanes = 1;                                      // the adjoint's row group: power of two
         while (lanes * v < L.gcols) lanes <<= 1;
         L.ldg = lanes * v;
         L.gblk = (size_t)n * L.ldg * L.elem;
-        L.stride = o.ckpt_stride > 0 ? std::min(o.ckpt_stride, degree) : auto_ckpt_stride(degree, L.gblk);
+        // the Newton-form path runs when the squared coefficients are
+        // ill-conditioned; it takes the smallest stride whose vectors fit the
+        // region (at least its sqrt(m) minimum)
+        const int smin = std::max(1, (int)std::ceil(std::sqrt((double)degree)));
+        L.stride = o.ckpt_stride > 0 ? std::min(o.ckpt_stride, degree) : smin;
+        const size_t region = std::max(L.sqb, fwd_region(L, degree, L.stride));
+        if (o.ckpt_stride <= 0)
+            for (int st = 1; st < L.stride; ++st)
+                if (fwd_region(L, degree, st) <= region) {
+                    L.stride = st;
+                    break;
+                }
         L.nckpt = (degree + L.stride - 1) / L.stride;     // segments of the reverse sweep
-        L.FX = make_blk(n, L.nc, L.nc, L.elem);             // F [Q_b | U], one row-major block
-        L.Gm = make_blk(n, L.kg, L.kg, L.elem);
-        L.T1 = make_blk(n, L.k, L.k, L.elem);
+        L.fwdb = fwd_region(L, degree, L.stride);
     }
     return L;
 }
@@ -263,9 +305,8 @@ size_t layout_bytes(const EstLayout& L, bool grad) {
         b += align_up(s);
     b += L.longb;
     if (grad) {
-        for (size_t s : {L.FX.bytes(), L.Gm.bytes(), L.T1.bytes(), L.mask}) b += align_up(s);
-        // L, R, two lambdas, nckpt-1 checkpoints, stride-1 segment vectors
-        b += align_up(L.gblk) * (size_t)(4 + (L.nckpt - 1) + (L.stride - 1));
+        for (size_t s : {L.FX.bytes(), L.Gm.bytes(), L.T1.bytes(), L.mask, L.grad64}) b += align_up(s);
+        b += std::max(L.sqb, L.fwdb);
     }
     return b;
 }
@@ -329,6 +370,27 @@ struct LongRows {
     bool skewed = false;              // entries far from even over the eight row bands
 };
 
+// Chunked XCD bands for stencils (diagonal storage) whose widest diagonal
+// offset D is large: chunks of D/8 rows go to the XCDs in turn, so each XCD's
+// consecutive chunks lie D rows apart and the neighbour rows r - D and r + D
+// of its active rows were gathered by the same XCD one chunk earlier or come
+// one chunk later.  Taken when the launch streams from HBM (its bytes exceed
+// the Infinity Cache) or when the three planes r - D, r, r + D of a
+// contiguous band would overflow half an XCD's 4 MB L2 (a 3-D grid).
+// Measured on gfx950: 128^3 grid 23.4 -> 24.5 estimates/s, 2048^2 GMRF
+// 47.1 -> 47.9, 5000^2 GMRF 10.1 -> 10.8; on the cache-resident 1024^2 grid
+// chunks cost a quarter of the rate, so contiguous bands stay there.
+constexpr double kL2Budget = 2.0 * (1 << 20);
+
+int xcd_chunk_rows(const LongRows& lr, int ld, size_t elem, bool streams) {
+    if (lr.dia_nd <= 0) return 0;
+    int D = 0;
+    for (int q = 0; q < lr.dia_nd; ++q) D = std::max(D, std::abs(lr.dia_off[q]));
+    if (D / kXcds < 64) return 0;
+    if (!streams && 3.0 * D * (double)ld * (double)elem <= kL2Budget) return 0;
+    return D / kXcds;
+}
+
 int run_step(bool f64, const ld_csr* A, StepArgs s, int ncols, int col_block, hipStream_t st,
              int* nwg_used, const LongRows& lr) {
     const CsrDev d = dev_of(A);
@@ -352,6 +414,7 @@ int run_step(bool f64, const ld_csr* A, StepArgs s, int ncols, int col_block, hi
     // next step reads the output back from the cache, and plain stores stay.
     s.nt_out = alg_bytes_step(A, ncols, s.kind, A->dtype == LD_F64 ? 8 : 4, lr.dia_nd, lr.dia_pres != nullptr) >
                kMallBudget;
+    s.chunk_rows = s.interleave ? 0 : xcd_chunk_rows(lr, s.ld, f64 ? 8 : 4, s.nt_out);
     int nwg = 0;
     const int gshift = s.gshift;
     // one row group spans at most a wave: 64 lanes of the launch's vector width
@@ -509,9 +572,37 @@ int choose_dot_mode(const Plan& p, int requested, std::vector<double>& coef) {
     return LD_DOT_SQUARED;
 }
 
+// Where a recurrence keeps its vectors: vector t (1 <= t <= last) in a
+// checkpoint buffer when t is a multiple of the stride s or t = last, else
+// in one of two temporaries (alternating with t) or, while a segment is
+// recomputed, in a scratch buffer.
+struct VecStore {
+    std::vector<void*> ck;        // checkpoints: slot t/s - 1 for multiples of s, then `last`
+    std::vector<void*> scratch;   // max(2, s-1) buffers when s > 1
+    int s = 1, last = 0;
+    void* slot(int t) const {
+        if (t % s == 0) return ck[t / s - 1];
+        if (t == last) return ck.back();
+        return nullptr;
+    }
+    void* tmp(int t) const { return scratch[t % 2]; }
+    void* at(int t) const { return slot(t) ? slot(t) : tmp(t); }
+};
+
+int carve_store(Arena& ar, VecStore& v, int last, int s, size_t bytes) {
+    v.s = s;
+    v.last = last;
+    for (int i = 0; i < sq_ckpts(last, s); ++i) v.ck.push_back(ar.take(bytes));
+    if (s > 1)
+        for (int i = 0; i < std::max(2, s - 1); ++i) v.scratch.push_back(ar.take(bytes));
+    return LD_OK;
+}
+
 // Horner evaluation of Y = P_m(Q~) S, block by block; S from the sign words
-// (Rademacher) or stored (Gaussian).
-int sketch_phase(const ld_csr* A, EstimateState& S, hipStream_t st) {
+// (Rademacher) or stored (Gaussian).  With `keep` (one block) the Horner
+// vectors r_t = sum_{j >= t} d_j prod_{l=t}^{j-1} (T - xi_l) S, t = 1..m, go
+// to its buffers (the squared gradient's adjoint of the sketch reads them).
+int sketch_phase(const ld_csr* A, EstimateState& S, hipStream_t st, const VecStore* keep = nullptr) {
     const bool f64 = A->dtype == LD_F64;
     const int n = (int)A->n;
     const Plan& p = S.plan;
@@ -525,7 +616,7 @@ int sketch_phase(const ld_csr* A, EstimateState& S, hipStream_t st) {
         const int cols = Y.bcols(b), gcol = b * Y.bw;
         // step j (= m-1 .. 0) writes (j even ? block : W0); r_m sits in the other one
         void* bufs[2] = {Y.block(b), S.W0};
-        void* const rm = bufs[(m - 1) % 2 == 0 ? 1 : 0];
+        void* const rm = keep ? keep->at(m) : bufs[(m - 1) % 2 == 0 ? 1 : 0];
         void* const sblk = S.L.Q1.block(b);
         if (gauss) {
             LD_CHECK_HIP(launch_gauss_fill(f64, n, cols, S.key0, gcol, 1.0, sblk, Blk::plain(S.L.Q1.ld), st));
@@ -536,8 +627,8 @@ int sketch_phase(const ld_csr* A, EstimateState& S, hipStream_t st) {
         for (int j = m - 1; j >= 0; --j) {
             StepArgs s{};
             s.kind = kind;
-            s.win = bufs[j % 2 == 0 ? 1 : 0];
-            s.wout = bufs[j % 2 == 0 ? 0 : 1];
+            s.win = keep ? keep->at(j + 1) : bufs[j % 2 == 0 ? 1 : 0];
+            s.wout = keep ? (j == 0 ? Y.block(b) : keep->at(j)) : bufs[j % 2 == 0 ? 0 : 1];
             s.ld = Y.ld;
             s.gshift = gcol;
             s.alpha = p.alpha;
@@ -555,7 +646,8 @@ int sketch_phase(const ld_csr* A, EstimateState& S, hipStream_t st) {
 }
 
 // Phases 1 (sketch), CholQR2 and deflation; leaves X = [Q_b | U].
-int estimate_front(const ld_csr* A, uint64_t seed, EstimateState& S, hipStream_t st, Timer& tm) {
+int estimate_front(const ld_csr* A, uint64_t seed, EstimateState& S, hipStream_t st, Timer& tm,
+                   const VecStore* keep = nullptr) {
     const bool f64 = A->dtype == LD_F64;
     const int n = (int)A->n;
     const EstLayout& L = S.L;
@@ -565,7 +657,7 @@ int estimate_front(const ld_csr* A, uint64_t seed, EstimateState& S, hipStream_t
 
     if (!gauss) LD_CHECK_HIP(launch_sign_mask(n, L.k, key0, (uint64_t*)S.mask, st));
     LD_CHECK(record(S, 0, st));
-    LD_CHECK(sketch_phase(A, S, st));
+    LD_CHECK(sketch_phase(A, S, st, keep));
     LD_CHECK(record(S, 1, st));
     S.spmm_launches += S.launches1;
     S.bytes_alg += S.bytes1;
@@ -599,7 +691,10 @@ int estimate_front(const ld_csr* A, uint64_t seed, EstimateState& S, hipStream_t
 }
 
 // Quadratic forms x^T P_m(Q~) x for every column of X; nu_host[slot][col].
-int estimate_dots(const ld_csr* A, EstimateState& S, hipStream_t st, std::vector<double>& nu_host) {
+// With `keep` (squared basis, one block) the forward vectors u_a = pi_a(T) X,
+// a = 1..H, go to its buffers (the squared gradient's reverse sweep reads them).
+int estimate_dots(const ld_csr* A, EstimateState& S, hipStream_t st, std::vector<double>& nu_host,
+                  const VecStore* keep = nullptr) {
     const bool f64 = A->dtype == LD_F64;
     const Plan& p = S.plan;
     const EstLayout& L = S.L;
@@ -618,7 +713,7 @@ int estimate_dots(const ld_csr* A, EstimateState& S, hipStream_t st, std::vector
             // X itself is read once and kept (the gradient needs it); W0/W1 ping-pong
             const void* cur = X.block(b);
             for (int a = 0; a < h; ++a) {
-                void* nxt = (a % 2 == 0) ? S.W0 : S.W1;
+                void* nxt = keep ? keep->at(a + 1) : (a % 2 == 0) ? S.W0 : S.W1;
                 StepArgs s{};
                 s.kind = STEP_DOT_SQ;
                 s.first = a == 0;
@@ -715,20 +810,44 @@ int check_estimate_args(const ld_csr* A, double lmin, double lmax, int degree, i
 // at fixed probes and interval is
 //     d est = tr(Q_b^T dF Q_b) + c tr(U^T dF U) + 2 tr(Z^T dF S),
 //     Z = (I - Q_b Q_b^T) X Q_b R^{-T},  X = F - c (F U G^T + G U^T F),
-// (the basis term comes from differentiating the QR factor of the sketch), so
-// one reverse sweep on L = [Q_b, c U, 2Z] and R = [Q_b, U, S] gives every
-// entry: grad[(r,c)] = alpha * sum_i <lam_{i+1}[r], w_i[c]>, with w_i the
-// forward Newton vectors of R and lam the Horner adjoint started at
-// lam_m = d_m L.
+// (the basis term comes from differentiating the QR factor of the sketch).
+// The derivative w.r.t. a stored entry (r, c) is computed (FP64 accumulator)
+// by one of two paths:
 //
+// Squared basis (the estimate's own quadratic forms, LD_DOT_SQUARED): the
+// quadratic forms are x^T F x = sum_a c_2a <u_a, u_a> + c_2a+1 <u_a, u_a+1>,
+// u_a = pi_a(T) x, a <= H = ceil(m/2).  Their derivative (for a symmetric
+// perturbation; the per-entry derivative of a quadratic form is symmetric in
+// (r, c), so the mean of the two mirrored entries is exact) comes from one
+// reverse sweep over [Q_b | U]:
+//     mu~_H = 2 c_2H u_H,
+//     mu~_i = 2 c_2i u_i + 2 c_2i+1 u_i+1 + (T - xi_i) mu~_i+1,
+//     grad[(r,c)] += alpha wgt sum_cols (mu~_i+1[r] + c_2i+1 u_i[r]) u_i[c],
+// whose end mu~_0 = 2 F [Q_b | U] gives Z.  The basis term is the adjoint of
+// the sketch's Horner evaluation r_t = (T - xi_t) r_t+1 + d_t S (Y = r_0):
+//     rbar_0 = 2Z, rbar_j+1 = (T - xi_j) rbar_j,
+//     grad[(r,c)] += alpha sum_cols rbar_j[r] r_j+1[c]   (per entry, as is).
+// Sweeps of H + m steps, against m forward plus m reverse steps over
+// [Q_b, U, S] in the Newton form.
+//
+// Newton form (when the squared coefficients are ill-conditioned): one reverse
+// sweep on L = [Q_b, c U, 2Z] and R = [Q_b, U, S]:
+// grad[(r,c)] = alpha * sum_i <lam_{i+1}[r], w_i[c]>, with w_i the forward
+// Newton vectors of R and lam the Horner adjoint started at lam_m = d_m L.
 // One forward pass over R produces the w_i (stored every `stride` steps, all
 // of them when memory allows) and, accumulated on the way (Alg. 2's sum),
 // F [Q_b | U]: that gives both the two traces of the estimate and the
 // k-column algebra of Z, so no separate quadratic-form pass is needed.
 // ---------------------------------------------------------------------------
 struct GradBufs {
-    void *mask2, *Lg, *Rg, *lam0, *lam1;
+    void* mask2 = nullptr;
+    double* grad64 = nullptr;          // FP64 accumulator (the output itself for an FP64 matrix)
+    // Newton-form path
+    void *Lg = nullptr, *Rg = nullptr, *lam0 = nullptr, *lam1 = nullptr;
     std::vector<void*> ckpt, seg;
+    // squared path
+    VecStore rs, us;                   // sketch Horner vectors r_t, forward vectors u_a
+    void *mu[2] = {nullptr, nullptr}, *rb[2] = {nullptr, nullptr};
 };
 
 int upload(const std::vector<double>& h, double* d, hipStream_t st) {
@@ -743,39 +862,128 @@ int download(const double* d, std::vector<double>& h, hipStream_t st) {
     return LD_OK;
 }
 
-int estimate_and_gradient(const ld_csr* A, uint64_t seed, EstimateState& S, GradBufs& B, void* grad,
-                          hipStream_t st, double* t_low, double* t_res) {
+std::vector<double> diag_matrix(int q, double v) {
+    std::vector<double> M((size_t)q * q, 0.0);
+    for (int i = 0; i < q; ++i) M[(size_t)i * q + i] = v;
+    return M;
+}
+
+// The basis term's left factor: writes 2Z (k columns) into `dst`/`dd`, from
+// F [Q_b | U] in L.FX.  Slot 2 holds C = Q_b^T G from the deflation.
+int basis_term(const ld_csr* A, uint64_t seed, EstimateState& S, GradBufs& B, void* dst, Blk dd, hipStream_t st) {
+    const bool f64 = A->dtype == LD_F64;
+    const int n = (int)A->n;
+    const EstLayout& L = S.L;
+    const int k = L.k, kg = L.kg;
+    const double c = 1.0 / kg;
+    const uint64_t key1 = probe_stream_key(seed, 1);
+    double* slot[kSmallSlots];
+    for (int i = 0; i < kSmallSlots; ++i) slot[i] = S.small + (size_t)i * 64 * 64;
+    const Blk X = L.X.desc(), FXd = L.FX.desc(), Gd = L.Gm.desc(), Td = L.T1.desc();
+    // the CholQR factors: Y = Q_b R2 R1
+    std::vector<double> R1((size_t)k * k), R2((size_t)k * k);
+    LD_CHECK(download(slot[kSlotR1], R1, st));
+    LD_CHECK(download(slot[kSlotR2], R2, st));
+    // small matrices C = Q_b^T G (slot 2, from the deflation), M1 = U^T F Q_b
+    if (S.probe == LD_PROBE_GAUSSIAN) {
+        LD_CHECK_HIP(launch_gauss_fill(f64, n, kg, key1, 0, 1.0, L.Gm.base, Gd, st));
+    } else {
+        LD_CHECK_HIP(launch_sign_mask(n, kg, key1, (uint64_t*)B.mask2, st));
+        LD_CHECK_HIP(launch_fill_signs(f64, n, kg, L.Gm.ld, 0, (const uint64_t*)B.mask2, 1.0, L.Gm.base, st));
+    }
+    std::vector<double> C((size_t)k * kg), Ct((size_t)kg * k);
+    LD_CHECK(download(slot[2], C, st));
+    for (int i = 0; i < k; ++i)
+        for (int j = 0; j < kg; ++j) Ct[(size_t)j * k + i] = C[(size_t)i * kg + j];
+    LD_CHECK(upload(Ct, slot[3], st));
+    LD_CHECK(cross_product(f64, n, L.X.base, X.shifted(k), kg, L.FX.base, FXd, k, nullptr, S.part,
+                           slot[4], st));
+    // T1 = F Q_b - c F U C^T ; then T1 -= c G M1  (= X Q_b of the derivation)
+    LD_CHECK_HIP(launch_rowmat(f64, n, L.FX.base, FXd.shifted(k), kg, slot[3], k, -c, nullptr,
+                               L.FX.base, FXd, L.T1.base, Td, st));
+    LD_CHECK_HIP(launch_rowmat(f64, n, L.Gm.base, Gd, kg, slot[4], k, -c, nullptr, L.T1.base, Td,
+                               L.T1.base, Td, st));
+    // P = T1 - Q_b (Q_b^T T1)
+    LD_CHECK(cross_product(f64, n, L.X.base, X, k, L.T1.base, Td, k, nullptr, S.part, slot[5], st));
+    LD_CHECK_HIP(launch_rowmat(f64, n, L.X.base, X, k, slot[5], k, -1.0, nullptr, L.T1.base, Td,
+                               L.T1.base, Td, st));
+    // Z = P R^{-T}, R = R2 R1 (upper triangular)
+    std::vector<double> R((size_t)k * k, 0.0), Rinv((size_t)k * k, 0.0), RinvT((size_t)k * k);
+    for (int i = 0; i < k; ++i)
+        for (int j = 0; j < k; ++j) {
+            double v = 0.0;
+            for (int t = 0; t < k; ++t) v += R2[(size_t)i * k + t] * R1[(size_t)t * k + j];
+            R[(size_t)i * k + j] = v;
+        }
+    for (int j = k - 1; j >= 0; --j) {   // inverse of the upper-triangular R by back substitution
+        Rinv[(size_t)j * k + j] = 1.0 / R[(size_t)j * k + j];
+        for (int i = j + 1; i < k; ++i) {
+            double v = 0.0;
+            for (int t = j + 1; t <= i; ++t) v += R[(size_t)j * k + t] * Rinv[(size_t)t * k + i];
+            Rinv[(size_t)j * k + i] = -v / R[(size_t)j * k + j];
+        }
+    }
+    for (int i = 0; i < k; ++i)
+        for (int j = 0; j < k; ++j) RinvT[(size_t)i * k + j] = Rinv[(size_t)j * k + i];
+    LD_CHECK(upload(RinvT, slot[6], st));
+    LD_CHECK_HIP(launch_rowmat(f64, n, L.T1.base, Td, k, slot[6], k, 2.0, nullptr, nullptr, Blk::plain(1), dst, dd,
+                               st));
+    return LD_OK;
+}
+
+// The estimate's two traces from F [Q_b | U]: diag(Q_b^T F Q_b), diag(U^T F U).
+int traces_from_fx(const ld_csr* A, EstimateState& S, hipStream_t st, double* t_low, double* t_res) {
+    const bool f64 = A->dtype == LD_F64;
+    const int n = (int)A->n;
+    const EstLayout& L = S.L;
+    const int k = L.k, kg = L.kg;
+    double* slot0 = S.small;
+    double* slot1 = S.small + 64 * 64;
+    const Blk X = L.X.desc(), FXd = L.FX.desc();
+    LD_CHECK(cross_product(f64, n, L.X.base, X, k, L.FX.base, FXd, k, nullptr, S.part, slot0, st));
+    LD_CHECK(cross_product(f64, n, L.X.base, X.shifted(k), kg, L.FX.base, FXd.shifted(k), kg, nullptr, S.part,
+                           slot1, st));
+    std::vector<double> ql((size_t)k * k), qr((size_t)kg * kg);
+    LD_CHECK(download(slot0, ql, st));
+    LD_CHECK(download(slot1, qr, st));
+    KahanSum tl, tr;
+    for (int i = 0; i < k; ++i) tl.add(ql[(size_t)i * k + i]);
+    for (int i = 0; i < kg; ++i) tr.add(qr[(size_t)i * kg + i]);
+    *t_low = tl.value();
+    *t_res = tr.value() / kg;
+    return LD_OK;
+}
+
+bool streams_from_hbm(const ld_csr* A, const EstLayout& L, int ld) {
+    return matrix_bytes(A, L.elem) + 4.0 * (double)A->n * ld * L.elem > kMallBudget;
+}
+
+// Newton-form path (see above); the traces come from F [Q_b | U].
+int gradient_newton_form(const ld_csr* A, uint64_t seed, EstimateState& S, GradBufs& B, hipStream_t st,
+                         double* t_low, double* t_res) {
     const bool f64 = A->dtype == LD_F64;
     const int n = (int)A->n;
     const EstLayout& L = S.L;
     const Plan& p = S.plan;
     const int m = p.degree, k = L.k, kg = L.kg, nc = L.nc;
     const double c = 1.0 / kg;
-    const uint64_t key0 = probe_stream_key(seed, 0), key1 = probe_stream_key(seed, 1);
+    const uint64_t key0 = probe_stream_key(seed, 0);
     double* slot[kSmallSlots];
     for (int i = 0; i < kSmallSlots; ++i) slot[i] = S.small + (size_t)i * 64 * 64;
-    const Blk X = L.X.desc(), FXd = L.FX.desc(), Gd = L.Gm.desc(), Td = L.T1.desc();
+    const Blk X = L.X.desc();
     const Blk Gb = Blk::plain(L.ldg);
     const int gcols = L.gcols, ldg = L.ldg, stride = L.stride;
-    // the CholQR factors: Y = Q_b R2 R1
-    std::vector<double> R1((size_t)k * k), R2((size_t)k * k);
     {
         int hflag[2] = {0, 0};
         LD_CHECK_HIP(hipMemcpyAsync(hflag, S.flag + 1, sizeof(hflag), hipMemcpyDeviceToHost, st));
-        LD_CHECK(download(slot[kSlotR1], R1, st));
-        LD_CHECK(download(slot[kSlotR2], R2, st));
+        LD_CHECK_HIP(hipStreamSynchronize(st));
         LD_CHECK(cholqr_status(hflag));
     }
 
     // ---- R = [Q_b, U, S]
-    auto diag = [](int q, double v) {
-        std::vector<double> M((size_t)q * q, 0.0);
-        for (int i = 0; i < q; ++i) M[(size_t)i * q + i] = v;
-        return M;
-    };
-    LD_CHECK(upload(diag(k, 1.0), slot[7], st));
-    LD_CHECK(upload(diag(kg, c), slot[8], st));
-    LD_CHECK(upload(diag(kg, 1.0), slot[9], st));
+    LD_CHECK(upload(diag_matrix(k, 1.0), slot[7], st));
+    LD_CHECK(upload(diag_matrix(kg, c), slot[8], st));
+    LD_CHECK(upload(diag_matrix(kg, 1.0), slot[9], st));
     LD_CHECK_HIP(launch_rowmat(f64, n, L.X.base, X, k, slot[7], k, 1.0, nullptr, nullptr, Blk::plain(1),
                                B.Rg, Gb, st));
     LD_CHECK_HIP(launch_rowmat(f64, n, L.X.base, X.shifted(k), kg, slot[9], kg, 1.0, nullptr, nullptr,
@@ -818,67 +1026,9 @@ int estimate_and_gradient(const ld_csr* A, uint64_t seed, EstimateState& S, Grad
             cur = dst;
         }
     }
-
-    // ---- the estimate's traces: diag(Q_b^T F Q_b), diag(U^T F U)
-    {
-        LD_CHECK(cross_product(f64, n, L.X.base, X, k, L.FX.base, FXd, k, nullptr, S.part, slot[0], st));
-        LD_CHECK(cross_product(f64, n, L.X.base, X.shifted(k), kg, L.FX.base, FXd.shifted(k), kg, nullptr,
-                               S.part, slot[1], st));
-        std::vector<double> ql((size_t)k * k), qr((size_t)kg * kg);
-        LD_CHECK(download(slot[0], ql, st));
-        LD_CHECK(download(slot[1], qr, st));
-        KahanSum tl, tr;
-        for (int i = 0; i < k; ++i) tl.add(ql[(size_t)i * k + i]);
-        for (int i = 0; i < kg; ++i) tr.add(qr[(size_t)i * kg + i]);
-        *t_low = tl.value();
-        *t_res = tr.value() * c;
-    }
-
-    // ---- Z: small matrices C = Q_b^T G (slot 2, from the deflation), M1 = U^T F Q_b
-    if (S.probe == LD_PROBE_GAUSSIAN) {
-        LD_CHECK_HIP(launch_gauss_fill(f64, n, kg, key1, 0, 1.0, L.Gm.base, Gd, st));
-    } else {
-        LD_CHECK_HIP(launch_sign_mask(n, kg, key1, (uint64_t*)B.mask2, st));
-        LD_CHECK_HIP(launch_fill_signs(f64, n, kg, L.Gm.ld, 0, (const uint64_t*)B.mask2, 1.0, L.Gm.base, st));
-    }
-    std::vector<double> C((size_t)k * kg), Ct((size_t)kg * k);
-    LD_CHECK(download(slot[2], C, st));
-    for (int i = 0; i < k; ++i)
-        for (int j = 0; j < kg; ++j) Ct[(size_t)j * k + i] = C[(size_t)i * kg + j];
-    LD_CHECK(upload(Ct, slot[3], st));
-    LD_CHECK(cross_product(f64, n, L.X.base, X.shifted(k), kg, L.FX.base, FXd, k, nullptr, S.part,
-                           slot[4], st));
-    // T1 = F Q_b - c F U C^T ; then T1 -= c G M1  (= X Q_b of the derivation)
-    LD_CHECK_HIP(launch_rowmat(f64, n, L.FX.base, FXd.shifted(k), kg, slot[3], k, -c, nullptr,
-                               L.FX.base, FXd, L.T1.base, Td, st));
-    LD_CHECK_HIP(launch_rowmat(f64, n, L.Gm.base, Gd, kg, slot[4], k, -c, nullptr, L.T1.base, Td,
-                               L.T1.base, Td, st));
-    // P = T1 - Q_b (Q_b^T T1)
-    LD_CHECK(cross_product(f64, n, L.X.base, X, k, L.T1.base, Td, k, nullptr, S.part, slot[5], st));
-    LD_CHECK_HIP(launch_rowmat(f64, n, L.X.base, X, k, slot[5], k, -1.0, nullptr, L.T1.base, Td,
-                               L.T1.base, Td, st));
-    // Z = P R^{-T}, R = R2 R1 (upper triangular)
-    std::vector<double> R((size_t)k * k, 0.0), Rinv((size_t)k * k, 0.0), RinvT((size_t)k * k);
-    for (int i = 0; i < k; ++i)
-        for (int j = 0; j < k; ++j) {
-            double v = 0.0;
-            for (int t = 0; t < k; ++t) v += R2[(size_t)i * k + t] * R1[(size_t)t * k + j];
-            R[(size_t)i * k + j] = v;
-        }
-    for (int j = k - 1; j >= 0; --j) {   // inverse of the upper-triangular R by back substitution
-        Rinv[(size_t)j * k + j] = 1.0 / R[(size_t)j * k + j];
-        for (int i = j + 1; i < k; ++i) {
-            double v = 0.0;
-            for (int t = j + 1; t <= i; ++t) v += R[(size_t)j * k + t] * Rinv[(size_t)t * k + i];
-            Rinv[(size_t)j * k + i] = -v / R[(size_t)j * k + j];
-        }
-    }
-    for (int i = 0; i < k; ++i)
-        for (int j = 0; j < k; ++j) RinvT[(size_t)i * k + j] = Rinv[(size_t)j * k + i];
-    LD_CHECK(upload(RinvT, slot[6], st));
-    // L = [Q_b, c U, 2 Z]
-    LD_CHECK_HIP(launch_rowmat(f64, n, L.T1.base, Td, k, slot[6], k, 2.0, nullptr, nullptr, Blk::plain(1),
-                               B.Lg, Gb.shifted(nc), st));
+    LD_CHECK(traces_from_fx(A, S, st, t_low, t_res));
+    // ---- L = [Q_b, c U, 2 Z]
+    LD_CHECK(basis_term(A, seed, S, B, B.Lg, Gb.shifted(nc), st));
     LD_CHECK_HIP(launch_rowmat(f64, n, L.X.base, X, k, slot[7], k, 1.0, nullptr, nullptr, Blk::plain(1),
                                B.Lg, Gb, st));
     LD_CHECK_HIP(launch_rowmat(f64, n, L.X.base, X.shifted(k), kg, slot[8], kg, 1.0, nullptr, nullptr,
@@ -900,11 +1050,12 @@ int estimate_and_gradient(const ld_csr* A, uint64_t seed, EstimateState& S, Grad
         }
         for (int i = s1 - 1; i >= s0; --i) {
             AdjArgs a{};
+            a.mode = ADJ_HORNER;
             a.lam_in = lam_in;
             a.lam_out = lam_out;
             a.w = w[i - s0];
             a.L = B.Lg;
-            a.grad = grad;
+            a.grad = B.grad64;
             a.ld = ldg;
             a.ncols = gcols;
             a.alpha = p.alpha;
@@ -913,11 +1064,139 @@ int estimate_and_gradient(const ld_csr* A, uint64_t seed, EstimateState& S, Grad
             a.first = i == m - 1;
             a.last = i == 0;
             // as the Newton steps: streaming stores once the sweep works beyond the Infinity Cache
-            a.nt_out = matrix_bytes(A, L.elem) + 4.0 * (double)n * ldg * L.elem > kMallBudget;
+            a.nt_out = streams_from_hbm(A, L, ldg);
             LD_CHECK_HIP(launch_adjoint(f64, d, a, st));
             std::swap(lam_in, lam_out);
         }
     }
+    return LD_OK;
+}
+
+// Squared-basis path (see above).  The sketch has kept its Horner vectors and
+// the quadratic-form pass its forward vectors; the traces came from that pass.
+int gradient_squared(const ld_csr* A, uint64_t seed, EstimateState& S, GradBufs& B, hipStream_t st) {
+    const bool f64 = A->dtype == LD_F64;
+    const int n = (int)A->n;
+    const EstLayout& L = S.L;
+    const Plan& p = S.plan;
+    const int m = p.degree, k = L.k, nc = L.nc, H = L.H;
+    const std::vector<double>& cf = S.coef;   // squared-basis coefficients c_0..c_m
+    auto coef = [&](int i) { return i >= 0 && i <= m ? cf[i] : 0.0; };
+    const CsrDev d = dev_of(A);
+    const int ldX = L.X.ld, ldY = L.Y.ld;
+    auto plain_step = [&](const void* in, void* out, int j, int ld, int cols) -> int {
+        StepArgs s{};
+        s.kind = STEP_PLAIN;
+        s.win = in;
+        s.wout = out;
+        s.ld = ld;
+        s.alpha = p.alpha;
+        s.beta = p.beta[j];
+        return run_step(f64, A, s, cols, cols, st, nullptr, S.longrows);
+    };
+    // u_a for a = 0..H: u_0 is X, the others stored or recomputed per segment
+    const VecStore& us = B.us;
+    const VecStore& rs = B.rs;
+
+    // ---- reverse sweep over [Q_b | U] (weights 1 and 1/k_G), segment by segment
+    LD_CHECK_HIP(launch_scale_copy(f64, n, nc, H == 0 ? L.X.base : us.at(H), ldX, 2.0 * coef(2 * H), B.mu[0], ldX,
+                                   st));
+    int cur = 0;
+    const int s = us.s;
+    for (int q = (H - 1) / s; q >= 0; --q) {
+        const int b0 = q * s, b1 = std::min(b0 + s, H);   // reverse steps i = b1-1 .. b0 need u_b0 .. u_b1-1
+        std::vector<const void*> u(b1 - b0);
+        u[0] = b0 == 0 ? L.X.base : us.slot(b0);
+        for (int t = 1; t < b1 - b0; ++t) {
+            void* dst = us.slot(b0 + t) ? us.slot(b0 + t) : us.scratch[t - 1];
+            if (!us.slot(b0 + t)) LD_CHECK(plain_step(u[t - 1], dst, b0 + t - 1, ldX, nc));
+            u[t] = dst;
+        }
+        for (int i = b1 - 1; i >= b0; --i) {
+            AdjArgs a{};
+            a.mode = ADJ_SQUARED;
+            a.lam_in = B.mu[cur];
+            a.lam_out = B.mu[1 - cur];
+            a.w = u[i - b0];
+            a.grad = B.grad64;
+            a.ld = ldX;
+            a.ncols = nc;
+            a.alpha = p.alpha;
+            a.beta = p.beta[i];
+            a.q0 = 2.0 * coef(2 * i);
+            a.q1 = 2.0 * coef(2 * i + 1);
+            a.p1 = coef(2 * i + 1);
+            a.wsplit = k;
+            a.whi = 1.0 / L.kg;
+            a.first = i == H - 1;
+            a.last = false;   // mu~_0 = 2 F [Q_b | U] is needed
+            a.nt_out = streams_from_hbm(A, L, ldX);
+            LD_CHECK_HIP(launch_adjoint(f64, d, a, st));
+            cur = 1 - cur;
+        }
+    }
+    // the quadratic forms' per-entry derivative is symmetric: mirrored means
+    LD_CHECK_HIP(hipMemsetAsync(S.flag + 3, 0, sizeof(int), st));
+    LD_CHECK_HIP(launch_symmetrize(d, B.grad64, S.flag + 3, st));
+    // F [Q_b | U] = mu~_0 / 2
+    LD_CHECK_HIP(launch_scale_copy(f64, n, nc, B.mu[cur], ldX, 0.5, L.FX.base, L.FX.ld, st));
+
+    // ---- basis term: the adjoint of the sketch's Horner evaluation, from 2Z
+    LD_CHECK(basis_term(A, seed, S, B, B.rb[0], Blk::plain(ldY), st));
+    if (rs.s > 1) {   // segments are recomputed from S: its sign words (or its Gaussian block) again
+        const uint64_t key0 = probe_stream_key(seed, 0);
+        if (S.probe == LD_PROBE_GAUSSIAN)
+            LD_CHECK_HIP(launch_gauss_fill(f64, n, k, key0, 0, 1.0, L.Q1.base, Blk::plain(L.Q1.ld), st));
+        else
+            LD_CHECK_HIP(launch_sign_mask(n, k, key0, (uint64_t*)S.mask, st));
+    }
+    int rc = 0;
+    for (int q = 0; q * rs.s < m; ++q) {
+        // steps j = j0 .. j1-1 read r_j+1 for j+1 in (j0, j1], recomputed
+        // downwards from the checkpoint r_j1 when not stored
+        const int j0 = q * rs.s, j1 = std::min(j0 + rs.s, m);
+        std::vector<const void*> r(j1 - j0);   // r[t] = r_{j0+1+t}
+        r[j1 - j0 - 1] = rs.slot(j1);
+        for (int t = j1 - 1; t > j0; --t) {
+            void* dst = rs.slot(t) ? rs.slot(t) : rs.scratch[t - j0 - 1];
+            if (!rs.slot(t)) {
+                StepArgs st2{};
+                st2.kind = S.probe == LD_PROBE_GAUSSIAN ? STEP_HORNER_VEC : STEP_HORNER_SIGNS;
+                st2.win = r[t - j0];
+                st2.wout = dst;
+                st2.ld = ldY;
+                st2.alpha = p.alpha;
+                st2.beta = p.beta[t];
+                st2.dj = p.d[t];
+                st2.mask = (const uint64_t*)S.mask;
+                st2.vsrc = S.probe == LD_PROBE_GAUSSIAN ? L.Q1.base : nullptr;
+                st2.ldv = L.Q1.ld;
+                LD_CHECK(run_step(f64, A, st2, k, k, st, nullptr, S.longrows));
+            }
+            r[t - j0 - 1] = dst;
+        }
+        for (int j = j0; j < j1; ++j) {
+            AdjArgs a{};
+            a.mode = ADJ_PLAIN;
+            a.lam_in = B.rb[rc];
+            a.lam_out = B.rb[1 - rc];
+            a.w = r[j - j0];
+            a.grad = B.grad64;
+            a.ld = ldY;
+            a.ncols = k;
+            a.alpha = p.alpha;
+            a.beta = p.beta[j];
+            a.first = false;
+            a.last = j == m - 1;
+            a.nt_out = streams_from_hbm(A, L, ldY);
+            LD_CHECK_HIP(launch_adjoint(f64, d, a, st));
+            rc = 1 - rc;
+        }
+    }
+    int hsym = 0;
+    LD_CHECK_HIP(hipMemcpyAsync(&hsym, S.flag + 3, sizeof(int), hipMemcpyDeviceToHost, st));
+    LD_CHECK_HIP(hipStreamSynchronize(st));
+    if (hsym) return fail(LD_EINVAL, "the gradient needs a symmetric sparsity pattern (an entry has no mirror)");
     return LD_OK;
 }
 
@@ -940,17 +1219,32 @@ int run_logdet(const ld_csr* A, double lmin, double lmax, int degree, int n_matv
     LD_CHECK(get_workspace(workspace, ws_bytes, layout_bytes(S.L, want_grad), own, ar));
     carve(ar, S.L, S);
     GradBufs B;
+    // the squared path takes [Q_b | U] as one block of at most 64 columns (one
+    // column-sum launch per step); wider sketches and ill-conditioned squared
+    // coefficients take the Newton form
+    const bool sq_grad = want_grad && S.mode == LD_DOT_SQUARED && S.L.nc <= kMaxDotBlock;
     if (want_grad) {
         S.L.FX.base = ar.take(S.L.FX.bytes());
         S.L.Gm.base = ar.take(S.L.Gm.bytes());
         S.L.T1.base = ar.take(S.L.T1.bytes());
         B.mask2 = ar.take(S.L.mask);
-        B.Lg = ar.take(S.L.gblk);
-        B.Rg = ar.take(S.L.gblk);
-        B.lam0 = ar.take(S.L.gblk);
-        B.lam1 = ar.take(S.L.gblk);
-        for (int i = 0; i < S.L.nckpt - 1; ++i) B.ckpt.push_back(ar.take(S.L.gblk));
-        for (int i = 0; i < S.L.stride - 1; ++i) B.seg.push_back(ar.take(S.L.gblk));
+        B.grad64 = S.L.grad64 ? (double*)ar.take(S.L.grad64) : (double*)grad;
+        // the chosen path's vectors share one region
+        Arena reg{(char*)ar.take(std::max(S.L.sqb, S.L.fwdb)), std::max(S.L.sqb, S.L.fwdb), 0};
+        if (sq_grad) {
+            carve_store(reg, B.rs, degree, S.L.sq_stride, S.L.Y.bytes());
+            carve_store(reg, B.us, S.L.H, S.L.sq_stride, S.L.X.bytes());
+            for (void*& b : B.mu) b = reg.take(S.L.X.bytes());
+            for (void*& b : B.rb) b = reg.take(S.L.Y.bytes());
+        } else {
+            B.Lg = reg.take(S.L.gblk);
+            B.Rg = reg.take(S.L.gblk);
+            B.lam0 = reg.take(S.L.gblk);
+            B.lam1 = reg.take(S.L.gblk);
+            for (int i = 0; i < S.L.nckpt - 1; ++i) B.ckpt.push_back(reg.take(S.L.gblk));
+            for (int i = 0; i < S.L.stride - 1; ++i) B.seg.push_back(reg.take(S.L.gblk));
+        }
+        if (reg.used > reg.size) return fail(LD_EINVAL, "internal: gradient region overflow");
     }
     if (ar.base && ar.used > layout_bytes(S.L, want_grad))
         return fail(LD_EINVAL, "internal: workspace layout overflow");
@@ -958,12 +1252,12 @@ int run_logdet(const ld_csr* A, double lmin, double lmax, int degree, int n_matv
     LD_CHECK(prepare_rows(A, o, ar, st, S.longrows));
     Timer tm(st, timed);
     tm.mark();
-    LD_CHECK(estimate_front(A, seed, S, st, tm));
+    LD_CHECK(estimate_front(A, seed, S, st, tm, sq_grad ? &B.rs : nullptr));
     const EstLayout& L = S.L;
     double t_low = 0.0, t_res = 0.0;
-    if (!want_grad) {
+    if (!want_grad || sq_grad) {
         std::vector<double> nu;
-        LD_CHECK(estimate_dots(A, S, st, nu));
+        LD_CHECK(estimate_dots(A, S, st, nu, sq_grad ? &B.us : nullptr));
         tm.mark();
         const int ncoef = S.plan.degree + 1;
         KahanSum tl, tr;
@@ -977,11 +1271,17 @@ int run_logdet(const ld_csr* A, double lmin, double lmax, int degree, int n_matv
             }
         t_low = tl.value();
         t_res = tr.value() / L.kg;
+        if (sq_grad) {
+            LD_CHECK(gradient_squared(A, seed, S, B, st));
+            tm.mark();
+        }
     } else {
         tm.mark();   // no separate quadratic-form pass
-        LD_CHECK(estimate_and_gradient(A, seed, S, B, grad, st, &t_low, &t_res));
+        LD_CHECK(gradient_newton_form(A, seed, S, B, st, &t_low, &t_res));
         tm.mark();
     }
+    if (want_grad && S.L.grad64)   // FP32 matrix: the FP64 accumulator rounded once
+        LD_CHECK_HIP(launch_narrow(A->nnz, B.grad64, (float*)grad, st));
     // ---- combine (Alg. 3 step 7): n log(sigma) + t_low + t_res
     KahanSum tot;
     tot.add((double)A->n * std::log(S.plan.sigma));
@@ -1007,13 +1307,20 @@ int run_logdet(const ld_csr* A, double lmin, double lmax, int degree, int n_matv
         out->hi = S.plan.hi;
         out->k = L.k;
         out->k_G = L.kg;
-        out->dot_mode_used = want_grad ? LD_DOT_FORWARD : S.mode;
+        out->dot_mode_used = S.mode;
         out->dia_diagonals = S.longrows.dia_nd;
         out->dia_constant = S.longrows.dia_pres != nullptr;
         out->tile_order_used = S.longrows.tile_order == LD_TILES_INTERLEAVED ||
                                          (S.longrows.tile_order == LD_TILES_AUTO && S.longrows.skewed)
                                      ? LD_TILES_INTERLEAVED
                                      : LD_TILES_XCD_BANDS;
+        out->xcd_chunk_rows =
+            out->tile_order_used == LD_TILES_XCD_BANDS
+                ? xcd_chunk_rows(S.longrows, L.X.ld, L.elem,
+                                 alg_bytes_step(A, L.X.bw, S.mode == LD_DOT_SQUARED ? STEP_DOT_SQ : STEP_DOT_FWD,
+                                                L.elem, S.longrows.dia_nd, S.longrows.dia_pres != nullptr) >
+                                     kMallBudget)
+                : 0;
         out->spmm_launches = S.spmm_launches;
         out->t_low = t_low;
         out->t_res = t_res;
@@ -1035,7 +1342,9 @@ int run_logdet(const ld_csr* A, double lmin, double lmax, int degree, int n_matv
                          out->launches1, out->launches23,
                          (out->bytes1 + out->bytes23) / ((out->ms_steps1 + out->ms_steps23) * 1e-3 + 1e-30) / 1e9,
                          out->dia_diagonals ? "diagonal" : "csr", out->dia_constant ? " (constant values)" : "",
-                         out->tile_order_used == LD_TILES_INTERLEAVED ? "interleaved" : "xcd-bands");
+                         out->tile_order_used == LD_TILES_INTERLEAVED ? "interleaved"
+                         : out->xcd_chunk_rows                          ? "xcd-chunks"
+                                                                        : "xcd-bands");
     }
     return LD_OK;
 }

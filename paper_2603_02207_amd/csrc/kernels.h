@@ -87,6 +87,10 @@ struct StepArgs {
     // takes tiles w, w + grid, ... (spreads each tile's neighbours over the
     // XCDs; faster once the blocks stream from HBM)
     int interleave;
+    // with interleave = 0: > 0 cuts the bands into chunks of about this many
+    // rows, chunk c going to XCD c % 8 (each XCD walks its chunks in order);
+    // 0 = one contiguous band per XCD
+    int chunk_rows;
     // 1: the output block is written with non-temporal (streaming) stores
     int nt_out;
 };
@@ -161,22 +165,37 @@ hipError_t launch_validate_csr(const CsrDev& A, int* flag, hipStream_t st);
 int gersh_num_wg(int n);
 hipError_t launch_gershgorin(bool f64, const CsrDev& A, double* part, hipStream_t st);
 
-// Adjoint step of the reverse sweep (all blocks n x ld row-major, ncols used):
-//   lam_out = alpha*A*lam_in - beta*lam_in + dj*L
-//   grad[nz(r,c)] (+)= alpha * sum_cols lam_in[r,:] * w[c,:]
+// Gradient sweep step (all blocks n x ld row-major, ncols used; grad FP64):
+//   grad[nz(r,c)] (+)= alpha * sum_cols own[r, col] * w[c, col]
+//   ADJ_HORNER:  lam_out = alpha*A*lam_in - beta*lam_in + dj*L,  own = lam_in
+//   ADJ_PLAIN:   lam_out = alpha*A*lam_in - beta*lam_in,         own = lam_in
+//   ADJ_SQUARED: lam_out = alpha*A*lam_in - beta*lam_in + q0*w + q1*(alpha*A*w - beta*w),
+//                own = wgt(col) * (lam_in + p1*w), wgt = 1 for col < wsplit, else whi
+enum AdjMode : int { ADJ_HORNER = 0, ADJ_PLAIN = 1, ADJ_SQUARED = 2 };
 struct AdjArgs {
+    int mode;
     const void* lam_in;
     void* lam_out;
     const void* w;
     const void* L;
-    void* grad;
+    double* grad;
     int ld, ncols;
     double alpha, beta, dj;
+    double q0, q1, p1;   // ADJ_SQUARED coefficients
+    int wsplit;          // ADJ_SQUARED column weights: 1 before wsplit, whi after
+    double whi;
     bool first;      // grad is overwritten instead of accumulated
     bool last;       // no lam_out needed (only the SDDMM)
     bool nt_out;     // lam_out written with non-temporal (streaming) stores
 };
 hipError_t launch_adjoint(bool f64, const CsrDev& A, const AdjArgs& a, hipStream_t st);
+
+// Mean of every mirrored pair g[(r,c)], g[(c,r)] (FP64, CSR positions); *flag
+// (device int) set to 1 when some entry has no mirror.
+hipError_t launch_symmetrize(const CsrDev& A, double* g, int* flag, hipStream_t st);
+
+// y[i] = (float)x[i], i < len.
+hipError_t launch_narrow(long long len, const double* x, float* y, hipStream_t st);
 
 // Row probe (info: device, 64 ints, preset to 0 by the caller): info[0] =
 // number of diagonals nd (distinct offsets col - row of 64 sampled rows,

@@ -134,7 +134,7 @@ __global__ __launch_bounds__(NT) void step_kernel(
     const uint64_t* __restrict__ mask, double* __restrict__ ps0, double* __restrict__ ps1,
     double* __restrict__ ps2, int part_ld, int lpr, int rpw, int skip_long, T* __restrict__ accum,
     int ldacc, int acc_cols, int ntiles, const uint64_t* __restrict__ active, const T* __restrict__ dia, int nd,
-    DiaOff off, int interleave, int nt_out, const uint16_t* __restrict__ dpres, DiaVal<T> cv) {
+    DiaOff off, int interleave, int chunk, int nt_out, const uint16_t* __restrict__ dpres, DiaVal<T> cv) {
     constexpr bool kDot = is_dot(KIND);
     constexpr int NW = NT / 64;
     constexpr int kSums = kDot ? ((FIRST ? 1 : 0) + 1 + (KIND == STEP_DOT_SQ ? 1 : 0)) : 0;
@@ -166,19 +166,37 @@ __global__ __launch_bounds__(NT) void step_kernel(
 #pragma unroll
     for (int e = 0; e < VEC; ++e) s0[e] = s1[e] = s2[e] = 0.0;
 
-    // Tiles of NW*rows_per_wave rows.  Banded order: XCD x (= blockIdx % 8)
-    // owns the contiguous band of tiles [x*base + min(x, rem), ...) and its
-    // workgroups take the band's tiles round-robin in order, so the XCD's
-    // active rows stay a narrow window.  Interleaved order: workgroup w takes
-    // tiles w, w + grid, ...  With one workgroup per tile each takes one.
+    // Tiles of NW*rows_per_wave rows.  Banded order (chunk = 0): XCD x (=
+    // blockIdx % 8) owns the contiguous band of tiles [x*base + min(x, rem),
+    // ...) and its workgroups take the band's tiles round-robin in order, so
+    // the XCD's active rows stay a narrow window.  Chunked bands (chunk > 0):
+    // the tiles are cut into chunks of `chunk` tiles, chunk c belongs to XCD
+    // c % 8, and each XCD's workgroups take its chunks' tiles round-robin in
+    // order, so an XCD's consecutive chunks lie 8 chunks apart (a 3-D
+    // stencil's plane: the plane neighbours of a row were gathered by the
+    // same XCD one chunk earlier, in its L2).  Interleaved order: workgroup w
+    // takes tiles w, w + grid, ...  With one workgroup per tile each takes one.
     const int xcd = blockIdx.x % kXcds;
     const int base = ntiles / kXcds, rem = ntiles % kXcds;
     const int band0 = interleave ? 0 : xcd * base + (xcd < rem ? xcd : rem);
     const int band_len = interleave ? ntiles : base + (xcd < rem ? 1 : 0);
     const int wgs_here =
         interleave ? (int)gridDim.x : (int)(gridDim.x / kXcds) + (xcd < (int)(gridDim.x % kXcds) ? 1 : 0);
-    for (int t = interleave ? (int)blockIdx.x : (int)(blockIdx.x / kXcds); t < band_len; t += wgs_here) {
-    const int W0 = (band0 + t) * (NW * rows_per_wave) + wave * rows_per_wave;   // first row of this wave
+    for (int t = interleave ? (int)blockIdx.x : (int)(blockIdx.x / kXcds);; t += wgs_here) {
+    int tile;
+    if (interleave) {
+        if (t >= ntiles) break;
+        tile = t;
+    } else if (chunk > 0) {
+        const int c = (t / chunk) * kXcds + xcd;
+        if ((long long)c * chunk >= ntiles) break;   // later chunks of this XCD lie further out
+        tile = c * chunk + t % chunk;
+        if (tile >= ntiles) continue;                // the tail of the last, partial chunk
+    } else {
+        if (t >= band_len) break;
+        tile = band0 + t;
+    }
+    const int W0 = tile * (NW * rows_per_wave) + wave * rows_per_wave;   // first row of this wave
     const int nrows = max(0, min(rows_per_wave, n - W0));
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");   // the previous tile's LDS reads come first
     __builtin_amdgcn_wave_barrier();
@@ -561,14 +579,19 @@ template <typename T, int VEC, int KIND, int ND>
 __global__ __launch_bounds__(kThreads) void dia_flat_kernel(
     int n, const T* __restrict__ win, T* __restrict__ wout, int ld, int lpr, int gshift, T alpha, T beta, T dj,
     const T* __restrict__ vsrc, int ldv, const uint64_t* __restrict__ mask, T* __restrict__ accum, int ldacc,
-    int acc_cols, const T* __restrict__ dia, int nd, DiaOff off, int interleave, int nt_out,
+    int acc_cols, const T* __restrict__ dia, int nd, DiaOff off, int interleave, int chunk, int nt_out,
     const uint16_t* __restrict__ dpres, DiaVal<T> cv) {
     static_assert(KIND == STEP_HORNER_SIGNS || KIND == STEP_HORNER_VEC || KIND == STEP_PLAIN ||
                   KIND == STEP_PLAIN_ACC, "kinds without column sums");
     unsigned blk = blockIdx.x;
-    if (!interleave) {   // XCD x (= blockIdx % 8) takes the x-th contiguous band of workgroups
-        const unsigned per = gridDim.x / kXcds;   // the grid is a multiple of 8
-        blk = (blk % kXcds) * per + blk / kXcds;
+    if (!interleave) {
+        const unsigned x = blk % kXcds, i = blk / kXcds;   // the i-th workgroup dispatched to XCD x
+        if (chunk > 0) {   // chunk c of `chunk` workgroups belongs to XCD c % 8, walked in order
+            blk = ((i / (unsigned)chunk) * kXcds + x) * (unsigned)chunk + i % (unsigned)chunk;
+        } else {           // XCD x takes the x-th contiguous band of workgroups
+            const unsigned per = gridDim.x / kXcds;   // the grid is a multiple of 8
+            blk = x * per + i;
+        }
     }
     const unsigned i = blk * kThreads + threadIdx.x;
     if (i >= (unsigned)n * (unsigned)lpr) return;   // the launch checks n * lpr < 2^31
@@ -668,6 +691,8 @@ hipError_t launch_step_t(const CsrDev& A, const StepArgs& s, hipStream_t st, int
     auto grid = [&](const void* fn_first, const void* fn_rest) {
         return is_dot(KIND) ? std::min({ntiles, resident_wgs(fn_first, NT), resident_wgs(fn_rest, NT)}) : ntiles;
     };
+    // chunked bands: s.chunk_rows rows per chunk, in tiles
+    const int ctiles = s.chunk_rows > 0 && !s.interleave ? std::max(1, s.chunk_rows / rows_per_wg) : 0;
     DiaOff off{};
     for (int q = 0; q < kMaxDiag; ++q) off.o[q] = q < s.dia_nd ? s.dia_off[q] : 0;
     DiaVal<T> cv{};
@@ -680,13 +705,18 @@ hipError_t launch_step_t(const CsrDev& A, const StepArgs& s, hipStream_t st, int
             // whole number of chunks: the chunk index counts from c0)
             const long long chunks = (long long)A.n * lpr;
             if (chunks < (1LL << 31)) {
-                const int nwg = div_up(div_up(chunks, kThreads), kXcds) * kXcds;
+                const int need = div_up(chunks, kThreads);
+                // chunked bands: s.chunk_rows rows per chunk, in workgroups; the grid
+                // covers whole rounds of 8 chunks (workgroups past the end return)
+                const int cwg = s.chunk_rows > 0 && !s.interleave ? std::max(1, s.chunk_rows * lpr / kThreads) : 0;
+                const int nwg = cwg > 0 ? div_up(div_up(need, cwg), kXcds) * kXcds * cwg
+                                        : div_up(need, kXcds) * kXcds;
 #define LD_FLAT_LAUNCH(ND_)                                                                                    \
     hipLaunchKernelGGL((dia_flat_kernel<T, VEC, KIND, ND_>), dim3(nwg), dim3(kThreads), 0, st, A.n,           \
                        (const T*)s.win + s.c0, (T*)s.wout + s.c0, s.ld, lpr, s.gshift + s.c0, (T)s.alpha,     \
                        (T)s.beta, (T)s.dj, s.vsrc ? (const T*)s.vsrc + s.c0 : nullptr, s.ldv, s.mask,         \
                        s.acc ? (T*)s.acc + s.c0 : nullptr, s.ldacc, s.acc_cols - s.c0, (const T*)s.dia,        \
-                       s.dia_nd, off, s.interleave, s.nt_out, s.dia_pres, cv)
+                       s.dia_nd, off, s.interleave, cwg, s.nt_out, s.dia_pres, cv)
                 if (s.dia_nd <= 3)
                     LD_FLAT_LAUNCH(3);
                 else if (s.dia_nd <= 5)
@@ -709,7 +739,7 @@ hipError_t launch_step_t(const CsrDev& A, const StepArgs& s, hipStream_t st, int
                            (const T*)s.win, (T*)s.wout, s.ld, s.c0, s.bcols, s.gshift, (T)s.alpha, (T)s.beta,   \
                            (T)s.dj, (const T*)s.vsrc, s.ldv, s.mask, s.ps0, s.ps1, s.ps2, s.part_ld, lpr, rpw, \
                            0, (T*)s.acc, s.ldacc, s.acc_cols, ntiles, s.active, (const T*)s.dia, s.dia_nd, off, \
-                           s.interleave, s.nt_out, s.dia_pres, cv);                                            \
+                           s.interleave, ctiles, s.nt_out, s.dia_pres, cv);                                    \
         if (nwg_out) *nwg_out = nwg;                                                                           \
     }
         if (s.dia_nd <= 3)
@@ -732,8 +762,8 @@ hipError_t launch_step_t(const CsrDev& A, const StepArgs& s, hipStream_t st, int
                        A.n, A.row_ptr, A.col_idx, (const T*)A.val, (const T*)s.win, (T*)s.wout, s.ld,
                        s.c0, s.bcols, s.gshift, (T)s.alpha, (T)s.beta, (T)s.dj, (const T*)s.vsrc,
                        s.ldv, s.mask, s.ps0, s.ps1, s.ps2, s.part_ld, lpr, rpw, skip, (T*)s.acc,
-                       s.ldacc, s.acc_cols, ntiles, s.active, (const T*)nullptr, 0, off, s.interleave, s.nt_out,
-                       (const uint16_t*)nullptr, cv);
+                       s.ldacc, s.acc_cols, ntiles, s.active, (const T*)nullptr, 0, off, s.interleave, ctiles,
+                       s.nt_out, (const uint16_t*)nullptr, cv);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess || !skip) return e;
     hipLaunchKernelGGL((long_row_kernel<T, VEC, KIND, FIRST>), dim3(kLongWgs), dim3(256), 0, st,
@@ -2008,30 +2038,40 @@ hipError_t launch_axpby(bool f64, long long len, double a, const void* x, double
 }
 
 // ---------------------------------------------------------------------------
-// Adjoint step of the reverse sweep.  For each stored entry (r, c) of A the
-// derivative of tr(L^T P(T) R) picks up alpha * <lam_{i+1}[r, :], w_i[c, :]>
-// (an SDDMM on A's pattern), and the Horner adjoint moves on:
-//   lam_i = alpha*A*lam_{i+1} - beta_i*lam_{i+1} + d_i L   (A symmetric).
+// Gradient sweep step: one Newton step of a block `lam` fused with an SDDMM on
+// A's pattern.  For each stored entry (r, c) of A the gradient (FP64) picks up
+//   alpha * sum_cols own[r, col] * w[c, col]
+// and the block moves on (A symmetric):
+//   ADJ_HORNER:  out = alpha*A*lam - beta*lam + dj*L,        own = lam[r]
+//                (the Horner adjoint of the Newton form: lam_i from lam_{i+1})
+//   ADJ_PLAIN:   out = alpha*A*lam - beta*lam,               own = lam[r]
+//                (the forward Newton vectors of the sketch's cotangent)
+//   ADJ_SQUARED: out = alpha*A*lam - beta*lam + q0*w[r] + q1*(alpha*A*w - beta*w)[r],
+//                own = wgt(col) * (lam[r] + p1*w[r])
+//                (the adjoint of the quadratic forms in the squared Newton basis:
+//                lam = mu~_{i+1}, w = u_i, q0 = 2c_{2i}, q1 = 2c_{2i+1}, p1 = c_{2i+1},
+//                wgt = 1 on the first wsplit columns and whi after them)
 // Row groups of LPR lanes (a power of two) own one row; lane li holds the
-// columns (q*LPR + li)*VEC + [0, VEC) for q < CPL.  A row's entries go in
-// batches of NB = min(LPR, kAdjBatch): the batch's gathers of w and lam are
-// issued together, then the NB per-lane partial dot products are reduced
-// across the row group (butterfly over the lane bits >= NB, then a
-// reduce-scatter over the low bits, NB-1 shuffles) so that lane li ends with
-// entry li's sum and the batch's gradient entries are read (ahead of the
-// gathers) and written by NB adjacent lanes.  Each entry's gradient is owned
-// by one lane: no atomics.  The workgroup's CSR slice is staged in LDS when it
-// fits.
+// columns (q*LPR + li)*VEC + [0, VEC) for q < CPL (chunks at or past ld are
+// not loaded).  A row's entries go in batches of NB = min(LPR, kAdjBatch):
+// the batch's gathers of w and lam are issued together, then the NB per-lane
+// partial dot products (FP64) are reduced across the row group (butterfly
+// over the lane bits >= NB, then a reduce-scatter over the low bits, NB-1
+// shuffles) so that lane li ends with entry li's sum and the batch's gradient
+// entries are read (ahead of the gathers) and written by NB adjacent lanes.
+// Each entry's gradient is owned by one lane: no atomics.  The workgroup's
+// CSR slice is staged in LDS when it fits.
 // ---------------------------------------------------------------------------
-template <typename T, int VEC, int LPR, int CPL>
+template <typename T, int VEC, int LPR, int CPL, int MODE>
 __global__ __launch_bounds__(kThreads) void adjoint_kernel(
     int n, const int* __restrict__ row_ptr, const int* __restrict__ col_idx,
     const T* __restrict__ val, const T* __restrict__ lam_in, T* __restrict__ lam_out,
-    const T* __restrict__ w, const T* __restrict__ L, T* __restrict__ grad, int ld, int ncols,
-    T alpha, T beta, T dj, int first, int last, int nt_out) {
+    const T* __restrict__ w, const T* __restrict__ L, double* __restrict__ grad, int ld, int ncols,
+    T alpha, T beta, T dj, T q0, T q1, T p1, int wsplit, T whi, int first, int last, int nt_out) {
     constexpr int RPW = 64 / LPR;
     constexpr int NB = LPR < kAdjBatch ? LPR : kAdjBatch;
     constexpr int rows_per_wg = kWaves * RPW;
+    constexpr bool kSq = MODE == ADJ_SQUARED;
     __shared__ int s_rp[rows_per_wg + 1];
     __shared__ int s_col[kAdjStageNz];
     __shared__ T s_val[kAdjStageNz];
@@ -2054,18 +2094,32 @@ __global__ __launch_bounds__(kThreads) void adjoint_kernel(
     const int lr = wave * RPW + g;
     if (lr >= nrows) return;                     // whole row groups leave together
     const int row = R0 + lr;
+    bool inld[CPL];                              // the lane's chunk lies inside the row
     bool valid[CPL][VEC];
-    Pack<T, VEC> own[CPL], Lr[CPL];
-    T acc[CPL][VEC];
+    Pack<T, VEC> own[CPL], Lr[CPL], wr[CPL];
+    T sown[CPL][VEC];                            // this row's side of the SDDMM
+    T acc[CPL][VEC], accw[CPL][VEC];
 #pragma unroll
     for (int q = 0; q < CPL; ++q) {
-        const size_t off = (size_t)row * ld + (q * LPR + li) * VEC;
-        own[q] = load_pack<T, VEC>(lam_in + off);
-        if (!last) Lr[q] = load_pack<T, VEC>(L + off);   // fetched early: used at the end
+        const int c0 = (q * LPR + li) * VEC;
+        inld[q] = c0 < ld;
+        const size_t off = (size_t)row * ld + c0;
 #pragma unroll
         for (int e = 0; e < VEC; ++e) {
-            valid[q][e] = (q * LPR + li) * VEC + e < ncols;
-            acc[q][e] = T(0);
+            own[q].v[e] = Lr[q].v[e] = wr[q].v[e] = T(0);
+            valid[q][e] = c0 + e < ncols;
+            acc[q][e] = accw[q][e] = T(0);
+        }
+        if (inld[q]) {
+            own[q] = load_pack<T, VEC>(lam_in + off);
+            if (MODE == ADJ_HORNER && !last) Lr[q] = load_pack<T, VEC>(L + off);   // fetched early: used at the end
+            if (kSq) wr[q] = load_pack<T, VEC>(w + off);
+        }
+#pragma unroll
+        for (int e = 0; e < VEC; ++e) {
+            T so = own[q].v[e];
+            if (kSq) so = (c0 + e < wsplit ? T(1) : whi) * fma(p1, wr[q].v[e], so);
+            sown[q][e] = valid[q][e] ? so : T(0);
         }
     }
     const int beg = s_rp[lr], end = s_rp[lr + 1];
@@ -2073,7 +2127,7 @@ __global__ __launch_bounds__(kThreads) void adjoint_kernel(
         // the gradient entry this lane updates, fetched ahead of the gathers
         const int kg = kb + li;
         const bool owner = li < NB && kg < end;
-        T gold = T(0);
+        double gold = 0.0;
         if (owner && !first) gold = grad[kg];
         int cidx[NB];
         T a[NB];
@@ -2087,18 +2141,23 @@ __global__ __launch_bounds__(kThreads) void adjoint_kernel(
                 a[u] = staged ? s_val[k - K0] : val[k];
             }
         }
-        T part[NB];
+        double part[NB];
 #pragma unroll
         for (int u = 0; u < NB; ++u) {
-            part[u] = T(0);
+            part[u] = 0.0;
             if (kb + u < end) {
 #pragma unroll
                 for (int q = 0; q < CPL; ++q) {
+                    if (!inld[q]) continue;
                     const size_t off = (size_t)cidx[u] * ld + (q * LPR + li) * VEC;
                     const Pack<T, VEC> wc = load_pack<T, VEC>(w + off);
 #pragma unroll
-                    for (int e = 0; e < VEC; ++e)
-                        part[u] = valid[q][e] ? fma(own[q].v[e], wc.v[e], part[u]) : part[u];
+                    for (int e = 0; e < VEC; ++e)   // a select: padding columns may hold anything
+                        part[u] = valid[q][e] ? fma((double)sown[q][e], (double)wc.v[e], part[u]) : part[u];
+                    if (kSq) {
+#pragma unroll
+                        for (int e = 0; e < VEC; ++e) accw[q][e] = fma(a[u], wc.v[e], accw[q][e]);
+                    }
                     if (!last) {
                         const Pack<T, VEC> lc = load_pack<T, VEC>(lam_in + off);
 #pragma unroll
@@ -2118,21 +2177,26 @@ __global__ __launch_bounds__(kThreads) void adjoint_kernel(
             const bool hi = (li & h) != 0;
 #pragma unroll
             for (int j = 0; j < h; ++j) {
-                const T send = hi ? part[j] : part[j + h];
-                const T keep = hi ? part[j + h] : part[j];
+                const double send = hi ? part[j] : part[j + h];
+                const double keep = hi ? part[j + h] : part[j];
                 part[j] = keep + __shfl_xor(send, h, 64);
             }
         }
-        if (owner) grad[kg] = gold + alpha * part[0];
+        if (owner) grad[kg] = fma((double)alpha, part[0], gold);
     }
     if (!last) {
 #pragma unroll
         for (int q = 0; q < CPL; ++q) {
+            if (!inld[q]) continue;
             const size_t off = (size_t)row * ld + (q * LPR + li) * VEC;
             Pack<T, VEC> o;
 #pragma unroll
-            for (int e = 0; e < VEC; ++e)
-                o.v[e] = fma(dj, Lr[q].v[e], alpha * acc[q][e] - beta * own[q].v[e]);
+            for (int e = 0; e < VEC; ++e) {
+                T x = alpha * acc[q][e] - beta * own[q].v[e];
+                if (MODE == ADJ_HORNER) x = fma(dj, Lr[q].v[e], x);
+                if (kSq) x = fma(q1, alpha * accw[q][e] - beta * wr[q].v[e], fma(q0, wr[q].v[e], x));
+                o.v[e] = x;
+            }
             if (nt_out)
                 store_pack_nt<T, VEC>(lam_out + off, o);
             else
@@ -2141,16 +2205,27 @@ __global__ __launch_bounds__(kThreads) void adjoint_kernel(
     }
 }
 
-template <typename T, int VEC, int LPR, int CPL>
-hipError_t launch_adjoint_t(const CsrDev& A, const AdjArgs& a, hipStream_t st) {
+template <typename T, int VEC, int LPR, int CPL, int MODE>
+hipError_t launch_adjoint_m(const CsrDev& A, const AdjArgs& a, hipStream_t st) {
     constexpr int rows_per_wg = kWaves * (64 / LPR);
     const int nwg = div_up(A.n, rows_per_wg);
     if (nwg == 0) return hipSuccess;
-    hipLaunchKernelGGL((adjoint_kernel<T, VEC, LPR, CPL>), dim3(nwg), dim3(kThreads), 0, st, A.n,
+    hipLaunchKernelGGL((adjoint_kernel<T, VEC, LPR, CPL, MODE>), dim3(nwg), dim3(kThreads), 0, st, A.n,
                        A.row_ptr, A.col_idx, (const T*)A.val, (const T*)a.lam_in, (T*)a.lam_out,
-                       (const T*)a.w, (const T*)a.L, (T*)a.grad, a.ld, a.ncols, (T)a.alpha, (T)a.beta,
-                       (T)a.dj, (int)a.first, (int)a.last, (int)a.nt_out);
+                       (const T*)a.w, (const T*)a.L, a.grad, a.ld, a.ncols, (T)a.alpha, (T)a.beta,
+                       (T)a.dj, (T)a.q0, (T)a.q1, (T)a.p1, a.wsplit, (T)a.whi, (int)a.first, (int)a.last,
+                       (int)a.nt_out);
     return hipGetLastError();
+}
+
+template <typename T, int VEC, int LPR, int CPL>
+hipError_t launch_adjoint_t(const CsrDev& A, const AdjArgs& a, hipStream_t st) {
+    switch (a.mode) {
+        case ADJ_HORNER: return launch_adjoint_m<T, VEC, LPR, CPL, ADJ_HORNER>(A, a, st);
+        case ADJ_PLAIN: return launch_adjoint_m<T, VEC, LPR, CPL, ADJ_PLAIN>(A, a, st);
+        case ADJ_SQUARED: return launch_adjoint_m<T, VEC, LPR, CPL, ADJ_SQUARED>(A, a, st);
+        default: return hipErrorInvalidValue;
+    }
 }
 
 template <typename T, int VEC>
@@ -2160,8 +2235,9 @@ hipError_t launch_adjoint_v(const CsrDev& A, const AdjArgs& a, hipStream_t st) {
     while (lp2 < lanes) lp2 <<= 1;
     const int cpl = lp2 > 64 ? lp2 / 64 : 1;
     const int lpr = lp2 > 64 ? 64 : lp2;
-    // every lane's vectors must lie inside the row: ld covers the padded row group
-    if (cpl > 2 || lpr * cpl * VEC > a.ld || a.ld % VEC) return hipErrorInvalidValue;
+    // every used column lies in the row (ld >= ncols, ld a multiple of VEC);
+    // lanes whose chunk starts at or past ld load nothing
+    if (cpl > 2 || a.ncols > a.ld || a.ld % VEC) return hipErrorInvalidValue;
     if (cpl == 2) return launch_adjoint_t<T, VEC, 64, 2>(A, a, st);
     switch (lpr) {
         case 1: return launch_adjoint_t<T, VEC, 1, 1>(A, a, st);
@@ -2172,6 +2248,57 @@ hipError_t launch_adjoint_v(const CsrDev& A, const AdjArgs& a, hipStream_t st) {
         case 32: return launch_adjoint_t<T, VEC, 32, 1>(A, a, st);
         default: return launch_adjoint_t<T, VEC, 64, 1>(A, a, st);
     }
+}
+
+// ---------------------------------------------------------------------------
+// g[e] and g[e'] of every mirrored pair of entries e = (r, c), e' = (c, r)
+// become their mean; diagonal entries stay.  The pair is owned by its row r <
+// c (one thread per row, grid-stride), which finds e' by binary search in row
+// c (sorted columns); a missing mirror (the pattern is not symmetric) sets
+// *flag to 1.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(kThreads) void symmetrize_kernel(int n, const int* __restrict__ row_ptr,
+                                                             const int* __restrict__ col_idx,
+                                                             double* __restrict__ g, int* __restrict__ flag) {
+    for (int r = blockIdx.x * kThreads + threadIdx.x; r < n; r += gridDim.x * kThreads) {
+        const int b = row_ptr[r], e = row_ptr[r + 1];
+        for (int k = b; k < e; ++k) {
+            const int c = col_idx[k];
+            if (c <= r) continue;
+            int lo = row_ptr[c], hi = row_ptr[c + 1];
+            while (lo < hi) {   // first position in row c with column >= r
+                const int mid = (lo + hi) >> 1;
+                if (col_idx[mid] < r) lo = mid + 1;
+                else hi = mid;
+            }
+            if (lo < row_ptr[c + 1] && col_idx[lo] == r) {
+                const double m = 0.5 * (g[k] + g[lo]);
+                g[k] = m;
+                g[lo] = m;
+            } else {
+                *flag = 1;
+            }
+        }
+    }
+}
+
+hipError_t launch_symmetrize(const CsrDev& A, double* g, int* flag, hipStream_t st) {
+    if (A.n == 0) return hipSuccess;
+    const int nwg = std::min(div_up(A.n, kThreads), 4096);
+    hipLaunchKernelGGL(symmetrize_kernel, dim3(nwg), dim3(kThreads), 0, st, A.n, A.row_ptr, A.col_idx, g, flag);
+    return hipGetLastError();
+}
+
+__global__ __launch_bounds__(kThreads) void narrow_kernel(long long len, const double* __restrict__ x,
+                                                          float* __restrict__ y) {
+    const long long i = (long long)blockIdx.x * kThreads + threadIdx.x;
+    if (i < len) y[i] = (float)x[i];
+}
+
+hipError_t launch_narrow(long long len, const double* x, float* y, hipStream_t st) {
+    if (len == 0) return hipSuccess;
+    hipLaunchKernelGGL(narrow_kernel, dim3(div_up(len, kThreads)), dim3(kThreads), 0, st, len, x, y);
+    return hipGetLastError();
 }
 
 hipError_t launch_adjoint(bool f64, const CsrDev& A, const AdjArgs& a, hipStream_t st) {

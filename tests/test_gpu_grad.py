@@ -126,14 +126,16 @@ def test_grad_gmrf2048_finite_difference_full_size():
 
 
 @pytest.mark.parametrize("dtype,tol", [(torch.float64, 1e-9), (torch.float32, 2e-4)])
-def test_grad_gaussian_probes(dtype, tol):
+@pytest.mark.parametrize("stride", [0, 4])
+def test_grad_gaussian_probes(dtype, tol, stride):
     # Gaussian S and G (the paper's other probe choice): stored probe blocks
-    # in the forward pass and the reverse sweep alike
+    # in the forward pass and the reverse sweep alike; with checkpoints the
+    # sketch's Horner vectors are recomputed from a regenerated S
     csr = random_spd_csr(300, 5, long_rows=2)
     A, vals = to_gpu(csr, dtype)
     csr_v = (csr[0], csr[1], vals, csr[3])
     lmin, lmax = bounds.gershgorin(csr_v)
-    est, g = ld.logdet_with_grad(A, lmin, lmax, 30, 21, 6, options=ld.Options(probe_dist=1))
+    est, g = ld.logdet_with_grad(A, lmin, lmax, 30, 21, 6, options=ld.Options(probe_dist=1, ckpt_stride=stride))
     ref_est, ref_g = ograd.logdet_grad(csr_v, lmin, lmax, 30, 21, 6, probes="gaussian")
     assert abs(est - ref_est) / abs(ref_est) < (1e-10 if dtype == torch.float64 else 1e-5)
     assert_cols_close(g.double().cpu().numpy(), ref_g, tol)
@@ -198,3 +200,41 @@ def test_grad_gmrf2048_fp32_against_fp64_finite_differences():
     assert abs(est32 - ld.logdet(A64, lmin, lmax, deg, mv, 0)) < 1e-4 * abs(est32)
     assert d_tau == pytest.approx(fd_tau, rel=1e-5)
     assert d_kap == pytest.approx(fd_kap, rel=1e-5)
+
+
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
+def test_grad_both_paths_agree(dtype):
+    # The squared-basis path (default) and the Newton-form path (forced by
+    # the forward quadratic-form mode) compute the same derivative in
+    # different orders: both against the oracle, and the estimate of the
+    # squared path equals the estimate entry point's bit for bit.
+    csr = random_spd_csr(2000, 8, long_rows=2)
+    A, vals = to_gpu(csr, dtype)
+    csr_v = (csr[0], csr[1], vals, csr[3])
+    lmin, lmax = bounds.gershgorin(csr_v)
+    lmin = max(lmin, 0.3)
+    ref_est, ref_g = ograd.logdet_grad(csr_v, lmin, lmax, 31, 24, 4)
+    tol = 1e-9 if dtype == torch.float64 else 2e-4
+    e_sq, g_sq, st_sq = ld.logdet_with_grad(A, lmin, lmax, 31, 24, 4, return_stats=True)
+    e_nf, g_nf, st_nf = ld.logdet_with_grad(A, lmin, lmax, 31, 24, 4, options=ld.Options(dot_mode=ld.LD_DOT_FORWARD),
+                                            return_stats=True)
+    assert st_sq["dot_mode_used"] == ld.LD_DOT_SQUARED and st_nf["dot_mode_used"] == ld.LD_DOT_FORWARD
+    assert e_sq == ld.logdet(A, lmin, lmax, 31, 24, 4)
+    for e, g in ((e_sq, g_sq), (e_nf, g_nf)):
+        assert abs(e - ref_est) < (1e-10 if dtype == torch.float64 else 1e-5) * abs(ref_est)
+        assert_cols_close(g.double().cpu().numpy(), ref_g, tol)
+
+
+def test_grad_gmrf2048_checkpoint_stride_is_exact():
+    """2048 x 2048 GMRF, degree 100, 32 probes, FP32: sqrt(m) checkpoints
+    (stride 10: the stored vectors recomputed segment by segment) give the
+    same gradient, bit for bit, as keeping every vector."""
+    N, k2, tau, deg, mv = 2048, 0.1, 1.5, 100, 32
+    csr = w.grid_laplacian_2d(N, k2, tau=tau)
+    A, _ = to_gpu(csr, torch.float32)
+    lmin, lmax = tau * k2 * 0.999, tau * (k2 + 8.0)
+    e1, g1 = ld.logdet_with_grad(A, lmin, lmax, deg, mv, 0, options=ld.Options(ckpt_stride=1))
+    e10, g10 = ld.logdet_with_grad(A, lmin, lmax, deg, mv, 0, options=ld.Options(ckpt_stride=10))
+    assert e1 == e10 and torch.equal(g1, g10)
+    assert ld.workspace_size(A, deg, mv, True, ld.Options(ckpt_stride=10)) < \
+        0.5 * ld.workspace_size(A, deg, mv, True, ld.Options(ckpt_stride=1))

@@ -351,6 +351,8 @@ def test_estimate_full_size_workloads(name, tol32):
     assert lo == pytest.approx(g["lmin"], rel=1e-12) and hi == pytest.approx(g["lmax"], rel=1e-12)
     e32, st = ld.logdet(A32, g["lmin"], g["lmax"], g["degree"], g["m_vec"], 0, return_stats=True)
     assert rel(e32, ref) < tol32, (e32, ref, st["dot_mode_used"])
+    if name == "grid128c_k0.05":   # streams from HBM: XCD bands in chunks of a plane / 8
+        assert st["xcd_chunk_rows"] == 128 * 128 // 8
     e64 = ld.logdet(A64, g["lmin"], g["lmax"], g["degree"], g["m_vec"], 0)
     assert rel(e64, ref) < 1e-10
 
@@ -457,6 +459,33 @@ def test_tile_orders_agree_with_oracle(dtype, tol):
         assert e1 == e2 and torch.equal(g1, g2)
     with pytest.raises(ld.NativeError):
         ld.logdet(A, lo, hi, 30, 24, 4, options=ld.Options(tile_order=3))
+
+
+@pytest.mark.parametrize("dtype,tol", [(torch.float64, 1e-11), (torch.float32, 2e-5)])
+def test_chunked_xcd_bands_for_3d_grids(dtype, tol):
+    # An 80^3 grid: the plane neighbours (6400 rows away) of a contiguous band
+    # would not stay in an XCD's L2 at 32 or 64 columns, so both phases cut
+    # the bands into chunks of 800 rows dealt to the XCDs in turn.  The
+    # recurrence vectors are per-row results (bit-identical to the other
+    # orders), the quadratic forms regroup their sums; both against the oracle.
+    csr = w.grid_laplacian_3d(80, 0.2)
+    A, vals = to_gpu(csr, dtype)
+    csr_v = (csr[0], csr[1], vals, csr[3])
+    lo, hi = bounds.gershgorin(csr_v)
+    ref = hutchpp.logdet_estimate(w.to_scipy(csr_v), lo, hi, 24, 96, 3)
+    est, st = ld.logdet(A, lo, hi, 24, 96, 3, return_stats=True)
+    assert st["tile_order_used"] == 1 and st["xcd_chunk_rows"] == 800
+    assert rel(est, ref) < tol, (est, ref)
+    for order in (1, 2):   # explicit bands are the chunked bands here; interleaved never chunks
+        e, so = ld.logdet(A, lo, hi, 24, 96, 3, options=ld.Options(tile_order=order), return_stats=True)
+        assert so["xcd_chunk_rows"] == (800 if order == 1 else 0)
+        assert rel(e, ref) < tol
+    V = torch.tensor(np.random.default_rng(2).standard_normal((csr[3], 32)), dtype=dtype, device=DEV)
+    out_b = ld.apply_log(A, lo, hi, 20, V, ld.Options(tile_order=1))
+    out_i = ld.apply_log(A, lo, hi, 20, V, ld.Options(tile_order=2))
+    assert torch.equal(out_b, out_i)
+    refv = newton.apply_log(w.to_scipy(csr_v), V.double().cpu().numpy(), lo, hi, 20)
+    assert_cols_close(out_b.double().cpu().numpy(), refv, 1e-12 if dtype == torch.float64 else 2e-5)
 
 
 def test_tile_order_follows_band_balance():
