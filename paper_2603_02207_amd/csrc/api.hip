@@ -363,6 +363,9 @@ struct LongRows {
     const void* dia = nullptr;
     int dia_nd = 0;
     int dia_off[kMaxDiag] = {};
+    // presence bits per row (bit q = the row stores diagonal q) whenever the
+    // diagonal storage is used
+    const uint16_t* pres_bits = nullptr;
     // every diagonal one constant: per-row presence bits and the constants
     const uint16_t* dia_pres = nullptr;
     double dia_cval[kMaxDiag] = {};
@@ -477,6 +480,7 @@ int prepare_rows(const ld_csr* A, const ld_options& o, Arena& ar, hipStream_t st
     if (want_dia && nd >= 1 && nd <= kMaxDiag && !h[12]) {
         lr.dia = buf;
         lr.dia_nd = nd;
+        lr.pres_bits = pres;
         for (int q = 0; q < kMaxDiag; ++q) lr.dia_off[q] = q < nd ? h[1 + q] : 0;
         if (!h[kConstFlag] && !o.csr_only) {   // every diagonal holds one value
             lr.dia_pres = pres;
@@ -1097,6 +1101,25 @@ int gradient_squared(const ld_csr* A, uint64_t seed, EstimateState& S, GradBufs&
     // u_a for a = 0..H: u_0 is X, the others stored or recomputed per segment
     const VecStore& us = B.us;
     const VecStore& rs = B.rs;
+    // on the diagonal storage the sweeps read the diagonals (and take two of
+    // the sketch's adjoint steps per gradient update), else the CSR arrays
+    const LongRows& lr = S.longrows;
+    AdjDia dg{};
+    const bool on_dia = lr.dia_nd > 0 && lr.pres_bits;
+    if (on_dia) {
+        dg.nd = lr.dia_nd;
+        for (int q = 0; q < kMaxDiag; ++q) {
+            dg.off[q] = lr.dia_off[q];
+            dg.cval[q] = lr.dia_cval[q];
+        }
+        dg.pres = lr.pres_bits;
+        dg.dia = lr.dia;
+        dg.constant = lr.dia_pres != nullptr;
+    }
+    auto sweep = [&](const AdjArgs& a) -> int {
+        LD_CHECK_HIP(on_dia ? launch_adjoint_dia(f64, d, a, dg, st) : launch_adjoint(f64, d, a, st));
+        return LD_OK;
+    };
 
     // ---- reverse sweep over [Q_b | U] (weights 1 and 1/k_G), segment by segment
     LD_CHECK_HIP(launch_scale_copy(f64, n, nc, H == 0 ? L.X.base : us.at(H), ldX, 2.0 * coef(2 * H), B.mu[0], ldX,
@@ -1131,7 +1154,7 @@ int gradient_squared(const ld_csr* A, uint64_t seed, EstimateState& S, GradBufs&
             a.first = i == H - 1;
             a.last = false;   // mu~_0 = 2 F [Q_b | U] is needed
             a.nt_out = streams_from_hbm(A, L, ldX);
-            LD_CHECK_HIP(launch_adjoint(f64, d, a, st));
+            LD_CHECK(sweep(a));
             cur = 1 - cur;
         }
     }
@@ -1151,10 +1174,11 @@ int gradient_squared(const ld_csr* A, uint64_t seed, EstimateState& S, GradBufs&
             LD_CHECK_HIP(launch_sign_mask(n, k, key0, (uint64_t*)S.mask, st));
     }
     int rc = 0;
-    for (int q = 0; q * rs.s < m; ++q) {
+    const int seg = rs.s > 1 ? rs.s : m;   // every vector stored: one segment
+    for (int q = 0; q * seg < m; ++q) {
         // steps j = j0 .. j1-1 read r_j+1 for j+1 in (j0, j1], recomputed
         // downwards from the checkpoint r_j1 when not stored
-        const int j0 = q * rs.s, j1 = std::min(j0 + rs.s, m);
+        const int j0 = q * seg, j1 = std::min(j0 + seg, m);
         std::vector<const void*> r(j1 - j0);   // r[t] = r_{j0+1+t}
         r[j1 - j0 - 1] = rs.slot(j1);
         for (int t = j1 - 1; t > j0; --t) {
@@ -1175,9 +1199,8 @@ int gradient_squared(const ld_csr* A, uint64_t seed, EstimateState& S, GradBufs&
             }
             r[t - j0 - 1] = dst;
         }
-        for (int j = j0; j < j1; ++j) {
+        for (int j = j0; j < j1;) {
             AdjArgs a{};
-            a.mode = ADJ_PLAIN;
             a.lam_in = B.rb[rc];
             a.lam_out = B.rb[1 - rc];
             a.w = r[j - j0];
@@ -1187,10 +1210,23 @@ int gradient_squared(const ld_csr* A, uint64_t seed, EstimateState& S, GradBufs&
             a.alpha = p.alpha;
             a.beta = p.beta[j];
             a.first = false;
-            a.last = j == m - 1;
             a.nt_out = streams_from_hbm(A, L, ldY);
-            LD_CHECK_HIP(launch_adjoint(f64, d, a, st));
-            rc = 1 - rc;
+            if (on_dia && j + 1 < j1) {
+                // steps j and j+1 in one update of the gradient: the launch writes
+                // rbar_j+1, a plain step then makes rbar_j+2 (if a later step needs it)
+                a.mode = ADJ_PLAIN2;
+                a.w2 = r[j + 1 - j0];
+                a.last = j + 2 >= m;   // rbar_j+1 feeds no later step
+                LD_CHECK(sweep(a));
+                if (j + 2 < m) LD_CHECK(plain_step(B.rb[1 - rc], B.rb[rc], j + 1, ldY, k));
+                j += 2;   // rbar_j+2 sits in B.rb[rc]
+            } else {
+                a.mode = ADJ_PLAIN;
+                a.last = j == m - 1;
+                LD_CHECK(sweep(a));
+                rc = 1 - rc;
+                j += 1;
+            }
         }
     }
     int hsym = 0;

@@ -171,12 +171,16 @@ hipError_t launch_gershgorin(bool f64, const CsrDev& A, double* part, hipStream_
 //   ADJ_PLAIN:   lam_out = alpha*A*lam_in - beta*lam_in,         own = lam_in
 //   ADJ_SQUARED: lam_out = alpha*A*lam_in - beta*lam_in + q0*w + q1*(alpha*A*w - beta*w),
 //                own = wgt(col) * (lam_in + p1*w), wgt = 1 for col < wsplit, else whi
-enum AdjMode : int { ADJ_HORNER = 0, ADJ_PLAIN = 1, ADJ_SQUARED = 2 };
+//   ADJ_PLAIN2 (diagonal storage only): ADJ_PLAIN, and the entry also picks up
+//                alpha * sum_cols lam_out[r, col] * w2[c, col] (two steps of the
+//                sketch's adjoint per read and write of the gradient)
+enum AdjMode : int { ADJ_HORNER = 0, ADJ_PLAIN = 1, ADJ_SQUARED = 2, ADJ_PLAIN2 = 3 };
 struct AdjArgs {
     int mode;
     const void* lam_in;
     void* lam_out;
     const void* w;
+    const void* w2;      // ADJ_PLAIN2
     const void* L;
     double* grad;
     int ld, ncols;
@@ -189,6 +193,20 @@ struct AdjArgs {
     bool nt_out;     // lam_out written with non-temporal (streaming) stores
 };
 hipError_t launch_adjoint(bool f64, const CsrDev& A, const AdjArgs& a, hipStream_t st);
+
+// The same step on the diagonal storage (modes ADJ_PLAIN, ADJ_PLAIN2,
+// ADJ_SQUARED): presence bits per row (pres), the values either one per
+// diagonal (constant) or dia[r*nd + q]; the gradient at A's CSR positions
+// (row_ptr of A).
+struct AdjDia {
+    int nd;
+    int off[kMaxDiag];
+    const uint16_t* pres;
+    const void* dia;
+    bool constant;
+    double cval[kMaxDiag];
+};
+hipError_t launch_adjoint_dia(bool f64, const CsrDev& A, const AdjArgs& a, const AdjDia& dg, hipStream_t st);
 
 // Mean of every mirrored pair g[(r,c)], g[(c,r)] (FP64, CSR positions); *flag
 // (device int) set to 1 when some entry has no mirror.

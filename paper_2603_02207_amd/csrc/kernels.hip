@@ -2251,6 +2251,204 @@ hipError_t launch_adjoint_v(const CsrDev& A, const AdjArgs& a, hipStream_t st) {
 }
 
 // ---------------------------------------------------------------------------
+// Gradient sweep step on the diagonal storage (stencils, banded matrices):
+// row r's stored entries are its present diagonals q (bit q of pres[r]), in
+// offset order, so entry (r, r + off[q]) sits at CSR position row_ptr[r] +
+// (number of present diagonals below q) and the gradient keeps A's CSR
+// layout.  A row group of LPR lanes (a power of two, VEC columns per lane;
+// chunks at or past ld load nothing) owns one row: it issues the ND gathers
+// of lam and of w together, forms the Newton step as ADJ_PLAIN / ADJ_SQUARED
+// of adjoint_kernel, and reduces the ND per-lane FP64 partial dot products
+// over the row group by a butterfly; lane q then updates entry q.
+// ADJ_PLAIN2 does two steps of the sketch's adjoint in one launch: with
+// out = rbar_j+1[r] computed from the gathered rbar_j, the entry also picks up
+// alpha * <out, w2[c]> (w2 = r_j+2), so the gradient is read and written once
+// for two steps; the next launch only needs rbar_j+1 -> rbar_j+2.
+// Matrix values: one per diagonal (cv) when `dpres` is the constant-value
+// mode, else dia[r*nd + q].
+// ---------------------------------------------------------------------------
+template <typename T, int VEC, int LPR, int ND, int MODE>
+__global__ __launch_bounds__(kThreads) void adjoint_dia_kernel(
+    int n, const int* __restrict__ row_ptr, const uint16_t* __restrict__ pres, const T* __restrict__ dia, int nd,
+    DiaOff off, DiaVal<T> cv, int constant, const T* __restrict__ lam_in, T* __restrict__ lam_out,
+    const T* __restrict__ w, const T* __restrict__ w2, double* __restrict__ grad, int ld, int ncols, T alpha,
+    T beta, T q0, T q1, T p1, int wsplit, T whi, int first, int last, int nt_out) {
+    static_assert(MODE == ADJ_PLAIN || MODE == ADJ_PLAIN2 || MODE == ADJ_SQUARED, "diagonal-storage modes");
+    constexpr int RPW = 64 / LPR;
+    constexpr int rows_per_wg = kWaves * RPW;
+    constexpr bool kSq = MODE == ADJ_SQUARED;
+    constexpr bool kTwo = MODE == ADJ_PLAIN2;
+    constexpr int PER = (ND + LPR - 1) / LPR;   // gradient entries per lane
+    const int lane = threadIdx.x & 63;
+    const int wave = threadIdx.x >> 6;
+    const int g = lane / LPR;
+    const int li = lane - g * LPR;
+    const int row = xcd_tile(blockIdx.x, gridDim.x) * rows_per_wg + wave * RPW + g;
+    if (row >= n) return;                         // whole row groups leave together
+    const int c0 = li * VEC;
+    const bool inld = c0 < ld;
+    const unsigned bits = pres[row];
+    const int rp = row_ptr[row];
+    // this lane's gradient entries (diagonals q = li, li + LPR, ...), read
+    // ahead of the gathers
+    int kgs[PER];
+    bool on[PER];
+    double gold[PER];
+#pragma unroll
+    for (int t = 0; t < PER; ++t) {
+        const int q = li + t * LPR;
+        on[t] = q < nd && q < ND && ((bits >> q) & 1u);
+        kgs[t] = rp + __popc(bits & ((1u << q) - 1u));
+        gold[t] = on[t] && !first ? grad[kgs[t]] : 0.0;
+    }
+    int cq[ND];
+    T aq[ND];
+#pragma unroll
+    for (int q = 0; q < ND; ++q) {
+        const int c = row + off.o[q];
+        const bool ok = q < nd && ((bits >> q) & 1u) && (unsigned)c < (unsigned)n;
+        cq[q] = ok ? c : row;
+        aq[q] = ok ? (constant ? cv.c[q] : dia[(size_t)row * nd + q]) : T(0);
+    }
+    // every gather of the row in flight at once
+    Pack<T, VEC> own, wr, lq[ND], wq[ND], w2q[kTwo ? ND : 1];
+#pragma unroll
+    for (int e = 0; e < VEC; ++e) own.v[e] = wr.v[e] = T(0);
+#pragma unroll
+    for (int q = 0; q < ND; ++q)
+#pragma unroll
+        for (int e = 0; e < VEC; ++e) {
+            lq[q].v[e] = wq[q].v[e] = T(0);
+            if (kTwo) w2q[q].v[e] = T(0);
+        }
+    if (inld) {
+        own = load_pack<T, VEC>(lam_in + (size_t)row * ld + c0);
+        if (kSq) wr = load_pack<T, VEC>(w + (size_t)row * ld + c0);
+#pragma unroll
+        for (int q = 0; q < ND; ++q) {
+            wq[q] = load_pack<T, VEC>(w + (size_t)cq[q] * ld + c0);
+            lq[q] = load_pack<T, VEC>(lam_in + (size_t)cq[q] * ld + c0);
+            if (kTwo) w2q[q] = load_pack<T, VEC>(w2 + (size_t)cq[q] * ld + c0);
+        }
+    }
+    bool valid[VEC];
+    T sown[VEC];
+#pragma unroll
+    for (int e = 0; e < VEC; ++e) {
+        valid[e] = inld && c0 + e < ncols;
+        T so = own.v[e];
+        if (kSq) so = (c0 + e < wsplit ? T(1) : whi) * fma(p1, wr.v[e], so);
+        sown[e] = valid[e] ? so : T(0);
+    }
+    // the Newton step (same products in the same order as the step kernels)
+    T acc[VEC], accw[VEC];
+#pragma unroll
+    for (int e = 0; e < VEC; ++e) acc[e] = accw[e] = T(0);
+#pragma unroll
+    for (int q = 0; q < ND; ++q)
+#pragma unroll
+        for (int e = 0; e < VEC; ++e) {
+            acc[e] = fma(aq[q], lq[q].v[e], acc[e]);
+            if (kSq) accw[e] = fma(aq[q], wq[q].v[e], accw[e]);
+        }
+    Pack<T, VEC> o;
+#pragma unroll
+    for (int e = 0; e < VEC; ++e) {
+        T x = alpha * acc[e] - beta * own.v[e];
+        if (kSq) x = fma(q1, alpha * accw[e] - beta * wr.v[e], fma(q0, wr.v[e], x));
+        o.v[e] = x;
+    }
+    if (!last && inld) {
+        if (nt_out)
+            store_pack_nt<T, VEC>(lam_out + (size_t)row * ld + c0, o);
+        else
+            store_pack<T, VEC>(lam_out + (size_t)row * ld + c0, o);
+    }
+    // per-entry partial dot products (a select: padding columns may hold anything)
+    double part[ND];
+#pragma unroll
+    for (int q = 0; q < ND; ++q) {
+        part[q] = 0.0;
+#pragma unroll
+        for (int e = 0; e < VEC; ++e)
+            part[q] = valid[e] ? fma((double)sown[e], (double)wq[q].v[e], part[q]) : part[q];
+        if (kTwo) {
+#pragma unroll
+            for (int e = 0; e < VEC; ++e)
+                part[q] = valid[e] ? fma((double)o.v[e], (double)w2q[q].v[e], part[q]) : part[q];
+        }
+    }
+#pragma unroll
+    for (int h = LPR / 2; h >= 1; h >>= 1)
+#pragma unroll
+        for (int q = 0; q < ND; ++q) part[q] += __shfl_xor(part[q], h, 64);
+#pragma unroll
+    for (int t = 0; t < PER; ++t) {
+        double v = 0.0;
+#pragma unroll
+        for (int q = 0; q < ND; ++q) v = q == li + t * LPR ? part[q] : v;
+        if (on[t]) grad[kgs[t]] = first ? (double)alpha * v : fma((double)alpha, v, gold[t]);
+    }
+}
+
+template <typename T, int VEC, int LPR, int ND>
+hipError_t launch_adjoint_dia_t(const CsrDev& A, const AdjArgs& a, const AdjDia& dg, hipStream_t st) {
+    constexpr int rows_per_wg = kWaves * (64 / LPR);
+    const int nwg = div_up(A.n, rows_per_wg);
+    if (nwg == 0) return hipSuccess;
+    DiaOff off{};
+    DiaVal<T> cv{};
+    for (int q = 0; q < kMaxDiag; ++q) {
+        off.o[q] = q < dg.nd ? dg.off[q] : 0;
+        cv.c[q] = (T)(q < dg.nd ? dg.cval[q] : 0.0);
+    }
+#define LD_ADJ_DIA(M_)                                                                                          \
+    hipLaunchKernelGGL((adjoint_dia_kernel<T, VEC, LPR, ND, M_>), dim3(nwg), dim3(kThreads), 0, st, A.n, A.row_ptr, \
+                       dg.pres, (const T*)dg.dia, dg.nd, off, cv, (int)dg.constant, (const T*)a.lam_in,          \
+                       (T*)a.lam_out, (const T*)a.w, (const T*)a.w2, a.grad, a.ld, a.ncols, (T)a.alpha,          \
+                       (T)a.beta, (T)a.q0, (T)a.q1, (T)a.p1, a.wsplit, (T)a.whi, (int)a.first, (int)a.last,      \
+                       (int)a.nt_out)
+    switch (a.mode) {
+        case ADJ_PLAIN: LD_ADJ_DIA(ADJ_PLAIN); break;
+        case ADJ_PLAIN2: LD_ADJ_DIA(ADJ_PLAIN2); break;
+        case ADJ_SQUARED: LD_ADJ_DIA(ADJ_SQUARED); break;
+        default: return hipErrorInvalidValue;
+    }
+#undef LD_ADJ_DIA
+    return hipGetLastError();
+}
+
+template <typename T, int VEC, int LPR>
+hipError_t launch_adjoint_dia_l(const CsrDev& A, const AdjArgs& a, const AdjDia& dg, hipStream_t st) {
+    if (dg.nd <= 3) return launch_adjoint_dia_t<T, VEC, LPR, 3>(A, a, dg, st);
+    if (dg.nd <= 5) return launch_adjoint_dia_t<T, VEC, LPR, 5>(A, a, dg, st);
+    if (dg.nd <= 7) return launch_adjoint_dia_t<T, VEC, LPR, 7>(A, a, dg, st);
+    return launch_adjoint_dia_t<T, VEC, LPR, 9>(A, a, dg, st);
+}
+
+template <typename T, int VEC>
+hipError_t launch_adjoint_dia_v(const CsrDev& A, const AdjArgs& a, const AdjDia& dg, hipStream_t st) {
+    const int lanes = lanes_per_row(a.ncols, VEC);
+    int lpr = 1;   // a power of two
+    while (lpr < lanes) lpr <<= 1;
+    if (lpr > 64 || a.ncols > a.ld || a.ld % VEC || dg.nd < 1 || dg.nd > kMaxDiag) return hipErrorInvalidValue;
+    switch (lpr) {
+        case 1: return launch_adjoint_dia_l<T, VEC, 1>(A, a, dg, st);
+        case 2: return launch_adjoint_dia_l<T, VEC, 2>(A, a, dg, st);
+        case 4: return launch_adjoint_dia_l<T, VEC, 4>(A, a, dg, st);
+        case 8: return launch_adjoint_dia_l<T, VEC, 8>(A, a, dg, st);
+        case 16: return launch_adjoint_dia_l<T, VEC, 16>(A, a, dg, st);
+        case 32: return launch_adjoint_dia_l<T, VEC, 32>(A, a, dg, st);
+        default: return launch_adjoint_dia_l<T, VEC, 64>(A, a, dg, st);
+    }
+}
+
+hipError_t launch_adjoint_dia(bool f64, const CsrDev& A, const AdjArgs& a, const AdjDia& dg, hipStream_t st) {
+    if (f64) return launch_adjoint_dia_v<double, 2>(A, a, dg, st);
+    return launch_adjoint_dia_v<float, 4>(A, a, dg, st);
+}
+
+// ---------------------------------------------------------------------------
 // g[e] and g[e'] of every mirrored pair of entries e = (r, c), e' = (c, r)
 // become their mean; diagonal entries stay.  The pair is owned by its row r <
 // c (one thread per row, grid-stride), which finds e' by binary search in row
