@@ -645,7 +645,23 @@ def run_workload(args, workload, steps):
                            "ms_gradient_part": stg["ms_adjoint"],
                            "call_over_estimate": dtg * 1e3 / t_est,
                            "extra_over_estimate": (dtg * 1e3 - t_est) / t_est,
-                           "ckpt_stride": "auto (every forward vector kept when they fit 64 GiB)"}
+                           "path": {2: "squared Newton basis", 1: "Newton form"}[stg["dot_mode_used"]],
+                           "ckpt_stride": "auto (every stored vector kept when they fit 64 GiB)",
+                           "workspace_GB": ld.workspace_size(A32, degree, m_vec, True, opts) / 1e9}
+        # sqrt(m) checkpoints: a fraction of the memory, segments recomputed
+        s_ck = max(1, math.ceil(math.sqrt(degree)))
+        o_ck = ld.Options(block_cols=args.block_cols, dot_mode=mode, trusted_csr=1, tile_order=tiles,
+                          ckpt_stride=s_ck)
+        ld.logdet_with_grad(A32, lmin, lmax, degree, m_vec, args.seed, options=o_ck)
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        for _ in range(k_g):
+            ld.logdet_with_grad(A32, lmin, lmax, degree, m_vec, args.seed, options=o_ck)
+        torch.cuda.synchronize()
+        dtc = (time.perf_counter() - t) / k_g
+        out["gradient"]["sqrt_m_checkpoints"] = {
+            "ckpt_stride": s_ck, "ms_estimate_and_gradient": dtc * 1e3, "call_over_estimate": dtc * 1e3 / t_est,
+            "workspace_GB": ld.workspace_size(A32, degree, m_vec, True, o_ck) / 1e9}
 
     if args.adaptive_tol > 0:
         out["apply_log_adaptive"] = time_adaptive(ld, A32, lmin, lmax, degree, st["k"], args.adaptive_tol, n,
