@@ -873,8 +873,10 @@ std::vector<double> diag_matrix(int q, double v) {
 }
 
 // The basis term's left factor: writes 2Z (k columns) into `dst`/`dd`, from
-// F [Q_b | U] in L.FX.  Slot 2 holds C = Q_b^T G from the deflation.
-int basis_term(const ld_csr* A, uint64_t seed, EstimateState& S, GradBufs& B, void* dst, Blk dd, hipStream_t st) {
+// fx = s F [Q_b | U] (layout of L.FX; s = 1 or 2, zscale = 2/s: the algebra
+// is linear in fx).  Slot 2 holds C = Q_b^T G from the deflation.
+int basis_term(const ld_csr* A, uint64_t seed, EstimateState& S, GradBufs& B, const void* fx, double zscale,
+               void* dst, Blk dd, hipStream_t st) {
     const bool f64 = A->dtype == LD_F64;
     const int n = (int)A->n;
     const EstLayout& L = S.L;
@@ -900,11 +902,10 @@ int basis_term(const ld_csr* A, uint64_t seed, EstimateState& S, GradBufs& B, vo
     for (int i = 0; i < k; ++i)
         for (int j = 0; j < kg; ++j) Ct[(size_t)j * k + i] = C[(size_t)i * kg + j];
     LD_CHECK(upload(Ct, slot[3], st));
-    LD_CHECK(cross_product(f64, n, L.X.base, X.shifted(k), kg, L.FX.base, FXd, k, nullptr, S.part,
-                           slot[4], st));
+    LD_CHECK(cross_product(f64, n, L.X.base, X.shifted(k), kg, fx, FXd, k, nullptr, S.part, slot[4], st));
     // T1 = F Q_b - c F U C^T ; then T1 -= c G M1  (= X Q_b of the derivation)
-    LD_CHECK_HIP(launch_rowmat(f64, n, L.FX.base, FXd.shifted(k), kg, slot[3], k, -c, nullptr,
-                               L.FX.base, FXd, L.T1.base, Td, st));
+    LD_CHECK_HIP(launch_rowmat(f64, n, fx, FXd.shifted(k), kg, slot[3], k, -c, nullptr, fx, FXd, L.T1.base, Td,
+                               st));
     LD_CHECK_HIP(launch_rowmat(f64, n, L.Gm.base, Gd, kg, slot[4], k, -c, nullptr, L.T1.base, Td,
                                L.T1.base, Td, st));
     // P = T1 - Q_b (Q_b^T T1)
@@ -930,8 +931,8 @@ int basis_term(const ld_csr* A, uint64_t seed, EstimateState& S, GradBufs& B, vo
     for (int i = 0; i < k; ++i)
         for (int j = 0; j < k; ++j) RinvT[(size_t)i * k + j] = Rinv[(size_t)j * k + i];
     LD_CHECK(upload(RinvT, slot[6], st));
-    LD_CHECK_HIP(launch_rowmat(f64, n, L.T1.base, Td, k, slot[6], k, 2.0, nullptr, nullptr, Blk::plain(1), dst, dd,
-                               st));
+    LD_CHECK_HIP(launch_rowmat(f64, n, L.T1.base, Td, k, slot[6], k, zscale, nullptr, nullptr, Blk::plain(1), dst,
+                               dd, st));
     return LD_OK;
 }
 
@@ -1032,7 +1033,7 @@ int gradient_newton_form(const ld_csr* A, uint64_t seed, EstimateState& S, GradB
     }
     LD_CHECK(traces_from_fx(A, S, st, t_low, t_res));
     // ---- L = [Q_b, c U, 2 Z]
-    LD_CHECK(basis_term(A, seed, S, B, B.Lg, Gb.shifted(nc), st));
+    LD_CHECK(basis_term(A, seed, S, B, L.FX.base, 2.0, B.Lg, Gb.shifted(nc), st));
     LD_CHECK_HIP(launch_rowmat(f64, n, L.X.base, X, k, slot[7], k, 1.0, nullptr, nullptr, Blk::plain(1),
                                B.Lg, Gb, st));
     LD_CHECK_HIP(launch_rowmat(f64, n, L.X.base, X.shifted(k), kg, slot[8], kg, 1.0, nullptr, nullptr,
@@ -1121,9 +1122,8 @@ int gradient_squared(const ld_csr* A, uint64_t seed, EstimateState& S, GradBufs&
         return LD_OK;
     };
 
-    // ---- reverse sweep over [Q_b | U] (weights 1 and 1/k_G), segment by segment
-    LD_CHECK_HIP(launch_scale_copy(f64, n, nc, H == 0 ? L.X.base : us.at(H), ldX, 2.0 * coef(2 * H), B.mu[0], ldX,
-                                   st));
+    // ---- reverse sweep over [Q_b | U] (weights 1 and 1/k_G), segment by segment;
+    //      the first step reads mu~_H = 2 c_2H u_H as u_H scaled in the kernel
     int cur = 0;
     const int s = us.s;
     for (int q = (H - 1) / s; q >= 0; --q) {
@@ -1138,7 +1138,8 @@ int gradient_squared(const ld_csr* A, uint64_t seed, EstimateState& S, GradBufs&
         for (int i = b1 - 1; i >= b0; --i) {
             AdjArgs a{};
             a.mode = ADJ_SQUARED;
-            a.lam_in = B.mu[cur];
+            a.lam_in = i == H - 1 ? us.at(H) : B.mu[cur];
+            a.lam_scale = i == H - 1 ? 2.0 * coef(2 * H) : 1.0;
             a.lam_out = B.mu[1 - cur];
             a.w = u[i - b0];
             a.grad = B.grad64;
@@ -1154,6 +1155,7 @@ int gradient_squared(const ld_csr* A, uint64_t seed, EstimateState& S, GradBufs&
             a.first = i == H - 1;
             a.last = false;   // mu~_0 = 2 F [Q_b | U] is needed
             a.nt_out = streams_from_hbm(A, L, ldX);
+            dg.chunk_rows = xcd_chunk_rows(lr, ldX, L.elem, a.nt_out);
             LD_CHECK(sweep(a));
             cur = 1 - cur;
         }
@@ -1161,11 +1163,9 @@ int gradient_squared(const ld_csr* A, uint64_t seed, EstimateState& S, GradBufs&
     // the quadratic forms' per-entry derivative is symmetric: mirrored means
     LD_CHECK_HIP(hipMemsetAsync(S.flag + 3, 0, sizeof(int), st));
     LD_CHECK_HIP(launch_symmetrize(d, B.grad64, S.flag + 3, st));
-    // F [Q_b | U] = mu~_0 / 2
-    LD_CHECK_HIP(launch_scale_copy(f64, n, nc, B.mu[cur], ldX, 0.5, L.FX.base, L.FX.ld, st));
-
     // ---- basis term: the adjoint of the sketch's Horner evaluation, from 2Z
-    LD_CHECK(basis_term(A, seed, S, B, B.rb[0], Blk::plain(ldY), st));
+    //      (computed from mu~_0 = 2 F [Q_b | U] directly)
+    LD_CHECK(basis_term(A, seed, S, B, B.mu[cur], 1.0, B.rb[0], Blk::plain(ldY), st));
     if (rs.s > 1) {   // segments are recomputed from S: its sign words (or its Gaussian block) again
         const uint64_t key0 = probe_stream_key(seed, 0);
         if (S.probe == LD_PROBE_GAUSSIAN)
@@ -1211,6 +1211,7 @@ int gradient_squared(const ld_csr* A, uint64_t seed, EstimateState& S, GradBufs&
             a.beta = p.beta[j];
             a.first = false;
             a.nt_out = streams_from_hbm(A, L, ldY);
+            dg.chunk_rows = xcd_chunk_rows(lr, ldY, L.elem, a.nt_out);
             if (on_dia && j + 1 < j1) {
                 // steps j and j+1 in one update of the gradient: the launch writes
                 // rbar_j+1, a plain step then makes rbar_j+2 (if a later step needs it)

@@ -191,6 +191,7 @@ struct AdjArgs {
     bool first;      // grad is overwritten instead of accumulated
     bool last;       // no lam_out needed (only the SDDMM)
     bool nt_out;     // lam_out written with non-temporal (streaming) stores
+    double lam_scale = 1.0;   // lam = lam_scale * lam_in (0: a zero block, lam_in not read)
 };
 hipError_t launch_adjoint(bool f64, const CsrDev& A, const AdjArgs& a, hipStream_t st);
 
@@ -205,6 +206,7 @@ struct AdjDia {
     const void* dia;
     bool constant;
     double cval[kMaxDiag];
+    int chunk_rows;   // > 0: chunked XCD bands of this many rows (0: contiguous bands)
 };
 hipError_t launch_adjoint_dia(bool f64, const CsrDev& A, const AdjArgs& a, const AdjDia& dg, hipStream_t st);
 

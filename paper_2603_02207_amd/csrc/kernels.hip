@@ -2068,7 +2068,7 @@ __global__ __launch_bounds__(kThreads) void adjoint_kernel(
     int n, const int* __restrict__ row_ptr, const int* __restrict__ col_idx,
     const T* __restrict__ val, const T* __restrict__ lam_in, T* __restrict__ lam_out,
     const T* __restrict__ w, const T* __restrict__ L, double* __restrict__ grad, int ld, int ncols,
-    T alpha, T beta, T dj, T q0, T q1, T p1, int wsplit, T whi, int first, int last, int nt_out) {
+    T alpha, T beta, T dj, T q0, T q1, T p1, int wsplit, T whi, int first, int last, int nt_out, T lam_scale) {
     constexpr int RPW = 64 / LPR;
     constexpr int NB = LPR < kAdjBatch ? LPR : kAdjBatch;
     constexpr int rows_per_wg = kWaves * RPW;
@@ -2112,12 +2112,13 @@ __global__ __launch_bounds__(kThreads) void adjoint_kernel(
             acc[q][e] = accw[q][e] = T(0);
         }
         if (inld[q]) {
-            own[q] = load_pack<T, VEC>(lam_in + off);
+            if (lam_scale != T(0)) own[q] = load_pack<T, VEC>(lam_in + off);   // lam = lam_scale * lam_in
             if (MODE == ADJ_HORNER && !last) Lr[q] = load_pack<T, VEC>(L + off);   // fetched early: used at the end
             if (kSq) wr[q] = load_pack<T, VEC>(w + off);
         }
 #pragma unroll
         for (int e = 0; e < VEC; ++e) {
+            own[q].v[e] *= lam_scale;
             T so = own[q].v[e];
             if (kSq) so = (c0 + e < wsplit ? T(1) : whi) * fma(p1, wr[q].v[e], so);
             sown[q][e] = valid[q][e] ? so : T(0);
@@ -2162,10 +2163,10 @@ __global__ __launch_bounds__(kThreads) void adjoint_kernel(
 #pragma unroll
                         for (int e = 0; e < VEC; ++e) accw[q][e] = fma(a[u], wc.v[e], accw[q][e]);
                     }
-                    if (!last) {
+                    if (!last && lam_scale != T(0)) {
                         const Pack<T, VEC> lc = load_pack<T, VEC>(lam_in + off);
 #pragma unroll
-                        for (int e = 0; e < VEC; ++e) acc[q][e] = fma(a[u], lc.v[e], acc[q][e]);
+                        for (int e = 0; e < VEC; ++e) acc[q][e] = fma(a[u], lam_scale * lc.v[e], acc[q][e]);
                     }
                 }
             }
@@ -2218,7 +2219,7 @@ hipError_t launch_adjoint_m(const CsrDev& A, const AdjArgs& a, hipStream_t st) {
                        A.row_ptr, A.col_idx, (const T*)A.val, (const T*)a.lam_in, (T*)a.lam_out,
                        (const T*)a.w, (const T*)a.L, a.grad, a.ld, a.ncols, (T)a.alpha, (T)a.beta,
                        (T)a.dj, (T)a.q0, (T)a.q1, (T)a.p1, a.wsplit, (T)a.whi, (int)a.first, (int)a.last,
-                       (int)a.nt_out);
+                       (int)a.nt_out, (T)a.lam_scale);
     return hipGetLastError();
 }
 
@@ -2276,7 +2277,7 @@ __global__ __launch_bounds__(kThreads) void adjoint_dia_kernel(
     int n, const int* __restrict__ row_ptr, const uint16_t* __restrict__ pres, const T* __restrict__ dia, int nd,
     DiaOff off, DiaVal<T> cv, int constant, const T* __restrict__ lam_in, T* __restrict__ lam_out,
     const T* __restrict__ w, const T* __restrict__ w2, double* __restrict__ grad, int ld, int ncols, T alpha,
-    T beta, T q0, T q1, T p1, int wsplit, T whi, int first, int last, int nt_out) {
+    T beta, T q0, T q1, T p1, int wsplit, T whi, int first, int last, int nt_out, T lam_scale, int chunk) {
     static_assert(MODE == ADJ_PLAIN || MODE == ADJ_PLAIN2 || MODE == ADJ_SQUARED, "diagonal-storage modes");
     constexpr int RPW = 64 / LPR;
     constexpr int rows_per_wg = kWaves * RPW;
@@ -2287,7 +2288,17 @@ __global__ __launch_bounds__(kThreads) void adjoint_dia_kernel(
     const int wave = threadIdx.x >> 6;
     const int g = lane / LPR;
     const int li = lane - g * LPR;
-    const int row = xcd_tile(blockIdx.x, gridDim.x) * rows_per_wg + wave * RPW + g;
+    // workgroup -> rows: contiguous XCD bands, or chunks of `chunk` workgroups
+    // dealt to the XCDs in turn (as the Newton steps of a launch that streams
+    // from HBM)
+    int tile;
+    if (chunk > 0) {
+        const int x = blockIdx.x % kXcds, i = blockIdx.x / kXcds;
+        tile = ((i / chunk) * kXcds + x) * chunk + i % chunk;
+    } else {
+        tile = xcd_tile(blockIdx.x, gridDim.x);
+    }
+    const int row = tile * rows_per_wg + wave * RPW + g;
     if (row >= n) return;                         // whole row groups leave together
     const int c0 = li * VEC;
     const bool inld = c0 < ld;
@@ -2325,15 +2336,25 @@ __global__ __launch_bounds__(kThreads) void adjoint_dia_kernel(
             lq[q].v[e] = wq[q].v[e] = T(0);
             if (kTwo) w2q[q].v[e] = T(0);
         }
+    // lam = lam_scale * lam_in (lam_scale = 0: a zero block, not read)
+    const bool lam_on = lam_scale != T(0);
     if (inld) {
-        own = load_pack<T, VEC>(lam_in + (size_t)row * ld + c0);
+        if (lam_on) own = load_pack<T, VEC>(lam_in + (size_t)row * ld + c0);
         if (kSq) wr = load_pack<T, VEC>(w + (size_t)row * ld + c0);
 #pragma unroll
         for (int q = 0; q < ND; ++q) {
             wq[q] = load_pack<T, VEC>(w + (size_t)cq[q] * ld + c0);
-            lq[q] = load_pack<T, VEC>(lam_in + (size_t)cq[q] * ld + c0);
+            if (lam_on) lq[q] = load_pack<T, VEC>(lam_in + (size_t)cq[q] * ld + c0);
             if (kTwo) w2q[q] = load_pack<T, VEC>(w2 + (size_t)cq[q] * ld + c0);
         }
+    }
+    if (lam_scale != T(1)) {
+#pragma unroll
+        for (int e = 0; e < VEC; ++e) own.v[e] *= lam_scale;
+#pragma unroll
+        for (int q = 0; q < ND; ++q)
+#pragma unroll
+            for (int e = 0; e < VEC; ++e) lq[q].v[e] *= lam_scale;
     }
     bool valid[VEC];
     T sown[VEC];
@@ -2409,12 +2430,16 @@ hipError_t launch_adjoint_dia_t(const CsrDev& A, const AdjArgs& a, const AdjDia&
         off.o[q] = q < dg.nd ? dg.off[q] : 0;
         cv.c[q] = (T)(q < dg.nd ? dg.cval[q] : 0.0);
     }
+    // chunked XCD bands: chunks of dg.chunk_rows rows, in workgroups; the grid
+    // covers whole rounds of 8 chunks (workgroups past the end return)
+    const int cwg = dg.chunk_rows >= rows_per_wg ? dg.chunk_rows / rows_per_wg : 0;
+    const int grid = cwg > 0 ? div_up(div_up(nwg, cwg), kXcds) * kXcds * cwg : nwg;
 #define LD_ADJ_DIA(M_)                                                                                          \
-    hipLaunchKernelGGL((adjoint_dia_kernel<T, VEC, LPR, ND, M_>), dim3(nwg), dim3(kThreads), 0, st, A.n, A.row_ptr, \
+    hipLaunchKernelGGL((adjoint_dia_kernel<T, VEC, LPR, ND, M_>), dim3(grid), dim3(kThreads), 0, st, A.n, A.row_ptr, \
                        dg.pres, (const T*)dg.dia, dg.nd, off, cv, (int)dg.constant, (const T*)a.lam_in,          \
                        (T*)a.lam_out, (const T*)a.w, (const T*)a.w2, a.grad, a.ld, a.ncols, (T)a.alpha,          \
                        (T)a.beta, (T)a.q0, (T)a.q1, (T)a.p1, a.wsplit, (T)a.whi, (int)a.first, (int)a.last,      \
-                       (int)a.nt_out)
+                       (int)a.nt_out, (T)a.lam_scale, cwg)
     switch (a.mode) {
         case ADJ_PLAIN: LD_ADJ_DIA(ADJ_PLAIN); break;
         case ADJ_PLAIN2: LD_ADJ_DIA(ADJ_PLAIN2); break;
