@@ -381,6 +381,8 @@ def traffic_summary(dirs, bench_log=None) -> str:
              "total / algorithmic |", "|---|---|---|---|---|---|"]
     blob = {}
     for k in sorted(set(fetch) | set(write)):
+        if k.startswith("at::") or k.startswith("__amd"):   # torch's copy and runtime fills
+            continue
         r = fetch.get(k, 0.0) * f_scale * 1024 / 1e6
         w = write.get(k, 0.0) * w_scale * 1024 / 1e6
         a = ""

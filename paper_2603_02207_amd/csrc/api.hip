@@ -1351,13 +1351,15 @@ int run_logdet(const ld_csr* A, double lmin, double lmax, int degree, int n_matv
                                          (S.longrows.tile_order == LD_TILES_AUTO && S.longrows.skewed)
                                      ? LD_TILES_INTERLEAVED
                                      : LD_TILES_XCD_BANDS;
-        out->xcd_chunk_rows =
+        // the chunk rows the quadratic-form launches take (chunks of whole tiles only)
+        const int crows =
             out->tile_order_used == LD_TILES_XCD_BANDS
                 ? xcd_chunk_rows(S.longrows, L.X.ld, L.elem,
                                  alg_bytes_step(A, L.X.bw, S.mode == LD_DOT_SQUARED ? STEP_DOT_SQ : STEP_DOT_FWD,
                                                 L.elem, S.longrows.dia_nd, S.longrows.dia_pres != nullptr) >
                                      kMallBudget)
                 : 0;
+        out->xcd_chunk_rows = crows > 0 && crows % step_tile_rows(L.X.bw, (int)L.elem) == 0 ? crows : 0;
         out->spmm_launches = S.spmm_launches;
         out->t_low = t_low;
         out->t_res = t_res;

@@ -109,6 +109,8 @@ int step_num_wg(bool f64, int n, const StepArgs& s);
 int step_max_cols(bool f64, const StepArgs& s);
 int step_num_wg_bound(int n, int bcols, int elem_bytes);
 int step_num_wg_any(int n);   // bound for the column-sum kinds at any layout
+// Rows of one tile of the column-sum kinds over bcols columns of 16-byte aligned blocks.
+int step_tile_rows(int bcols, int elem_bytes);
 
 // *nwg_out (may be null): workgroup partial rows the launch wrote (dot kinds:
 // the grid, which is the number of resident workgroups or less, plus the

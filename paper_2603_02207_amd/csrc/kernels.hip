@@ -691,8 +691,12 @@ hipError_t launch_step_t(const CsrDev& A, const StepArgs& s, hipStream_t st, int
     auto grid = [&](const void* fn_first, const void* fn_rest) {
         return is_dot(KIND) ? std::min({ntiles, resident_wgs(fn_first, NT), resident_wgs(fn_rest, NT)}) : ntiles;
     };
-    // chunked bands: s.chunk_rows rows per chunk, in tiles
-    const int ctiles = s.chunk_rows > 0 && !s.interleave ? std::max(1, s.chunk_rows / rows_per_wg) : 0;
+    // chunked bands: s.chunk_rows rows per chunk, in tiles (only when a chunk is
+    // a whole number of tiles, so that an XCD's consecutive chunks lie exactly
+    // chunk_rows * 8 rows apart; else contiguous bands)
+    const int ctiles = s.chunk_rows > 0 && !s.interleave && s.chunk_rows % rows_per_wg == 0
+                           ? s.chunk_rows / rows_per_wg
+                           : 0;
     DiaOff off{};
     for (int q = 0; q < kMaxDiag; ++q) off.o[q] = q < s.dia_nd ? s.dia_off[q] : 0;
     DiaVal<T> cv{};
@@ -708,7 +712,11 @@ hipError_t launch_step_t(const CsrDev& A, const StepArgs& s, hipStream_t st, int
                 const int need = div_up(chunks, kThreads);
                 // chunked bands: s.chunk_rows rows per chunk, in workgroups; the grid
                 // covers whole rounds of 8 chunks (workgroups past the end return)
-                const int cwg = s.chunk_rows > 0 && !s.interleave ? std::max(1, s.chunk_rows * lpr / kThreads) : 0;
+                // (only when a chunk is a whole number of workgroups: otherwise the
+                // XCD's consecutive chunks would not lie a stencil offset apart)
+                const int cwg = s.chunk_rows > 0 && !s.interleave && (long long)s.chunk_rows * lpr % kThreads == 0
+                                    ? (int)((long long)s.chunk_rows * lpr / kThreads)
+                                    : 0;
                 const int nwg = cwg > 0 ? div_up(div_up(need, cwg), kXcds) * kXcds * cwg
                                         : div_up(need, kXcds) * kXcds;
 #define LD_FLAT_LAUNCH(ND_)                                                                                    \
@@ -820,6 +828,10 @@ int step_num_wg_bound(int n, int bcols, int elem_bytes) {
 }
 
 int step_max_cols(bool f64, const StepArgs& s) { return 64 * pick_vec(s, f64 ? 8 : 4); }
+
+int step_tile_rows(int bcols, int elem_bytes) {
+    return (threads_of(STEP_DOT_SQ) / 64) * (64 / lanes_per_row(bcols, 16 / elem_bytes)) * kStepIters;
+}
 
 int step_num_wg_any(int n) {
     // any vector width and column count: at most 8 rows per tile, at most kDotWgs tiles' workgroups
@@ -2432,7 +2444,7 @@ hipError_t launch_adjoint_dia_t(const CsrDev& A, const AdjArgs& a, const AdjDia&
     }
     // chunked XCD bands: chunks of dg.chunk_rows rows, in workgroups; the grid
     // covers whole rounds of 8 chunks (workgroups past the end return)
-    const int cwg = dg.chunk_rows >= rows_per_wg ? dg.chunk_rows / rows_per_wg : 0;
+    const int cwg = dg.chunk_rows > 0 && dg.chunk_rows % rows_per_wg == 0 ? dg.chunk_rows / rows_per_wg : 0;
     const int grid = cwg > 0 ? div_up(div_up(nwg, cwg), kXcds) * kXcds * cwg : nwg;
 #define LD_ADJ_DIA(M_)                                                                                          \
     hipLaunchKernelGGL((adjoint_dia_kernel<T, VEC, LPR, ND, M_>), dim3(grid), dim3(kThreads), 0, st, A.n, A.row_ptr, \

@@ -467,22 +467,22 @@ def test_tile_orders_agree_with_oracle(dtype, tol):
 
 @pytest.mark.parametrize("dtype,tol", [(torch.float64, 1e-11), (torch.float32, 2e-5)])
 def test_chunked_xcd_bands_for_3d_grids(dtype, tol):
-    # An 80^3 grid: the plane neighbours (6400 rows away) of a contiguous band
-    # would not stay in an XCD's L2 at 32 or 64 columns, so both phases cut
-    # the bands into chunks of 800 rows dealt to the XCDs in turn.  The
+    # A 64^3 grid: the plane neighbours (4096 rows away) of a contiguous band
+    # would not stay in an XCD's L2 at 64 columns, so the quadratic forms cut
+    # the bands into chunks of 512 rows dealt to the XCDs in turn.  The
     # recurrence vectors are per-row results (bit-identical to the other
     # orders), the quadratic forms regroup their sums; both against the oracle.
-    csr = w.grid_laplacian_3d(80, 0.2)
+    csr = w.grid_laplacian_3d(64, 0.2)
     A, vals = to_gpu(csr, dtype)
     csr_v = (csr[0], csr[1], vals, csr[3])
     lo, hi = bounds.gershgorin(csr_v)
     ref = hutchpp.logdet_estimate(w.to_scipy(csr_v), lo, hi, 24, 96, 3)
     est, st = ld.logdet(A, lo, hi, 24, 96, 3, return_stats=True)
-    assert st["tile_order_used"] == 1 and st["xcd_chunk_rows"] == 800
+    assert st["tile_order_used"] == 1 and st["xcd_chunk_rows"] == 512
     assert rel(est, ref) < tol, (est, ref)
     for order in (1, 2):   # explicit bands are the chunked bands here; interleaved never chunks
         e, so = ld.logdet(A, lo, hi, 24, 96, 3, options=ld.Options(tile_order=order), return_stats=True)
-        assert so["xcd_chunk_rows"] == (800 if order == 1 else 0)
+        assert so["xcd_chunk_rows"] == (512 if order == 1 else 0)
         assert rel(e, ref) < tol
     V = torch.tensor(np.random.default_rng(2).standard_normal((csr[3], 32)), dtype=dtype, device=DEV)
     out_b = ld.apply_log(A, lo, hi, 20, V, ld.Options(tile_order=1))
