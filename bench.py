@@ -200,6 +200,30 @@ def time_adaptive(ld, A, lmin, lmax, degree, ncols, rel_tol, n, nnz, reps=5):
             "steps_launched": steps, "adaptive_GBps": steps * step_bytes / out["adaptive"] / 1e9}
 
 
+def time_adaptive_estimate(ld, A, lmin, lmax, degree, m_vec, seed, rel_tol, n, s_fixed, reps=3):
+    """Alg. 3 with Alg. 2's stopping rule (tol = rel_tol * sqrt(n), the degree as the
+    cap) against the fixed-degree estimate of the same call."""
+    import numpy as np
+    import torch
+
+    tol = rel_tol * math.sqrt(n)
+    ld.logdet_adaptive(A, lmin, lmax, degree, tol, m_vec, seed)
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    for _ in range(reps):
+        est, deg, st = ld.logdet_adaptive(A, lmin, lmax, degree, tol, m_vec, seed, return_stats=True)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t) / reps
+    k = st["k"]
+    return {"tol": tol, "tol_over_sqrt_n": rel_tol, "max_degree": degree, "estimate": est,
+            "ms_per_estimate": dt * 1e3, "over_fixed_degree": dt / s_fixed,
+            "degrees_sketch": sorted(set(int(x) for x in deg[:k])),
+            "degrees_basis": sorted(set(int(x) for x in deg[k:2 * k])),
+            "degrees_residual": sorted(set(int(x) for x in deg[2 * k:])),
+            "newton_steps": [st["launches1"], st["launches23"]],
+            "note": "forward Newton form with the accumulator (Alg. 2 as printed), no Horner or squared basis"}
+
+
 def cpu_model() -> str:
     try:
         with open("/proc/cpuinfo") as f:
@@ -668,6 +692,8 @@ def run_workload(args, workload, steps):
     if args.adaptive_tol > 0:
         out["apply_log_adaptive"] = time_adaptive(ld, A32, lmin, lmax, degree, st["k"], args.adaptive_tol, n,
                                                   nnz)
+        out["logdet_adaptive"] = time_adaptive_estimate(ld, A32, lmin, lmax, degree, m_vec, args.seed,
+                                                        args.adaptive_tol, n, dt / args.steps)
 
     if args.extras:
         # the same workload on the CSR path (no diagonal storage): the general SpMM kernels

@@ -226,13 +226,37 @@ int ld_apply_log(const ld_csr* A, double lmin, double lmax, int32_t degree, cons
  * the degree m at which each column stopped (max_degree if it never met tol).
  * The norms are FP64 sums of the column's squares; the stopping test runs on
  * the device after every step, and the host stops launching steps once every
- * column has stopped (checked after steps 1, 2 and 4, then every 8 steps).
+ * column has stopped (checked before the first step, after steps 1, 2 and 4,
+ * then every 8 steps).
  * V, PV: device, n x ncols row-major, dtype of A, must not overlap.
  * Errors: LD_EINVAL (0 < lmin < lmax, max_degree >= 1, ncols >= 0, tol finite
  * and >= 0), LD_ECSR, LD_EWORKSPACE, LD_EHIP. */
 int ld_apply_log_adaptive(const ld_csr* A, double lmin, double lmax, int32_t max_degree, double tol,
                           const void* V, void* PV, int64_t ncols, const ld_options* opts,
                           void* workspace, size_t ws_bytes, void* stream, int32_t* degrees);
+
+/* Bytes of workspace needed by ld_logdet_estimate_adaptive for this matrix,
+ * largest degree and query count.  opts may be NULL.  Errors: LD_EINVAL. */
+int ld_adaptive_workspace_size(const ld_csr* A, int32_t max_degree, int32_t n_matvec,
+                               const ld_options* opts, size_t* bytes);
+
+/* Alg. 3 with Alg. 2's stopping rule in each of its three applications of
+ * log(Q~) (Alg. 3 steps 3, 5 and 6, Sec. 4.1): Y = F S, Q_b = orth(Y) (CholQR2),
+ * U = (I - Q_b Q_b^T) G, estimate = n log(sigma) + sum_i q_i^T F q_i +
+ * (1/k_G) sum_j u_j^T F u_j, where F x is ld_apply_log_adaptive's P for the
+ * column x (forward Newton order, each column its own degree: it stops at the
+ * first m with |d_m| ||w_m||_2 <= tol, tol absolute, or at max_degree).
+ * Probes, k, k_G, seeds and limits as ld_logdet_estimate.
+ * degrees: host, n_matvec int32 (may be NULL): the degree each column stopped
+ * at, in the order the columns of S (k), of Q_b (k) and of U (k_G).
+ * out_logdet: host double.  stats: host, may be NULL (launches1/launches23 =
+ * Newton steps of step 3 / steps 5 and 6; no byte counts).
+ * Errors: LD_EINVAL (as ld_logdet_estimate, tol finite and >= 0), LD_ECSR,
+ * LD_EBREAKDOWN, LD_EWORKSPACE, LD_EHIP. */
+int ld_logdet_estimate_adaptive(const ld_csr* A, double lmin, double lmax, int32_t max_degree, double tol,
+                                int32_t n_matvec, uint64_t seed, const ld_options* opts, void* workspace,
+                                size_t ws_bytes, void* stream, double* out_logdet, int32_t* degrees,
+                                ld_stats* stats);
 
 /* Léja + Hutch++ estimate of log det A (Alg. 3) with n_matvec queries:
  * k = floor(n_matvec/3) sketch columns (probe stream 0), k_G = n_matvec - 2k

@@ -16,13 +16,19 @@ Steps (Sec. 4.1, Alg. 3), with F = P_m(Q~) the Léja interpolant of log(Q~):
   7. logdet ~= n log(sigma) + t_low + t_res (Eq. eq_lejdeteq and Alg. 3 output),
      summed with math.fsum.
 
+``logdet_estimate_adaptive`` runs the same steps with Alg. 2's stopping rule
+in each application of log (every column its own degree).
+
 ``exact_trace`` is the same polynomial traced exactly (n log sigma +
 sum_i P_m(lambda_i/sigma)) and isolates the interpolation error from the
 Monte-Carlo error.
 
 Pinned by: exactness when k >= n (the sketch spans everything), invariance
 to the choice of orthonormal basis, unbiasedness over seeds, closed-form and
-Cholesky log-determinants (tests/test_oracle_hutchpp.py).
+Cholesky log-determinants (tests/test_oracle_hutchpp.py); the adaptive form
+by its tol = 0 and degree-0 special cases, stopping degrees from closed-form
+eigenvector products, and the exact log det at k >= n
+(tests/test_oracle_hutchpp_adaptive.py).
 """
 from __future__ import annotations
 
@@ -69,6 +75,49 @@ def logdet_estimate(Q, lmin: float, lmax: float, degree: int, m_vec: int, seed: 
         return dict(logdet=est, t_low=t_low, t_res=t_res, sigma=plan.sigma, lo=plan.lo,
                     hi=plan.hi, k=k, k_G=k_g, Y=Y, A=A, U=U, S=S, G=G, plan=plan)
     return est
+
+
+def positive_qr(Y):
+    """Thin QR basis of Y whose R has a positive diagonal (the unique one for a
+    full-rank Y; any orthonormal basis differs from it by an orthogonal factor)."""
+    A, R = np.linalg.qr(Y)
+    sgn = np.where(np.diag(R) < 0, -1.0, 1.0)
+    return A * sgn
+
+
+def logdet_estimate_adaptive(Q, lmin: float, lmax: float, max_degree: int, tol: float, m_vec: int,
+                             seed: int, probes: str = "rademacher", return_parts: bool = False):
+    """Alg. 3 with Alg. 2's loop in its three applications of log(Q~) (steps 3,
+    5 and 6): every column x gets its own degree m_x (the first m with
+    |d_m| ||w_m||_2 <= tol, at most max_degree) and F x = P_{m_x}(Q~) x.
+
+    Reading: with per-column degrees the deterministic term sum_i a_i^T F a_i
+    depends on which orthonormal basis A of span(Y) step 4 takes (with one
+    common degree it does not); A is the thin QR basis with a positive R
+    diagonal, the one CholQR also produces.  Column signs change neither a
+    column's degree nor its quadratic form.
+    Returns (estimate, degrees) with degrees = [S (k), A (k), U (k_G)].
+    """
+    n = Q.shape[0]
+    plan = NewtonPlan(lmin, lmax, max_degree)
+    k, k_g = split_queries(m_vec)
+    if k > n:
+        raise ValueError("sketch wider than the matrix")
+    S = draw_probes(probes, seed, 0, n, k)
+    G = draw_probes(probes, seed, 1, n, k_g)
+    Y, deg_s = plan.apply_poly_adaptive(Q, S, tol)          # step 3
+    A = positive_qr(Y)                                     # step 4
+    FA, deg_a = plan.apply_poly_adaptive(Q, A, tol)         # step 5
+    U = G - A @ (A.T @ G)                                  # step 6
+    FU, deg_u = plan.apply_poly_adaptive(Q, U, tol)
+    t_low = math.fsum(float(v) for v in (A * FA).ravel())
+    t_res = math.fsum(float(v) for v in (U * FU).ravel()) / k_g
+    est = math.fsum([n * math.log(plan.sigma), t_low, t_res])
+    degrees = np.concatenate([deg_s, deg_a, deg_u])
+    if return_parts:
+        return dict(logdet=est, degrees=degrees, t_low=t_low, t_res=t_res, sigma=plan.sigma, Y=Y, A=A, U=U,
+                    S=S, G=G, plan=plan)
+    return est, degrees
 
 
 def hutchinson_estimate(Q, lmin: float, lmax: float, degree: int, m_vec: int, seed: int):

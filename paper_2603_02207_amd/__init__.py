@@ -28,7 +28,8 @@ from ._native import (LD_DOT_AUTO, LD_DOT_FORWARD, LD_DOT_SQUARED, LD_F32, LD_F6
                       LD_SVAL_CENTER, LD_SVAL_HALF_LMAX, NativeError)
 
 __all__ = [
-    "CSR", "Options", "logdet", "logdet_noalloc", "logdet_with_grad", "logdet_autograd", "LogdetFunction",
+    "CSR", "Options", "logdet", "logdet_adaptive", "logdet_noalloc", "logdet_with_grad", "logdet_autograd",
+    "LogdetFunction", "apply_log_adaptive",
     "apply_log", "spectral_bounds", "leja_points", "divided_differences", "rademacher_host",
     "squared_basis_coefficients", "workspace_size", "NativeError", "library_path",
 ]
@@ -161,6 +162,31 @@ def logdet(A: CSR, lmin: float, lmax: float, degree: int, n_matvec: int, seed: i
     if return_stats:
         return out.value, st.as_dict()
     return out.value
+
+
+def logdet_adaptive(A: CSR, lmin: float, lmax: float, max_degree: int, tol: float, n_matvec: int,
+                    seed: int = 0, options=None, return_stats: bool = False):
+    """Alg. 3 with Alg. 2's stopping rule in each application of log: (estimate,
+    degrees), degrees = the degree each column stopped at, for the columns of
+    S, Q_b and U in that order (n_matvec entries)."""
+    lib = nat.load()
+    c = A.c_struct()
+    o = _opts(options)
+    b = ctypes.c_size_t(0)
+    nat.check(lib.ld_adaptive_workspace_size(ctypes.byref(c), int(max_degree), int(n_matvec), ctypes.byref(o),
+                                             ctypes.byref(b)), "ld_adaptive_workspace_size")
+    ws = _workspace(int(b.value), A.val.device)
+    out = ctypes.c_double(0.0)
+    st = nat.LdStats()
+    degrees = np.zeros(int(n_matvec), dtype=np.int32)
+    nat.check(lib.ld_logdet_estimate_adaptive(
+        ctypes.byref(c), float(lmin), float(lmax), int(max_degree), float(tol), int(n_matvec),
+        ctypes.c_uint64(int(seed) & (2**64 - 1)), ctypes.byref(o), ctypes.c_void_p(ws.data_ptr()), ws.numel(),
+        _stream_handle(A.val.device), ctypes.byref(out), degrees.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),
+        ctypes.byref(st)), "ld_logdet_estimate_adaptive")
+    if return_stats:
+        return out.value, degrees, st.as_dict()
+    return out.value, degrees
 
 
 def logdet_noalloc(A: CSR, lmin: float, lmax: float, degree: int, n_matvec: int, seed: int = 0,

@@ -125,6 +125,14 @@ SIGNATURES = {
                                              ctypes.c_void_p, ctypes.c_int64, ctypes.POINTER(LdOptions),
                                              ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p,
                                              ctypes.POINTER(ctypes.c_int32)]),
+    "ld_adaptive_workspace_size": (ctypes.c_int, [ctypes.POINTER(LdCsr), ctypes.c_int32, ctypes.c_int32,
+                                                  ctypes.POINTER(LdOptions), ctypes.POINTER(ctypes.c_size_t)]),
+    "ld_logdet_estimate_adaptive": (ctypes.c_int, [ctypes.POINTER(LdCsr), ctypes.c_double, ctypes.c_double,
+                                                   ctypes.c_int32, ctypes.c_double, ctypes.c_int32,
+                                                   ctypes.c_uint64, ctypes.POINTER(LdOptions), ctypes.c_void_p,
+                                                   ctypes.c_size_t, ctypes.c_void_p,
+                                                   ctypes.POINTER(ctypes.c_double),
+                                                   ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(LdStats)]),
     "ld_logdet_estimate": (ctypes.c_int, [ctypes.POINTER(LdCsr), ctypes.c_double, ctypes.c_double,
                                           ctypes.c_int32, ctypes.c_int32, ctypes.c_uint64,
                                           ctypes.POINTER(LdOptions), ctypes.c_void_p, ctypes.c_size_t,

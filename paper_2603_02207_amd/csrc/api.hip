@@ -649,13 +649,14 @@ int sketch_phase(const ld_csr* A, EstimateState& S, hipStream_t st, const VecSto
     return LD_OK;
 }
 
+int orthonormalize_and_deflate(const ld_csr* A, uint64_t seed, EstimateState& S, hipStream_t st);
+
 // Phases 1 (sketch), CholQR2 and deflation; leaves X = [Q_b | U].
 int estimate_front(const ld_csr* A, uint64_t seed, EstimateState& S, hipStream_t st, Timer& tm,
                    const VecStore* keep = nullptr) {
-    const bool f64 = A->dtype == LD_F64;
     const int n = (int)A->n;
     const EstLayout& L = S.L;
-    const uint64_t key0 = probe_stream_key(seed, 0), key1 = probe_stream_key(seed, 1);
+    const uint64_t key0 = probe_stream_key(seed, 0);
     const bool gauss = S.probe == LD_PROBE_GAUSSIAN;
     S.key0 = key0;
 
@@ -666,7 +667,21 @@ int estimate_front(const ld_csr* A, uint64_t seed, EstimateState& S, hipStream_t
     S.spmm_launches += S.launches1;
     S.bytes_alg += S.bytes1;
     tm.mark();
+    LD_CHECK(orthonormalize_and_deflate(A, seed, S, st));
+    tm.mark();
+    return LD_OK;
+}
 
+// Alg. 3 steps 4 and 6: CholQR2 of the sketch Y (Q1 = Y R1^{-1}, Q_b = Q1
+// R2^{-1}, into X[:, :k]) and the deflated residual probes U = G - Q_b Q_b^T G
+// (into X[:, k:]); G is probe stream 1.  S's sign words are no longer needed:
+// their buffer takes G's.
+int orthonormalize_and_deflate(const ld_csr* A, uint64_t seed, EstimateState& S, hipStream_t st) {
+    const bool f64 = A->dtype == LD_F64;
+    const int n = (int)A->n;
+    const EstLayout& L = S.L;
+    const uint64_t key1 = probe_stream_key(seed, 1);
+    const bool gauss = S.probe == LD_PROBE_GAUSSIAN;
     // ---- CholQR2: Q1 = Y R1^{-1}, Q_b = Q1 R2^{-1} (into X[:, :k])
     double* dG = S.small;
     double* dRinv = S.small + 64 * 64;
@@ -690,7 +705,6 @@ int estimate_front(const ld_csr* A, uint64_t seed, EstimateState& S, hipStream_t
         LD_CHECK_HIP(launch_rowmat(f64, n, L.X.base, L.X.desc(), L.k, dC, L.kg, -1.0, gmask, nullptr,
                                    Blk::plain(1), L.X.base, L.X.desc().shifted(L.k), st));
     }
-    tm.mark();
     return LD_OK;
 }
 
@@ -1521,6 +1535,215 @@ size_t adaptive_ws_bytes(const ld_csr* A, int ncols, const ld_options& o) {
            align_up((size_t)ncols * 4) + align_up(256) + long_rows_bytes(A) + dia_bytes(A, o);
 }
 
+// Buffers of Alg. 2's adaptive loop: two n x ld temporaries (ld of the
+// input), step partials (step_num_wg_any(n) x 64 doubles), Gram partials
+// (cross_num_wg(n) x 64 x 64 doubles), 64 x 64 sums, the active mask, degrees.
+struct AdaptBufs {
+    void* W[2] = {nullptr, nullptr};
+    double *part = nullptr, *gpart = nullptr, *sums = nullptr;
+    uint64_t* mask = nullptr;
+    int* deg = nullptr;
+};
+
+// Alg. 2 with each column's own stopping rule on the n x nc block V (leading
+// dimension ld) into P (leading dimension ldp): column c starts with w_0 = v,
+// P = (d_0 + shift) v and, while |d_m| ||w_m||_2 > tol and m < p.degree, takes
+// w_{m+1} = (T - xi_m) w_m, m += 1, P += d_m w_m.  hdeg[c] = the m it stopped
+// at.  Chunks of 64 columns; the host polls the active mask before the first
+// step, after steps 1, 2, 4 and then every kAdaptPoll steps, and stops a
+// chunk once no column is active.  `launches` counts the Newton steps.
+int adaptive_apply(const ld_csr* A, const Plan& p, double tol, double shift, const void* V, int ld, int nc,
+                   void* P, int ldp, const AdaptBufs& b, const LongRows& lr, hipStream_t st,
+                   std::vector<int>& hdeg, int* launches) {
+    const bool f64 = A->dtype == LD_F64;
+    const size_t elem = f64 ? 8 : 4;
+    const int n = (int)A->n;
+    const int nwg_max = step_num_wg_any(n);
+    const int m = p.degree;
+    const std::vector<int> deg0((size_t)nc, m);   // columns that never meet tol stop at the cap
+    LD_CHECK_HIP(hipMemcpyAsync(b.deg, deg0.data(), (size_t)nc * 4, hipMemcpyHostToDevice, st));
+    const uint64_t all = ~0ull;
+    const uint8_t* v8 = (const uint8_t*)V;
+    uint8_t* p8 = (uint8_t*)P;
+    for (int q0 = 0; q0 < nc; q0 += 64) {
+        const int qc = std::min(64, nc - q0);
+        const uint8_t* Vq = v8 + (size_t)q0 * elem;
+        uint8_t* Pq = p8 + (size_t)q0 * elem;
+        // P_0 = (d_0 + shift) w_0, w_0 = v
+        LD_CHECK_HIP(launch_scale_copy(f64, n, qc, Vq, ld, p.d[0] + shift, Pq, ldp, st));
+        // e_0 = |d_0| ||v||: the diagonal of the chunk's Gram matrix
+        LD_CHECK(cross_product(f64, n, Vq, Blk::plain(ld), qc, Vq, Blk::plain(ld), qc, nullptr, b.gpart, b.sums,
+                               st));
+        LD_CHECK_HIP(hipMemcpyAsync(b.mask, &all, 8, hipMemcpyHostToDevice, st));
+        LD_CHECK_HIP(launch_adapt_decide(b.sums, qc + 1, qc, std::fabs(p.d[0]), tol, 0, b.mask, b.deg + q0, st));
+        {   // columns that stop at degree 0 need no product at all
+            uint64_t h = 0;
+            LD_CHECK_HIP(hipMemcpyAsync(&h, b.mask, 8, hipMemcpyDeviceToHost, st));
+            LD_CHECK_HIP(hipStreamSynchronize(st));
+            if (h == 0) continue;
+        }
+        const uint8_t* cur = Vq;
+        for (int j = 0; j < m; ++j) {
+            uint8_t* out = (uint8_t*)b.W[j % 2] + (size_t)q0 * elem;
+            StepArgs s{};
+            s.kind = STEP_ACC_NORM;
+            s.win = cur;
+            s.wout = out;
+            s.ld = ld;
+            s.alpha = p.alpha;
+            s.beta = p.beta[j];
+            s.dj = p.d[j + 1];
+            s.acc = Pq;
+            s.ldacc = ldp;
+            s.acc_cols = qc;
+            s.active = b.mask;
+            s.ps1 = b.part;
+            s.part_ld = 64;
+            int nwg = 0;
+            LD_CHECK(run_step(f64, A, s, qc, qc, st, &nwg, lr));
+            if (nwg > nwg_max) return fail(LD_EINVAL, "internal: partial sums overflow");
+            if (launches) *launches += 1;
+            LD_CHECK_HIP(launch_reduce(b.part, nwg, qc, 64, 1, 0, b.sums, qc, st));
+            LD_CHECK_HIP(
+                launch_adapt_decide(b.sums, 1, qc, std::fabs(p.d[j + 1]), tol, j + 1, b.mask, b.deg + q0, st));
+            cur = out;
+            const int done = j + 1;   // poll after steps 1, 2, 4, then every kAdaptPoll: stop once all columns are done
+            if (done < m && (done == 1 || done == 2 || done == 4 || done % kAdaptPoll == 0)) {
+                uint64_t h = 0;
+                LD_CHECK_HIP(hipMemcpyAsync(&h, b.mask, 8, hipMemcpyDeviceToHost, st));
+                LD_CHECK_HIP(hipStreamSynchronize(st));
+                if (h == 0) break;
+            }
+        }
+    }
+    hdeg.assign((size_t)nc, 0);
+    LD_CHECK_HIP(hipMemcpyAsync(hdeg.data(), b.deg, (size_t)nc * 4, hipMemcpyDeviceToHost, st));
+    LD_CHECK_HIP(hipStreamSynchronize(st));   // also keeps deg0 and `all` alive until their copies ran
+    return LD_OK;
+}
+
+// Alg. 3 with Alg. 2's stopping rule in its three applications of log(Q~)
+// (steps 3, 5, 6): the estimate's column blocks and CholQR2/deflation, the
+// sketch Y = P(Q~)S and F[Q_b | U] by adaptive_apply (forward Newton form,
+// each column its own degree, at most p.degree), then the quadratic forms
+// x^T F x as the diagonal of block cross products.  Workspace: the
+// estimate's, a copy of X's blocks for F[Q_b | U], and the adaptive buffers.
+EstLayout layout_adaptive(const ld_csr* A, int max_degree, int n_matvec, const ld_options& o) {
+    return layout_estimate(A, max_degree, n_matvec, false, o);
+}
+
+size_t adaptive_estimate_ws_bytes(const ld_csr* A, int max_degree, int n_matvec, const ld_options& o) {
+    const EstLayout L = layout_adaptive(A, max_degree, n_matvec, o);
+    const int n = (int)A->n;
+    return layout_bytes(L, false) + align_up(L.X.bytes()) + align_up((size_t)step_num_wg_any(n) * 64 * 8) +
+           align_up((size_t)cross_num_wg(n) * 64 * 64 * 8) + align_up(64 * 64 * 8) + 2 * align_up(256) + 256;
+}
+
+int run_logdet_adaptive(const ld_csr* A, double lmin, double lmax, int max_degree, double tol, int n_matvec,
+                        uint64_t seed, const ld_options& o, void* workspace, size_t ws_bytes, hipStream_t st,
+                        double* out_logdet, int32_t* degrees, ld_stats* stats) {
+    const auto t0 = std::chrono::steady_clock::now();
+    const bool f64 = A->dtype == LD_F64;
+    const int n = (int)A->n;
+    EstimateState S;
+    LD_CHECK(make_plan(lmin, lmax, max_degree, o, S.plan));
+    S.L = layout_adaptive(A, max_degree, n_matvec, o);
+    S.mode = LD_DOT_FORWARD;
+    if (o.probe_dist != LD_PROBE_RADEMACHER && o.probe_dist != LD_PROBE_GAUSSIAN)
+        return fail(LD_EINVAL, "probe_dist must be LD_PROBE_RADEMACHER or LD_PROBE_GAUSSIAN");
+    S.probe = o.probe_dist;
+    OwnedWs own;
+    Arena ar;
+    LD_CHECK(get_workspace(workspace, ws_bytes, adaptive_estimate_ws_bytes(A, max_degree, n_matvec, o), own, ar));
+    carve(ar, S.L, S);
+    const EstLayout& L = S.L;
+    BlkMat PX = L.X;   // F [Q_b | U], the layout of X
+    PX.base = ar.take(L.X.bytes());
+    AdaptBufs b;
+    b.W[0] = S.W0;
+    b.W[1] = S.W1;
+    b.part = (double*)ar.take((size_t)step_num_wg_any(n) * 64 * 8);
+    b.gpart = (double*)ar.take((size_t)cross_num_wg(n) * 64 * 64 * 8);
+    b.sums = (double*)ar.take(64 * 64 * 8);
+    b.mask = (uint64_t*)ar.take(256);
+    b.deg = (int*)ar.take(256);   // one block's columns (at most 64)
+    if (ar.base && ar.used > adaptive_estimate_ws_bytes(A, max_degree, n_matvec, o))
+        return fail(LD_EINVAL, "internal: workspace layout overflow");
+    if (!o.trusted_csr) LD_CHECK(validate_csr(A, S.flag, st));
+    LD_CHECK(prepare_rows(A, o, ar, st, S.longrows));
+    Timer tm(st, true);
+    tm.mark();
+    std::vector<int> deg_all((size_t)n_matvec, 0), hdeg;
+    // ---- step 3: Y = F S column block by column block; S written out in Q1's block
+    S.key0 = probe_stream_key(seed, 0);
+    if (S.probe == LD_PROBE_RADEMACHER) LD_CHECK_HIP(launch_sign_mask(n, L.k, S.key0, (uint64_t*)S.mask, st));
+    for (int blk = 0; blk < L.Y.nblocks(); ++blk) {
+        const int cols = L.Y.bcols(blk), gcol = blk * L.Y.bw;
+        void* const sblk = L.Q1.block(blk);
+        if (S.probe == LD_PROBE_GAUSSIAN)
+            LD_CHECK_HIP(launch_gauss_fill(f64, n, cols, S.key0, gcol, 1.0, sblk, Blk::plain(L.Q1.ld), st));
+        else
+            LD_CHECK_HIP(launch_fill_signs(f64, n, cols, L.Q1.ld, gcol, (const uint64_t*)S.mask, 1.0, sblk, st));
+        LD_CHECK(adaptive_apply(A, S.plan, tol, 0.0, sblk, L.Q1.ld, cols, L.Y.block(blk), L.Y.ld, b, S.longrows,
+                                st, hdeg, &S.launches1));
+        for (int c = 0; c < cols; ++c) deg_all[(size_t)(gcol + c)] = hdeg[(size_t)c];
+    }
+    tm.mark();
+    // ---- steps 4 and 6: Q_b and U into X
+    LD_CHECK(orthonormalize_and_deflate(A, seed, S, st));
+    tm.mark();
+    // ---- steps 5 and 6: F [Q_b | U] and the quadratic forms x^T F x
+    std::vector<double> nu((size_t)L.nc, 0.0), g(64 * 64);
+    for (int blk = 0; blk < L.X.nblocks(); ++blk) {
+        const int cols = L.X.bcols(blk), gcol = blk * L.X.bw;
+        LD_CHECK(adaptive_apply(A, S.plan, tol, 0.0, L.X.block(blk), L.X.ld, cols, PX.block(blk), L.X.ld, b,
+                                S.longrows, st, hdeg, &S.launches23));
+        for (int c = 0; c < cols; ++c) deg_all[(size_t)(L.k + gcol + c)] = hdeg[(size_t)c];
+        LD_CHECK(cross_product(f64, n, L.X.block(blk), Blk::plain(L.X.ld), cols, PX.block(blk), Blk::plain(L.X.ld),
+                               cols, nullptr, b.gpart, b.sums, st));
+        LD_CHECK_HIP(hipMemcpyAsync(g.data(), b.sums, (size_t)cols * cols * 8, hipMemcpyDeviceToHost, st));
+        LD_CHECK_HIP(hipStreamSynchronize(st));
+        for (int c = 0; c < cols; ++c) nu[(size_t)(gcol + c)] = g[(size_t)c * cols + c];
+    }
+    int hflag[2] = {0, 0};
+    LD_CHECK_HIP(hipMemcpyAsync(hflag, S.flag + 1, 2 * sizeof(int), hipMemcpyDeviceToHost, st));
+    LD_CHECK_HIP(hipStreamSynchronize(st));
+    LD_CHECK(cholqr_status(hflag));
+    tm.mark();
+    // ---- step 7: n log(sigma) + t_low + t_res
+    KahanSum tl, tr, tot;
+    for (int c = 0; c < L.nc; ++c) (c < L.k ? tl : tr).add(nu[(size_t)c]);
+    const double t_low = tl.value(), t_res = tr.value() / L.kg;
+    tot.add((double)A->n * std::log(S.plan.sigma));
+    tot.add(t_low);
+    tot.add(t_res);
+    *out_logdet = tot.value();
+    if (degrees)
+        for (int c = 0; c < n_matvec; ++c) degrees[c] = deg_all[(size_t)c];
+    if (stats) {
+        std::memset(stats, 0, sizeof(*stats));
+        stats->ms_phase1 = tm.ms(0, 1);
+        stats->ms_qr = tm.ms(1, 2);
+        stats->ms_phase23 = tm.ms(2, 3);
+        stats->taylor_terms = S.plan.taylor_terms;
+        stats->sigma = S.plan.sigma;
+        stats->lo = S.plan.lo;
+        stats->hi = S.plan.hi;
+        stats->k = L.k;
+        stats->k_G = L.kg;
+        stats->dot_mode_used = LD_DOT_FORWARD;
+        stats->dia_diagonals = S.longrows.dia_nd;
+        stats->dia_constant = S.longrows.dia_pres != nullptr;
+        stats->spmm_launches = S.launches1 + S.launches23;
+        stats->launches1 = S.launches1;
+        stats->launches23 = S.launches23;
+        stats->t_low = t_low;
+        stats->t_res = t_res;
+        stats->ms_total = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+    }
+    return LD_OK;
+}
+
 extern "C" {
 
 int ld_workspace_size(const ld_csr* A, int32_t degree, int32_t n_matvec, int32_t want_grad,
@@ -1618,75 +1841,51 @@ int ld_apply_log_adaptive(const ld_csr* A, double lmin, double lmax, int32_t max
     const int n = (int)A->n, nc = (int)ncols;
     const size_t blk = (size_t)n * nc * elem;
     const uint8_t* v8 = (const uint8_t*)V;
-    uint8_t* p8 = (uint8_t*)PV;
+    const uint8_t* p8 = (const uint8_t*)PV;
     if (v8 < p8 + blk && p8 < v8 + blk) return fail(LD_EINVAL, "V and PV overlap");
     OwnedWs own;
     Arena ar;
     LD_CHECK(get_workspace(workspace, ws_bytes, adaptive_ws_bytes(A, nc, o), own, ar));
-    uint8_t* W[2] = {(uint8_t*)ar.take(blk), (uint8_t*)ar.take(blk)};
-    const int nwg_max = step_num_wg_any(n);
-    double* part = (double*)ar.take((size_t)nwg_max * 64 * 8);
-    double* gpart = (double*)ar.take((size_t)cross_num_wg(n) * 64 * 64 * 8);
-    double* sums = (double*)ar.take(64 * 64 * 8);
-    uint64_t* mask = (uint64_t*)ar.take(256);
-    int* deg = (int*)ar.take((size_t)nc * 4);
+    AdaptBufs b;
+    b.W[0] = ar.take(blk);
+    b.W[1] = ar.take(blk);
+    b.part = (double*)ar.take((size_t)step_num_wg_any(n) * 64 * 8);
+    b.gpart = (double*)ar.take((size_t)cross_num_wg(n) * 64 * 64 * 8);
+    b.sums = (double*)ar.take(64 * 64 * 8);
+    b.mask = (uint64_t*)ar.take(256);
+    b.deg = (int*)ar.take((size_t)nc * 4);
     int* flag = (int*)ar.take(256);
     if (!o.trusted_csr) LD_CHECK(validate_csr(A, flag, st));
     LongRows lr;
     LD_CHECK(prepare_rows(A, o, ar, st, lr));
-    const int m = p.degree;
-    const std::vector<int> deg0((size_t)nc, m);   // columns that never meet tol stop at the cap
-    LD_CHECK_HIP(hipMemcpyAsync(deg, deg0.data(), (size_t)nc * 4, hipMemcpyHostToDevice, st));
-    const uint64_t all = ~0ull;
-    for (int q0 = 0; q0 < nc; q0 += 64) {
-        const int qc = std::min(64, nc - q0);
-        const uint8_t* Vq = v8 + (size_t)q0 * elem;
-        uint8_t* Pq = p8 + (size_t)q0 * elem;
-        // P_0 = d_0 w_0 (+ log(sigma) v, the scaling term), w_0 = v
-        LD_CHECK_HIP(launch_scale_copy(f64, n, qc, Vq, nc, p.d[0] + std::log(p.sigma), Pq, nc, st));
-        // e_0 = |d_0| ||v||: the diagonal of the chunk's Gram matrix
-        LD_CHECK(cross_product(f64, n, Vq, Blk::plain(nc), qc, Vq, Blk::plain(nc), qc, nullptr, gpart, sums,
-                               st));
-        LD_CHECK_HIP(hipMemcpyAsync(mask, &all, 8, hipMemcpyHostToDevice, st));
-        LD_CHECK_HIP(launch_adapt_decide(sums, qc + 1, qc, std::fabs(p.d[0]), tol, 0, mask, deg + q0, st));
-        const uint8_t* cur = Vq;
-        for (int j = 0; j < m; ++j) {
-            uint8_t* out = W[j % 2] + (size_t)q0 * elem;
-            StepArgs s{};
-            s.kind = STEP_ACC_NORM;
-            s.win = cur;
-            s.wout = out;
-            s.ld = nc;
-            s.alpha = p.alpha;
-            s.beta = p.beta[j];
-            s.dj = p.d[j + 1];
-            s.acc = Pq;
-            s.ldacc = nc;
-            s.acc_cols = qc;
-            s.active = mask;
-            s.ps1 = part;
-            s.part_ld = 64;
-            int nwg = 0;
-            LD_CHECK(run_step(f64, A, s, qc, qc, st, &nwg, lr));
-            if (nwg > nwg_max) return fail(LD_EINVAL, "internal: partial sums overflow");
-            LD_CHECK_HIP(launch_reduce(part, nwg, qc, 64, 1, 0, sums, qc, st));
-            LD_CHECK_HIP(launch_adapt_decide(sums, 1, qc, std::fabs(p.d[j + 1]), tol, j + 1, mask, deg + q0, st));
-            cur = out;
-            const int done = j + 1;   // poll after steps 1, 2, 4, then every kAdaptPoll: stop once all columns are done
-            if (done < m && (done == 1 || done == 2 || done == 4 || done % kAdaptPoll == 0)) {
-                uint64_t h = 0;
-                LD_CHECK_HIP(hipMemcpyAsync(&h, mask, 8, hipMemcpyDeviceToHost, st));
-                LD_CHECK_HIP(hipStreamSynchronize(st));
-                if (h == 0) break;
-            }
-        }
-    }
-    std::vector<int> hdeg((size_t)nc);
-    LD_CHECK_HIP(hipMemcpyAsync(hdeg.data(), deg, (size_t)nc * 4, hipMemcpyDeviceToHost, st));
-    LD_CHECK_HIP(hipStreamSynchronize(st));   // also keeps deg0 and `all` alive until their copies ran
+    std::vector<int> hdeg;
+    LD_CHECK(adaptive_apply(A, p, tol, std::log(p.sigma), V, nc, nc, PV, nc, b, lr, st, hdeg, nullptr));
     if (degrees)
         for (int c = 0; c < nc; ++c) degrees[c] = hdeg[(size_t)c];
     return LD_OK;
+}
+
+int ld_adaptive_workspace_size(const ld_csr* A, int32_t max_degree, int32_t n_matvec, const ld_options* opts,
+                               size_t* bytes) {
+    clear_error();
+    if (!bytes) return fail(LD_EINVAL, "bytes is null");
+    LD_CHECK(check_csr_args(A));
+    if (max_degree < 1) return fail(LD_EINVAL, "max_degree must be >= 1");
+    if (n_matvec < 3) return fail(LD_EINVAL, "n_matvec must be >= 3");
+    *bytes = adaptive_estimate_ws_bytes(A, max_degree, n_matvec, resolve(opts));
+    return LD_OK;
+}
+
+int ld_logdet_estimate_adaptive(const ld_csr* A, double lmin, double lmax, int32_t max_degree, double tol,
+                                int32_t n_matvec, uint64_t seed, const ld_options* opts, void* workspace,
+                                size_t ws_bytes, void* stream, double* out_logdet, int32_t* degrees,
+                                ld_stats* stats) {
+    clear_error();
+    if (!out_logdet) return fail(LD_EINVAL, "out_logdet is null");
+    LD_CHECK(check_estimate_args(A, lmin, lmax, max_degree, n_matvec));
+    if (!(tol >= 0.0) || !std::isfinite(tol)) return fail(LD_EINVAL, "tol must be finite and >= 0");
+    return run_logdet_adaptive(A, lmin, lmax, max_degree, tol, n_matvec, seed, resolve(opts), workspace, ws_bytes,
+                               (hipStream_t)stream, out_logdet, degrees, stats);
 }
 
 int ld_logdet_estimate(const ld_csr* A, double lmin, double lmax, int32_t degree,

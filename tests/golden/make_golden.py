@@ -93,10 +93,55 @@ def make_gmrf_theta_sweep(name="gmrf5000_theta_sweep"):
         json.dump(out, f, indent=1)
 
 
+def stop_margin(plan, Q, X, degrees, tol):
+    """Smallest |e_m / tol - 1| over the columns of X and the m up to each
+    column's stop, e_m = |d_m| ||w_m||_2 of the forward recurrence: how far the
+    stopping decisions sit from a tie with tol."""
+    W = np.array(X, dtype=np.float64, copy=True)
+    worst = np.inf
+    for m in range(int(np.max(degrees)) + 1):
+        if m > 0:
+            W = plan.alpha * (Q @ W) - plan.beta[m - 1] * W
+        e = abs(plan.d[m]) * np.linalg.norm(W, axis=0)
+        live = np.asarray(degrees) >= m
+        if live.any():
+            worst = min(worst, float(np.min(np.abs(e[live] / tol - 1.0))))
+    return worst
+
+
+def make_adaptive(name="gmrf2048_adaptive", wl="gmrf2048", tol_per_sqrt_n=1e-7, seed=0):
+    """Alg. 3 with Alg. 2's stopping rule (absolute tol = tol_per_sqrt_n * sqrt(n),
+    the norm of a Rademacher probe times tol_per_sqrt_n) at the workload's
+    degree as the cap: estimate, every column's degree, and the stopping margin."""
+    cfg = dict(workloads.CONFIGS[wl])
+    csr = workloads.build(wl)
+    Q = workloads.to_scipy(csr)
+    n = int(csr[3])
+    lmin, lmax = bounds.gershgorin(csr)
+    tol = tol_per_sqrt_n * float(np.sqrt(n))
+    t = time.perf_counter()
+    parts = hutchpp.logdet_estimate_adaptive(Q, lmin, lmax, cfg["degree"], tol, cfg["m_vec"], seed,
+                                             return_parts=True)
+    secs = time.perf_counter() - t
+    k = parts["A"].shape[1]
+    deg = parts["degrees"]
+    margin = min(stop_margin(parts["plan"], Q, parts["S"], deg[:k], tol),
+                 stop_margin(parts["plan"], Q, parts["A"], deg[k:2 * k], tol),
+                 stop_margin(parts["plan"], Q, parts["U"], deg[2 * k:], tol))
+    out = dict(workload=wl, n=n, nnz=int(len(csr[1])), lmin=lmin, lmax=lmax, max_degree=cfg["degree"],
+               m_vec=cfg["m_vec"], seed=seed, tol=tol, logdet=parts["logdet"], t_low=parts["t_low"],
+               t_res=parts["t_res"], degrees=[int(x) for x in deg], stop_margin=margin, seconds=secs)
+    print(name, parts["logdet"], sorted(set(out["degrees"])), f"margin {margin:.2e}", f"{secs:.1f}s", flush=True)
+    with open(os.path.join(HERE, f"{name}.json"), "w") as f:
+        json.dump(out, f, indent=1)
+
+
 if __name__ == "__main__":
-    names = sys.argv[1:] or list(ENTRIES) + ["gmrf5000_theta_sweep"]
+    names = sys.argv[1:] or list(ENTRIES) + ["gmrf5000_theta_sweep", "gmrf2048_adaptive"]
     for nm in names:
         if nm == "gmrf5000_theta_sweep":
             make_gmrf_theta_sweep()
+        elif nm == "gmrf2048_adaptive":
+            make_adaptive()
         else:
             make(nm)

@@ -13,7 +13,7 @@ import pytest
 
 import workloads as w
 from oracle import exact, newton
-from tests.gpu_common import assert_cols_close, random_spd_csr
+from tests.gpu_common import assert_cols_close, golden, random_spd_csr
 
 pytestmark = pytest.mark.gpu
 
@@ -138,3 +138,83 @@ def test_adaptive_limits_and_errors():
             ld.apply_log_adaptive(A, 0.5, 8.5, 30, bad, V)
     out, deg = ld.apply_log_adaptive(A, 0.5, 8.5, 30, 1e-6, V[:, :0])
     assert out.shape == (1600, 0) and deg.shape == (0,)
+
+
+# ---- Alg. 3 with Alg. 2's stopping rule (ld_logdet_estimate_adaptive) ----------
+
+def estimator_margins_ok(plan, Q, parts, tol, margin=1e-3):
+    """clear_of_ties for the columns of S, Q_b and U the oracle's estimate used."""
+    return all(clear_of_ties(e_sequence(plan, Q, parts[key]), tol, margin) for key in ("S", "A", "U"))
+
+
+@pytest.mark.parametrize("dtype,rtol", [(torch.float64, 1e-10), (torch.float32, 1e-5)])
+@pytest.mark.parametrize("case", ["grid", "irregular", "blocks", "gaussian"])
+def test_adaptive_estimate_against_oracle(case, dtype, rtol):
+    # same probes, same stopping rule: identical per-column degrees and the
+    # oracle's estimate; "blocks" forces 4-column blocks (several sketch and
+    # quadratic-form blocks, a ragged last one), "irregular" has near-dense rows
+    if case == "irregular":
+        csr = random_spd_csr(3000, 17, long_rows=3)
+    else:
+        csr = w.grid_laplacian_2d(48, 0.3)
+    A, vals = to_gpu(csr, dtype)
+    Q = w.to_scipy((csr[0], csr[1], vals, csr[3]))
+    lo = 0.3 if case != "irregular" else 0.5
+    hi = 1.02 * float(np.abs(Q).sum(axis=1).max())
+    M, m_vec, seed = 70, 31, 4
+    probes = "gaussian" if case == "gaussian" else "rademacher"
+    opts = ld.Options(block_cols=4 if case == "blocks" else 0,
+                      probe_dist=1 if case == "gaussian" else 0)   # 1: Gaussian, 0: Rademacher
+    used = 0
+    for tol in np.geomspace(1e-1, 1e-9, 9) * math.sqrt(csr[3]):
+        parts = hutchpp_adaptive(Q, lo, hi, M, float(tol), m_vec, seed, probes)
+        if not estimator_margins_ok(parts["plan"], Q, parts, float(tol)):
+            continue
+        est, deg = ld.logdet_adaptive(A, lo, hi, M, float(tol), m_vec, seed, options=opts)
+        np.testing.assert_array_equal(deg, parts["degrees"])
+        assert abs(est - parts["logdet"]) <= rtol * abs(parts["logdet"]), (tol, est, parts["logdet"])
+        used += 1
+        if used == 3:
+            break
+    assert used >= 2
+
+
+def hutchpp_adaptive(Q, lo, hi, M, tol, m_vec, seed, probes):
+    from oracle import hutchpp
+    return hutchpp.logdet_estimate_adaptive(Q, lo, hi, M, tol, m_vec, seed, probes=probes, return_parts=True)
+
+
+def test_adaptive_estimate_special_cases():
+    csr = w.grid_laplacian_2d(30, 0.5)
+    A, _ = to_gpu(csr, torch.float64)
+    # tol = 0: every application runs to the cap (the fixed degree, forward form)
+    est, deg = ld.logdet_adaptive(A, 0.5, 8.5, 40, 0.0, 30, 2)
+    assert (deg == 40).all()
+    fixed = ld.logdet(A, 0.5, 8.5, 40, 30, 2)
+    assert abs(est - fixed) <= 1e-11 * abs(fixed)
+    # tol above every |d_0| ||x||: no products, F = d_0 I
+    est, deg, st = ld.logdet_adaptive(A, 0.5, 8.5, 40, 1e30, 30, 2, return_stats=True)
+    assert (deg == 0).all() and st["launches1"] == 0 and st["launches23"] == 0
+    from oracle import hutchpp
+    Q = w.to_scipy(csr)
+    ref, rdeg = hutchpp.logdet_estimate_adaptive(Q, 0.5, 8.5, 40, 1e30, 30, 2)
+    assert abs(est - ref) <= 1e-12 * abs(ref)
+    for bad in (-1.0, float("nan"), float("inf")):
+        with pytest.raises(ld.NativeError):
+            ld.logdet_adaptive(A, 0.5, 8.5, 40, bad, 30, 2)
+    with pytest.raises(ld.NativeError):
+        ld.logdet_adaptive(A, 0.5, 8.5, 40, 1e-6, 2, 2)      # n_matvec < 3
+
+
+@pytest.mark.parametrize("dtype,rtol", [(torch.float64, 1e-10), (torch.float32, 1e-6)])
+def test_adaptive_estimate_gmrf2048_full_size(dtype, rtol):
+    # the 2048^2 GMRF (cap 100, 32 queries) against the stored oracle run, whose
+    # stopping decisions all sit at least 1e-3 (relative) away from tol
+    g = golden("gmrf2048_adaptive")
+    if g is None:
+        pytest.skip("no stored value")
+    assert g["stop_margin"] > 1e-3
+    A, _ = to_gpu(w.build("gmrf2048"), dtype)
+    est, deg = ld.logdet_adaptive(A, g["lmin"], g["lmax"], g["max_degree"], g["tol"], g["m_vec"], g["seed"])
+    np.testing.assert_array_equal(deg, g["degrees"])
+    assert abs(est - g["logdet"]) <= rtol * abs(g["logdet"])
