@@ -688,6 +688,11 @@ hipError_t launch_step_t(const CsrDev& A, const StepArgs& s, hipStream_t st, int
     // occupancy is the smaller of the first and the other steps' variants, so
     // every step of a phase writes the same number of partial rows (they are
     // reduced together) and every launch's workgroups are all resident.
+    // Measured at 20 and 22 FP32 columns (first step 78 VGPRs: 6 workgroups
+    // per CU; the others 70: 7): the other steps' occupancy as the grid made
+    // them slower, 34 -> 41 us at the 1024^2 bench shape and 205 -> 252 us on
+    // the 2048^2 GMRF, with 96- or 48-row tiles alike; a grid balanced to
+    // whole rounds of tiles (1368 workgroups) took 36.5 us.
     auto grid = [&](const void* fn_first, const void* fn_rest) {
         return is_dot(KIND) ? std::min({ntiles, resident_wgs(fn_first, NT), resident_wgs(fn_rest, NT)}) : ntiles;
     };
