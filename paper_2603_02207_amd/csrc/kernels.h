@@ -102,13 +102,12 @@ constexpr int kLongWgs = 1024;   // workgroups of the long-row launch
 // list[0..count) ascending, *count on the device.  tmp: >= n/256 + 2 ints.
 hipError_t launch_long_rows(const CsrDev& A, int* tmp, int* list, int* count, hipStream_t st);
 
-// Workgroups of a step launch (the dot kinds write one partial row per
-// workgroup); the bound holds for 16-byte aligned blocks of at most bcols.
-int step_num_wg(bool f64, int n, const StepArgs& s);
 // Widest column range of one launch (a row group spans at most one wave).
 int step_max_cols(bool f64, const StepArgs& s);
+// Partial rows a column-sum launch writes (one per workgroup), at most: for
+// 16-byte aligned blocks of at most bcols columns, and for any layout.
 int step_num_wg_bound(int n, int bcols, int elem_bytes);
-int step_num_wg_any(int n);   // bound for the column-sum kinds at any layout
+int step_num_wg_any(int n);
 // Rows of one tile of the column-sum kinds over bcols columns of 16-byte aligned blocks.
 int step_tile_rows(int bcols, int elem_bytes);
 

@@ -843,12 +843,6 @@ int step_num_wg_any(int n) {
     return grid_of(STEP_DOT_SQ, div_up(n, (threads_of(STEP_PLAIN) / 64) * kStepIters)) + kLongWgs;
 }
 
-int step_num_wg(bool f64, int n, const StepArgs& s) {
-    const int vec = pick_vec(s, f64 ? 8 : 4);
-    const int rows = (threads_of(s.kind) / 64) * (64 / lanes_per_row(s.bcols, vec)) * kStepIters;
-    return grid_of(s.kind, div_up(n, rows)) + (s.long_rows && s.dia_nd == 0 ? kLongWgs : 0);   // partial rows written
-}
-
 hipError_t launch_step(bool f64, const CsrDev& A, const StepArgs& s, hipStream_t st, int* nwg_out) {
     if (f64) {
         const int vec = pick_vec(s, 8);
