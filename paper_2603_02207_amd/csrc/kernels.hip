@@ -1419,62 +1419,56 @@ hipError_t launch_reduce(const double* part, int nwg, int len, int part_ld, int 
 
 // ---------------------------------------------------------------------------
 // CholQR's small factorisation on the device: G = R^T R (upper R) and R^{-1},
-// k <= 64, one wavefront (lane c owns column c; the steps are ordered by
-// wavefront barriers, no workgroup barrier).  Right-looking elimination
-// subtracts the rank-one terms R[t][i] R[t][l] in increasing t, the order of
-// the textbook column-oriented Cholesky; R^{-1} solves R X = I row by row from
-// the last, each row's contribution subtracted from all rows above it.  A
-// non-finite Gram entry sets *flag = 1 and a non-positive or relatively tiny
-// pivot (rank-deficient sketch: r_jj <= 1e-7 sqrt(G_jj)) sets 2; then R^{-1}
-// is left zero.  *flag is written on every call.
+// k <= 64, one workgroup.  Right-looking elimination subtracts the rank-one
+// terms R[t][i] R[t][l] in increasing t, the order of the textbook
+// column-oriented Cholesky; R^{-1} solves R X = I row by row from the last,
+// each row's contribution subtracted from all rows above it at once.  A non-finite Gram entry sets *flag = 1 and a non-positive or
+// relatively tiny pivot (rank-deficient sketch: r_jj <= 1e-7 sqrt(G_jj))
+// sets 2; then R^{-1} is left zero.  *flag is written on every call.
 // ---------------------------------------------------------------------------
 constexpr int kCholMax = 64;
+constexpr int kCholThreads = 256;   // a 16 x 16 grid over the entries
 constexpr int kCholLd = kCholMax + 1;
 
-__device__ __forceinline__ void wave_sync_lds() {
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-}
-
-__global__ __launch_bounds__(64) void chol_factor_kernel(const double* __restrict__ G, int k,
-                                                         double* __restrict__ R, double* __restrict__ Rinv,
-                                                         int* __restrict__ flag) {
+__global__ __launch_bounds__(kCholThreads) void chol_factor_kernel(const double* __restrict__ G, int k,
+                                                                   double* __restrict__ R,
+                                                                   double* __restrict__ Rinv,
+                                                                   int* __restrict__ flag) {
     // R in the upper triangle of a; R^{-1} transposed in its strict lower
     // triangle, inv(j, i) at a[i][j], with the diagonal of R^{-1} in invd.
+    // Threads form a 16 x 16 grid (tx, ty) over the matrix entries.
     __shared__ double a[kCholMax * kCholLd];
     __shared__ double invd[kCholMax];
-    const int c = threadIdx.x;            // this lane's column
-    const bool mine = c < k;
-    double gcc = 0.0;                     // G_cc, for the relative pivot test
-    bool finite = true;
-    if (mine)
-        for (int r = 0; r < k; ++r) {
+    __shared__ double gdiag[kCholMax];   // the Gram's diagonal, for the relative pivot test
+    __shared__ int bad;
+    const int tid = threadIdx.x, tx = tid & 15, ty = tid >> 4;
+    if (tid == 0) bad = 0;
+    __syncthreads();
+    for (int r = ty; r < k; r += 16)
+        for (int c = tx; c < k; c += 16) {
             const double v = G[r * k + c];
-            finite = finite && isfinite(v);
+            if (!isfinite(v)) bad = 1;
             a[r * kCholLd + c] = v;
-            if (r == c) gcc = v;
+            if (r == c) gdiag[r] = v;
         }
-    int bad = __any(!finite) ? 1 : 0;
-    wave_sync_lds();
+    __syncthreads();
     for (int j = 0; j < k && bad == 0; ++j) {
         const double s = a[j * kCholLd + j];
         const double rjj = sqrt(s);
-        const double gjj = __shfl(gcc, j, 64);
-        if (!(s > 0.0 && isfinite(s) && rjj > 1e-7 * sqrt(fabs(gjj)))) {
-            bad = 2;
+        const bool ok = s > 0.0 && isfinite(s) && rjj > 1e-7 * sqrt(fabs(gdiag[j]));
+        __syncthreads();   // every lane has read the pivot before row j changes
+        if (!ok) {
+            if (tid == 0) bad = 2;
+            __syncthreads();
             break;
         }
-        wave_sync_lds();   // every lane has read the pivot before row j changes
-        double rjc = 0.0;
-        if (mine && c >= j) {
-            rjc = c == j ? rjj : a[j * kCholLd + c] / rjj;
-            a[j * kCholLd + c] = rjc;
-        }
-        wave_sync_lds();
-        if (mine && c > j)
-            for (int r = j + 1; r <= c; ++r) a[r * kCholLd + c] -= a[j * kCholLd + r] * rjc;
-        wave_sync_lds();
+        for (int i = j + tid; i < k; i += kCholThreads)
+            a[j * kCholLd + i] = i == j ? rjj : a[j * kCholLd + i] / rjj;
+        __syncthreads();
+        for (int r = j + 1 + ty; r < k; r += 16)
+            for (int c = j + 1 + tx; c < k; c += 16)
+                if (c >= r) a[r * kCholLd + c] -= a[j * kCholLd + r] * a[j * kCholLd + c];
+        __syncthreads();
     }
     const int ok = bad == 0;
     // R X = I solved by rows, last first: row j of X is final once the rows
@@ -1482,42 +1476,41 @@ __global__ __launch_bounds__(64) void chol_factor_kernel(const double* __restric
     // start); then every row i < j takes away R[i][j] X[j][:].  B and X are
     // upper triangular: B[i][c] (i < c) lives at a[c][i], its diagonal in invd.
     if (ok) {
-        if (mine) {
-            for (int r = c + 1; r < k; ++r) a[r * kCholLd + c] = 0.0;
-            invd[c] = 1.0;
-        }
-        wave_sync_lds();
+        for (int r = ty; r < k; r += 16)
+            for (int c = tx; c < r; c += 16) a[r * kCholLd + c] = 0.0;
+        for (int i = tid; i < k; i += kCholThreads) invd[i] = 1.0;
+        __syncthreads();
         for (int j = k - 1; j >= 0; --j) {
             const double rjj = a[j * kCholLd + j];
-            double xjc = 0.0;
-            if (mine && c >= j) {
-                if (c == j) {
-                    xjc = invd[j] / rjj;
-                    invd[j] = xjc;
-                } else {
-                    xjc = a[c * kCholLd + j] / rjj;
-                    a[c * kCholLd + j] = xjc;
-                }
+            for (int c = j + tid; c < k; c += kCholThreads) {
+                if (c == j)
+                    invd[j] = invd[j] / rjj;
+                else
+                    a[c * kCholLd + j] = a[c * kCholLd + j] / rjj;
             }
-            wave_sync_lds();
-            if (mine && c >= j)
-                for (int i = 0; i < j; ++i) a[c * kCholLd + i] -= a[i * kCholLd + j] * xjc;
-            wave_sync_lds();
+            __syncthreads();
+            for (int i = ty; i < j; i += 16)
+                for (int c = j + tx; c < k; c += 16) {
+                    const double xjc = c == j ? invd[j] : a[c * kCholLd + j];
+                    a[c * kCholLd + i] -= a[i * kCholLd + j] * xjc;
+                }
+            __syncthreads();
         }
     }
-    if (mine)
-        for (int r = 0; r < k; ++r) {
+    __syncthreads();
+    for (int r = ty; r < k; r += 16)
+        for (int c = tx; c < k; c += 16) {
             const bool on = ok && c >= r;
             if (R) R[r * k + c] = on ? a[r * kCholLd + c] : 0.0;
             Rinv[r * k + c] = on ? (c == r ? invd[r] : a[c * kCholLd + r]) : 0.0;
         }
-    if (c == 0) *flag = bad;
+    if (tid == 0) *flag = bad;
 }
 
 hipError_t launch_chol_factor(const double* G, int k, double* R, double* Rinv, int* flag,
                               hipStream_t st) {
     if (k < 1 || k > kCholMax) return hipErrorInvalidValue;
-    hipLaunchKernelGGL(chol_factor_kernel, dim3(1), dim3(64), 0, st, G, k, R, Rinv, flag);
+    hipLaunchKernelGGL(chol_factor_kernel, dim3(1), dim3(kCholThreads), 0, st, G, k, R, Rinv, flag);
     return hipGetLastError();
 }
 
