@@ -189,6 +189,7 @@ struct EstLayout {
     // segment (fwdb bytes at stride `stride`); the region is the larger one.
     BlkMat FX, Gm, T1;
     size_t grad64 = 0;
+    size_t ghalf = 0;          // the squared sweep's half accumulator (diagonal storage)
     int H = 0, sq_stride = 0;        // squared path: forward steps ceil(m/2), checkpoint stride
     size_t sqb = 0;
     int gcols = 0, ldg = 0, nckpt = 0, stride = 0;   // Newton-form path
@@ -270,6 +271,9 @@ EstLayout layout_estimate(const ld_csr* A, int degree, int n_matvec, bool grad,
         L.Gm = make_blk(n, L.kg, L.kg, L.elem);
         L.T1 = make_blk(n, L.k, L.k, L.elem);
         L.grad64 = L.elem == 8 ? 0 : (size_t)A->nnz * 8;
+        // upper-entry pair sums of the squared sweep on the diagonal storage:
+        // at most (kMaxDiag + 1) / 2 slots per row
+        L.ghalf = o.csr_only ? 0 : (size_t)n * ((kMaxDiag + 1) / 2) * 8;
         L.H = (degree + 1) / 2;
         L.sq_stride = o.ckpt_stride > 0 ? std::min(o.ckpt_stride, degree)
                                         : auto_ckpt_stride(degree, [&](int s) { return sq_region(L, degree, s); });
@@ -305,7 +309,7 @@ size_t layout_bytes(const EstLayout& L, bool grad) {
         b += align_up(s);
     b += L.longb;
     if (grad) {
-        for (size_t s : {L.FX.bytes(), L.Gm.bytes(), L.T1.bytes(), L.mask, L.grad64}) b += align_up(s);
+        for (size_t s : {L.FX.bytes(), L.Gm.bytes(), L.T1.bytes(), L.mask, L.grad64, L.ghalf}) b += align_up(s);
         b += std::max(L.sqb, L.fwdb);
     }
     return b;
@@ -860,6 +864,7 @@ int check_estimate_args(const ld_csr* A, double lmin, double lmax, int degree, i
 struct GradBufs {
     void* mask2 = nullptr;
     double* grad64 = nullptr;          // FP64 accumulator (the output itself for an FP64 matrix)
+    double* ghalf = nullptr;           // squared sweep's upper-entry pair sums (diagonal storage)
     // Newton-form path
     void *Lg = nullptr, *Rg = nullptr, *lam0 = nullptr, *lam1 = nullptr;
     std::vector<void*> ckpt, seg;
@@ -1131,6 +1136,21 @@ int gradient_squared(const ld_csr* A, uint64_t seed, EstimateState& S, GradBufs&
         dg.dia = lr.dia;
         dg.constant = lr.dia_pres != nullptr;
     }
+    // offsets symmetric about the main diagonal (a symmetric pattern): the
+    // squared sweep adds each mirrored pair into one slot of the upper entry
+    // (half the accumulator traffic), expanded to every entry afterwards
+    bool sym = on_dia && B.ghalf;
+    if (sym) {
+        int q0 = -1;
+        for (int q = 0; q < dg.nd; ++q)
+            if (dg.off[q] == 0) q0 = q;
+        sym = q0 >= 0 && 2 * q0 + 1 == dg.nd;
+        for (int h = 1; sym && h <= q0; ++h) sym = dg.off[q0 + h] == -dg.off[q0 - h];
+        if (sym) {
+            dg.qh0 = q0;
+            dg.nh = dg.nd - q0;
+        }
+    }
     auto sweep = [&](const AdjArgs& a) -> int {
         LD_CHECK_HIP(on_dia ? launch_adjoint_dia(f64, d, a, dg, st) : launch_adjoint(f64, d, a, st));
         return LD_OK;
@@ -1151,12 +1171,12 @@ int gradient_squared(const ld_csr* A, uint64_t seed, EstimateState& S, GradBufs&
         }
         for (int i = b1 - 1; i >= b0; --i) {
             AdjArgs a{};
-            a.mode = ADJ_SQUARED;
+            a.mode = sym ? ADJ_SQUARED_SYM : ADJ_SQUARED;
             a.lam_in = i == H - 1 ? us.at(H) : B.mu[cur];
             a.lam_scale = i == H - 1 ? 2.0 * coef(2 * H) : 1.0;
             a.lam_out = B.mu[1 - cur];
             a.w = u[i - b0];
-            a.grad = B.grad64;
+            a.grad = sym ? B.ghalf : B.grad64;
             a.ld = ldX;
             a.ncols = nc;
             a.alpha = p.alpha;
@@ -1175,8 +1195,12 @@ int gradient_squared(const ld_csr* A, uint64_t seed, EstimateState& S, GradBufs&
         }
     }
     // the quadratic forms' per-entry derivative is symmetric: mirrored means
+    // (from the pair sums of the half accumulator, or in place)
     LD_CHECK_HIP(hipMemsetAsync(S.flag + 3, 0, sizeof(int), st));
-    LD_CHECK_HIP(launch_symmetrize(d, B.grad64, S.flag + 3, st));
+    if (sym)
+        LD_CHECK_HIP(launch_expand_half(d, dg, B.ghalf, B.grad64, S.flag + 3, st));
+    else
+        LD_CHECK_HIP(launch_symmetrize(d, B.grad64, S.flag + 3, st));
     // ---- basis term: the adjoint of the sketch's Horner evaluation, from 2Z
     //      (computed from mu~_0 = 2 F [Q_b | U] directly)
     LD_CHECK(basis_term(A, seed, S, B, B.mu[cur], 1.0, B.rb[0], Blk::plain(ldY), st));
@@ -1280,6 +1304,7 @@ int run_logdet(const ld_csr* A, double lmin, double lmax, int degree, int n_matv
         S.L.T1.base = ar.take(S.L.T1.bytes());
         B.mask2 = ar.take(S.L.mask);
         B.grad64 = S.L.grad64 ? (double*)ar.take(S.L.grad64) : (double*)grad;
+        B.ghalf = S.L.ghalf ? (double*)ar.take(S.L.ghalf) : nullptr;
         // the chosen path's vectors share one region
         Arena reg{(char*)ar.take(std::max(S.L.sqb, S.L.fwdb)), std::max(S.L.sqb, S.L.fwdb), 0};
         if (sq_grad) {

@@ -175,7 +175,14 @@ hipError_t launch_gershgorin(bool f64, const CsrDev& A, double* part, hipStream_
 //   ADJ_PLAIN2 (diagonal storage only): ADJ_PLAIN, and the entry also picks up
 //                alpha * sum_cols lam_out[r, col] * w2[c, col] (two steps of the
 //                sketch's adjoint per read and write of the gradient)
-enum AdjMode : int { ADJ_HORNER = 0, ADJ_PLAIN = 1, ADJ_SQUARED = 2, ADJ_PLAIN2 = 3 };
+//   ADJ_SQUARED_SYM (diagonal storage with offsets symmetric about the main
+//                diagonal): ADJ_SQUARED's step, and each mirrored pair is summed
+//                into the half accumulator of its upper entry: for c > r the
+//                slot (r, c) picks up alpha * sum_cols (own[r] w[c] + own[c] w[r]),
+//                the diagonal slot alpha * sum_cols own[r] w[r]; slots are
+//                grad[r * nh + h] for the h-th non-negative offset (the lower
+//                entries have no slot)
+enum AdjMode : int { ADJ_HORNER = 0, ADJ_PLAIN = 1, ADJ_SQUARED = 2, ADJ_PLAIN2 = 3, ADJ_SQUARED_SYM = 4 };
 struct AdjArgs {
     int mode;
     const void* lam_in;
@@ -197,7 +204,7 @@ struct AdjArgs {
 hipError_t launch_adjoint(bool f64, const CsrDev& A, const AdjArgs& a, hipStream_t st);
 
 // The same step on the diagonal storage (modes ADJ_PLAIN, ADJ_PLAIN2,
-// ADJ_SQUARED): presence bits per row (pres), the values either one per
+// ADJ_SQUARED, ADJ_SQUARED_SYM): presence bits per row (pres), the values either one per
 // diagonal (constant) or dia[r*nd + q]; the gradient at A's CSR positions
 // (row_ptr of A).
 struct AdjDia {
@@ -208,8 +215,17 @@ struct AdjDia {
     bool constant;
     double cval[kMaxDiag];
     int chunk_rows;   // > 0: chunked XCD bands of this many rows (0: contiguous bands)
+    int qh0 = 0, nh = 0;   // ADJ_SQUARED_SYM: index of offset 0, number of offsets >= 0
 };
 hipError_t launch_adjoint_dia(bool f64, const CsrDev& A, const AdjArgs& a, const AdjDia& dg, hipStream_t st);
+
+// Every stored entry of the gradient from the half accumulator of
+// ADJ_SQUARED_SYM (half[r * nh + h], nh = dg.nh): g at the CSR position of
+// (r, c) = half of the upper entry's pair sum for r != c, the diagonal slot
+// for r = c (a mean of mirrored pairs, as launch_symmetrize gives); *flag
+// (device int) set to 1 when an entry's mirror is absent.
+hipError_t launch_expand_half(const CsrDev& A, const AdjDia& dg, const double* half, double* g, int* flag,
+                              hipStream_t st);
 
 // Mean of every mirrored pair g[(r,c)], g[(c,r)] (FP64, CSR positions); *flag
 // (device int) set to 1 when some entry has no mirror.

@@ -21,6 +21,7 @@
 #include <climits>
 #include <cstdint>
 #include <mutex>
+#include <type_traits>
 #include <unordered_map>
 
 #include "kernels.h"
@@ -2288,13 +2289,17 @@ __global__ __launch_bounds__(kThreads) void adjoint_dia_kernel(
     int n, const int* __restrict__ row_ptr, const uint16_t* __restrict__ pres, const T* __restrict__ dia, int nd,
     DiaOff off, DiaVal<T> cv, int constant, const T* __restrict__ lam_in, T* __restrict__ lam_out,
     const T* __restrict__ w, const T* __restrict__ w2, double* __restrict__ grad, int ld, int ncols, T alpha,
-    T beta, T q0, T q1, T p1, int wsplit, T whi, int first, int last, int nt_out, T lam_scale, int chunk) {
-    static_assert(MODE == ADJ_PLAIN || MODE == ADJ_PLAIN2 || MODE == ADJ_SQUARED, "diagonal-storage modes");
+    T beta, T q0, T q1, T p1, int wsplit, T whi, int first, int last, int nt_out, T lam_scale, int chunk,
+    int qh0, int nh) {
+    static_assert(MODE == ADJ_PLAIN || MODE == ADJ_PLAIN2 || MODE == ADJ_SQUARED || MODE == ADJ_SQUARED_SYM,
+                  "diagonal-storage modes");
     constexpr int RPW = 64 / LPR;
     constexpr int rows_per_wg = kWaves * RPW;
-    constexpr bool kSq = MODE == ADJ_SQUARED;
+    constexpr bool kSym = MODE == ADJ_SQUARED_SYM;   // pair sums into the upper entries' half slots
+    constexpr bool kSq = MODE == ADJ_SQUARED || kSym;
     constexpr bool kTwo = MODE == ADJ_PLAIN2;
-    constexpr int PER = (ND + LPR - 1) / LPR;   // gradient entries per lane
+    constexpr int NE = kSym ? (ND + 1) / 2 : ND;   // gradient slots of a row
+    constexpr int PER = (NE + LPR - 1) / LPR;      // gradient slots per lane
     const int lane = threadIdx.x & 63;
     const int wave = threadIdx.x >> 6;
     const int g = lane / LPR;
@@ -2315,16 +2320,24 @@ __global__ __launch_bounds__(kThreads) void adjoint_dia_kernel(
     const bool inld = c0 < ld;
     const unsigned bits = pres[row];
     const int rp = row_ptr[row];
-    // this lane's gradient entries (diagonals q = li, li + LPR, ...), read
-    // ahead of the gathers
-    int kgs[PER];
+    // this lane's gradient slots (diagonals q = li, li + LPR, ...; with the
+    // half accumulator the non-negative offsets q = qh0 + h, h = li, li + LPR,
+    // ...), read ahead of the gathers
+    using KIdx = std::conditional_t<kSym, long long, int>;
+    KIdx kgs[PER];
     bool on[PER];
     double gold[PER];
 #pragma unroll
     for (int t = 0; t < PER; ++t) {
-        const int q = li + t * LPR;
-        on[t] = q < nd && q < ND && ((bits >> q) & 1u);
-        kgs[t] = rp + __popc(bits & ((1u << q) - 1u));
+        if constexpr (kSym) {
+            const int h = li + t * LPR, q = qh0 + h;
+            on[t] = h < nh && q < nd && ((bits >> q) & 1u);
+            kgs[t] = (long long)row * nh + h;
+        } else {
+            const int q = li + t * LPR;
+            on[t] = q < nd && q < ND && ((bits >> q) & 1u);
+            kgs[t] = rp + __popc(bits & ((1u << q) - 1u));
+        }
         gold[t] = on[t] && !first ? grad[kgs[t]] : 0.0;
     }
     int cq[ND];
@@ -2411,6 +2424,14 @@ __global__ __launch_bounds__(kThreads) void adjoint_dia_kernel(
         T p1q = T(0), p2q = T(0);
 #pragma unroll
         for (int e = 0; e < VEC; ++e) p1q = valid[e] ? fma(sown[e], wq[q].v[e], p1q) : p1q;
+        if (kSym && q > qh0) {   // the mirror (c, r): own at the neighbour times w at the row
+            // (its own lane sum, as the CSR path forms it in row c)
+#pragma unroll
+            for (int e = 0; e < VEC; ++e) {
+                const T oc = (c0 + e < wsplit ? T(1) : whi) * fma(p1, wq[q].v[e], lq[q].v[e]);
+                p2q = valid[e] ? fma(oc, wr.v[e], p2q) : p2q;
+            }
+        }
         if (kTwo) {
 #pragma unroll
             for (int e = 0; e < VEC; ++e) p2q = valid[e] ? fma(o.v[e], w2q[q].v[e], p2q) : p2q;
@@ -2424,8 +2445,9 @@ __global__ __launch_bounds__(kThreads) void adjoint_dia_kernel(
 #pragma unroll
     for (int t = 0; t < PER; ++t) {
         double v = 0.0;
+        const int qsel = (kSym ? qh0 : 0) + li + t * LPR;
 #pragma unroll
-        for (int q = 0; q < ND; ++q) v = q == li + t * LPR ? part[q] : v;
+        for (int q = 0; q < ND; ++q) v = q == qsel ? part[q] : v;
         if (on[t]) grad[kgs[t]] = first ? (double)alpha * v : fma((double)alpha, v, gold[t]);
     }
 }
@@ -2450,11 +2472,19 @@ hipError_t launch_adjoint_dia_t(const CsrDev& A, const AdjArgs& a, const AdjDia&
                        dg.pres, (const T*)dg.dia, dg.nd, off, cv, (int)dg.constant, (const T*)a.lam_in,          \
                        (T*)a.lam_out, (const T*)a.w, (const T*)a.w2, a.grad, a.ld, a.ncols, (T)a.alpha,          \
                        (T)a.beta, (T)a.q0, (T)a.q1, (T)a.p1, a.wsplit, (T)a.whi, (int)a.first, (int)a.last,      \
-                       (int)a.nt_out, (T)a.lam_scale, cwg)
+                       (int)a.nt_out, (T)a.lam_scale, cwg, dg.qh0, dg.nh)
     switch (a.mode) {
         case ADJ_PLAIN: LD_ADJ_DIA(ADJ_PLAIN); break;
         case ADJ_PLAIN2: LD_ADJ_DIA(ADJ_PLAIN2); break;
         case ADJ_SQUARED: LD_ADJ_DIA(ADJ_SQUARED); break;
+        case ADJ_SQUARED_SYM:
+            // offsets symmetric about the main diagonal, which sits at qh0
+            if (dg.nh < 1 || dg.qh0 + dg.nh != dg.nd || 2 * dg.qh0 + 1 != dg.nd || dg.off[dg.qh0] != 0)
+                return hipErrorInvalidValue;
+            for (int h = 1; h < dg.nh; ++h)
+                if (dg.off[dg.qh0 + h] != -dg.off[dg.qh0 - h]) return hipErrorInvalidValue;
+            LD_ADJ_DIA(ADJ_SQUARED_SYM);
+            break;
         default: return hipErrorInvalidValue;
     }
 #undef LD_ADJ_DIA
@@ -2489,6 +2519,50 @@ hipError_t launch_adjoint_dia_v(const CsrDev& A, const AdjArgs& a, const AdjDia&
 hipError_t launch_adjoint_dia(bool f64, const CsrDev& A, const AdjArgs& a, const AdjDia& dg, hipStream_t st) {
     if (f64) return launch_adjoint_dia_v<double, 2>(A, a, dg, st);
     return launch_adjoint_dia_v<float, 4>(A, a, dg, st);
+}
+
+// The stored entries of row r from the half accumulator (one thread per row,
+// grid-stride): diagonal q of r (present bit) sits at CSR position row_ptr[r]
+// + (present diagonals below q); it takes the diagonal slot (q = qh0), or
+// half the pair sum in the upper entry's slot: row r's own slot q - qh0 for
+// q > qh0, row c's slot qm - qh0 of the mirrored diagonal qm = 2 qh0 - q for
+// q < qh0.  An absent mirror sets *flag.
+__global__ __launch_bounds__(kThreads) void expand_half_kernel(int n, const int* __restrict__ row_ptr,
+                                                               const uint16_t* __restrict__ pres, int nd,
+                                                               DiaOff off, int qh0, int nh,
+                                                               const double* __restrict__ half,
+                                                               double* __restrict__ g, int* __restrict__ flag) {
+    for (int r = blockIdx.x * kThreads + threadIdx.x; r < n; r += gridDim.x * kThreads) {
+        const unsigned bits = pres[r];
+        int k = row_ptr[r];
+#pragma unroll
+        for (int q = 0; q < kMaxDiag; ++q) {
+            if (q >= nd || !((bits >> q) & 1u)) continue;
+            double v;
+            if (q == qh0) {
+                v = half[(size_t)r * nh];
+            } else {
+                const int c = r + off.o[q], qm = 2 * qh0 - q;
+                const bool mirror = (unsigned)c < (unsigned)n && qm >= 0 && qm < nd && ((pres[c] >> qm) & 1u);
+                if (!mirror) *flag = 1;
+                v = q > qh0 ? 0.5 * half[(size_t)r * nh + (q - qh0)]
+                            : (mirror ? 0.5 * half[(size_t)c * nh + (qm - qh0)] : 0.0);
+            }
+            g[k++] = v;
+        }
+    }
+}
+
+hipError_t launch_expand_half(const CsrDev& A, const AdjDia& dg, const double* half, double* g, int* flag,
+                              hipStream_t st) {
+    if (A.n == 0) return hipSuccess;
+    if (dg.nh < 1 || dg.qh0 + dg.nh != dg.nd || dg.nd > kMaxDiag) return hipErrorInvalidValue;
+    DiaOff off{};
+    for (int q = 0; q < kMaxDiag; ++q) off.o[q] = q < dg.nd ? dg.off[q] : 0;
+    const int nwg = std::min(div_up(A.n, kThreads), 4096);
+    hipLaunchKernelGGL(expand_half_kernel, dim3(nwg), dim3(kThreads), 0, st, A.n, A.row_ptr, dg.pres, dg.nd, off,
+                       dg.qh0, dg.nh, half, g, flag);
+    return hipGetLastError();
 }
 
 // ---------------------------------------------------------------------------
