@@ -238,3 +238,29 @@ def test_grad_gmrf2048_checkpoint_stride_is_exact():
     assert e1 == e10 and torch.equal(g1, g10)
     assert ld.workspace_size(A, deg, mv, True, ld.Options(ckpt_stride=10)) < \
         0.5 * ld.workspace_size(A, deg, mv, True, ld.Options(ckpt_stride=1))
+
+
+def test_grad_rejects_a_pattern_without_mirrors():
+    # A grid Laplacian plus an explicit zero at (r, r+1) for r at the end of a
+    # grid line, whose mirror (r+1, r) is not stored: the same matrix, but the
+    # per-entry derivative of the quadratic forms has no mirrored entry to be
+    # averaged with.  Both the diagonal storage (offsets still -N, -1, 0, 1, N)
+    # and the CSR path refuse the gradient; the estimate is unaffected.
+    N = 24
+    row_ptr, col_idx, val, n = w.grid_laplacian_2d(N, 0.5)
+    r_x = 5 * N + N - 1                       # last point of grid line 5
+    rows = np.repeat(np.arange(n), np.diff(row_ptr))
+    rr = np.concatenate([rows, [r_x]])
+    cc = np.concatenate([col_idx, [r_x + 1]])
+    vv = np.concatenate([val, [0.0]])
+    order = np.lexsort((cc, rr))
+    rp2 = np.concatenate([[0], np.cumsum(np.bincount(rr[order], minlength=n))]).astype(np.int32)
+    csr = (rp2, cc[order].astype(np.int32), vv[order], n)
+    A, _ = to_gpu(csr, torch.float64)
+    A_ref, _ = to_gpu((row_ptr, col_idx, val, n), torch.float64)
+    est, st = ld.logdet(A, 0.5, 8.5, 20, 12, 1, return_stats=True)
+    assert st["dia_diagonals"] == 5
+    assert abs(est - ld.logdet(A_ref, 0.5, 8.5, 20, 12, 1)) <= 1e-12 * abs(est)
+    for opts in (None, ld.Options(csr_only=1)):
+        with pytest.raises(ld.NativeError, match="symmetric sparsity pattern"):
+            ld.logdet_with_grad(A, 0.5, 8.5, 20, 12, 1, options=opts)
