@@ -1528,7 +1528,7 @@ hipError_t launch_chol_factor(const double* G, int k, double* R, double* Rinv, i
 // coalesced, adding the optional base matrix and probe signs.  Y, base and
 // out are column-blocked (Blk).
 constexpr int kRowmatWgs = 1024;
-constexpr int kRowmatBatch = 16;   // loads a thread keeps in flight while staging
+constexpr int kRowmatBatch = 8;    // loads a thread keeps in flight while staging (16: 151-214 VGPRs, 19-21% slower)
 
 // FAST: Y's columns lie in one block whose rows (ld <= max(KY, KO), 16-byte
 // multiple) the tile holds whole, and out (and base) cover whole rows of
