@@ -29,8 +29,10 @@
  *     which must be 256-byte aligned (LD_EINVAL otherwise); with
  *     workspace == NULL the library allocates and frees it itself.
  *   - The matrix must be symmetric positive definite with sorted column
- *     indices in each row (CSR, int32 indices).  Symmetry is assumed, not
- *     checked; the CSR structure is checked unless opts->trusted_csr != 0.
+ *     indices in each row (CSR, int32 indices).  Symmetry of the values is
+ *     assumed, not checked (the gradient refuses a sparsity pattern that is
+ *     not symmetric); the CSR structure is checked unless
+ *     opts->trusted_csr != 0.
  *   - Results are deterministic for fixed inputs and options (no atomics in
  *     any reduction).
  */
@@ -101,7 +103,8 @@ typedef struct {
                                 and gathers from it instead of the CSR arrays,
                                 keeping one value per diagonal when each
                                 diagonal's entries are all equal; same sums in
-                                the same order)                                 */
+                                the same order, except the gradient's per-entry
+                                sums, grouped differently: equal to rounding)  */
     int32_t tile_order;      /* LD_TILES_AUTO / LD_TILES_XCD_BANDS /
                                 LD_TILES_INTERLEAVED: how the workgroups of a
                                 Newton-step launch walk the row tiles (auto:
@@ -119,10 +122,11 @@ typedef struct {
     double ms_total;         /* wall time of the call (host clock)             */
     double ms_phase1;        /* sketch Y = P_m(Q~) S                           */
     double ms_qr;            /* CholQR2 + deflation                            */
-    double ms_phase23;       /* quadratic forms on [Q_b | U] (estimate only)   */
-    double ms_adjoint;       /* gradient only: forward pass over [Q_b, U, S]
-                                with F [Q_b | U] accumulated, the k-column
-                                algebra and the reverse sweep                  */
+    double ms_phase23;       /* quadratic forms on [Q_b | U] (not run by a
+                                gradient call that takes the Newton form)      */
+    double ms_adjoint;       /* gradient only: the reverse sweeps and the
+                                k-column algebra (in the Newton form also its
+                                forward pass over [Q_b, U, S])                 */
     double bytes_alg;        /* algorithmic HBM bytes of the recurrence kernels */
     int64_t taylor_terms;    /* Taylor order used by Alg. 1                    */
     double sigma, lo, hi;    /* scaling and interval of Q~                     */
@@ -143,8 +147,11 @@ typedef struct {
     int32_t xcd_chunk_rows;  /* with XCD bands: 0 = one contiguous band of rows
                                 per XCD; > 0 = the bands are cut into chunks of
                                 this many rows dealt to the XCDs in turn (a
-                                3-D stencil whose plane neighbours would not
-                                stay in an XCD's L2), for the quadratic forms */
+                                launch that streams from HBM, or a 3-D stencil
+                                whose plane neighbours would not stay in an
+                                XCD's L2), as the quadratic-form launches took
+                                them (0 when a chunk is not a whole number of
+                                their tiles)                                   */
 } ld_stats;
 
 /* Defaults for ld_options (all zero except as documented). */
@@ -295,13 +302,20 @@ int ld_logdet_estimate_noalloc(const ld_csr* A, double lmin, double lmax, int32_
 
 /* As ld_logdet_estimate, and the exact derivative of the returned estimate
  * with respect to each stored value of A (same probes, interval and sigma
- * held fixed; includes the dependence of the sketch basis on A), by a reverse
- * sweep of the Newton recurrence with checkpoints every opts->ckpt_stride
- * steps.  The traces of the estimate come from F [Q_b | U] accumulated in the
- * forward form of Alg. 2 (the same polynomial as ld_logdet_estimate's
- * quadratic forms, summed in another order: the two estimates agree to
- * rounding, not bitwise).  grad_val: device, nnz entries of A's dtype,
- * overwritten.  Errors: as ld_logdet_estimate. */
+ * held fixed; includes the dependence of the sketch basis on A: the
+ * estimate's method is Alg. 3 of Sec. 4.1, the derivative is not in the
+ * paper).  When the estimate takes the squared basis for its quadratic forms
+ * (opts->dot_mode) and k + k_G <= 64, the forward vectors of the estimate's
+ * own passes are kept and swept in reverse (the returned estimate is then
+ * bit-identical to ld_logdet_estimate's); otherwise one forward pass in the
+ * Newton form and one reverse sweep (estimates agree to rounding).  Vectors
+ * are kept every opts->ckpt_stride steps (0: all of them while they fit
+ * 64 GiB, else the smallest stride that does) and recomputed in between.
+ * The quadratic forms' per-entry derivative is symmetric in (r, c) for a
+ * symmetric A, so mirrored entries take their mean: A's sparsity pattern
+ * must be symmetric.  Sums in FP64 (an FP32 matrix's gradient is rounded to
+ * FP32 once).  grad_val: device, nnz entries of A's dtype, overwritten.
+ * Errors: as ld_logdet_estimate; LD_EINVAL also when an entry has no mirror. */
 int ld_logdet_grad(const ld_csr* A, double lmin, double lmax, int32_t degree, int32_t n_matvec,
                    uint64_t seed, const ld_options* opts, void* workspace, size_t ws_bytes,
                    void* stream, double* out_logdet, void* grad_val, ld_stats* stats);
