@@ -33,7 +33,10 @@ sys.path.insert(0, ROOT)
 METRIC = "logdet estimates/sec & SpMM HBM GB/s at ≤1e-4 rel err, FP32 vs FP64, 1 GPU"
 HBM_PEAK_GBS = 8000.0
 INFINITY_CACHE_BYTES = 256e6   # MI355X last-level (MALL) cache: a launch below this can run from it
-HBM_WORKLOAD = "gmrf2048"      # blocks far beyond the Infinity Cache: the steps stream from HBM
+LARGE_WORKLOADS = {           # extra records of the default line
+    "gmrf2048": "gmrf2048",        # the 2048^2 GMRF: column blocks that fit the Infinity Cache
+    "hbm_bound": "gmrf5000_theta",  # n = 2.5e7: no block fits the cache, the steps stream from HBM
+}
 
 
 def parse():
@@ -412,7 +415,11 @@ def traffic_summary(dirs, bench_log=None) -> str:
         a = ""
         ratio = ""
         for tag, rec in alg.items():
-            if any(k.startswith(p) for p in KERNEL_PREFIXES.get((tag, rec["kernel"]), ())) and ", true" not in k:
+            prefixes = KERNEL_PREFIXES.get((tag, rec["kernel"]), ())
+            # a library launch of a step kernel may be several dispatches over row ranges
+            if any(k.startswith(p.replace(", false", "")) for p in prefixes):
+                r, w = (x * rec.get("dispatches_per_launch", 1) for x in (r, w))
+            if any(k.startswith(p) for p in prefixes) and ", true" not in k:
                 a = f"{rec['bytes_per_launch'] / 1e6:.1f}"
                 ratio = f"{(r + w) / (rec['bytes_per_launch'] / 1e6):.2f}"
         lines.append(f"| {k[:160]} | {r:.1f} | {w:.1f} | {r + w:.1f} | {a} | {ratio} |")
@@ -453,7 +460,9 @@ def main():
         out = run_workload(args, args.workload, args.steps)
         if args.extras:
             torch.cuda.empty_cache()
-            out["hbm_bound"] = hbm_record(args)
+            for key, name in LARGE_WORKLOADS.items():
+                out[key] = large_record(args, name)
+                torch.cuda.empty_cache()
         print(json.dumps(out), flush=True)
         return
     args.extras = False
@@ -493,7 +502,9 @@ def kernel_records(st):
             avg_s = ms / 1e3 / nl
             kernels[tag] = {"kernel": step_kernel_name(tag, st), "launches": nl, "avg_us": avg_s * 1e6,
                             "bytes_per_launch": by / nl,
-                            "GBps": by / nl / avg_s / 1e9, "total_ms": ms}
+                            "GBps": by / nl / avg_s / 1e9, "total_ms": ms,
+                            # kernel dispatches per library launch (row ranges of a streaming step)
+                            "dispatches_per_launch": st.get("ranges23", 1) if tag == "quadform" else 1}
     return kernels
 
 
@@ -586,6 +597,7 @@ def run_workload(args, workload, steps):
                                 (", one value each, presence bits per row)" if st.get("dia_constant") else ")"))
                                if st.get("dia_diagonals") else "csr"),
             "block_cols": args.block_cols,
+            "column_blocks": {"sketch": st["block_cols1"], "quadform": st["block_cols23"]},
             "tile_order": {1: "bands", 2: "interleaved"}[st["tile_order_used"]],
             "probes": args.probe_dist,
             "seed": args.seed,
@@ -605,7 +617,8 @@ def run_workload(args, workload, steps):
             "alg_bytes_per_launch": kernels[dom]["bytes_per_launch"],
             "working_set": (f"{kernels[dom]['bytes_per_launch'] / 1e6:.0f} MB per launch "
                             + ("<= the 256 MB Infinity Cache: the blocks stream from the cache, so frac "
-                               "against the HBM peak is not an HBM efficiency (see hbm_bound)" if in_cache
+                               "against the HBM peak is not an HBM efficiency (hbm_bound: a workload whose "
+                               "blocks cannot fit it)" if in_cache
                                else "> the 256 MB Infinity Cache: the blocks stream from HBM")),
         },
         "spmm_recurrence_GBps": total_bytes / (total_ms / 1e3) / 1e9,
@@ -718,16 +731,15 @@ def run_workload(args, workload, steps):
     return out
 
 
-def hbm_record(args):
-    """The HBM-bound workload: estimates/s, its dominant step kernel against
-    8 TB/s and against a 1 GiB copy measured here, counter bytes if taken on
-    the current sources."""
+def large_record(args, name):
+    """A large workload in FP32: estimates/s, its dominant step kernel against
+    8 TB/s and against a 1 GiB copy measured here, whether its launches fit the
+    Infinity Cache, and counter bytes if taken on the current sources."""
     import torch
 
     import paper_2603_02207_amd as ld
     import workloads
 
-    name = HBM_WORKLOAD
     cfg = dict(workloads.CONFIGS[name])
     row_ptr, col_idx, val, n = workloads.build(name)
     nnz = int(len(col_idx))
@@ -755,7 +767,9 @@ def hbm_record(args):
         "matrix_storage": ((f"diagonal ({st['dia_diagonals']} diagonals" +
                             (", one value each)" if st.get("dia_constant") else ")"))
                            if st.get("dia_diagonals") else "csr"),
+        "column_blocks": {"sketch": st["block_cols1"], "quadform": st["block_cols23"]},
         "dominant_kernel": f"{kernels[dom]['kernel']} ({dom})",
+        "bound": "infinity_cache" if kernels[dom]["bytes_per_launch"] <= INFINITY_CACHE_BYTES else "hbm",
         "avg_us": kernels[dom]["avg_us"],
         "alg_bytes_per_launch": kernels[dom]["bytes_per_launch"],
         "achieved_GBps": kernels[dom]["GBps"],

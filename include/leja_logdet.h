@@ -89,7 +89,18 @@ typedef struct {
 
 typedef struct {
     int32_t s_val_mode;      /* LD_SVAL_CENTER (default) or LD_SVAL_HALF_LMAX  */
-    int32_t block_cols;      /* columns per kernel launch; 0 = all at once      */
+    int32_t block_cols;      /* columns per Newton-step launch, rounded up to
+                                whole 16-byte vectors.  0 = the library's
+                                choice: ld_apply_log takes up to 64 columns at
+                                once; the estimate splits the sketch and
+                                [Q_b | U] into equal column blocks as wide as
+                                the two blocks a step reads and writes allow
+                                within 170 MB and, with the matrix as stored,
+                                within 240 MB (the Infinity Cache), else one
+                                block of at most 64 columns (the gradient's
+                                blocks are always of that kind).  The blocks
+                                set how the quadratic forms' sums are
+                                grouped, hence their last bits              */
     int64_t taylor_cap;      /* max Taylor order of Alg. 1; 0 = 100000000      */
     int32_t ckpt_stride;     /* gradient checkpoint stride; 0 = auto: 1 (every
                                 forward vector kept, no recomputation) when the
@@ -102,9 +113,12 @@ typedef struct {
                                 every entry lies on one of at most 9 diagonals,
                                 and gathers from it instead of the CSR arrays,
                                 keeping one value per diagonal when each
-                                diagonal's entries are all equal; same sums in
-                                the same order, except the gradient's per-entry
-                                sums, grouped differently: equal to rounding)  */
+                                diagonal's entries are all equal; the same sums
+                                in the same order at the same column blocks,
+                                but the default blocks follow the stored bytes
+                                (see block_cols) and the gradient groups its
+                                per-entry sums differently: equal to rounding
+                                there)                                         */
     int32_t tile_order;      /* LD_TILES_AUTO / LD_TILES_XCD_BANDS /
                                 LD_TILES_INTERLEAVED: how the workgroups of a
                                 Newton-step launch walk the row tiles (auto:
@@ -152,6 +166,11 @@ typedef struct {
                                 XCD's L2), as the quadratic-form launches took
                                 them (0 when a chunk is not a whole number of
                                 their tiles)                                   */
+    int32_t block_cols1;     /* column block width of the sketch's launches    */
+    int32_t block_cols23;    /* and of the quadratic forms' (see block_cols)   */
+    int32_t ranges23;        /* launches per quadratic-form step: 1, or the
+                                consecutive row ranges a step that streams
+                                from HBM on a far-reaching stencil takes      */
 } ld_stats;
 
 /* Defaults for ld_options (all zero except as documented). */

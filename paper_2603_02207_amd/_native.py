@@ -91,6 +91,9 @@ class LdStats(ctypes.Structure):
         ("tile_order_used", ctypes.c_int32),
         ("dia_constant", ctypes.c_int32),
         ("xcd_chunk_rows", ctypes.c_int32),
+        ("block_cols1", ctypes.c_int32),
+        ("block_cols23", ctypes.c_int32),
+        ("ranges23", ctypes.c_int32),
     ]
 
     def as_dict(self):

@@ -141,15 +141,35 @@ double matrix_bytes(const ld_csr* A, size_t elem) {
     return (double)A->nnz * (double)(elem + 4) + 4.0 * (double)(A->n + 1);
 }
 
-int choose_block_width(const ld_csr* A, size_t elem, int cols, int user) {
+// Bytes a launch reads of the matrix as stored: CSR, or the diagonal storage
+// (n x nd values; with constant diagonals 2 bytes of presence bits per row).
+double stored_bytes(const ld_csr* A, size_t elem, int dia_nd, bool dia_const) {
+    return dia_nd > 0 ? (dia_const ? 2.0 * (double)A->n : (double)A->n * dia_nd * elem) : matrix_bytes(A, elem);
+}
+
+// Column blocks of the sketch and of [Q_b | U]: as wide as the two blocks a
+// step reads and writes (2 n elem bytes per column) allow within
+// kBlockPairBudget and, with the matrix as stored, within the Infinity Cache,
+// so that the steps run from the cache rather than HBM.  Every block re-reads
+// the matrix, so blocks under 8 columns are taken only while those extra
+// reads stay below a tenth of the blocks' own bytes.  Measured on gfx950
+// (estimates/s at a forced width): 128^3 grid FP32 one 64-column block 24.7,
+// 16 columns 25.2, 12: 28.9, 8: 32.1, 4: 26.5; FP64 one block 11.5, 8: 12.8,
+// 4: 16.4; 2048^2 GMRF FP32 one 24-column block 47.9, 8: 41.1, 4: 54.6; FP64
+// one block 25.9, 4: 23.9, 2: 32.0; 1024^2 grid FP32 20 columns (a 168 MB
+// pair) 168-175, narrower 125-127.
+constexpr double kBlockPairBudget = 170e6;
+
+int choose_block_width(const ld_csr* A, size_t elem, int cols, int user, double stored) {
     const int v = 16 / (int)elem;
     if (user > 0) return std::min(cols, (user + v - 1) / v * v);
     const double per_col = 2.0 * (double)A->n * (double)elem;   // block in + block out
-    const double room = kMallBudget - matrix_bytes(A, elem);
+    const double room = std::min(kBlockPairBudget, kMallBudget - stored);
     int fit = room > 0 ? (int)(room / per_col) : 0;
     fit = fit / v * v;
-    if (fit >= cols || fit < 8) return cols;   // one block, or no block fits the cache
+    if (fit >= cols || fit < v) return cols;   // one block, or no block fits the cache
     const int nb = (cols + fit - 1) / fit;
+    if (fit < 8 && (double)(nb - 1) * stored > 0.1 * per_col * cols) return cols;
     const int bw = (cols + nb - 1) / nb;
     return (bw + v - 1) / v * v;
 }
@@ -181,6 +201,7 @@ struct EstLayout {
     int k, kg, nc, nslots, nwg_dot;
     size_t elem;
     BlkMat Y, Q1, X;          // sketch, first CholQR factor, [Q_b | U]
+    size_t yb, q1b, xb;       // their regions (see layout_envelope)
     size_t mask, W, part, small, nu, flag;
     // gradient extras: F [Q_b|U], the materialised residual probes, a k-column
     // temporary, the FP64 gradient accumulator of an FP32 matrix, then one of
@@ -234,7 +255,7 @@ int dot_slots(int degree, int mode) {
 }
 
 EstLayout layout_estimate(const ld_csr* A, int degree, int n_matvec, bool grad,
-                          const ld_options& o) {
+                          const ld_options& o, double stored) {
     EstLayout L{};
     const long long n = A->n;
     L.elem = A->dtype == LD_F64 ? 8 : 4;
@@ -243,8 +264,8 @@ EstLayout layout_estimate(const ld_csr* A, int degree, int n_matvec, bool grad,
     L.nc = L.k + L.kg;
     // the gradient keeps the sketch and [Q_b | U] as single blocks (its sweeps
     // take every column of a vector in one row group)
-    const int bw1 = grad ? L.k : choose_block_width(A, L.elem, L.k, o.block_cols);
-    int bw23 = grad ? L.nc : choose_block_width(A, L.elem, L.nc, o.block_cols);
+    const int bw1 = grad ? L.k : choose_block_width(A, L.elem, L.k, o.block_cols, stored);
+    int bw23 = grad ? L.nc : choose_block_width(A, L.elem, L.nc, o.block_cols, stored);
     if (bw23 > kMaxDotBlock) {   // the column-sum kernels take at most 64 columns per launch
         const int v = 16 / (int)L.elem, nb = (bw23 + kMaxDotBlock - 1) / kMaxDotBlock;
         bw23 = ((L.nc + nb - 1) / nb + v - 1) / v * v;
@@ -253,6 +274,9 @@ EstLayout layout_estimate(const ld_csr* A, int degree, int n_matvec, bool grad,
     L.Y = make_blk(n, L.k, bw1, L.elem);
     L.Q1 = make_blk(n, L.k, bw1, L.elem);
     L.X = make_blk(n, L.nc, bw23, L.elem);
+    L.yb = L.Y.bytes();
+    L.q1b = L.Q1.bytes();
+    L.xb = L.X.bytes();
     const int ldmax = std::max(L.Y.ld, L.X.ld);
     L.nslots = std::max(dot_slots(degree, LD_DOT_SQUARED), dot_slots(degree, LD_DOT_FORWARD));
     L.nwg_dot = step_num_wg_bound((int)n, L.X.bw, (int)L.elem);
@@ -304,8 +328,7 @@ EstLayout layout_estimate(const ld_csr* A, int degree, int n_matvec, bool grad,
 
 size_t layout_bytes(const EstLayout& L, bool grad) {
     size_t b = 0;
-    for (size_t s : {L.mask, L.Y.bytes(), L.Q1.bytes(), L.X.bytes(), L.W, L.W, L.part, L.small, L.nu,
-                     L.flag})
+    for (size_t s : {L.mask, L.yb, L.q1b, L.xb, L.W, L.W, L.part, L.small, L.nu, L.flag})
         b += align_up(s);
     b += L.longb;
     if (grad) {
@@ -313,6 +336,28 @@ size_t layout_bytes(const EstLayout& L, bool grad) {
         b += std::max(L.sqb, L.fwdb);
     }
     return b;
+}
+
+// The workspace is laid out before the call learns how the matrix is stored
+// (the diagonal probe runs on the device), while the column blocks depend on
+// the stored bytes: the envelope is the CSR layout with each block region as
+// large as any storage the call may pick needs, and fit_blocks sets the
+// blocks once the storage is known.  The gradient's blocks are fixed (one
+// block each), as are blocks the caller sets.
+EstLayout layout_envelope(const ld_csr* A, int degree, int n_matvec, bool grad, const ld_options& o) {
+    const size_t elem = A->dtype == LD_F64 ? 8 : 4;
+    EstLayout L = layout_estimate(A, degree, n_matvec, grad, o, matrix_bytes(A, elem));
+    if (grad || o.csr_only || o.block_cols > 0) return L;
+    for (int nd = 1; nd <= kMaxDiag; ++nd)
+        for (bool cst : {false, true}) {
+            const EstLayout M = layout_estimate(A, degree, n_matvec, false, o, stored_bytes(A, elem, nd, cst));
+            L.yb = std::max(L.yb, M.yb);
+            L.q1b = std::max(L.q1b, M.q1b);
+            L.xb = std::max(L.xb, M.xb);
+            L.W = std::max(L.W, M.W);
+            L.part = std::max(L.part, M.part);
+        }
+    return L;
 }
 
 struct Timer {
@@ -350,11 +395,7 @@ double alg_bytes_step(const ld_csr* A, int cols, int kind, size_t elem, int dia_
         case STEP_DOT_SQ: per = 2.0 * elem * cols; break;
         default: per = 2.0 * elem * cols; break;
     }
-    // diagonal storage: the values only, n x nd; constant diagonals: 2 bytes
-    // of presence bits per row
-    const double mat = dia_nd > 0 ? (dia_const ? 2.0 * (double)A->n : (double)A->n * dia_nd * elem)
-                                  : matrix_bytes(A, elem);
-    return mat + per * (double)A->n;
+    return stored_bytes(A, elem, dia_nd, dia_const) + per * (double)A->n;
 }
 
 // Launch one Newton step over all columns of a row-major block, in column
@@ -527,6 +568,7 @@ struct EstimateState {
     int spmm_launches = 0;
     double bytes_alg = 0;
     int launches1 = 0, launches23 = 0;
+    int ranges23 = 1;               // row-range launches per quadratic-form step
     double bytes1 = 0, bytes23 = 0;
     hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};   // step-phase brackets
     bool timed = true;              // false: no HIP events (ld_logdet_estimate_noalloc)
@@ -748,6 +790,7 @@ int estimate_dots(const ld_csr* A, EstimateState& S, hipStream_t st, std::vector
                 s.ps1 = part + (size_t)(2 * a + 1) * slot_stride;
                 s.ps2 = part + (size_t)(2 * a + 2) * slot_stride;
                 s.part_ld = X.bw;
+                s.ranges_out = &S.ranges23;
                 int used = 0;
                 LD_CHECK(run_step(f64, A, s, cols, cols, st, &used, S.longrows));
                 if (a > 0 && used != nwg) return fail(LD_EINVAL, "internal: partial rows differ between steps");
@@ -773,6 +816,7 @@ int estimate_dots(const ld_csr* A, EstimateState& S, hipStream_t st, std::vector
                 s.ps0 = part;
                 s.ps1 = part + (size_t)(j + 1) * slot_stride;
                 s.part_ld = X.bw;
+                s.ranges_out = &S.ranges23;
                 int used = 0;
                 LD_CHECK(run_step(f64, A, s, cols, cols, st, &used, S.longrows));
                 if (j > 0 && used != nwg) return fail(LD_EINVAL, "internal: partial rows differ between steps");
@@ -800,15 +844,35 @@ int estimate_dots(const ld_csr* A, EstimateState& S, hipStream_t st, std::vector
 
 int carve(Arena& ar, EstLayout& L, EstimateState& S) {
     S.mask = ar.take(L.mask);
-    L.Y.base = ar.take(L.Y.bytes());
-    L.Q1.base = ar.take(L.Q1.bytes());
-    L.X.base = ar.take(L.X.bytes());
+    L.Y.base = ar.take(L.yb);
+    L.Q1.base = ar.take(L.q1b);
+    L.X.base = ar.take(L.xb);
     S.W0 = ar.take(L.W);
     S.W1 = ar.take(L.W);
     S.part = (double*)ar.take(L.part);
     S.small = (double*)ar.take(L.small);
     S.nu = (double*)ar.take(L.nu);
     S.flag = (int*)ar.take(L.flag);
+    return LD_OK;
+}
+
+// The column blocks for the storage prepare_rows picked, inside the regions
+// of the envelope the workspace was carved with.
+int fit_blocks(const ld_csr* A, int degree, int n_matvec, const ld_options& o, const LongRows& lr, EstLayout& L) {
+    if (o.csr_only || o.block_cols > 0 || lr.dia_nd <= 0) return LD_OK;   // the envelope's own blocks
+    const EstLayout M =
+        layout_estimate(A, degree, n_matvec, false, o, stored_bytes(A, L.elem, lr.dia_nd, lr.dia_pres != nullptr));
+    if (M.yb > L.yb || M.q1b > L.q1b || M.xb > L.xb || M.W > L.W || M.part > L.part)
+        return fail(LD_EINVAL, "internal: column blocks outgrow the workspace");
+    const auto refit = [](BlkMat& dst, const BlkMat& src) {
+        void* const base = dst.base;
+        dst = src;
+        dst.base = base;
+    };
+    refit(L.Y, M.Y);
+    refit(L.Q1, M.Q1);
+    refit(L.X, M.X);
+    L.nwg_dot = M.nwg_dot;
     return LD_OK;
 }
 
@@ -1284,7 +1348,7 @@ int run_logdet(const ld_csr* A, double lmin, double lmax, int degree, int n_matv
     EstimateState S;
     S.timed = timed;
     LD_CHECK(make_plan(lmin, lmax, degree, o, S.plan));
-    S.L = layout_estimate(A, degree, n_matvec, want_grad, o);
+    S.L = layout_envelope(A, degree, n_matvec, want_grad, o);
     S.mode = choose_dot_mode(S.plan, o.dot_mode, S.coef);
     if (o.probe_dist != LD_PROBE_RADEMACHER && o.probe_dist != LD_PROBE_GAUSSIAN)
         return fail(LD_EINVAL, "probe_dist must be LD_PROBE_RADEMACHER or LD_PROBE_GAUSSIAN");
@@ -1326,6 +1390,7 @@ int run_logdet(const ld_csr* A, double lmin, double lmax, int degree, int n_matv
         return fail(LD_EINVAL, "internal: workspace layout overflow");
     if (!o.trusted_csr) LD_CHECK(validate_csr(A, S.flag, st));
     LD_CHECK(prepare_rows(A, o, ar, st, S.longrows));
+    if (!want_grad) LD_CHECK(fit_blocks(A, degree, n_matvec, o, S.longrows, S.L));
     Timer tm(st, timed);
     tm.mark();
     LD_CHECK(estimate_front(A, seed, S, st, tm, sq_grad ? &B.rs : nullptr));
@@ -1399,6 +1464,9 @@ int run_logdet(const ld_csr* A, double lmin, double lmax, int degree, int n_matv
                                      kMallBudget)
                 : 0;
         out->xcd_chunk_rows = crows > 0 && crows % step_tile_rows(L.X.bw, (int)L.elem) == 0 ? crows : 0;
+        out->block_cols1 = L.Y.bw;
+        out->block_cols23 = L.X.bw;
+        out->ranges23 = S.ranges23;
         out->spmm_launches = S.spmm_launches;
         out->t_low = t_low;
         out->t_res = t_res;
@@ -1654,13 +1722,15 @@ int adaptive_apply(const ld_csr* A, const Plan& p, double tol, double shift, con
 // x^T F x as the diagonal of block cross products.  Workspace: the
 // estimate's, a copy of X's blocks for F[Q_b | U], and the adaptive buffers.
 EstLayout layout_adaptive(const ld_csr* A, int max_degree, int n_matvec, const ld_options& o) {
-    return layout_estimate(A, max_degree, n_matvec, false, o);
+    // blocks sized by the CSR bytes whatever the storage: the loop polls each
+    // block's columns, and narrower blocks would multiply the polls
+    return layout_estimate(A, max_degree, n_matvec, false, o, matrix_bytes(A, A->dtype == LD_F64 ? 8 : 4));
 }
 
 size_t adaptive_estimate_ws_bytes(const ld_csr* A, int max_degree, int n_matvec, const ld_options& o) {
     const EstLayout L = layout_adaptive(A, max_degree, n_matvec, o);
     const int n = (int)A->n;
-    return layout_bytes(L, false) + align_up(L.X.bytes()) + align_up((size_t)step_num_wg_any(n) * 64 * 8) +
+    return layout_bytes(L, false) + align_up(L.xb) + align_up((size_t)step_num_wg_any(n) * 64 * 8) +
            align_up((size_t)cross_num_wg(n) * 64 * 64 * 8) + align_up(64 * 64 * 8) + 2 * align_up(256) + 256;
 }
 
@@ -1683,7 +1753,7 @@ int run_logdet_adaptive(const ld_csr* A, double lmin, double lmax, int max_degre
     carve(ar, S.L, S);
     const EstLayout& L = S.L;
     BlkMat PX = L.X;   // F [Q_b | U], the layout of X
-    PX.base = ar.take(L.X.bytes());
+    PX.base = ar.take(L.xb);
     AdaptBufs b;
     b.W[0] = S.W0;
     b.W[1] = S.W1;
@@ -1758,6 +1828,8 @@ int run_logdet_adaptive(const ld_csr* A, double lmin, double lmax, int max_degre
         stats->k_G = L.kg;
         stats->dot_mode_used = LD_DOT_FORWARD;
         stats->dia_diagonals = S.longrows.dia_nd;
+        stats->block_cols1 = L.Y.bw;
+        stats->block_cols23 = L.X.bw;
         stats->dia_constant = S.longrows.dia_pres != nullptr;
         stats->spmm_launches = S.launches1 + S.launches23;
         stats->launches1 = S.launches1;
@@ -1789,7 +1861,7 @@ int ld_workspace_size(const ld_csr* A, int32_t degree, int32_t n_matvec, int32_t
         return LD_OK;
     }
     if (n_matvec < 3) return fail(LD_EINVAL, "n_matvec must be >= 3");
-    const EstLayout L = layout_estimate(A, degree, n_matvec, want_grad != 0, o);
+    const EstLayout L = layout_envelope(A, degree, n_matvec, want_grad != 0, o);
     *bytes = layout_bytes(L, want_grad != 0);
     return LD_OK;
 }
@@ -1930,7 +2002,7 @@ int ld_logdet_estimate_noalloc(const ld_csr* A, double lmin, double lmax, int32_
     if (!out_logdet) return fail(LD_EINVAL, "out_logdet is null");
     LD_CHECK(check_estimate_args(A, lmin, lmax, degree, n_matvec));
     const ld_options o = resolve(opts);
-    const size_t need = layout_bytes(layout_estimate(A, degree, n_matvec, false, o), false);
+    const size_t need = layout_bytes(layout_envelope(A, degree, n_matvec, false, o), false);
     if (need > kNoAllocScratchBytes)
         return fail(LD_EWORKSPACE, "the estimate needs " + std::to_string(need) +
                                        " bytes of scratch; the library's static scratch holds " +

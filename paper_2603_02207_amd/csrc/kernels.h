@@ -93,6 +93,9 @@ struct StepArgs {
     int chunk_rows;
     // 1: the output block is written with non-temporal (streaming) stores
     int nt_out;
+    // when non-null: set to the number of launches over consecutive row
+    // ranges the step took (1 but for streaming steps with column sums)
+    int* ranges_out = nullptr;
 };
 
 constexpr int kLongRow = 64;     // entries above which a row is "long"

@@ -84,6 +84,7 @@ __device__ __forceinline__ int div_up_dev(int a, int b) { return (int)(((long lo
 inline int lanes_per_row(int bcols, int vec) { return (bcols + vec - 1) / vec; }
 
 constexpr int kStepIters = 2;      // row groups per wave and launch
+constexpr int kRangeTiles = 48;    // tiles per workgroup and launch of a streaming step with column sums
 constexpr int kWaveNz = 384;       // CSR entries one wave stages in LDS
 constexpr int kMaxDotCols = 64;    // columns of one launch of the kinds with column sums
 constexpr int kAdjBatch = 4;       // CSR entries of a row whose gathers the adjoint issues together
@@ -135,7 +136,8 @@ __global__ __launch_bounds__(NT) void step_kernel(
     const uint64_t* __restrict__ mask, double* __restrict__ ps0, double* __restrict__ ps1,
     double* __restrict__ ps2, int part_ld, int lpr, int rpw, int skip_long, T* __restrict__ accum,
     int ldacc, int acc_cols, int ntiles, const uint64_t* __restrict__ active, const T* __restrict__ dia, int nd,
-    DiaOff off, int interleave, int chunk, int nt_out, const uint16_t* __restrict__ dpres, DiaVal<T> cv) {
+    DiaOff off, int interleave, int chunk, int nt_out, const uint16_t* __restrict__ dpres, DiaVal<T> cv,
+    int tile0, int add_parts) {
     constexpr bool kDot = is_dot(KIND);
     constexpr int NW = NT / 64;
     constexpr int kSums = kDot ? ((FIRST ? 1 : 0) + 1 + (KIND == STEP_DOT_SQ ? 1 : 0)) : 0;
@@ -197,7 +199,7 @@ __global__ __launch_bounds__(NT) void step_kernel(
         if (t >= band_len) break;
         tile = band0 + t;
     }
-    const int W0 = tile * (NW * rows_per_wave) + wave * rows_per_wave;   // first row of this wave
+    const int W0 = (tile0 + tile) * (NW * rows_per_wave) + wave * rows_per_wave;   // first row of this wave
     const int nrows = max(0, min(rows_per_wave, n - W0));
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");   // the previous tile's LDS reads come first
     __builtin_amdgcn_wave_barrier();
@@ -417,7 +419,8 @@ __global__ __launch_bounds__(NT) void step_kernel(
 #pragma unroll
                 for (int wv = 0; wv < NW; ++wv) acc += s_cols[(wv * kSums + qq) * kMaxDotCols + cc];
                 double* const dst = qq == 0 ? outs[0] : (qq == 1 ? outs[1] : outs[2]);
-                dst[(size_t)blockIdx.x * part_ld + c0 + gshift + cc] = acc;
+                const size_t at = (size_t)blockIdx.x * part_ld + c0 + gshift + cc;
+                dst[at] = add_parts ? dst[at] + acc : acc;   // later row ranges of one step add on
             }
         }
     }
@@ -703,6 +706,24 @@ hipError_t launch_step_t(const CsrDev& A, const StepArgs& s, hipStream_t st, int
     const int ctiles = s.chunk_rows > 0 && !s.interleave && s.chunk_rows % rows_per_wg == 0
                            ? s.chunk_rows / rows_per_wg
                            : 0;
+    // A step with column sums that streams from HBM, on a stencil whose widest
+    // offset reaches beyond a tile, goes in launches over consecutive row
+    // ranges of at most kRangeTiles tiles per workgroup, each adding its sums
+    // to the same partial rows: a persistent workgroup that walks many tiles
+    // drifts away from the others, and the XCD's active rows then spread
+    // beyond what its L2 holds of their neighbour rows.  Measured on gfx950
+    // (FP32 quadratic-form step): 5000^2 GMRF, about 170 tiles per workgroup,
+    // 1176 us in one launch, 1056 us at 24 or 48 tiles per range, 1125 us at
+    // 12; ranges cost 2-3% where the workgroups walk few tiles or the
+    // neighbours are near (2048^2 GMRF in one block, 28 tiles: 205 -> 209 us at
+    // 24; pentadiagonal n = 10^7: 412 -> 425 us).  XCD bands only; chunked
+    // bands keep one launch.
+    int reach = 0;
+    for (int q = 0; q < s.dia_nd && q < kMaxDiag; ++q) reach = std::max(reach, std::abs(s.dia_off[q]));
+    auto row_ranges = [&](int nwg) {
+        if (!is_dot(KIND) || !s.nt_out || s.interleave || ctiles > 0 || reach <= rows_per_wg || nwg <= 0) return 1;
+        return std::max(1, div_up(div_up(ntiles, nwg), kRangeTiles));
+    };
     DiaOff off{};
     for (int q = 0; q < kMaxDiag; ++q) off.o[q] = q < s.dia_nd ? s.dia_off[q] : 0;
     DiaVal<T> cv{};
@@ -749,12 +770,18 @@ hipError_t launch_step_t(const CsrDev& A, const StepArgs& s, hipStream_t st, int
         const auto fn = step_kernel<T, VEC, KIND, FIRST, kIters, NT, ND_>;                                     \
         const int nwg = grid(reinterpret_cast<const void*>(step_kernel<T, VEC, KIND, has_first(KIND), kIters, NT, ND_>), \
                              reinterpret_cast<const void*>(step_kernel<T, VEC, KIND, false, kIters, NT, ND_>));  \
-        hipLaunchKernelGGL(fn, dim3(nwg), dim3(NT), 0, st, A.n, A.row_ptr, A.col_idx, (const T*)A.val,         \
-                           (const T*)s.win, (T*)s.wout, s.ld, s.c0, s.bcols, s.gshift, (T)s.alpha, (T)s.beta,   \
-                           (T)s.dj, (const T*)s.vsrc, s.ldv, s.mask, s.ps0, s.ps1, s.ps2, s.part_ld, lpr, rpw, \
-                           0, (T*)s.acc, s.ldacc, s.acc_cols, ntiles, s.active, (const T*)s.dia, s.dia_nd, off, \
-                           s.interleave, ctiles, s.nt_out, s.dia_pres, cv);                                    \
+        const int nsub = row_ranges(nwg);                                                                      \
+        for (int k = 0; k < nsub; ++k) {                                                                       \
+            const int t0 = (int)((long long)ntiles * k / nsub), t1 = (int)((long long)ntiles * (k + 1) / nsub); \
+            hipLaunchKernelGGL(fn, dim3(nwg), dim3(NT), 0, st, A.n, A.row_ptr, A.col_idx, (const T*)A.val,     \
+                               (const T*)s.win, (T*)s.wout, s.ld, s.c0, s.bcols, s.gshift, (T)s.alpha,         \
+                               (T)s.beta, (T)s.dj, (const T*)s.vsrc, s.ldv, s.mask, s.ps0, s.ps1, s.ps2,       \
+                               s.part_ld, lpr, rpw, 0, (T*)s.acc, s.ldacc, s.acc_cols, t1 - t0, s.active,      \
+                               (const T*)s.dia, s.dia_nd, off, s.interleave, ctiles, s.nt_out, s.dia_pres, cv, \
+                               t0, k > 0 ? 1 : 0);                                                            \
+        }                                                                                                      \
         if (nwg_out) *nwg_out = nwg;                                                                           \
+        if (s.ranges_out) *s.ranges_out = nsub;                                                                \
     }
         if (s.dia_nd <= 3)
             LD_DIA_LAUNCH(3)
@@ -767,6 +794,7 @@ hipError_t launch_step_t(const CsrDev& A, const StepArgs& s, hipStream_t st, int
 #undef LD_DIA_LAUNCH
         return hipGetLastError();
     }
+    if (s.ranges_out) *s.ranges_out = 1;
     const int skip = s.long_rows != nullptr;
     const auto fn = step_kernel<T, VEC, KIND, FIRST, kIters, NT, 0>;
     const int nwg = grid(reinterpret_cast<const void*>(step_kernel<T, VEC, KIND, has_first(KIND), kIters, NT, 0>),
@@ -777,7 +805,7 @@ hipError_t launch_step_t(const CsrDev& A, const StepArgs& s, hipStream_t st, int
                        s.c0, s.bcols, s.gshift, (T)s.alpha, (T)s.beta, (T)s.dj, (const T*)s.vsrc,
                        s.ldv, s.mask, s.ps0, s.ps1, s.ps2, s.part_ld, lpr, rpw, skip, (T*)s.acc,
                        s.ldacc, s.acc_cols, ntiles, s.active, (const T*)nullptr, 0, off, s.interleave, ctiles,
-                       s.nt_out, (const uint16_t*)nullptr, cv);
+                       s.nt_out, (const uint16_t*)nullptr, cv, 0, 0);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess || !skip) return e;
     hipLaunchKernelGGL((long_row_kernel<T, VEC, KIND, FIRST>), dim3(kLongWgs), dim3(256), 0, st,

@@ -120,3 +120,29 @@ def test_bench_runs_on_one_gpu_only():
     out = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"], capture_output=True,
                          text=True, timeout=120)
     assert out.returncode != 0 and "exactly one GPU" in (out.stdout + out.stderr)
+
+
+def test_traffic_summary_counts_row_range_dispatches(tmp_path):
+    # a quadratic-form step that runs as 4 dispatches over row ranges: the
+    # counters per dispatch times 4 are the bytes of one library launch
+    copy = "void at::native::copy_kernel(float const*)"
+    first = "void ld::(anonymous namespace)::step_kernel<float, 4, 3, true, 2, 256, 5>(int)"
+    rest = "void ld::(anonymous namespace)::step_kernel<float, 4, 3, false, 2, 256, 5>(int)"
+    gib_kib = (1 << 30) / 1024
+    _write_counters(tmp_path / "cf", [(1, copy, "FETCH_SIZE", gib_kib / 2)])
+    _write_counters(tmp_path / "cw", [(1, copy, "WRITE_SIZE", gib_kib)])
+    _write_counters(tmp_path / "f", [(2, first, "FETCH_SIZE", 500.0)] +
+                    [(3 + i, rest, "FETCH_SIZE", 1000.0) for i in range(8)])
+    _write_counters(tmp_path / "w", [(2, first, "WRITE_SIZE", 250.0)] +
+                    [(3 + i, rest, "WRITE_SIZE", 500.0) for i in range(8)])
+    log = tmp_path / "line.log"
+    alg = 9e6
+    log.write_text(json.dumps({"kernels": {"quadform": {"kernel": "step_kernel", "bytes_per_launch": alg,
+                                                        "dispatches_per_launch": 4}}}) + "\n")
+    out = bench.traffic_summary([str(tmp_path / x) for x in ("f", "w", "cf", "cw")], str(log))
+    blob = json.loads(out.split("```json", 1)[1].split("```", 1)[0])["traffic_MB_per_launch"]
+    per_launch = 4 * (1000.0 * 2 + 500.0) * 1024 / 1e6
+    assert blob["step_kernel<float, 4, 3, false, 2, 256, 5>"] == pytest.approx(per_launch, abs=1e-3)
+    assert blob["step_kernel<float, 4, 3, true, 2, 256, 5>"] == pytest.approx(per_launch / 2, abs=1e-3)
+    row = [l for l in out.splitlines() if l.startswith("| step_kernel<float, 4, 3, false")][0].split("|")
+    assert float(row[6]) == pytest.approx(per_launch / (alg / 1e6), abs=0.005)

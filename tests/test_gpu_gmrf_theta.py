@@ -81,3 +81,23 @@ def test_full_size_estimate_within_hutchinson_error(full_pattern, theta):
     z = (est - g["expectation"]) / g["sd_hutchinson"]
     assert abs(z) < 6.0, (theta, est, g["expectation"], z)
     assert abs(g["expectation"] - g["logdet_exact"]) < 1e-9 * abs(g["logdet_exact"])
+
+
+def test_full_size_row_ranges_cover_every_row(full_pattern):
+    # At 25e6 rows each persistent workgroup of the quadratic-form step would
+    # walk about 170 tiles, so with XCD bands the step runs as several launches
+    # over consecutive row ranges that add to the same partial sums; with
+    # interleaved tiles it is one launch.  The recurrence vectors are per-row
+    # results (the same bits in both orders) and the FP64 column sums differ
+    # only in grouping, so the two estimates agree to FP64 rounding: a row
+    # range skipped or taken twice would move the estimate by a large share.
+    N, A, diag = full_pattern
+    lmin, lmax = ld.spectral_bounds(A)
+    e_b, s_b = ld.logdet(A, lmin, lmax, 80, 30, 0, options=ld.Options(tile_order=1), return_stats=True)
+    e_i, s_i = ld.logdet(A, lmin, lmax, 80, 30, 0, options=ld.Options(tile_order=2), return_stats=True)
+    assert s_b["tile_order_used"] == 1 and s_i["tile_order_used"] == 2
+    assert s_b["block_cols23"] == 20 and s_b["dot_mode_used"] == 2
+    assert s_b["ranges23"] > 1 and s_i["ranges23"] == 1
+    assert abs(e_b - e_i) <= 1e-10 * abs(e_i), (e_b, e_i)
+    g = golden("gmrf5000_theta_sweep")["results"][repr(-0.22)]
+    assert abs((e_b - g["expectation"]) / g["sd_hutchinson"]) < 6.0
