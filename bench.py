@@ -687,6 +687,15 @@ def run_workload(args, workload, steps):
                            "path": {2: "squared Newton basis", 1: "Newton form"}[stg["dot_mode_used"]],
                            "ckpt_stride": "auto (every stored vector kept when they fit 64 GiB)",
                            "workspace_GB": ld.workspace_size(A32, degree, m_vec, True, opts) / 1e9}
+        # the estimate in the gradient's layout (one column block per phase):
+        # its default blocks may run from the Infinity Cache, the gradient's
+        # stored vectors cannot
+        o_one = ld.Options(block_cols=64, dot_mode=mode, trusted_csr=1, tile_order=tiles)
+        _, st_one, dt_one = time_estimates(ld, A32, lmin, lmax, degree, m_vec, args.seed, o_one, k_g, 1)
+        t_one = dt_one / k_g * 1e3
+        out["gradient"]["one_block_estimate"] = {
+            "column_blocks": {"sketch": st_one["block_cols1"], "quadform": st_one["block_cols23"]},
+            "ms_estimate": t_one, "call_over_estimate": dtg * 1e3 / t_one}
         # sqrt(m) checkpoints: a fraction of the memory, segments recomputed
         s_ck = max(1, math.ceil(math.sqrt(degree)))
         o_ck = ld.Options(block_cols=args.block_cols, dot_mode=mode, trusted_csr=1, tile_order=tiles,
