@@ -83,15 +83,18 @@ def test_full_size_estimate_within_hutchinson_error(full_pattern, theta):
     assert abs(g["expectation"] - g["logdet_exact"]) < 1e-9 * abs(g["logdet_exact"])
 
 
-def test_full_size_row_ranges_cover_every_row(full_pattern):
+@pytest.mark.parametrize("dtype", [torch.float32, torch.float64])
+def test_full_size_row_ranges_cover_every_row(full_pattern, dtype):
     # At 25e6 rows each persistent workgroup of the quadratic-form step would
-    # walk about 170 tiles, so with XCD bands the step runs as several launches
+    # walk about 170 tiles in FP32 (340 in FP64), so with XCD bands the step runs as several launches
     # over consecutive row ranges that add to the same partial sums; with
     # interleaved tiles it is one launch.  The recurrence vectors are per-row
     # results (the same bits in both orders) and the FP64 column sums differ
     # only in grouping, so the two estimates agree to FP64 rounding: a row
     # range skipped or taken twice would move the estimate by a large share.
     N, A, diag = full_pattern
+    if dtype == torch.float64:   # the same pattern and values in FP64 (2-wide vectors, its own tiles)
+        A = A.with_values(A.val.double())
     lmin, lmax = ld.spectral_bounds(A)
     e_b, s_b = ld.logdet(A, lmin, lmax, 80, 30, 0, options=ld.Options(tile_order=1), return_stats=True)
     e_i, s_i = ld.logdet(A, lmin, lmax, 80, 30, 0, options=ld.Options(tile_order=2), return_stats=True)
