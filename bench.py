@@ -419,7 +419,8 @@ def traffic_summary(dirs, bench_log=None) -> str:
             # a library launch of a step kernel may be several dispatches over row ranges
             if any(k.startswith(p.replace(", false", "")) for p in prefixes):
                 r, w = (x * rec.get("dispatches_per_launch", 1) for x in (r, w))
-            if any(k.startswith(p) for p in prefixes) and ", true" not in k:
+            # (a step kernel's first-step variant, ", true, ...", is not the phase's typical launch)
+            if any(k.startswith(p) for p in prefixes) and not (k.startswith("step_kernel") and ", true," in k):
                 a = f"{rec['bytes_per_launch'] / 1e6:.1f}"
                 ratio = f"{(r + w) / (rec['bytes_per_launch'] / 1e6):.2f}"
         lines.append(f"| {k[:160]} | {r:.1f} | {w:.1f} | {r + w:.1f} | {a} | {ratio} |")

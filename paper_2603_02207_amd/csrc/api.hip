@@ -202,7 +202,7 @@ struct EstLayout {
     size_t elem;
     BlkMat Y, Q1, X;          // sketch, first CholQR factor, [Q_b | U]
     size_t yb, q1b, xb;       // their regions (see layout_envelope)
-    size_t mask, W, part, small, nu, flag;
+    size_t mask, planes, W, part, small, nu, flag;
     // gradient extras: F [Q_b|U], the materialised residual probes, a k-column
     // temporary, the FP64 gradient accumulator of an FP32 matrix, then one of
     // two regions: the squared-basis path's stored vectors (sqb bytes) or the
@@ -281,6 +281,7 @@ EstLayout layout_estimate(const ld_csr* A, int degree, int n_matvec, bool grad,
     L.nslots = std::max(dot_slots(degree, LD_DOT_SQUARED), dot_slots(degree, LD_DOT_FORWARD));
     L.nwg_dot = step_num_wg_bound((int)n, L.X.bw, (int)L.elem);
     L.mask = (size_t)n * 8;
+    L.planes = (size_t)n * 8;   // the sketch's sign words as byte planes
     L.W = (size_t)n * ldmax * L.elem;
     const int kmax = std::max(L.k, L.kg);
     const size_t cross = (size_t)cross_num_wg((int)n) * kmax * kmax * 8;
@@ -328,7 +329,7 @@ EstLayout layout_estimate(const ld_csr* A, int degree, int n_matvec, bool grad,
 
 size_t layout_bytes(const EstLayout& L, bool grad) {
     size_t b = 0;
-    for (size_t s : {L.mask, L.yb, L.q1b, L.xb, L.W, L.W, L.part, L.small, L.nu, L.flag})
+    for (size_t s : {L.mask, L.planes, L.yb, L.q1b, L.xb, L.W, L.W, L.part, L.small, L.nu, L.flag})
         b += align_up(s);
     b += L.longb;
     if (grad) {
@@ -386,10 +387,11 @@ struct Timer {
 
 // bytes the recurrence kernels must move (FP values, int32 indices; the
 // matrix once per launch, blocks as listed per step kind)
-double alg_bytes_step(const ld_csr* A, int cols, int kind, size_t elem, int dia_nd = 0, bool dia_const = false) {
+double alg_bytes_step(const ld_csr* A, int cols, int kind, size_t elem, int dia_nd = 0, bool dia_const = false,
+                      int sign_bytes = 8) {
     double per = 0;
     switch (kind) {
-        case STEP_HORNER_SIGNS: per = 2.0 * elem * cols + 8.0; break;   // + sign-mask word
+        case STEP_HORNER_SIGNS: per = 2.0 * elem * cols + sign_bytes; break;   // + sign word or byte planes
         case STEP_HORNER_VEC: per = 3.0 * elem * cols; break;
         case STEP_DOT_FWD: per = 3.0 * elem * cols; break;
         case STEP_DOT_SQ: per = 2.0 * elem * cols; break;
@@ -569,6 +571,7 @@ struct EstimateState {
     double bytes_alg = 0;
     int launches1 = 0, launches23 = 0;
     int ranges23 = 1;               // row-range launches per quadratic-form step
+    uint8_t* planes = nullptr;      // S's sign words as byte planes (the sketch's flat steps)
     double bytes1 = 0, bytes23 = 0;
     hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};   // step-phase brackets
     bool timed = true;              // false: no HIP events (ld_logdet_estimate_noalloc)
@@ -664,6 +667,15 @@ int sketch_phase(const ld_csr* A, EstimateState& S, hipStream_t st, const VecSto
     const int kind = gauss ? STEP_HORNER_VEC : STEP_HORNER_SIGNS;
     for (int b = 0; b < Y.nblocks(); ++b) {
         const int cols = Y.bcols(b), gcol = b * Y.bw;
+        // a block whose columns lie in one byte of the sign words reads that byte
+        // plane on the diagonal storage (the flat kernel: one contiguous byte per
+        // row and wave), else the words.  Measured on gfx950, sketch step: 2048^2
+        // GMRF at 4 columns 27.9 -> 25.4 us, 128^3 grid at 8: 31.1 -> 29.5 us;
+        // blocks over several planes got slower (a wave then reads several short
+        // runs): 1024^2 grid at 20 columns 29.0 -> 33.2 us, 5000^2 GMRF at 10:
+        // 569 -> 628 us.
+        const bool one_plane = (gcol >> 3) == ((gcol + cols - 1) >> 3);
+        const int sign_bytes = one_plane && S.planes && S.longrows.dia_nd > 0 ? 1 : 8;
         // step j (= m-1 .. 0) writes (j even ? block : W0); r_m sits in the other one
         void* bufs[2] = {Y.block(b), S.W0};
         void* const rm = keep ? keep->at(m) : bufs[(m - 1) % 2 == 0 ? 1 : 0];
@@ -685,11 +697,13 @@ int sketch_phase(const ld_csr* A, EstimateState& S, hipStream_t st, const VecSto
             s.beta = p.beta[j];
             s.dj = p.d[j];
             s.mask = (const uint64_t*)S.mask;
+            s.planes = one_plane ? S.planes : nullptr;
             s.vsrc = gauss ? sblk : nullptr;
             s.ldv = S.L.Q1.ld;
             LD_CHECK(run_step(f64, A, s, cols, cols, st, nullptr, S.longrows));
             S.launches1 += 1;
-            S.bytes1 += alg_bytes_step(A, cols, kind, S.L.elem, S.longrows.dia_nd, S.longrows.dia_pres != nullptr);
+            S.bytes1 += alg_bytes_step(A, cols, kind, S.L.elem, S.longrows.dia_nd, S.longrows.dia_pres != nullptr,
+                                       sign_bytes);
         }
     }
     return LD_OK;
@@ -706,7 +720,7 @@ int estimate_front(const ld_csr* A, uint64_t seed, EstimateState& S, hipStream_t
     const bool gauss = S.probe == LD_PROBE_GAUSSIAN;
     S.key0 = key0;
 
-    if (!gauss) LD_CHECK_HIP(launch_sign_mask(n, L.k, key0, (uint64_t*)S.mask, st));
+    if (!gauss) LD_CHECK_HIP(launch_sign_mask(n, L.k, key0, (uint64_t*)S.mask, st, S.planes));
     LD_CHECK(record(S, 0, st));
     LD_CHECK(sketch_phase(A, S, st, keep));
     LD_CHECK(record(S, 1, st));
@@ -844,6 +858,7 @@ int estimate_dots(const ld_csr* A, EstimateState& S, hipStream_t st, std::vector
 
 int carve(Arena& ar, EstLayout& L, EstimateState& S) {
     S.mask = ar.take(L.mask);
+    S.planes = (uint8_t*)ar.take(L.planes);
     L.Y.base = ar.take(L.yb);
     L.Q1.base = ar.take(L.q1b);
     L.X.base = ar.take(L.xb);

@@ -60,6 +60,10 @@ struct StepArgs {
     const void* vsrc;          // HORNER_VEC: V;  DOT_FWD: X
     int ldv;
     const uint64_t* mask;      // HORNER_SIGNS: one word of sign bits per row
+    // HORNER_SIGNS on the diagonal storage, when non-null: the same bits as
+    // eight byte planes (plane p, n bytes: byte p of every row's word), so a
+    // step reads one byte per row and 16-byte chunk instead of the word
+    const uint8_t* planes = nullptr;
     double* ps0;               // partial sums [nwg][part_ld], may be null
     double* ps1;
     double* ps2;
@@ -120,7 +124,10 @@ int step_tile_rows(int bcols, int elem_bytes);
 hipError_t launch_step(bool f64, const CsrDev& A, const StepArgs& s, hipStream_t st, int* nwg_out = nullptr);
 
 // Sign mask of stream `key`: bit c of word r = (probe(r, c) == -1), c < k <= 64.
-hipError_t launch_sign_mask(int n, int k, uint64_t key, uint64_t* mask, hipStream_t st);
+// With `planes` non-null also its eight byte planes: planes[p*n + r] = byte p
+// of word r (8n bytes).
+hipError_t launch_sign_mask(int n, int k, uint64_t key, uint64_t* mask, hipStream_t st,
+                            uint8_t* planes = nullptr);
 
 // out[r*ld + c] = scale * S[r, c + gshift] for c < k (other columns untouched).
 hipError_t launch_fill_signs(bool f64, int n, int k, int ld, int gshift, const uint64_t* mask,

@@ -579,12 +579,12 @@ __global__ __launch_bounds__(256) void long_row_kernel(
 // extra traffic.  Per row the arithmetic and the order of the sums are those
 // of step_kernel, so the results are the same bits.
 // ---------------------------------------------------------------------------
-template <typename T, int VEC, int KIND, int ND>
+template <typename T, int VEC, int KIND, int ND, bool PLANES>
 __global__ __launch_bounds__(kThreads) void dia_flat_kernel(
     int n, const T* __restrict__ win, T* __restrict__ wout, int ld, int lpr, int gshift, T alpha, T beta, T dj,
     const T* __restrict__ vsrc, int ldv, const uint64_t* __restrict__ mask, T* __restrict__ accum, int ldacc,
     int acc_cols, const T* __restrict__ dia, int nd, DiaOff off, int interleave, int chunk, int nt_out,
-    const uint16_t* __restrict__ dpres, DiaVal<T> cv) {
+    const uint16_t* __restrict__ dpres, DiaVal<T> cv, const uint8_t* __restrict__ planes) {
     static_assert(KIND == STEP_HORNER_SIGNS || KIND == STEP_HORNER_VEC || KIND == STEP_PLAIN ||
                   KIND == STEP_PLAIN_ACC, "kinds without column sums");
     unsigned blk = blockIdx.x;
@@ -601,6 +601,14 @@ __global__ __launch_bounds__(kThreads) void dia_flat_kernel(
     if (i >= (unsigned)n * (unsigned)lpr) return;   // the launch checks n * lpr < 2^31
     const int row = (int)(i / (unsigned)lpr);
     const int col = (int)(i - (unsigned)row * (unsigned)lpr) * VEC;
+    // HORNER_SIGNS from byte planes: the chunk's VEC columns start at a
+    // multiple of VEC, so their sign bits lie in one byte of the row's word,
+    // read from its plane (issued up front)
+    unsigned sbits = 0;
+    if constexpr (KIND == STEP_HORNER_SIGNS && PLANES) {
+        const int g = col + gshift;
+        sbits = (unsigned)planes[(size_t)((g >> 3) & 7) * n + row] >> (g & 7);
+    }
     int cq[ND];
     T aq[ND];
     const unsigned pbits = dpres ? dpres[row] : 0u;
@@ -630,7 +638,13 @@ __global__ __launch_bounds__(kThreads) void dia_flat_kernel(
     Pack<T, VEC> o;
 #pragma unroll
     for (int e = 0; e < VEC; ++e) o.v[e] = alpha * acc[e] - beta * w.v[e];
-    if constexpr (KIND == STEP_HORNER_SIGNS) {
+    if constexpr (KIND == STEP_HORNER_SIGNS && PLANES) {
+#pragma unroll
+        for (int e = 0; e < VEC; ++e) {
+            const T sgn = ((sbits >> e) & 1u) ? T(-1) : T(1);
+            o.v[e] = fma(dj, sgn, o.v[e]);
+        }
+    } else if constexpr (KIND == STEP_HORNER_SIGNS) {
         const uint64_t bits = mask[row];
 #pragma unroll
         for (int e = 0; e < VEC; ++e) {
@@ -746,12 +760,23 @@ hipError_t launch_step_t(const CsrDev& A, const StepArgs& s, hipStream_t st, int
                                     : 0;
                 const int nwg = cwg > 0 ? div_up(div_up(need, cwg), kXcds) * kXcds * cwg
                                         : div_up(need, kXcds) * kXcds;
-#define LD_FLAT_LAUNCH(ND_)                                                                                    \
-    hipLaunchKernelGGL((dia_flat_kernel<T, VEC, KIND, ND_>), dim3(nwg), dim3(kThreads), 0, st, A.n,           \
+                // byte planes of the sign words (HORNER_SIGNS): a chunk's columns must
+                // start at a multiple of VEC (then they lie in one byte)
+                const uint8_t* const planes =
+                    KIND == STEP_HORNER_SIGNS && (s.gshift + s.c0) % VEC == 0 ? s.planes : nullptr;
+#define LD_FLAT_LAUNCH_P(ND_, P_)                                                                              \
+    hipLaunchKernelGGL((dia_flat_kernel<T, VEC, KIND, ND_, P_>), dim3(nwg), dim3(kThreads), 0, st, A.n,       \
                        (const T*)s.win + s.c0, (T*)s.wout + s.c0, s.ld, lpr, s.gshift + s.c0, (T)s.alpha,     \
                        (T)s.beta, (T)s.dj, s.vsrc ? (const T*)s.vsrc + s.c0 : nullptr, s.ldv, s.mask,         \
                        s.acc ? (T*)s.acc + s.c0 : nullptr, s.ldacc, s.acc_cols - s.c0, (const T*)s.dia,        \
-                       s.dia_nd, off, s.interleave, cwg, s.nt_out, s.dia_pres, cv)
+                       s.dia_nd, off, s.interleave, cwg, s.nt_out, s.dia_pres, cv, planes)
+#define LD_FLAT_LAUNCH(ND_)                                                                                    \
+    do {                                                                                                       \
+        if (planes)                                                                                            \
+            LD_FLAT_LAUNCH_P(ND_, KIND == STEP_HORNER_SIGNS);                                                  \
+        else                                                                                                   \
+            LD_FLAT_LAUNCH_P(ND_, false);                                                                      \
+    } while (0)
                 if (s.dia_nd <= 3)
                     LD_FLAT_LAUNCH(3);
                 else if (s.dia_nd <= 5)
@@ -761,6 +786,7 @@ hipError_t launch_step_t(const CsrDev& A, const StepArgs& s, hipStream_t st, int
                 else
                     LD_FLAT_LAUNCH(9);
 #undef LD_FLAT_LAUNCH
+#undef LD_FLAT_LAUNCH_P
                 if (nwg_out) *nwg_out = 0;   // no partial rows
                 return hipGetLastError();
             }
@@ -954,7 +980,8 @@ hipError_t launch_long_rows(const CsrDev& A, int* tmp, int* list, int* count, hi
 // probe signs
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(kThreads) void sign_mask_kernel(int n, int k, uint64_t key,
-                                                             uint64_t* __restrict__ mask) {
+                                                             uint64_t* __restrict__ mask,
+                                                             uint8_t* __restrict__ planes) {
     const int r = blockIdx.x * kThreads + threadIdx.x;
     if (r >= n) return;
     uint64_t bits = 0;
@@ -963,12 +990,14 @@ __global__ __launch_bounds__(kThreads) void sign_mask_kernel(int n, int k, uint6
         bits |= (x >> 63) << c;
     }
     mask[r] = bits;
+    if (planes)
+        for (int p = 0; p < 8; ++p) planes[(size_t)p * n + r] = (uint8_t)(bits >> (8 * p));
 }
 
-hipError_t launch_sign_mask(int n, int k, uint64_t key, uint64_t* mask, hipStream_t st) {
+hipError_t launch_sign_mask(int n, int k, uint64_t key, uint64_t* mask, hipStream_t st, uint8_t* planes) {
     if (n == 0) return hipSuccess;
     hipLaunchKernelGGL(sign_mask_kernel, dim3(div_up(n, kThreads)), dim3(kThreads), 0, st, n, k,
-                       key, mask);
+                       key, mask, planes);
     return hipGetLastError();
 }
 
