@@ -131,13 +131,20 @@ def test_estimate_dot_modes(mode, dtype, tol):
         assert rel(est, ref) < tol
 
 
-def test_estimate_block_cols_invariance():
+@pytest.mark.parametrize("dtype,widths", [(torch.float32, (4, 8, 12, 16, 20)), (torch.float64, (2, 4, 6))])
+def test_estimate_block_cols_invariance(dtype, widths):
+    # narrow sketch blocks on the diagonal storage read their signs from the
+    # byte planes when the block lies in one byte of the sign word (every
+    # block at 4 and 8 FP32 columns, 2 and 4 FP64; some at 12 and 6), the
+    # 64-bit words otherwise (16 and 20 take all k = 16 columns): the same
+    # estimate to the grouping of the FP64 sums
     csr = w.grid_laplacian_2d(40, 0.5)
-    A, _ = to_gpu(csr, torch.float32)
+    A, _ = to_gpu(csr, dtype)
     base = ld.logdet(A, 0.5, 8.5, 30, 48, 1)
-    for b in (4, 16, 20):
-        e = ld.logdet(A, 0.5, 8.5, 30, 48, 1, options=ld.Options(block_cols=b))
-        assert rel(e, base) < 1e-12
+    for b in widths:
+        e, st = ld.logdet(A, 0.5, 8.5, 30, 48, 1, options=ld.Options(block_cols=b), return_stats=True)
+        assert st["block_cols1"] == min(b, 16) and st["dia_constant"] == 1
+        assert rel(e, base) < 1e-12, b
     # deterministic repeat
     assert ld.logdet(A, 0.5, 8.5, 30, 48, 1) == base
 
