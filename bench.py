@@ -331,7 +331,7 @@ def copy_GBps(nbytes: int = 1 << 30, reps: int = 5) -> float:
     return 2.0 * nbytes / dt / 1e9
 
 
-def survey_bytes_per_estimate(n, nnz, degree, k, kg, elem=4):
+def method_bytes_per_estimate(n, nnz, degree, k, kg, elem=4):
     """The method's plain bytes per estimate: each Newton step reads the CSR
     matrix once (values + int32 indices + row pointers); the sketch step
     reads and writes the block and reads and writes the accumulator of
@@ -569,7 +569,7 @@ def run_workload(args, workload, steps):
     # a launch whose bytes fit the Infinity Cache streams (largely) from it:
     # its GB/s is then not an HBM bandwidth
     in_cache = kernels[dom]["bytes_per_launch"] <= INFINITY_CACHE_BYTES
-    survey = survey_bytes_per_estimate(n, nnz, degree, st["k"], st["k_G"])
+    method = method_bytes_per_estimate(n, nnz, degree, st["k"], st["k_G"])
 
     out = {
         "metric": METRIC,
@@ -626,8 +626,8 @@ def run_workload(args, workload, steps):
         "kernels": kernels,
         "alg_bytes": {
             "implementation_GB_per_estimate": total_bytes / 1e9,
-            "method_GB_per_estimate": survey / 1e9,
-            "reformulation_factor": survey / total_bytes,
+            "method_GB_per_estimate": method / 1e9,
+            "reformulation_factor": method / total_bytes,
             "note": ("method: Alg. 2 forward steps over the CSR matrix (8 B per entry + row pointers) for the "
                      "sketch (16 B per block element: read and write the block and the accumulator) and the "
                      "quadratic forms (12 B: read and write the block, read X), m steps each; "

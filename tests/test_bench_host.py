@@ -28,7 +28,7 @@ def test_method_bytes_of_the_bench_workload():
     sketch = a + 16 * n * 20
     quad = a + 12 * n * 40
     assert round(sketch / 1e6, 1) == 381.6 and round(quad / 1e6, 1) == 549.4
-    total = bench.survey_bytes_per_estimate(n, nnz, 80, 20, 20)
+    total = bench.method_bytes_per_estimate(n, nnz, 80, 20, 20)
     assert total == pytest.approx(80 * (sketch + quad), rel=1e-15)
     assert round(total / 1e9, 2) == 74.49
 
